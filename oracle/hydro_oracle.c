@@ -1,0 +1,343 @@
+/*
+ * Plain FP64 CPU oracle of the unsplit second-order Godunov hydro step.
+ * TEST INFRASTRUCTURE ONLY: see hydro_oracle.h for scope, layout and the
+ * readings of the method.  Compiled with -O2 -fno-fast-math -ffp-contract=off
+ * so that every operation below is one IEEE-754 double operation in the
+ * written order.  Loops are the definition written out; the only parallelism
+ * is an OpenMP loop over independent blocks, which changes no arithmetic.
+ */
+#include "hydro_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- layout ------------------------------------------------------------ */
+
+static int edge(const oracle_grid *g) { return g->n + 2 * g->ng; }
+
+size_t oracle_block_doubles(const oracle_grid *g) {
+  size_t P = (size_t)edge(g);
+  return 5 * P * P * P;
+}
+
+/* Offset of (var, i, j, k) inside a block; i, j, k are interior-relative
+ * (interior cells are 0..n-1, guards are -ng..-1 and n..n+ng-1). */
+static size_t at(const oracle_grid *g, int var, int i, int j, int k) {
+  size_t P = (size_t)edge(g);
+  return (((size_t)var * P + (size_t)(k + g->ng)) * P + (size_t)(j + g->ng)) * P + (size_t)(i + g->ng);
+}
+
+/* ---- a1: same-level guard fill (§2: block-by-block update with boundary
+ *      data supplied by the Grid unit; reading: periodic = mod, outflow =
+ *      clamp, composed per axis) ----------------------------------------- */
+
+static long map_index(long I, long N, int bc) {
+  if (bc == ORACLE_BC_PERIODIC) {
+    long r = I % N;
+    return r < 0 ? r + N : r;
+  }
+  if (I < 0) return 0;
+  if (I > N - 1) return N - 1;
+  return I;
+}
+
+void oracle_fill_guards_block(const oracle_grid *g, double *U, long b) {
+  const int n = g->n, ng = g->ng;
+  const long nbx = g->nb[0], nby = g->nb[1];
+  const long bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+  const long N[3] = {(long)g->nb[0] * n, (long)g->nb[1] * n, (long)g->nb[2] * n};
+  const size_t bd = oracle_block_doubles(g);
+  double *dst = U + (size_t)b * bd;
+  for (int k = -ng; k < n + ng; ++k)
+    for (int j = -ng; j < n + ng; ++j)
+      for (int i = -ng; i < n + ng; ++i) {
+        int interior = i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n;
+        if (interior) continue;
+        long I = map_index(bx * n + i, N[0], g->bc[0]);
+        long J = map_index(by * n + j, N[1], g->bc[1]);
+        long K = map_index(bz * n + k, N[2], g->bc[2]);
+        long sb = (I / n) + nbx * ((J / n) + nby * (K / n));
+        const double *src = U + (size_t)sb * bd;
+        for (int v = 0; v < 5; ++v)
+          dst[at(g, v, i, j, k)] = src[at(g, v, (int)(I % n), (int)(J % n), (int)(K % n))];
+      }
+}
+
+void oracle_fill_guards(const oracle_grid *g, double *U) {
+  long nblk = (long)g->nb[0] * g->nb[1] * g->nb[2];
+  /* Guards are written only from interiors, so blocks are independent. */
+#pragma omp parallel for schedule(dynamic, 4)
+  for (long b = 0; b < nblk; ++b) oracle_fill_guards_block(g, U, b);
+}
+
+/* ---- a2: conservative -> primitive, gamma-law EOS (§2.2, Equations of
+ *      State: the perfect-gas EOS) --------------------------------------- */
+
+int oracle_cons_to_prim(const double U[5], double gamma, double small_p, double W[5]) {
+  double rho = U[0];
+  double u = U[1] / rho;
+  double v = U[2] / rho;
+  double w = U[3] / rho;
+  double kinetic = 0.5 * rho * ((u * u + v * v) + w * w);
+  double p = (gamma - 1.0) * (U[4] - kinetic);
+  int floored = 0;
+  if (p < small_p) {
+    p = small_p;
+    floored = 1;
+  }
+  W[0] = rho;
+  W[1] = u;
+  W[2] = v;
+  W[3] = w;
+  W[4] = p;
+  return floored;
+}
+
+/* ---- a3: van Leer harmonic slope ---------------------------------------- */
+
+double oracle_van_leer(double dl, double dr) {
+  double prod = dl * dr;
+  if (prod > 0.0) return (2.0 * prod) / (dl + dr);
+  return 0.0;
+}
+
+/* ---- a4: Euler flux and HLLC (§2: explicit methods for compressible flow
+ *      with strong shocks; HLLC with Davis speeds and Batten's S*) ------- */
+
+static double total_energy(const double W[5], double gamma) {
+  return W[4] / (gamma - 1.0) + 0.5 * W[0] * ((W[1] * W[1] + W[2] * W[2]) + W[3] * W[3]);
+}
+
+void oracle_euler_flux(const double W[5], int d, double gamma, double F[5]) {
+  double un = W[1 + d];
+  double E = total_energy(W, gamma);
+  double mass = W[0] * un;
+  F[0] = mass;
+  F[1] = mass * W[1];
+  F[2] = mass * W[2];
+  F[3] = mass * W[3];
+  F[1 + d] += W[4];
+  F[4] = un * (E + W[4]);
+}
+
+/* Conserved star state of side K (Toro's HLLC star state with the normal
+ * velocity replaced by S*, tangential velocities kept). */
+static void star_state(const double W[5], int d, double gamma, double S, double Sstar, double Us[5]) {
+  double rho = W[0], un = W[1 + d], p = W[4];
+  double E = total_energy(W, gamma);
+  double factor = rho * (S - un) / (S - Sstar);
+  Us[0] = factor;
+  Us[1] = factor * W[1];
+  Us[2] = factor * W[2];
+  Us[3] = factor * W[3];
+  Us[1 + d] = factor * Sstar;
+  Us[4] = factor * (E / rho + (Sstar - un) * (Sstar + p / (rho * (S - un))));
+}
+
+static void prim_to_cons(const double W[5], double gamma, double U[5]) {
+  U[0] = W[0];
+  U[1] = W[0] * W[1];
+  U[2] = W[0] * W[2];
+  U[3] = W[0] * W[3];
+  U[4] = total_energy(W, gamma);
+}
+
+void oracle_hllc(const double WL[5], const double WR[5], int d, double gamma, double F[5]) {
+  double rL = WL[0], uL = WL[1 + d], pL = WL[4];
+  double rR = WR[0], uR = WR[1 + d], pR = WR[4];
+  double cL = sqrt(gamma * pL / rL);
+  double cR = sqrt(gamma * pR / rR);
+  double SL = (uL - cL < uR - cR) ? uL - cL : uR - cR;
+  double SR = (uL + cL > uR + cR) ? uL + cL : uR + cR;
+  double Sstar = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
+                 (rL * (SL - uL) - rR * (SR - uR));
+  if (SL >= 0.0) {
+    oracle_euler_flux(WL, d, gamma, F);
+  } else if (Sstar >= 0.0) {
+    double FK[5], UK[5], Us[5];
+    oracle_euler_flux(WL, d, gamma, FK);
+    prim_to_cons(WL, gamma, UK);
+    star_state(WL, d, gamma, SL, Sstar, Us);
+    for (int v = 0; v < 5; ++v) F[v] = FK[v] + SL * (Us[v] - UK[v]);
+  } else if (SR > 0.0) {
+    double FK[5], UK[5], Us[5];
+    oracle_euler_flux(WR, d, gamma, FK);
+    prim_to_cons(WR, gamma, UK);
+    star_state(WR, d, gamma, SR, Sstar, Us);
+    for (int v = 0; v < 5; ++v) F[v] = FK[v] + SR * (Us[v] - UK[v]);
+  } else {
+    oracle_euler_flux(WR, d, gamma, F);
+  }
+}
+
+/* ---- a3 predictor: A_d(W) * dW, the primitive-form Euler Jacobian along d - */
+
+static void jacobian_times(const double W[5], int d, double gamma, const double dW[5], double out[5]) {
+  double rho = W[0], un = W[1 + d], p = W[4];
+  out[0] = un * dW[0] + rho * dW[1 + d];
+  out[1] = un * dW[1];
+  out[2] = un * dW[2];
+  out[3] = un * dW[3];
+  out[1 + d] += dW[4] / rho;
+  out[4] = gamma * p * dW[1 + d] + un * dW[4];
+}
+
+/* ---- one block: a2..a5 (§2.2 Hydrodynamics: predictor, then corrector) --- */
+
+void oracle_step_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+                       long cnt[ORACLE_NCNT]) {
+  const int n = g->n, ng = g->ng, P = edge(g);
+  const double gamma = g->gamma;
+  const double lam[3] = {dt / g->dx[0], dt / g->dx[1], dt / g->dx[2]};
+  const size_t bd = oracle_block_doubles(g);
+  const double *Ub = U + (size_t)b * bd;
+  /* Cells that need face states: interior plus one layer, i.e. -1..n per axis. */
+  const int M = n + 2;
+  size_t ncell = (size_t)P * P * P;
+  size_t nm = (size_t)M * M * M;
+  double *W = (double *)malloc(sizeof(double) * 5 * ncell);    /* primitives, all cells */
+  double *S = (double *)malloc(sizeof(double) * 15 * nm);      /* slopes [d][var] */
+  double *Wp = (double *)malloc(sizeof(double) * 5 * nm);      /* predicted centre */
+  char *fb = (char *)malloc(nm);                               /* fallback flag */
+  size_t nf = (size_t)(n + 1) * n * n;
+  double *F[3];
+  for (int d = 0; d < 3; ++d) F[d] = (double *)malloc(sizeof(double) * 5 * nf);
+
+#define WI(i, j, k) (W + 5 * (((size_t)((k) + ng) * P + (size_t)((j) + ng)) * P + (size_t)((i) + ng)))
+#define MI(i, j, k) ((((size_t)((k) + 1) * M + (size_t)((j) + 1)) * M + (size_t)((i) + 1)))
+
+  /* a2: primitives of every stored cell; floor hits counted on the interior. */
+  for (int k = -ng; k < n + ng; ++k)
+    for (int j = -ng; j < n + ng; ++j)
+      for (int i = -ng; i < n + ng; ++i) {
+        double Uc[5];
+        for (int v = 0; v < 5; ++v) Uc[v] = Ub[at(g, v, i, j, k)];
+        int fl = oracle_cons_to_prim(Uc, gamma, g->small_p, WI(i, j, k));
+        if (fl && i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n) cnt[ORACLE_CNT_FLOOR]++;
+      }
+
+  /* a3: slopes, Hancock predictor, positivity check of the six face states. */
+  for (int k = -1; k <= n; ++k)
+    for (int j = -1; j <= n; ++j)
+      for (int i = -1; i <= n; ++i) {
+        const double *Wc = WI(i, j, k);
+        double *Sc = S + 15 * MI(i, j, k);
+        const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        for (int d = 0; d < 3; ++d) {
+          const double *Wm = WI(i - off[d][0], j - off[d][1], k - off[d][2]);
+          const double *Wq = WI(i + off[d][0], j + off[d][1], k + off[d][2]);
+          for (int v = 0; v < 5; ++v) Sc[5 * d + v] = oracle_van_leer(Wc[v] - Wm[v], Wq[v] - Wc[v]);
+        }
+        double A[3][5];
+        for (int d = 0; d < 3; ++d) jacobian_times(Wc, d, gamma, Sc + 5 * d, A[d]);
+        double *Wt = Wp + 5 * MI(i, j, k);
+        for (int v = 0; v < 5; ++v)
+          Wt[v] = Wc[v] - 0.5 * ((lam[0] * A[0][v] + lam[1] * A[1][v]) + lam[2] * A[2][v]);
+        int bad = 0;
+        for (int d = 0; d < 3; ++d)
+          for (int s = -1; s <= 1; s += 2) {
+            double r = Wt[0] + 0.5 * s * Sc[5 * d + 0];
+            double p = Wt[4] + 0.5 * s * Sc[5 * d + 4];
+            if (!(r > 0.0) || !(p > 0.0)) bad = 1;
+          }
+        fb[MI(i, j, k)] = (char)bad;
+        if (bad && i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n) cnt[ORACLE_CNT_FALLBACK]++;
+      }
+
+  /* a4: HLLC on every face of the interior; face (d, i, j, k) lies on the low
+   * side of cell (i, j, k) along d, with i (or j, k) running 0..n. */
+  for (int d = 0; d < 3; ++d) {
+    const int ex = d == 0, ey = d == 1, ez = d == 2;
+    const int ni = n + ex, nj = n + ey, nk = n + ez;
+    for (int k = 0; k < nk; ++k)
+      for (int j = 0; j < nj; ++j)
+        for (int i = 0; i < ni; ++i) {
+          int li = i - ex, lj = j - ey, lk = k - ez;
+          double WL[5], WR[5];
+          size_t mL = MI(li, lj, lk), mR = MI(i, j, k);
+          for (int v = 0; v < 5; ++v) {
+            WL[v] = fb[mL] ? WI(li, lj, lk)[v] : Wp[5 * mL + v] + 0.5 * S[15 * mL + 5 * d + v];
+            WR[v] = fb[mR] ? WI(i, j, k)[v] : Wp[5 * mR + v] - 0.5 * S[15 * mR + 5 * d + v];
+          }
+          size_t f = ((size_t)k * nj + (size_t)j) * ni + (size_t)i;
+          oracle_hllc(WL, WR, d, gamma, F[d] + 5 * f);
+        }
+  }
+
+  /* a5: conservative update of the interior. */
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        size_t fx0 = ((size_t)k * n + j) * (n + 1) + i, fx1 = fx0 + 1;
+        size_t fy0 = ((size_t)k * (n + 1) + j) * n + i, fy1 = fy0 + n;
+        size_t fz0 = ((size_t)k * n + j) * n + i, fz1 = fz0 + (size_t)n * n;
+        double Un[5];
+        for (int v = 0; v < 5; ++v) {
+          double div = (lam[0] * (F[0][5 * fx1 + v] - F[0][5 * fx0 + v]) +
+                        lam[1] * (F[1][5 * fy1 + v] - F[1][5 * fy0 + v])) +
+                       lam[2] * (F[2][5 * fz1 + v] - F[2][5 * fz0 + v]);
+          Un[v] = Ub[at(g, v, i, j, k)] - div;
+          Uo[at(g, v, i, j, k)] = Un[v];
+        }
+        int ok = Un[0] > 0.0 && Un[4] > 0.0;
+        for (int v = 0; v < 5; ++v) ok = ok && isfinite(Un[v]);
+        if (!ok) cnt[ORACLE_CNT_NONPHYS]++;
+      }
+#undef WI
+#undef MI
+  free(W);
+  free(S);
+  free(Wp);
+  free(fb);
+  for (int d = 0; d < 3; ++d) free(F[d]);
+}
+
+void oracle_step(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]) {
+  long nblk = (long)g->nb[0] * g->nb[1] * g->nb[2];
+  oracle_fill_guards(g, U);
+  long c0 = 0, c1 = 0, c2 = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : c0, c1, c2)
+  for (long b = 0; b < nblk; ++b) {
+    long c[ORACLE_NCNT] = {0, 0, 0};
+    oracle_step_block(g, U, b, Unew + (size_t)b * oracle_block_doubles(g), dt, c);
+    c0 += c[0];
+    c1 += c[1];
+    c2 += c[2];
+  }
+  cnt[ORACLE_CNT_FLOOR] += c0;
+  cnt[ORACLE_CNT_FALLBACK] += c1;
+  cnt[ORACLE_CNT_NONPHYS] += c2;
+}
+
+/* ---- a6: CFL signal speed and dt ---------------------------------------- */
+
+double oracle_max_signal(const oracle_grid *g, const double *U, long b0, long b1) {
+  const int n = g->n;
+  const size_t bd = oracle_block_doubles(g);
+  double smax = 0.0;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(max : smax) reduction(| : bad)
+  for (long b = b0; b < b1; ++b) {
+    const double *Ub = U + (size_t)b * bd;
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double Uc[5], W[5];
+          for (int v = 0; v < 5; ++v) Uc[v] = Ub[at(g, v, i, j, k)];
+          oracle_cons_to_prim(Uc, g->gamma, g->small_p, W);
+          double c = sqrt(g->gamma * W[4] / W[0]);
+          double s = ((fabs(W[1]) + c) / g->dx[0] + (fabs(W[2]) + c) / g->dx[1]) + (fabs(W[3]) + c) / g->dx[2];
+          if (!isfinite(s)) bad = 1;
+          else if (s > smax) smax = s;
+        }
+  }
+  return bad ? NAN : smax;
+}
+
+double oracle_dt(const oracle_grid *g, const double *U, double cfl) {
+  long nblk = (long)g->nb[0] * g->nb[1] * g->nb[2];
+  double s = oracle_max_signal(g, U, 0, nblk);
+  if (!(s > 0.0) || !isfinite(s)) return -1.0;
+  return cfl / s;
+}

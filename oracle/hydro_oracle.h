@@ -1,0 +1,93 @@
+/*
+ * Plain FP64 CPU oracle of the unsplit second-order Godunov hydro step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the HIP path; it is
+ * called from the test suite, from the package's smoke check and from the
+ * CPU-baseline leg of the benchmark, never from the product path.  It shares
+ * no code, header, table or helper with the HIP library.
+ *
+ * What it computes (the method behind the paper's compressible solver, §2
+ * "Software Description": explicit shock-capturing methods, block-by-block
+ * update on a uniform grid; §2.2 "Software Functionalities", Hydrodynamics:
+ * the predictor-corrector unsplit compressible solver; §2.2, Equations of
+ * State: the perfect-gas EOS).  The paper states the method by name only, so
+ * the formulas follow the textbook statement of each ingredient:
+ *   - same-level guard fill: periodic (index mod N) or zero-gradient outflow
+ *     (index clamped into the domain), composed per axis;
+ *   - conservative -> primitive with a gamma-law EOS and a pressure floor;
+ *   - van Leer harmonic slope 2ab/(a+b) for ab>0 (else 0) on primitives;
+ *   - MUSCL-Hancock half-step predictor in primitive form, all three
+ *     directions at once (fully unsplit, no transverse corner coupling);
+ *   - HLLC fluxes with Davis wave speeds and the Batten contact speed;
+ *   - the conservative flux-difference update;
+ *   - dt = CFL / max over cells of sum_d (|u_d| + c) / dx_d.
+ *
+ * Layout: a grid of nb[0]*nb[1]*nb[2] cubic blocks, block id
+ * b = bx + nb0*(by + nb1*bz).  Each block stores 5 conserved variables
+ * (rho, rho*u, rho*v, rho*w, E), each as a P^3 array (P = n + 2*ng), x
+ * fastest:  U[((b*5 + var)*P + k)*P*P + j*P + i], guard layers included.
+ *
+ * Every function is pinned by CPU tests against facts independent of this
+ * code: closed forms, special cases that reduce to textbook schemes, the
+ * exact Sod Riemann solution, conservation, symmetry and convergence order.
+ */
+#ifndef HYDRO_ORACLE_H
+#define HYDRO_ORACLE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORACLE_BC_PERIODIC 0
+#define ORACLE_BC_OUTFLOW 1
+
+typedef struct {
+  int n;          /* interior cells per block edge */
+  int ng;         /* guard layers per side (>= 2 needed by the stencil) */
+  int nb[3];      /* blocks per axis */
+  double dx[3];   /* cell widths */
+  int bc[3];      /* ORACLE_BC_* per axis (both sides) */
+  double gamma;   /* ratio of specific heats */
+  double small_p; /* pressure floor */
+} oracle_grid;
+
+/* Event counters of one step: [0] pressure-floor hits on interior cells,
+ * [1] interior cells whose face states fell back to first order,
+ * [2] interior cells left nonphysical (rho<=0, E<=0 or non-finite). */
+enum { ORACLE_CNT_FLOOR = 0, ORACLE_CNT_FALLBACK = 1, ORACLE_CNT_NONPHYS = 2, ORACLE_NCNT = 3 };
+
+size_t oracle_block_doubles(const oracle_grid *g);
+
+/* Primitive recovery of one cell; returns 1 when the pressure floor was hit. */
+int oracle_cons_to_prim(const double U[5], double gamma, double small_p, double W[5]);
+/* van Leer harmonic slope. */
+double oracle_van_leer(double dl, double dr);
+/* HLLC flux across a face normal to axis d (0,1,2) between primitive states. */
+void oracle_hllc(const double WL[5], const double WR[5], int d, double gamma, double F[5]);
+/* Exact Euler flux along axis d of a primitive state. */
+void oracle_euler_flux(const double W[5], int d, double gamma, double F[5]);
+
+/* Fill the guard layers of block b (or of every block) from block interiors. */
+void oracle_fill_guards_block(const oracle_grid *g, double *U, long b);
+void oracle_fill_guards(const oracle_grid *g, double *U);
+
+/* New interior of block b after one step of size dt.  U must hold block b's
+ * guards filled.  Uo is one block's storage (oracle_block_doubles values);
+ * its interior receives the result, its guards are left untouched. */
+void oracle_step_block(const oracle_grid *g, const double *U, long b, double *Uo,
+                       double dt, long cnt[ORACLE_NCNT]);
+
+/* One full step: fills U's guards, then updates every block into Unew. */
+void oracle_step(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]);
+
+/* max over interior cells of sum_d (|u_d| + c)/dx_d; the block range [b0,b1). */
+double oracle_max_signal(const oracle_grid *g, const double *U, long b0, long b1);
+/* dt = cfl / max signal over all blocks; returns -1 when the maximum is not positive and finite. */
+double oracle_dt(const oracle_grid *g, const double *U, double cfl);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,58 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake (a dropped term, a wrong sign, a swapped operand
+or index) in a copy of the oracle's C source, builds it on the CPU, and runs
+the pin tests against the broken copy in a subprocess: at least one pin must
+fail.  Nothing here touches the GPU or the HIP library.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "hydro_oracle.c")
+
+MUTATIONS = {
+    "eos_drops_kinetic": ("(gamma - 1.0) * (U[4] - kinetic)", "(gamma - 1.0) * (U[4])"),
+    "limiter_drops_factor_2": ("(2.0 * prod) / (dl + dr)", "prod / (dl + dr)"),
+    "predictor_sign": ("Wt[v] = Wc[v] - 0.5 *", "Wt[v] = Wc[v] + 0.5 *"),
+    "predictor_drops_dp_over_rho": ("out[1 + d] += dW[4] / rho;", ""),
+    "predictor_drops_gamma": ("out[4] = gamma * p * dW[1 + d]", "out[4] = p * dW[1 + d]"),
+    "predictor_tangential_uses_normal": ("out[2] = un * dW[2];", "out[2] = un * dW[1];"),
+    "face_state_sign": ("Wp[5 * mL + v] + 0.5 * S", "Wp[5 * mL + v] - 0.5 * S"),
+    "face_state_wrong_direction": ("S[15 * mR + 5 * d + v]", "S[15 * mR + 5 * ((d + 1) % 3) + v]"),
+    "davis_speed_swapped": ("(uL - cL < uR - cR) ? uL - cL : uR - cR", "(uL - cL < uR - cR) ? uR - cR : uL - cL"),
+    "star_energy_sign": ("(Sstar + p / (rho * (S - un)))", "(Sstar - p / (rho * (S - un)))"),
+    "star_tangential_dropped": ("Us[2] = factor * W[2];", "Us[2] = factor;"),
+    "energy_flux_drops_p": ("F[4] = un * (E + W[4]);", "F[4] = un * E;"),
+    "update_sign": ("Un[v] = Ub[at(g, v, i, j, k)] - div;", "Un[v] = Ub[at(g, v, i, j, k)] + div;"),
+    "lambda_z_uses_dy": ("dt / g->dx[2]}", "dt / g->dx[1]}"),
+    "outflow_clamp_wrong_end": ("if (I > N - 1) return N - 1;", "if (I > N - 1) return N - 2;"),
+    "periodic_wrap_off_by_one": ("return r < 0 ? r + N : r;", "return r < 0 ? r + N - 1 : r;"),
+    "dt_drops_sound_speed_in_z": ("(fabs(W[3]) + c) / g->dx[2]", "fabs(W[3]) / g->dx[2]"),
+    "fallback_never_applies": ("if (!(r > 0.0) || !(p > 0.0)) bad = 1;", ""),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique/found: {old!r}"
+    mut = tmp_path / "hydro_oracle.c"
+    mut.write_text(src.replace(old, new))
+    hdr = os.path.join(ROOT, "oracle", "hydro_oracle.h")
+    (tmp_path / "hydro_oracle.h").write_text(open(hdr).read())
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+                    "-shared", "-std=c99", "-o", str(lib), str(mut), "-lm"], check=True)
+    env = dict(os.environ, HYDRO_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "tests/test_oracle_units.py", "tests/test_oracle_step.py",
+                        "tests/test_oracle_fallback.py"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutation {name} survived all pins:\n{r.stdout[-2000:]}"

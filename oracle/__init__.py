@@ -75,6 +75,8 @@ def lib():
         L.oracle_fill_guards.restype = None
         L.oracle_step_block.argtypes = [gp, dp, ctypes.c_long, dp, ctypes.c_double, lp]
         L.oracle_step_block.restype = None
+        L.oracle_step_block_list.argtypes = [gp, dp, lp, ctypes.c_long, dp, ctypes.c_double, lp]
+        L.oracle_step_block_list.restype = None
         L.oracle_step.argtypes = [gp, dp, dp, ctypes.c_double, lp]
         L.oracle_step.restype = None
         L.oracle_max_signal.argtypes = [gp, dp, ctypes.c_long, ctypes.c_long]
@@ -179,20 +181,19 @@ def step(g: Grid, U: np.ndarray, dt: float):
 
 
 def step_blocks(g: Grid, U: np.ndarray, blocks: Sequence[int], dt: float):
-    """New interiors of the listed blocks (guards of those blocks filled first).
-    Returns an array [len(blocks), 5, n, n, n] and the summed counters."""
+    """New interiors of the listed blocks (guards of those blocks filled first,
+    blocks spread over the host cores).  Returns [len(blocks), 5, n, n, n] and
+    the summed counters."""
     g.check(U)
     gc = g.c()
-    L = lib()
     n, ng = g.n, g.ng
-    res = np.empty((len(blocks), 5, n, n, n))
+    bl = np.ascontiguousarray(blocks, dtype=np.int64)
+    tmp = np.empty((len(bl),) + g.shape()[1:])
     cnt = (ctypes.c_long * 3)(0, 0, 0)
-    tmp = np.empty((1,) + g.shape()[1:])
-    for t, b in enumerate(blocks):
-        L.oracle_fill_guards_block(ctypes.byref(gc), _dptr(U), int(b))
-        L.oracle_step_block(ctypes.byref(gc), _dptr(U), int(b), _dptr(tmp), float(dt), cnt)
-        res[t] = tmp[0, :, ng:ng + n, ng:ng + n, ng:ng + n]
-    return res, np.array(list(cnt), dtype=np.int64)
+    lib().oracle_step_block_list(ctypes.byref(gc), _dptr(U),
+                                 bl.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(bl),
+                                 _dptr(tmp), float(dt), cnt)
+    return np.ascontiguousarray(tmp[:, :, ng:ng + n, ng:ng + n, ng:ng + n]), np.array(list(cnt), dtype=np.int64)
 
 
 def max_signal(g: Grid, U: np.ndarray) -> float:

@@ -310,6 +310,27 @@ void oracle_step(const oracle_grid *g, double *U, double *Unew, double dt, long 
   cnt[ORACLE_CNT_NONPHYS] += c2;
 }
 
+/* The listed blocks only (their guards filled first); block t's new interior
+ * goes to out + t * oracle_block_doubles(g).  Blocks are independent, so an
+ * OpenMP loop spreads them over the host cores. */
+void oracle_step_block_list(const oracle_grid *g, double *U, const long *blocks, long nlist,
+                            double *out, double dt, long cnt[ORACLE_NCNT]) {
+  const size_t bd = oracle_block_doubles(g);
+  long c0 = 0, c1 = 0, c2 = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : c0, c1, c2)
+  for (long t = 0; t < nlist; ++t) {
+    long c[ORACLE_NCNT] = {0, 0, 0};
+    oracle_fill_guards_block(g, U, blocks[t]);
+    oracle_step_block(g, U, blocks[t], out + (size_t)t * bd, dt, c);
+    c0 += c[0];
+    c1 += c[1];
+    c2 += c[2];
+  }
+  cnt[ORACLE_CNT_FLOOR] += c0;
+  cnt[ORACLE_CNT_FALLBACK] += c1;
+  cnt[ORACLE_CNT_NONPHYS] += c2;
+}
+
 /* ---- a6: CFL signal speed and dt ---------------------------------------- */
 
 double oracle_max_signal(const oracle_grid *g, const double *U, long b0, long b1) {

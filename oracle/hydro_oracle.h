@@ -79,6 +79,12 @@ void oracle_fill_guards(const oracle_grid *g, double *U);
 void oracle_step_block(const oracle_grid *g, const double *U, long b, double *Uo,
                        double dt, long cnt[ORACLE_NCNT]);
 
+/* Step a list of blocks (guards of each filled first, then updated); block
+ * t's result goes to out + t*oracle_block_doubles(g).  Guards are written
+ * only from interiors, so the blocks are independent. */
+void oracle_step_block_list(const oracle_grid *g, double *U, const long *blocks, long nlist,
+                            double *out, double dt, long cnt[ORACLE_NCNT]);
+
 /* One full step: fills U's guards, then updates every block into Unew. */
 void oracle_step(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]);
 

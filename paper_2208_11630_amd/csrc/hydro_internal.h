@@ -1,0 +1,49 @@
+// Internal interface between the C-ABI host code (api.cpp) and the HIP
+// kernels (hydro_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hydro {
+
+// Device workspace header, at the start of the caller's workspace buffer.
+// sig[] hold the bit patterns of the maximum CFL signal speed (non-negative
+// doubles order like their unsigned bit patterns), triple-buffered by step
+// number s: a step reads sig[s%3] (device-side dt), reduces the new state
+// into sig[(s+1)%3] and clears sig[(s+2)%3] for the step after next.
+struct WorkHeader {
+  unsigned long long sig[3];
+  unsigned long long cnt[3];  // floor hits, fallbacks, nonphysical cells
+  double dt_last;             // dt of the most recent step
+  unsigned long long pad[25];
+};
+static_assert(sizeof(WorkHeader) == 256, "workspace header is 256 bytes");
+
+// Geometry and physics shared by every kernel of one grid.
+struct GridGeom {
+  int nb[3];          // blocks per axis
+  int bc[3];          // 0 periodic, 1 outflow
+  double inv_dx[3];   // 1/dx per axis
+  double gamma;
+  double small_p;
+};
+
+// Per-launch arguments of the step kernel.
+struct StepArgs {
+  const double* Uin;  // input state (compact layout, see hydro.h)
+  double* Uout;       // output state
+  WorkHeader* ws;
+  double dt;          // used when cfl <= 0
+  double cfl;         // > 0: dt = cfl / max signal speed in ws->sig[slot]
+  int slot;           // step number mod 3
+};
+
+hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, hipStream_t s);
+hipError_t launch_fill_guards(int nxb, const GridGeom& g, const double* U, double* out, hipStream_t s);
+hipError_t launch_signal(int nxb, const GridGeom& g, const double* U, WorkHeader* ws, int slot,
+                         hipStream_t s);
+hipError_t launch_clear_slot(WorkHeader* ws, int slot, hipStream_t s);
+hipError_t launch_copy(const double* src, double* dst, long n, hipStream_t s);
+
+}  // namespace hydro

@@ -1,0 +1,235 @@
+"""Thin Python binding of libhydro.so (C ABI declared in include/hydro.h).
+
+Argument marshalling only: torch provides device memory and the stream, every
+step of the computation runs in the library's HIP kernels.  Loading fails
+loudly (``HydroLibraryMissing``) when the library has not been built; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhydro.so")
+
+HYDRO_OK = 0
+HYDRO_EINVAL = -1
+HYDRO_ESIZE = -2
+HYDRO_EDEVICE = -3
+HYDRO_ENONPHYS = -4
+BC_PERIODIC = 0
+BC_OUTFLOW = 1
+NGUARD = 4
+
+# Every entry point include/hydro.h declares, with its ctypes signature.
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Desc(ctypes.Structure):
+    """hydro_grid_desc."""
+
+    _fields_ = [
+        ("nxb", ctypes.c_int),
+        ("nguard", ctypes.c_int),
+        ("nblk", ctypes.c_int * 3),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("bc", ctypes.c_int * 3),
+        ("gamma", ctypes.c_double),
+        ("small_p", ctypes.c_double),
+        ("U", ctypes.c_void_p),
+        ("U_alt", ctypes.c_void_p),
+        ("work", ctypes.c_void_p),
+        ("work_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_DP = ctypes.POINTER(Desc)
+_HP = ctypes.c_void_p
+SIGNATURES = {
+    "hydro_state_doubles": ([_DP], ctypes.c_size_t),
+    "hydro_guarded_doubles": ([_DP], ctypes.c_size_t),
+    "hydro_work_bytes": ([_DP], ctypes.c_size_t),
+    "hydro_init_grid": ([_DP, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "hydro_fill_guards": ([_HP, ctypes.c_void_p], ctypes.c_int),
+    "hydro_step": ([_HP, ctypes.c_double], ctypes.c_int),
+    "hydro_step_cfl": ([_HP, ctypes.c_double], ctypes.c_int),
+    "hydro_dt": ([_HP, ctypes.c_double, _dp], ctypes.c_int),
+    "hydro_last_dt": ([_HP, _dp], ctypes.c_int),
+    "hydro_state_changed": ([_HP], ctypes.c_int),
+    "hydro_current": ([_HP, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "hydro_counters": ([_HP, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+    "hydro_free_grid": ([_HP], ctypes.c_int),
+    "hydro_copy_probe": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "hydro_last_error": ([], ctypes.c_char_p),
+}
+
+
+class HydroLibraryMissing(ImportError):
+    pass
+
+
+class HydroError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libhydro error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhydro.so (raises HydroLibraryMissing if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HydroLibraryMissing(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc != HYDRO_OK:
+        raise HydroError(rc, lib().hydro_last_error().decode())
+    return rc
+
+
+def make_desc(nxb: int, nblk: Sequence[int], lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+              bc=(BC_PERIODIC,) * 3, gamma: float = 1.4, small_p: float = 1e-10,
+              nguard: int = NGUARD) -> Desc:
+    d = Desc()
+    d.nxb, d.nguard = int(nxb), int(nguard)
+    d.nblk[:] = [int(x) for x in nblk]
+    d.lo[:] = [float(x) for x in lo]
+    d.hi[:] = [float(x) for x in hi]
+    d.bc[:] = [int(x) for x in bc]
+    d.gamma, d.small_p = float(gamma), float(small_p)
+    return d
+
+
+class Grid:
+    """A grid handle over two torch state tensors and a workspace tensor.
+
+    State tensors have the compact shape ``[nblk, 5, nxb, nxb, nxb]``,
+    float64, on ``device``; the current one is ``self.state``."""
+
+    def __init__(self, nxb: int, nblk: Sequence[int], lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                 bc=(BC_PERIODIC,) * 3, gamma: float = 1.4, small_p: float = 1e-10,
+                 device: str = "cuda", stream=None, nguard: int = NGUARD):
+        import torch
+
+        L = lib()
+        self._torch = torch
+        self.nxb, self.nblk = int(nxb), tuple(int(x) for x in nblk)
+        self.nguard = int(nguard)
+        d = make_desc(nxb, nblk, lo, hi, bc, gamma, small_p, nguard)
+        nd = L.hydro_state_doubles(ctypes.byref(d))
+        n = self.nxb
+        nb = self.nblk[0] * self.nblk[1] * self.nblk[2]
+        if nd != nb * 5 * n ** 3:
+            raise HydroError(HYDRO_EINVAL, "invalid grid shape")
+        self.shape = (nb, 5, n, n, n)
+        P = n + 2 * self.nguard
+        self.guarded_shape = (nb, 5, P, P, P)
+        self.bufs = [torch.empty(self.shape, dtype=torch.float64, device=device) for _ in range(2)]
+        wb = L.hydro_work_bytes(ctypes.byref(d))
+        self.work = torch.zeros(max(wb, 256), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.bufs[0].device)
+        d.U = self.bufs[0].data_ptr()
+        d.U_alt = self.bufs[1].data_ptr()
+        d.work = self.work.data_ptr()
+        d.work_bytes = self.work.numel()
+        d.stream = self.stream.cuda_stream
+        self.desc = d
+        h = ctypes.c_void_p()
+        _check(L.hydro_init_grid(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+
+    # -- state access ---------------------------------------------------------
+    @property
+    def state(self):
+        p = ctypes.c_void_p()
+        _check(lib().hydro_current(self.handle, ctypes.byref(p)))
+        return self.bufs[0] if p.value == self.bufs[0].data_ptr() else self.bufs[1]
+
+    def upload(self, U: np.ndarray) -> None:
+        """Copy a host state (compact blocked layout) into the current buffer."""
+        t = self._torch.from_numpy(np.ascontiguousarray(U, dtype=np.float64))
+        with self._torch.cuda.stream(self.stream):
+            self.state.copy_(t, non_blocking=False)
+        _check(lib().hydro_state_changed(self.handle))
+
+    def download(self) -> np.ndarray:
+        self.stream.synchronize()
+        return self.state.cpu().numpy()
+
+    # -- the operations ---------------------------------------------------------
+    def fill_guards(self, out=None):
+        """Guarded view [nblk, 5, P, P, P] of the current state (a torch tensor)."""
+        if out is None:
+            out = self._torch.empty(self.guarded_shape, dtype=self._torch.float64, device=self.bufs[0].device)
+        _check(lib().hydro_fill_guards(self.handle, out.data_ptr()))
+        return out
+
+    def step(self, dt: float) -> None:
+        _check(lib().hydro_step(self.handle, float(dt)))
+
+    def step_cfl(self, cfl: float) -> None:
+        _check(lib().hydro_step_cfl(self.handle, float(cfl)))
+
+    def dt(self, cfl: float) -> float:
+        out = ctypes.c_double()
+        _check(lib().hydro_dt(self.handle, float(cfl), ctypes.byref(out)))
+        return out.value
+
+    def last_dt(self) -> float:
+        out = ctypes.c_double()
+        _check(lib().hydro_last_dt(self.handle, ctypes.byref(out)))
+        return out.value
+
+    def counters(self) -> np.ndarray:
+        out = (ctypes.c_longlong * 3)()
+        _check(lib().hydro_counters(self.handle, out))
+        return np.array(list(out), dtype=np.int64)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            lib().hydro_free_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def copy_probe(src, dst, stream=None) -> None:
+    """Streaming copy of src into dst (float64 torch tensors, same size)."""
+    import torch
+
+    if src.dtype != torch.float64 or dst.dtype != torch.float64 or src.numel() != dst.numel():
+        raise ValueError("copy_probe needs two float64 tensors of the same size")
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    _check(lib().hydro_copy_probe(src.data_ptr(), dst.data_ptr(), src.numel(), st.cuda_stream))
+
+
+def grid_for(problem, device: str = "cuda", stream=None) -> Grid:
+    """A Grid shaped for an ``ics.Problem`` with its initial state uploaded."""
+    lo = problem.lo
+    hi = problem.hi
+    g = Grid(problem.n, problem.nb, lo, hi, problem.bc, problem.gamma, problem.small_p,
+             device=device, stream=stream, nguard=problem.ng)
+    g.upload(problem.Uc)
+    return g

@@ -2,9 +2,10 @@
 
 This module is shared by the HIP path's tests and the oracle's tests: it
 draws initial states and rearranges arrays between the global ``[5, Z, Y, X]``
-order and the blocked ``[nblk, 5, P, P, P]`` storage (P = n + 2*ng, x
-fastest, block id b = bx + nbx*(by + nby*bz)).  It holds none of the step's
-arithmetic.  The only formula it evaluates is the definition of the initial
+order, the compact blocked storage ``[nblk, 5, n, n, n]`` of the HIP library
+and the guarded blocked storage ``[nblk, 5, P, P, P]`` (P = n + 2*ng) the
+oracle works on; x fastest, block id b = bx + nbx*(by + nby*bz).  It holds
+none of the step's arithmetic.  The only formula it evaluates is the definition of the initial
 total energy of a gamma-law gas, E = p/(gamma-1) + rho*|v|^2/2, which sets up
 the problem.
 
@@ -30,7 +31,12 @@ NGUARD = 4
 
 @dataclass
 class Problem:
-    """A grid plus its initial conserved state in blocked, guarded storage."""
+    """A grid plus its initial conserved state.
+
+    ``data`` is either the compact blocked array ``[nblk, 5, n, n, n]`` (the
+    state layout of the HIP library) or the guarded blocked array
+    ``[nblk, 5, P, P, P]`` (P = n + 2*ng, the textbook layout the oracle works
+    on); ``Uc`` and ``U`` give each view, converting (and caching) on demand."""
 
     name: str
     n: int                      # interior cells per block edge
@@ -38,12 +44,35 @@ class Problem:
     dx: Tuple[float, float, float]
     bc: Tuple[int, int, int]
     gamma: float
-    U: np.ndarray               # [nblk, 5, P, P, P] float64, guards zero
+    data: np.ndarray
     small_p: float = 1e-10
     cfl: float = 0.8
     steps: int = 1
     ng: int = NGUARD
     meta: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        P = self.n + 2 * self.ng
+        if self.data.shape[2:] == (self.n,) * 3:
+            self._c, self._g = self.data, None
+        elif self.data.shape[2:] == (P,) * 3:
+            self._c, self._g = None, self.data
+        else:
+            raise ValueError(f"state shape {self.data.shape} fits neither layout")
+
+    @property
+    def U(self) -> np.ndarray:
+        """Guarded layout [nblk, 5, P, P, P] (guards zero until filled)."""
+        if self._g is None:
+            self._g = guard_layout(self._c, self.n, self.ng)
+        return self._g
+
+    @property
+    def Uc(self) -> np.ndarray:
+        """Compact layout [nblk, 5, n, n, n]."""
+        if self._c is None:
+            self._c = np.ascontiguousarray(interior(self._g, self.n, self.ng))
+        return self._c
 
     @property
     def nblk(self) -> int:
@@ -79,16 +108,37 @@ def to_blocks(G: np.ndarray, n: int, ng: int = NGUARD, out: np.ndarray | None = 
     return out
 
 
-def from_blocks(B: np.ndarray, n: int, nb: Tuple[int, int, int], ng: int = NGUARD) -> np.ndarray:
-    """Blocked ``[nblk, 5, P, P, P]`` -> global interior ``[5, Z, Y, X]``."""
-    nbx, nby, nbz = nb
+def to_compact(G: np.ndarray, n: int) -> np.ndarray:
+    """Global ``[5, Z, Y, X]`` -> compact blocked ``[nblk, 5, n, n, n]``."""
+    _, Z, Y, X = G.shape
+    if X % n or Y % n or Z % n:
+        raise ValueError("grid extent must be a multiple of the block size")
+    nbx, nby, nbz = X // n, Y // n, Z // n
+    v = G.reshape(5, nbz, n, nby, n, nbx, n).transpose(1, 3, 5, 0, 2, 4, 6)
+    return np.ascontiguousarray(v).reshape(nbx * nby * nbz, 5, n, n, n)
+
+
+def guard_layout(C: np.ndarray, n: int, ng: int = NGUARD) -> np.ndarray:
+    """Compact ``[nblk, 5, n, n, n]`` -> guarded ``[nblk, 5, P, P, P]`` (guards zero)."""
     P = n + 2 * ng
-    I = B.reshape(nbz, nby, nbx, 5, P, P, P)[..., ng:ng + n, ng:ng + n, ng:ng + n]
+    out = np.zeros((C.shape[0], 5, P, P, P))
+    out[:, :, ng:ng + n, ng:ng + n, ng:ng + n] = C
+    return out
+
+
+def from_blocks(B: np.ndarray, n: int, nb: Tuple[int, int, int], ng: int = NGUARD) -> np.ndarray:
+    """Blocked storage (guarded or compact) -> global interior ``[5, Z, Y, X]``."""
+    nbx, nby, nbz = nb
+    I = interior(B, n, ng)
+    I = I.reshape(nbz, nby, nbx, 5, n, n, n)
     return np.ascontiguousarray(I.transpose(3, 0, 4, 1, 5, 2, 6)).reshape(5, nbz * n, nby * n, nbx * n)
 
 
 def interior(B: np.ndarray, n: int, ng: int = NGUARD) -> np.ndarray:
-    """View of the interiors ``[nblk, 5, n, n, n]`` of blocked storage."""
+    """Interiors ``[nblk, 5, n, n, n]`` of blocked storage (a view; compact
+    storage is returned as is)."""
+    if B.shape[2] == n:
+        return B
     return B[:, :, ng:ng + n, ng:ng + n, ng:ng + n]
 
 
@@ -145,7 +195,7 @@ def sod(N: int = 64, n: int = 16, axis: int = 0, shape=None) -> Problem:
     bc = [PERIODIC] * 3
     bc[axis] = OUTFLOW
     return Problem("sod", n, (X // n, Y // n, Z // n), (h, h, h), tuple(bc), 1.4,
-                   to_blocks(G, n), steps=20, meta={"axis": axis})
+                   to_compact(G, n), steps=20, meta={"axis": axis})
 
 
 def sedov_deposit_mask(N: int) -> np.ndarray:
@@ -168,7 +218,7 @@ def sedov(N: int = 256, n: int = 16, steps: int = 100) -> Problem:
     nin = int(mask.sum())
     G[4][mask] = 1.0 / (nin * h ** 3)
     return Problem("sedov", n, (N // n,) * 3, (h, h, h), (PERIODIC,) * 3, gamma,
-                   to_blocks(G, n), steps=steps, meta={"n_deposit": nin})
+                   to_compact(G, n), steps=steps, meta={"n_deposit": nin})
 
 
 def kelvin_helmholtz(shape=(512, 512, 256), n: int = 16, seed: int = 1, steps: int = 10) -> Problem:
@@ -187,7 +237,7 @@ def kelvin_helmholtz(shape=(512, 512, 256), n: int = 16, seed: int = 1, steps: i
     dvy = rng.uniform(-0.01, 0.01, size=(Z, Y, X))
     G = conserved(rho, vx0 + dvx, dvy, np.zeros((Z, Y, X)), np.full((Z, Y, X), 2.5), gamma)
     return Problem("kh", n, (X // n, Y // n, Z // n), (h, h, h), (PERIODIC,) * 3, gamma,
-                   to_blocks(G, n), steps=steps)
+                   to_compact(G, n), steps=steps)
 
 
 def random_state(rng: np.random.Generator, shape, gamma: float = 1.4) -> np.ndarray:
@@ -230,7 +280,7 @@ def ensemble(count: int = 512, seed: int = 2, steps: int = 50, shapes=None) -> L
         G = random_state(rng, (Z, Y, X))
         h = 1.0 / X
         sims.append(Problem(f"ens{s}", n, nb, (h, h, h), (PERIODIC,) * 3, 1.4,
-                            to_blocks(G, n), steps=steps))
+                            to_compact(G, n), steps=steps))
     return sims
 
 
@@ -249,7 +299,7 @@ def served_sim(sim: int, L: int, seed: int = 3, n: int = 16) -> Problem:
     G = random_state(rng, (L, L, L))
     h = 1.0 / L
     return Problem(f"srv{sim}", n, (L // n,) * 3, (h, h, h), (PERIODIC,) * 3, 1.4,
-                   to_blocks(G, n), steps=1)
+                   to_compact(G, n), steps=1)
 
 
 def uniform(n: int = 16, nb=(2, 2, 2), rho=1.3, vel=(0.3, -0.2, 0.1), p=0.7, gamma=1.4,
@@ -259,11 +309,11 @@ def uniform(n: int = 16, nb=(2, 2, 2), rho=1.3, vel=(0.3, -0.2, 0.1), p=0.7, gam
     one = np.ones((Z, Y, X))
     G = conserved(rho * one, vel[0] * one, vel[1] * one, vel[2] * one, p * one, gamma)
     h = dx if dx is not None else (1.0 / X,) * 3
-    return Problem("uniform", n, tuple(nb), tuple(h), tuple(bc), gamma, to_blocks(G, n))
+    return Problem("uniform", n, tuple(nb), tuple(h), tuple(bc), gamma, to_compact(G, n))
 
 
 def from_primitive(name: str, n: int, rho, u, v, w, p, gamma: float, dx, bc) -> Problem:
     """Blocked problem from primitive global fields [Z, Y, X] (helper for tests)."""
     G = conserved(rho, u, v, w, p, gamma)
     Z, Y, X = G.shape[1:]
-    return Problem(name, n, (X // n, Y // n, Z // n), tuple(dx), tuple(bc), gamma, to_blocks(G, n))
+    return Problem(name, n, (X // n, Y // n, Z // n), tuple(dx), tuple(bc), gamma, to_compact(G, n))

@@ -1,0 +1,104 @@
+"""The C-ABI library loads on the CPU, exports every declared entry point, and
+rejects bad descriptors before touching a device.  No compute calls here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2208_11630_amd import hydro
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(hydro_\w+)\s*\(", text, flags=re.M)
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(hydro.LIB_PATH):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    return hydro.lib()
+
+
+def test_every_declared_symbol_is_exported_and_bound(L):
+    names = declared_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in hydro.SIGNATURES, f"binding misses {n}"
+    assert set(hydro.SIGNATURES) <= set(names)
+
+
+def _good():
+    d = hydro.make_desc(16, (2, 3, 4))
+    d.U, d.U_alt, d.work, d.work_bytes = 1 << 20, 1 << 36, 1 << 40, 256
+    return d
+
+
+def test_sizes(L):
+    d = _good()
+    assert L.hydro_state_doubles(ctypes.byref(d)) == 24 * 5 * 16 ** 3
+    assert L.hydro_guarded_doubles(ctypes.byref(d)) == 24 * 5 * 24 ** 3
+    assert L.hydro_work_bytes(ctypes.byref(d)) == 256
+    assert L.hydro_state_doubles(None) == 0
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("nxb", 12, hydro.HYDRO_EINVAL),
+    ("nxb", 0, hydro.HYDRO_EINVAL),
+    ("nguard", 2, hydro.HYDRO_EINVAL),
+    ("gamma", 1.0, hydro.HYDRO_EINVAL),
+    ("gamma", float("nan"), hydro.HYDRO_EINVAL),
+    ("small_p", -1.0, hydro.HYDRO_EINVAL),
+    ("U", 0, hydro.HYDRO_EINVAL),
+    ("U", (1 << 20) + 8, hydro.HYDRO_EINVAL),      # misaligned
+    ("U_alt", 1 << 20, hydro.HYDRO_EINVAL),        # same buffer
+    ("work", 0, hydro.HYDRO_EINVAL),
+    ("work_bytes", 128, hydro.HYDRO_ESIZE),
+])
+def test_descriptor_validation(L, field, value, code):
+    d = _good()
+    setattr(d, field, value)
+    h = ctypes.c_void_p()
+    assert L.hydro_init_grid(ctypes.byref(d), ctypes.byref(h)) == code
+    assert h.value is None
+    assert L.hydro_last_error().decode()
+
+
+@pytest.mark.parametrize("arr,idx,value", [("nblk", 1, 0), ("bc", 2, 7), ("hi", 0, 0.0), ("lo", 2, float("inf"))])
+def test_descriptor_array_validation(L, arr, idx, value):
+    d = _good()
+    getattr(d, arr)[idx] = value
+    h = ctypes.c_void_p()
+    assert L.hydro_init_grid(ctypes.byref(d), ctypes.byref(h)) == hydro.HYDRO_EINVAL
+
+
+def test_null_arguments(L):
+    h = ctypes.c_void_p()
+    assert L.hydro_init_grid(None, ctypes.byref(h)) == hydro.HYDRO_EINVAL
+    assert L.hydro_fill_guards(None, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_step(None, 1e-3) == hydro.HYDRO_EINVAL
+    assert L.hydro_step_cfl(None, 0.8) == hydro.HYDRO_EINVAL
+    out = ctypes.c_double()
+    assert L.hydro_dt(None, 0.8, ctypes.byref(out)) == hydro.HYDRO_EINVAL
+    assert L.hydro_last_dt(None, ctypes.byref(out)) == hydro.HYDRO_EINVAL
+    assert L.hydro_state_changed(None) == hydro.HYDRO_EINVAL
+    assert L.hydro_counters(None, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_free_grid(None) == hydro.HYDRO_OK
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(hydro, "_lib", None)
+    monkeypatch.setattr(hydro, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(hydro.HydroLibraryMissing):
+        hydro.lib()

@@ -38,7 +38,8 @@ def make_workload(name):
 
 def cpu_baseline(P, seconds_target=15.0):
     """The oracle (plain FP64 C, OpenMP over blocks) on a bounded sample of the
-    same workload: the first blocks of the grid, one step each."""
+    same workload: one step of the first nb blocks of the grid, nb doubling
+    until one timing takes at least half the target (or covers the grid)."""
     import numpy as np
 
     import oracle
@@ -47,23 +48,18 @@ def cpu_baseline(P, seconds_target=15.0):
     dt = oracle.dt(g, P.U, P.cfl) if P.nblk <= 4096 else 1e-4
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     nb = min(64, P.nblk)
-    used = 0
-    elapsed = 0.0
-    t0 = time.perf_counter()
     while True:
-        blocks = np.arange(used, used + nb) % P.nblk
+        blocks = np.arange(nb)
         t1 = time.perf_counter()
         oracle.step_blocks(g, P.U, blocks, dt)
-        elapsed += time.perf_counter() - t1
-        used += nb
-        if elapsed >= seconds_target or time.perf_counter() - t0 > 2 * seconds_target:
+        elapsed = time.perf_counter() - t1
+        if elapsed >= seconds_target / 2 or nb == P.nblk:
             break
-        if elapsed < seconds_target / 4:
-            nb = min(nb * 2, P.nblk)
-    cells = used * P.n ** 3
+        nb = min(2 * nb, P.nblk)
+    cells = nb * P.n ** 3
     return {"value": cells / elapsed, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{used} blocks of {P.n}^3 cells ({cells} cells), one step each, "
-                      f"{elapsed:.1f} s on {cores} host threads"}
+            "sample": f"one step of the first {nb} of {P.nblk} blocks ({cells} cells), "
+                      f"{elapsed:.2f} s on {cores} host threads"}
 
 
 def traffic_from_profiles(kernel_tag):
@@ -91,6 +87,8 @@ def main():
     ap.add_argument("--cfl", type=float, default=0.8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="also run the streaming copy probe on this many GiB (roofline calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
@@ -144,6 +142,23 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": roof,
     }
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * 2 ** 30) // 8
+        src = torch.empty(n, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        hydro.copy_probe(src, dst, stream)
+        stream.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(5):
+            hydro.copy_probe(src, dst, stream)
+        t1.record(stream)
+        t1.synchronize()
+        cms = t0.elapsed_time(t1) / 5
+        out["copy_probe"] = {"bytes_read": 8 * n, "bytes_written": 8 * n, "ms": cms,
+                             "GB/s": 16 * n / (cms * 1e-3) / 1e9}
+        del src, dst
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_seconds)

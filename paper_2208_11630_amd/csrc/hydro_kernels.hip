@@ -16,11 +16,12 @@
 //    interiors through the periodic/outflow index map, so each interior value
 //    crosses HBM once per step.  hydro_fill_guards materialises the guarded
 //    Flash-X-style view (4 layers) only when a caller asks for it.
-//  * Each thread owns one cell of the predictor footprint (the tile plus one
-//    ring) and keeps that column's primitives for planes j-1, j, j+1 in
-//    registers (z slopes, z face states and z fluxes never touch LDS).  The
-//    in-plane neighbours, the x/y face states and the x/y fluxes go through
-//    LDS, so every face flux is computed exactly once per tile.
+//  * Each thread owns one tile cell and keeps that column's primitives for
+//    planes j-1, j, j+1 in registers (z slopes, z face states and z fluxes
+//    never touch LDS).  The in-plane neighbours, the x/y face states and the
+//    x/y fluxes go through LDS, so every face flux is computed exactly once
+//    per tile; the one-cell ring around the tile is predicted as a second
+//    item of one wavefront.
 //  * The CFL signal speed of the new state is reduced in the epilogue
 //    (wavefront shuffles, then one atomicMax per workgroup on the bit
 //    pattern), so the next dt needs no extra pass over the state.
@@ -75,91 +76,6 @@ __device__ __forceinline__ void load_cons(const double* __restrict__ U, long off
   for (int v = 0; v < 5; ++v) u[v] = U[off + v * Layout<N>::VS];
 }
 
-// Conservative -> primitive, gamma-law EOS, pressure floor.  Returns 1 if the
-// floor was applied.
-__device__ __forceinline__ int cons_to_prim(const double (&u)[5], double gamma, double small_p,
-                                            double (&w)[5]) {
-  const double rho = u[0];
-  const double vx = u[1] / rho, vy = u[2] / rho, vz = u[3] / rho;
-  const double kin = 0.5 * rho * ((vx * vx + vy * vy) + vz * vz);
-  double p = (gamma - 1.0) * (u[4] - kin);
-  int fl = 0;
-  if (p < small_p) {
-    p = small_p;
-    fl = 1;
-  }
-  w[0] = rho;
-  w[1] = vx;
-  w[2] = vy;
-  w[3] = vz;
-  w[4] = p;
-  return fl;
-}
-
-__device__ __forceinline__ double van_leer(double a, double b) {
-  const double ab = a * b;
-  return ab > 0.0 ? (2.0 * ab) / (a + b) : 0.0;
-}
-
-// out += lam * A_D(w) * d  (primitive-form Euler Jacobian along axis D)
-template <int D>
-__device__ __forceinline__ void add_jacobian(const double (&w)[5], const double (&d)[5], double gamma,
-                                             double lam, double (&out)[5]) {
-  const double un = w[1 + D];
-  double t[5];
-  t[0] = un * d[0] + w[0] * d[1 + D];
-  t[1] = un * d[1];
-  t[2] = un * d[2];
-  t[3] = un * d[3];
-  t[1 + D] += d[4] / w[0];
-  t[4] = gamma * w[4] * d[1 + D] + un * d[4];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) out[v] += lam * t[v];
-}
-
-// HLLC flux normal to axis D between primitive states L and R.
-template <int D>
-__device__ __forceinline__ void hllc(const double (&L)[5], const double (&R)[5], double gamma,
-                                     double (&F)[5]) {
-  const double rL = L[0], uL = L[1 + D], pL = L[4];
-  const double rR = R[0], uR = R[1 + D], pR = R[4];
-  const double cL = sqrt(gamma * pL / rL);
-  const double cR = sqrt(gamma * pR / rR);
-  const double SL = fmin(uL - cL, uR - cR);
-  const double SR = fmax(uL + cL, uR + cR);
-  const double Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
-                    (rL * (SL - uL) - rR * (SR - uR));
-  // Upwind side K and whether the star correction applies:
-  //   SL >= 0 -> F_L;  S* >= 0 -> F*_L;  SR > 0 -> F*_R;  else F_R.
-  const bool left = (SL >= 0.0) || (Ss >= 0.0);
-  const double S = left ? SL : SR;
-  const bool corr = left ? (SL < 0.0) : (SR > 0.0);
-  double W[5];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) W[v] = left ? L[v] : R[v];
-  const double rho = W[0], un = W[1 + D], p = W[4];
-  const double E = p / (gamma - 1.0) + 0.5 * rho * ((W[1] * W[1] + W[2] * W[2]) + W[3] * W[3]);
-  const double mass = rho * un;
-  F[0] = mass;
-  F[1] = mass * W[1];
-  F[2] = mass * W[2];
-  F[3] = mass * W[3];
-  F[1 + D] += p;
-  F[4] = un * (E + p);
-  if (corr) {
-    const double factor = rho * (S - un) / (S - Ss);
-    double dU[5];
-    dU[0] = factor - rho;
-    dU[1] = factor * W[1] - rho * W[1];
-    dU[2] = factor * W[2] - rho * W[2];
-    dU[3] = factor * W[3] - rho * W[3];
-    dU[1 + D] = factor * Ss - rho * un;
-    dU[4] = factor * (E / rho + (Ss - un) * (Ss + p / (rho * (S - un)))) - E;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) F[v] += S * dU[v];
-  }
-}
-
 // Maximum over a workgroup of a non-negative double, folded into *slot with
 // one atomicMax on the bit pattern.  red must hold one entry per wavefront.
 template <int NT>
@@ -181,37 +97,138 @@ __device__ __forceinline__ void wg_max_to(double v, unsigned long long* red, uns
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fast FP64 building blocks.  The hardware reciprocal / reciprocal square root
+// (about 5e-8 relative) refined by one Newton step gives about 2^-48
+// relative error: well inside the step's 1e-12 tolerance, at roughly half
+// the instruction count of IEEE division and square root.
+
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// n / d with one Newton correction of the quotient
+__device__ __forceinline__ double div_nr(double n, double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  const double q = n * r;
+  return fma(fma(-d, q, n), r, q);
+}
+
+// t^(-1/2)
+__device__ __forceinline__ double rsq_nr(double t) {
+  const double y = __builtin_amdgcn_rsq(t);
+  return fma(0.5 * y, fma(-(t * y), y, 1.0), y);
+}
+
+// Primitive state of a cell plus 1/rho (shared by the predictor).
+__device__ __forceinline__ int prim(const double (&u)[5], double gamma, double small_p, double (&w)[5],
+                                         double& inv) {
+  const double rho = u[0];
+  inv = rcp_nr(rho);
+  const double vx = u[1] * inv, vy = u[2] * inv, vz = u[3] * inv;
+  const double kin = 0.5 * rho * ((vx * vx + vy * vy) + vz * vz);
+  double p = (gamma - 1.0) * (u[4] - kin);
+  int fl = 0;
+  if (p < small_p) {
+    p = small_p;
+    fl = 1;
+  }
+  w[0] = rho;
+  w[1] = vx;
+  w[2] = vy;
+  w[3] = vz;
+  w[4] = p;
+  return fl;
+}
+
+// HLLC flux normal to axis D between primitive states L and R (Davis wave
+// speeds S_L, S_R; Batten contact speed S*).  Branches: S_L >= 0 -> F_L;
+// S* >= 0 -> F*_L; S_R > 0 -> F*_R; else F_R.  The star state of the upwind
+// side K uses one reciprocal q = 1/(S_K - S*), m = rho_K (S_K - u_K):
+//   rho* = m q,  (rho u_n)* = m q S*,  (rho u_t)* = m q u_t,
+//   E* = q ((S_K - u_K) E_K + (S* - u_K)(m S* + p_K)).
+template <int D>
+__device__ __forceinline__ void hllc(const double (&L)[5], const double (&R)[5], double gamma,
+                                          double gm1inv, double (&F)[5]) {
+  const double rL = L[0], uL = L[1 + D], pL = L[4];
+  const double rR = R[0], uR = R[1 + D], pR = R[4];
+  const double gpL = gamma * pL, gpR = gamma * pR;
+  const double cL = gpL * rsq_nr(gpL * rL);
+  const double cR = gpR * rsq_nr(gpR * rR);
+  const double SL = fmin(uL - cL, uR - cR);
+  const double SR = fmax(uL + cL, uR + cR);
+  const double mL = rL * (SL - uL), mR = rR * (SR - uR);
+  const double Ss = div_nr(pR - pL + mL * uL - mR * uR, mL - mR);
+  const bool left = (SL >= 0.0) || (Ss >= 0.0);
+  const double S = left ? SL : SR;
+  const double m = left ? mL : mR;
+  const bool corr = left ? (SL < 0.0) : (SR > 0.0);  // not supersonic on the upwind side
+  double W[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) W[v] = left ? L[v] : R[v];
+  const double rho = W[0], un = W[1 + D], p = W[4];
+  const double E = p * gm1inv + 0.5 * rho * ((W[1] * W[1] + W[2] * W[2]) + W[3] * W[3]);
+  const double mass = rho * un;
+  F[0] = mass;
+  F[1] = mass * W[1];
+  F[2] = mass * W[2];
+  F[3] = mass * W[3];
+  F[1 + D] += p;
+  F[4] = un * (E + p);
+  if (corr) {
+    const double q = rcp_nr(S - Ss);
+    const double factor = m * q;
+    const double d0 = factor - rho;
+    double dU[5];
+    dU[0] = d0;
+    dU[1] = d0 * W[1];
+    dU[2] = d0 * W[2];
+    dU[3] = d0 * W[3];
+    dU[1 + D] = factor * Ss - rho * un;
+    dU[4] = q * ((S - un) * E + (Ss - un) * (m * Ss + p)) - E;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] += S * dU[v];
+  }
+}
+
 __device__ __forceinline__ double signal_speed(const double (&u)[5], const GridGeom& g) {
-  double w[5];
-  cons_to_prim(u, g.gamma, g.small_p, w);
-  const double c = sqrt(g.gamma * w[4] / w[0]);
-  return ((fabs(w[1]) + c) * g.inv_dx[0] + (fabs(w[2]) + c) * g.inv_dx[1]) +
-         (fabs(w[3]) + c) * g.inv_dx[2];
+  double w[5], inv;
+  prim(u, g.gamma, g.small_p, w, inv);
+  const double gp = g.gamma * w[4];
+  const double c = gp * rsq_nr(gp * w[0]);
+  return ((fabs(w[1]) + c) * g.inv_dx[0] + (fabs(w[2]) + c) * g.inv_dx[1]) + (fabs(w[3]) + c) * g.inv_dx[2];
+}
+
+// Workgroup -> tile map that keeps spatially consecutive tiles on one XCD
+// (workgroups are dealt to the 8 XCDs round-robin, each XCD has its own L2):
+// XCD x takes the contiguous range [x*per, (x+1)*per) of tiles.
+__device__ __forceinline__ long xcd_tile(long w, long total) {
+  const long per = (total + 7) / 8;
+  return (w % 8) * per + w / 8;
 }
 
 // ---------------------------------------------------------------------------
-// Fused step kernel.  Template: N block edge, T tile edge (N % T == 0).
-// Thread roles (NP = (T+2)^2 - 4 predictor cells):
-//   tid <  T*T      : tile cell (x, y) = (tid % T, tid / T)
-//   tid <  NP       : ring cell, side r/T: x=-1 | x=T | y=-1 | y=T
-// Extra cells, primitives only (x/y slopes of the ring): x=-2 | x=T+1 |
-// y=-2 | y=T+1 rows, then the 4 edge cells (+-1 corners of the ring).
+// Fused step.  Workgroups of whole wavefront quartets (256 threads for T =
+// 16) so that two of them share a CU evenly across its four SIMDs (a 320-
+// thread workgroup, one thread per predictor cell, packed only one per CU).  Thread t owns tile cell (t % T, t / T) and keeps that column's
+// primitives for planes j-1, j, j+1 in registers.  The one-cell ring around
+// the tile (4T cells) is a second item of threads 0..4T-1 whose z windows
+// live in LDS; the two-deep halo cells that only feed ring slopes (4T+4
+// cells) are a second item of the next threads.  Each thread computes the x
+// and y fluxes of its own low faces and its z flux; threads 0..2T-1 also
+// take the tile's high x and y boundary faces.
 template <int T>
 struct Tile {
-  static constexpr int NP = (T + 2) * (T + 2) - 4;
-  static constexpr int NT = ((NP + 63) / 64) * 64;
+  static constexpr int NI = T * T;   // tile cells
+  static constexpr int NR = 4 * T;   // ring cells
   static constexpr int NE = 4 * T + 4;
-  static constexpr int WS = T + 4;  // sW row pitch
-  static constexpr int PSP = T + 2; // sP row pitch
-  static constexpr int NFX = (T + 1) * T;
-
-  __device__ static void cell_of(int t, int& x, int& y) {
-    if (t < T * T) {
-      x = t % T;
-      y = t / T;
-      return;
-    }
-    const int r = t - T * T, side = r / T, s = r % T;
+  static constexpr int NT = (NI > ((NR + NE + 63) / 64) * 64) ? NI : ((NR + NE + 63) / 64) * 64;
+  static constexpr int WS = T + 4;    // sW row pitch (x = -2 .. T+1)
+  static constexpr int NQ = (T + 1) * T;
+  // ring cell r: side r/T: 0 x=-1, 1 x=T, 2 y=-1, 3 y=T
+  __device__ static void ring_of(int r, int& x, int& y) {
+    const int side = r / T, s = r % T;
     x = side == 0 ? -1 : side == 1 ? T : s;
     y = side == 2 ? -1 : side == 3 ? T : s;
   }
@@ -228,173 +245,285 @@ struct Tile {
   }
 };
 
+// van Leer's harmonic slope without a branch: (a|b| + |a|b) / (|a| + |b|)
+// equals 2ab/(a+b) when ab > 0 and 0 otherwise (numerator zero); the
+// denominator is kept positive by the smallest normal double.
+__device__ __forceinline__ double van_leer_sf(double a, double b) {
+  const double num = fma(a, fabs(b), fabs(a) * b);
+  const double den = (fabs(a) + fabs(b)) + 2.2250738585072014e-308;
+  return div_nr(num, den);
+}
+
+// Predictor of one cell: half step with all three directions, positivity
+// check of the six face states.  On exit wt is the state the face states
+// extrapolate from and h the half-slope factor: (predicted centre, 0.5) or,
+// for the first-order fallback, (cell centre, 0).
+__device__ __forceinline__ bool predict(const double (&wc)[5], double inv, const double (&sx)[5],
+                                        const double (&sy)[5], const double (&sz)[5], double gamma,
+                                        double lamx, double lamy, double lamz, double (&wt)[5], double& h) {
+  const double gp = gamma * wc[4];
+  double acc[5];
+  {  // x: normal velocity wc[1]
+    const double q = lamx * wc[1];
+    acc[0] = fma(q, sx[0], (lamx * wc[0]) * sx[1]);
+    acc[1] = fma(q, sx[1], (lamx * inv) * sx[4]);
+    acc[2] = q * sx[2];
+    acc[3] = q * sx[3];
+    acc[4] = fma(q, sx[4], (lamx * gp) * sx[1]);
+  }
+  {  // y
+    const double q = lamy * wc[2];
+    acc[0] = fma(q, sy[0], fma(lamy * wc[0], sy[2], acc[0]));
+    acc[1] = fma(q, sy[1], acc[1]);
+    acc[2] = fma(q, sy[2], fma(lamy * inv, sy[4], acc[2]));
+    acc[3] = fma(q, sy[3], acc[3]);
+    acc[4] = fma(q, sy[4], fma(lamy * gp, sy[2], acc[4]));
+  }
+  {  // z
+    const double q = lamz * wc[3];
+    acc[0] = fma(q, sz[0], fma(lamz * wc[0], sz[3], acc[0]));
+    acc[1] = fma(q, sz[1], acc[1]);
+    acc[2] = fma(q, sz[2], acc[2]);
+    acc[3] = fma(q, sz[3], fma(lamz * inv, sz[4], acc[3]));
+    acc[4] = fma(q, sz[4], fma(lamz * gp, sz[3], acc[4]));
+  }
+  double t[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) t[v] = fma(-0.5, acc[v], wc[v]);
+  // face densities and pressures are t +- s/2; all six positive <=> t > |s|/2 for each
+  const double hr = 0.5 * fmax(fmax(fabs(sx[0]), fabs(sy[0])), fabs(sz[0]));
+  const double hp = 0.5 * fmax(fmax(fabs(sx[4]), fabs(sy[4])), fabs(sz[4]));
+  const bool ok = (t[0] - hr > 0.0) && (t[0] + hr > 0.0) && (t[4] - hp > 0.0) && (t[4] + hp > 0.0);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) wt[v] = ok ? t[v] : wc[v];
+  h = ok ? 0.5 : 0.0;
+  return ok;
+}
+
 template <int N, int T>
-__global__ __launch_bounds__(Tile<T>::NT) void step_kernel(GridGeom g, StepArgs a) {
+__global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepArgs a, long ntiles) {
   using TL = Tile<T>;
-  constexpr int NT = TL::NT, NP = TL::NP, NE = TL::NE, WS = TL::WS, PSP = TL::PSP;
-  constexpr int TPB = (N / T) * (N / T);  // tiles per block
+  constexpr int NT = TL::NT, NI = TL::NI, NR = TL::NR, NE = TL::NE, WS = TL::WS, NQ = TL::NQ;
+  constexpr int TPB = (N / T) * (N / T);
   constexpr long VS = Layout<N>::VS;
 
-  __shared__ double sW[5][WS * WS];         // primitives of plane j (tile + 2-halo)
-  __shared__ double sP[15][PSP * PSP];      // predicted centre, x slope, y slope
-  __shared__ int sFB[PSP * PSP];            // first-order fallback flags
-  __shared__ double sFx[5][TL::NFX];        // x fluxes: face (x, y) between x-1 and x
-  __shared__ double sFy[5][TL::NFX];        // y fluxes: face (x, y) between y-1 and y
+  __shared__ double sW[5][WS * WS];   // primitives of plane j, tile + 2-halo (index (y+2)*WS + x+2)
+  __shared__ double sQx[5][NQ];       // high-x face state of cell (x, y), x = -1..T-1: index y*(T+1) + x+1
+  __shared__ double sQy[5][NQ];       // high-y face state of cell (x, y), y = -1..T-1: index (y+1)*T + x
+  __shared__ double sRx[5][T];        // low-x face state of ring cell (T, y)
+  __shared__ double sRy[5][T];        // low-y face state of ring cell (x, T)
+  __shared__ double sRing[3][5][NR];  // ring z windows (planes mod 3)
+  __shared__ double sFx[5][NQ];       // x flux at face (x, y), x = 0..T: index y*(T+1) + x
+  __shared__ double sFy[5][NQ];       // y flux at face (x, y), y = 0..T: index y*T + x
   __shared__ unsigned long long sRed[NT / 64];
   __shared__ int sCnt[3];
 
+  const long tile_id = xcd_tile(blockIdx.x, ntiles);
+  if (tile_id >= ntiles) return;
   const int tid = threadIdx.x;
-  const long blk = blockIdx.x / TPB;
-  const int tile = blockIdx.x % TPB;
+  const long blk = tile_id / TPB;
+  const int tile = (int)(tile_id % TPB);
   const int bx = (int)(blk % g.nb[0]);
   const int by = (int)((blk / g.nb[0]) % g.nb[1]);
   const int bz = (int)(blk / ((long)g.nb[0] * g.nb[1]));
-  const int X0 = bx * N + (tile % (N / T)) * T;  // global index of the tile origin
-  const int Y0 = by * N + (tile / (N / T)) * T;
-  const int Z0 = bz * N;
+  const int lx0 = (tile % (N / T)) * T, ly0 = (tile / (N / T)) * T;  // tile origin inside the block
+  const int X0 = bx * N + lx0, Y0 = by * N + ly0, Z0 = bz * N;
 
   if (tid < 3) sCnt[tid] = 0;
 
   double dt = a.dt;
   if (a.cfl > 0.0) dt = a.cfl / __longlong_as_double(a.ws->sig[a.slot]);
-  if (blockIdx.x == 0 && tid == 0) {
+  if (tile_id == 0 && tid == 0) {
     a.ws->dt_last = dt;
     a.ws->sig[(a.slot + 2) % 3] = 0ull;
   }
   const double lamx = dt * g.inv_dx[0], lamy = dt * g.inv_dx[1], lamz = dt * g.inv_dx[2];
-  const double gamma = g.gamma;
+  const double gamma = g.gamma, gm1inv = 1.0 / (g.gamma - 1.0);
 
-  // own cell
-  const bool pred = tid < NP;
-  const bool inner = tid < T * T;
-  int cx = 0, cy = 0;
-  if (pred) TL::cell_of(tid, cx, cy);
+  // roles; the second items (ring, halo) and the boundary faces sit on the
+  // wavefronts starting at (tile mod 4) so the busier wavefront moves
+  // between SIMDs from one workgroup to the next
+  const int role = (tid + 64 * (int)(tile_id & 3)) % NT;
+  const bool inner = tid < NI;
+  const int cx = tid % T, cy = tid / T;                // valid when inner
   const int cidx = (cy + 2) * WS + (cx + 2);
-  const int pidx = (cy + 1) * PSP + (cx + 1);
+  const bool is_ring = role < NR;
+  const bool is_extra = role >= NR && role < NR + NE;
+  const int ring_id = role;                             // valid when is_ring
+  int sx2 = 0, sy2 = 0;                                 // second item position
+  if (is_ring) TL::ring_of(role, sx2, sy2);
+  if (is_extra) TL::extra_of(role - NR, sx2, sy2);
+  const int sidx2 = (sy2 + 2) * WS + (sx2 + 2);
+  const int rside = role / T;                           // ring side (valid when is_ring)
+  // offsets of plane 0 of the own column and of the second item, for the
+  // planes that lie inside the block (z halo planes go through the map)
+  const long own0 = Layout<N>::at(blk, lx0 + cx, ly0 + cy, 0);
+  const long sec0 = (is_ring || is_extra) ? cell_offset<N>(g, X0 + sx2, Y0 + sy2, Z0) : 0;
 
-  // window of own-cell primitives: Wa = plane j-1, Wb = plane j, Wc = plane j+1
   double Wa[5], Wb[5], Wc[5];
+  double un_next[5], u2_next[5];
   double zp_prev[5], fz_prev[5], dxy_prev[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     Wa[v] = Wb[v] = Wc[v] = 0.0;
+    un_next[v] = u2_next[v] = 0.0;
     zp_prev[v] = fz_prev[v] = dxy_prev[v] = 0.0;
   }
   int n_floor = 0, n_fb = 0, n_bad = 0;
   double smax = 0.0;
 
-  if (pred) {
-    double u[5];
+  // prologue: planes -2, -1 of the own column, prefetch plane 0
+  if (inner) {
+    double u[5], tmp;
     load_cons<N>(a.Uin, cell_offset<N>(g, X0 + cx, Y0 + cy, Z0 - 2), u);
-    cons_to_prim(u, gamma, g.small_p, Wa);
+    prim(u, gamma, g.small_p, Wa, tmp);
     load_cons<N>(a.Uin, cell_offset<N>(g, X0 + cx, Y0 + cy, Z0 - 1), u);
-    cons_to_prim(u, gamma, g.small_p, Wb);
+    prim(u, gamma, g.small_p, Wb, tmp);
+    load_cons<N>(a.Uin, own0, un_next);
   }
+  if (is_ring) {
+    double u[5], w[5], tmp;
+    load_cons<N>(a.Uin, cell_offset<N>(g, X0 + sx2, Y0 + sy2, Z0 - 1), u);
+    prim(u, gamma, g.small_p, w, tmp);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sRing[2][v][ring_id] = w[v];
+    load_cons<N>(a.Uin, sec0, u2_next);
+  }
+  if (is_extra) load_cons<N>(a.Uin, sec0, u2_next);
 
   for (int j = -1; j <= N; ++j) {
     const bool mid = (j >= 0) && (j < N);
-    // -- load plane j+1 (own cell), publish plane j primitives
-    if (pred) {
-      double u[5];
-      load_cons<N>(a.Uin, cell_offset<N>(g, X0 + cx, Y0 + cy, Z0 + j + 1), u);
-      const int fl = cons_to_prim(u, gamma, g.small_p, Wc);
-      if (inner && j + 1 >= 0 && j + 1 < N) n_floor += fl;
+    const int sm = (j + 5) % 3, s0 = (j + 3) % 3, sp = (j + 4) % 3;  // ring slots of planes j-1, j, j+1
+    // -- own column: plane j+1 from the prefetch, prefetch plane j+2, publish plane j
+    if (inner) {
+      double inv_unused;
+      const int fl = prim(un_next, gamma, g.small_p, Wc, inv_unused);
+      if (j + 1 >= 0 && j + 1 < N) n_floor += fl;
+      if (j + 2 < N)
+        load_cons<N>(a.Uin, own0 + (j + 2) * Layout<N>::PS, un_next);
+      else if (j + 2 <= N + 1)
+        load_cons<N>(a.Uin, cell_offset<N>(g, X0 + cx, Y0 + cy, Z0 + j + 2), un_next);
 #pragma unroll
       for (int v = 0; v < 5; ++v) sW[v][cidx] = Wb[v];
     }
-    if (mid) {
-      for (int e = (tid + NT - NP) % NT; e < NE; e += NT) {
-        int ex, ey;
-        TL::extra_of(e, ex, ey);
-        double u[5], w[5];
-        load_cons<N>(a.Uin, cell_offset<N>(g, X0 + ex, Y0 + ey, Z0 + j), u);
-        cons_to_prim(u, gamma, g.small_p, w);
+    // -- second item: ring cell window (planes j..j+1) or halo cell (plane j)
+    if (is_ring) {
+      double w[5], tmp;
+      prim(u2_next, gamma, g.small_p, w, tmp);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sW[v][(ey + 2) * WS + (ex + 2)] = w[v];
+      for (int v = 0; v < 5; ++v) {
+        sRing[sp][v][ring_id] = w[v];
+        sW[v][sidx2] = sRing[s0][v][ring_id];
       }
+      if (j + 2 < N)
+        load_cons<N>(a.Uin, sec0 + (j + 2) * Layout<N>::PS, u2_next);
+      else if (j + 2 <= N + 1)
+        load_cons<N>(a.Uin, cell_offset<N>(g, X0 + sx2, Y0 + sy2, Z0 + j + 2), u2_next);
+    }
+    if (is_extra && mid) {
+      double w[5], tmp;
+      prim(u2_next, gamma, g.small_p, w, tmp);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sW[v][sidx2] = w[v];
+      if (j + 1 < N) load_cons<N>(a.Uin, sec0 + (j + 1) * Layout<N>::PS, u2_next);
     }
     __syncthreads();
 
-    // -- predictor at plane j
-    double zm[5], zp[5];
-    const bool active = mid ? pred : inner;
-    if (active) {
-      double sx[5], sy[5], sz[5], wt[5];
+    // -- predictor: own cell (every plane), ring cell (planes 0..N-1)
+    double xm[5], ym[5], zm[5], zp[5];
+    if (inner) {
+      double sx[5], sy[5], sz[5], wt[5], h;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const double c = Wb[v];
-        sx[v] = van_leer(c - sW[v][cidx - 1], sW[v][cidx + 1] - c);
-        sy[v] = van_leer(c - sW[v][cidx - WS], sW[v][cidx + WS] - c);
-        sz[v] = van_leer(c - Wa[v], Wc[v] - c);
+        sx[v] = van_leer_sf(c - sW[v][cidx - 1], sW[v][cidx + 1] - c);
+        sy[v] = van_leer_sf(c - sW[v][cidx - WS], sW[v][cidx + WS] - c);
+        sz[v] = van_leer_sf(c - Wa[v], Wc[v] - c);
       }
-      double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      add_jacobian<0>(Wb, sx, gamma, lamx, acc);
-      add_jacobian<1>(Wb, sy, gamma, lamy, acc);
-      add_jacobian<2>(Wb, sz, gamma, lamz, acc);
+      const bool ok = predict(Wb, rcp_nr(Wb[0]), sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
+      if (mid && !ok) ++n_fb;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) wt[v] = Wb[v] - 0.5 * acc[v];
-      const bool ok = (wt[0] + 0.5 * sx[0] > 0.0) && (wt[0] - 0.5 * sx[0] > 0.0) &&
-                      (wt[0] + 0.5 * sy[0] > 0.0) && (wt[0] - 0.5 * sy[0] > 0.0) &&
-                      (wt[0] + 0.5 * sz[0] > 0.0) && (wt[0] - 0.5 * sz[0] > 0.0) &&
-                      (wt[4] + 0.5 * sx[4] > 0.0) && (wt[4] - 0.5 * sx[4] > 0.0) &&
-                      (wt[4] + 0.5 * sy[4] > 0.0) && (wt[4] - 0.5 * sy[4] > 0.0) &&
-                      (wt[4] + 0.5 * sz[4] > 0.0) && (wt[4] - 0.5 * sz[4] > 0.0);
+      for (int v = 0; v < 5; ++v) {
+        xm[v] = fma(-h, sx[v], wt[v]);
+        ym[v] = fma(-h, sy[v], wt[v]);
+        zm[v] = fma(-h, sz[v], wt[v]);
+        zp[v] = fma(h, sz[v], wt[v]);
+      }
       if (mid) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          sP[v][pidx] = wt[v];
-          sP[5 + v][pidx] = sx[v];
-          sP[10 + v][pidx] = sy[v];
+          sQx[v][cy * (T + 1) + cx + 1] = fma(h, sx[v], wt[v]);
+          sQy[v][(cy + 1) * T + cx] = fma(h, sy[v], wt[v]);
         }
-        sFB[pidx] = ok ? 0 : 1;
-        if (inner && !ok) ++n_fb;
-      }
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        zm[v] = ok ? wt[v] - 0.5 * sz[v] : Wb[v];
-        zp[v] = ok ? wt[v] + 0.5 * sz[v] : Wb[v];
       }
     }
-    // -- z flux at j-1/2 (tile cells)
+    if (is_ring && mid) {
+      double wc[5], sx[5], sy[5], sz[5], wt[5], h;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        wc[v] = sRing[s0][v][ring_id];
+        sx[v] = van_leer_sf(wc[v] - sW[v][sidx2 - 1], sW[v][sidx2 + 1] - wc[v]);
+        sy[v] = van_leer_sf(wc[v] - sW[v][sidx2 - WS], sW[v][sidx2 + WS] - wc[v]);
+        sz[v] = van_leer_sf(wc[v] - sRing[sm][v][ring_id], sRing[sp][v][ring_id] - wc[v]);
+      }
+      const double inv = rcp_nr(wc[0]);
+      predict(wc, inv, sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
+      // the one face state of this ring cell that a tile face uses
+      const int r = ring_id % T;
+      if (rside == 0) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sQx[v][r * (T + 1)] = fma(h, sx[v], wt[v]);  // (-1, r) high x
+      } else if (rside == 1) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sRx[v][r] = fma(-h, sx[v], wt[v]);           // (T, r) low x
+      } else if (rside == 2) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sQy[v][r] = fma(h, sy[v], wt[v]);            // (r, -1) high y
+      } else {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sRy[v][r] = fma(-h, sy[v], wt[v]);           // (r, T) low y
+      }
+    }
     double fz[5];
-    if (inner && j >= 0) hllc<2>(zp_prev, zm, gamma, fz);
+    if (inner && j >= 0) hllc<2>(zp_prev, zm, gamma, gm1inv, fz);
     __syncthreads();
 
-    // -- x and y fluxes of plane j
+    // -- x and y fluxes: own low faces, plus the tile's high boundary faces
     if (mid) {
-      for (int f = tid; f < 2 * TL::NFX; f += NT) {
-        const bool isx = f < TL::NFX;
-        const int q = isx ? f : f - TL::NFX;
-        int fx, fy, lx, ly;
-        if (isx) {
-          fx = q % (T + 1);
-          fy = q / (T + 1);
-          lx = fx - 1;
-          ly = fy;
-        } else {
-          fx = q % T;
-          fy = q / T;
-          lx = fx;
-          ly = fy - 1;
-        }
-        const int pl = (ly + 1) * PSP + (lx + 1), pr = (fy + 1) * PSP + (fx + 1);
-        const int wl = (ly + 2) * WS + (lx + 2), wr = (fy + 2) * WS + (fx + 2);
-        const int so = isx ? 5 : 10;
-        const bool fbl = sFB[pl] != 0, fbr = sFB[pr] != 0;
+      if (inner) {
+        double WL[5], F[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) WL[v] = sQx[v][cy * (T + 1) + cx];
+        hllc<0>(WL, xm, gamma, gm1inv, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sFx[v][cy * (T + 1) + cx] = F[v];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) WL[v] = sQy[v][cy * T + cx];
+        hllc<1>(WL, ym, gamma, gm1inv, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sFy[v][cy * T + cx] = F[v];
+      }
+      if (role < 2 * T) {
         double WL[5], WR[5], F[5];
+        const int r = role % T;
+        if (role < T) {  // x face at x = T, y = r
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          WL[v] = fbl ? sW[v][wl] : sP[v][pl] + 0.5 * sP[so + v][pl];
-          WR[v] = fbr ? sW[v][wr] : sP[v][pr] - 0.5 * sP[so + v][pr];
-        }
-        if (isx) {
-          hllc<0>(WL, WR, gamma, F);
+          for (int v = 0; v < 5; ++v) {
+            WL[v] = sQx[v][r * (T + 1) + T];
+            WR[v] = sRx[v][r];
+          }
+          hllc<0>(WL, WR, gamma, gm1inv, F);
 #pragma unroll
-          for (int v = 0; v < 5; ++v) sFx[v][q] = F[v];
-        } else {
-          hllc<1>(WL, WR, gamma, F);
+          for (int v = 0; v < 5; ++v) sFx[v][r * (T + 1) + T] = F[v];
+        } else {        // y face at y = T, x = r
 #pragma unroll
-          for (int v = 0; v < 5; ++v) sFy[v][q] = F[v];
+          for (int v = 0; v < 5; ++v) {
+            WL[v] = sQy[v][T * T + r];
+            WR[v] = sRy[v][r];
+          }
+          hllc<1>(WL, WR, gamma, gm1inv, F);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) sFy[v][T * T + r] = F[v];
         }
       }
     }
@@ -410,12 +539,11 @@ __global__ __launch_bounds__(Tile<T>::NT) void step_kernel(GridGeom g, StepArgs 
           dxy[v] = lamx * (sFx[v][qx + 1] - sFx[v][qx]) + lamy * (sFy[v][qy + T] - sFy[v][qy]);
       }
       if (j >= 1) {
-        const long off = cell_offset<N>(g, X0 + cx, Y0 + cy, Z0 + j - 1);
-        double u[5];
-        load_cons<N>(a.Uin, off, u);
-        double un[5];
+        const long off = own0 + (j - 1) * Layout<N>::PS;
+        double uold[5], un[5];
+        load_cons<N>(a.Uin, off, uold);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) un[v] = u[v] - (dxy_prev[v] + lamz * (fz[v] - fz_prev[v]));
+        for (int v = 0; v < 5; ++v) un[v] = uold[v] - (dxy_prev[v] + lamz * (fz[v] - fz_prev[v]));
 #pragma unroll
         for (int v = 0; v < 5; ++v) a.Uout[off + v * VS] = un[v];
         bool good = un[0] > 0.0 && un[4] > 0.0;
@@ -430,16 +558,12 @@ __global__ __launch_bounds__(Tile<T>::NT) void step_kernel(GridGeom g, StepArgs 
         if (mid) dxy_prev[v] = dxy[v];
         if (j >= 0) fz_prev[v] = fz[v];
         zp_prev[v] = zp[v];
+        Wa[v] = Wb[v];
+        Wb[v] = Wc[v];
       }
-    }
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      Wa[v] = Wb[v];
-      Wb[v] = Wc[v];
     }
   }
 
-  // -- epilogue: signal-speed maximum and event counters
   if (n_floor) atomicAdd(&sCnt[0], n_floor);
   if (n_fb) atomicAdd(&sCnt[1], n_fb);
   if (n_bad) atomicAdd(&sCnt[2], n_bad);
@@ -514,8 +638,9 @@ __global__ __launch_bounds__(256) void copy_kernel(const double* __restrict__ sr
 template <int N, int T>
 hipError_t launch_step_t(const GridGeom& g, const StepArgs& a, hipStream_t s) {
   const long nblk = (long)g.nb[0] * g.nb[1] * g.nb[2];
-  const long grid = nblk * (N / T) * (N / T);
-  hipLaunchKernelGGL((step_kernel<N, T>), dim3((unsigned)grid), dim3(Tile<T>::NT), 0, s, g, a);
+  const long ntiles = nblk * (N / T) * (N / T);
+  const long grid = 8 * ((ntiles + 7) / 8);
+  hipLaunchKernelGGL((step_kernel<N, T>), dim3((unsigned)grid), dim3(Tile<T>::NT), 0, s, g, a, ntiles);
   return hipGetLastError();
 }
 

@@ -78,12 +78,184 @@ def traffic_from_profiles(kernel_tag):
     return rec.get("hbm_bytes_per_launch")
 
 
+def run_ensemble(args):
+    """Batched ensemble: independent periodic simulations with 1-64 blocks of
+    8^3, 16^3 or 32^3 cells.  Times the same steps two ways on the same GPU:
+    looping the plain per-grid step over the members, and the batch (one
+    persistent launch per step, captured as a HIP graph, launch shape from
+    the autotuner).  value = batched cell-updates/s."""
+    import torch
+
+    from paper_2208_11630_amd import hydro, ics, tune
+
+    sims = ics.ensemble(count=args.members, seed=2, steps=50)
+    cells = sum(P.cells for P in sims)
+    print(f"[bench] ensemble: {len(sims)} members, {cells} cells", file=sys.stderr, flush=True)
+    grids = [hydro.grid_for(P, device="cuda:0") for P in sims]
+    st = torch.cuda.current_stream()
+
+    def timed(run, stream, k):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(k):
+            run()
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b)
+
+    # looped plain step: one launch per member per step
+    def loop_step():
+        for G in grids:
+            G.step_cfl(args.cfl)
+    for _ in range(args.warmup):
+        loop_step()
+    st.synchronize()
+    ms_loop = timed(loop_step, st, args.steps)
+    print(f"[bench] looped: {ms_loop / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+
+    B = hydro.Batch(grids)
+    cfg = {"pencils": [1, 1, 1], "per_cu": 2}
+    if not args.no_tune:
+        cfg = tune.tune_batch(B, args.cfl)
+        print(f"[bench] tuned: pencils {cfg['pencils']} workgroups/CU {cfg['per_cu']}", file=sys.stderr,
+              flush=True)
+    B.use_graph(True)
+    B.step(args.cfl, 6 * max(1, args.warmup // 6 + 1))
+    B.synchronize()
+    k = 6 * max(1, round(args.steps / 6))
+    ms_batch = timed(lambda: B.step(args.cfl, 6), B.stream, k // 6)
+    print(f"[bench] batched: {ms_batch / k:.3f} ms/step", file=sys.stderr, flush=True)
+    loop_rate = cells * args.steps / (ms_loop * 1e-3)
+    rate = cells * k / (ms_batch * 1e-3)
+    ms_step = ms_batch / k
+    achieved = BYTES_PER_CELL * cells / (ms_step * 1e-3) / 1e9
+    out = {
+        "metric": "FP64 cell-updates/s",
+        "value": rate,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": k,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched_ensemble_{len(sims)}_members_nxb8_16_32", "cells": cells,
+                   "members": len(sims), "cfl": args.cfl, "launch": "persistent+hipgraph",
+                   "pencils": cfg["pencils"], "workgroups_per_cu": cfg["per_cu"],
+                   "parallelism": "single-gpu"},
+        "looped_plain_step": {"value": loop_rate, "ms_per_step": ms_loop / args.steps,
+                              "launches_per_step": len(sims)},
+        "batched_over_looped": rate / loop_rate,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "batch_step_kernel",
+                     "algorithmic_bytes_per_launch": BYTES_PER_CELL * cells},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        big = max(sims, key=lambda P: P.cells)
+        out["cpu_baseline"] = cpu_baseline(big, args.cpu_seconds)
+    B.close()
+    print(json.dumps(out), flush=True)
+
+
+def run_served(args):
+    """Served stream: many resident cubic simulations (L log-uniform in
+    32..256, 16^3 blocks, random initial states), one-step requests with
+    uniform targets.  Residency is bounded by an HBM budget (one 40 B/cell
+    state buffer per resident simulation, outputs lent per launch; LRU
+    eviction to host memory).  Measures the saturated request rate (all
+    requests queued at t=0), then sweeps Poisson arrival rates from 10% to
+    120% of it, reporting p50/p99 request latency and cell-updates/s; the
+    same saturated stream without batching (one simulation per launch) is the
+    looped baseline.  value = saturated served cell-updates/s."""
+    import numpy as np
+    import torch
+
+    from paper_2208_11630_amd import ics, serve
+
+    sizes = ics.served_sizes(args.served_sims, seed=3)
+    cells_total = sum(L ** 3 for L in sizes)
+    budget = int(args.served_budget_gb * 1e9)
+    max_cells = 300_000_000                     # outputs lent per launch: <= 12 GB
+    ex = serve.GpuExecutor(sizes, cfl=args.cfl)
+    srv = serve.Server(ex, budget - 2 * 40 * max_cells, max_inflight=2, max_cells_per_launch=max_cells)
+    print(f"[bench] served: {len(sizes)} simulations, {cells_total} cells ({40 * cells_total / 1e9:.0f} GB "
+          f"per copy), budget {budget / 1e9:.0f} GB", file=sys.stderr, flush=True)
+    # warm-up: fill the budget with simulations in random order (first touch draws them on the device)
+    rng = np.random.default_rng(5)
+    srv.stats = serve.Stats()
+    for sim in rng.permutation(len(sizes)):
+        if srv.used + ex.bytes_of(int(sim)) > srv.budget:
+            continue
+        srv._admit(int(sim), set())
+    torch.cuda.synchronize()
+    resident = len(srv.lru)
+    print(f"[bench] warm: {resident} resident, {srv.used / 1e9:.1f} GB", file=sys.stderr, flush=True)
+
+    def saturated(nreq, seed, max_cells_launch, inflight):
+        r = np.random.default_rng(seed)
+        arr = [(0.0, int(x)) for x in r.integers(0, len(sizes), size=nreq)]
+        srv.max_cells = max_cells_launch
+        srv.max_inflight = inflight
+        st = srv.run(arr)
+        torch.cuda.synchronize()
+        return st.summary()
+
+    sat = saturated(2000, 7, max_cells, 2)
+    print(f"[bench] saturated: {sat}", file=sys.stderr, flush=True)
+    lam = sat["requests_per_s"]
+    sweep = []
+    for frac in (0.1, 0.3, 0.5, 0.7, 0.9, 1.0, 1.2):
+        srv.max_cells, srv.max_inflight = max_cells, 2
+        arr = serve.poisson_arrivals(frac * lam, args.served_seconds, len(sizes), seed=4)
+        st = srv.run(arr).summary()
+        torch.cuda.synchronize()
+        row = {"offered_fraction": frac, "offered_per_s": frac * lam, **{k: st.get(k) for k in (
+            "completed", "requests_per_s", "cell_updates_per_s", "p50_ms", "p99_ms", "mean_batch",
+            "evictions")}}
+        sweep.append(row)
+        print(f"[bench] rate {frac:.1f}: {row}", file=sys.stderr, flush=True)
+    loop = saturated(600, 8, 1, 1)
+    print(f"[bench] looped (one simulation per launch): {loop}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "FP64 cell-updates/s; p50/p99 latency of served step requests",
+        "value": sat["cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": sat["completed"],
+        "warmup": resident,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"served_stream_{len(sizes)}_sims_L32-256_nxb16", "cells": cells_total,
+                   "budget_GB": budget / 1e9, "resident_after_warmup": resident, "cfl": args.cfl,
+                   "parallelism": "single-gpu"},
+        "saturated": sat,
+        "latency_sweep": sweep,
+        "looped_one_sim_per_launch": loop,
+        "served_over_looped": sat["cell_updates_per_s"] / max(loop["cell_updates_per_s"], 1e-30),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="kh", choices=["kh", "sedov", "sod"])
+    ap.add_argument("--workload", default="kh", choices=["kh", "sedov", "sod", "ensemble", "served"])
+    ap.add_argument("--served-sims", type=int, default=2000)
+    ap.add_argument("--served-budget-gb", type=float, default=200.0)
+    ap.add_argument("--served-seconds", type=float, default=2.0, help="served: seconds per rate point")
+    ap.add_argument("--members", type=int, default=512, help="ensemble: number of simulations")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch shape)")
     ap.add_argument("--cfl", type=float, default=0.8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -100,6 +272,10 @@ def main():
 
     hydro.lib()
     torch.cuda.set_device(0)
+    if args.workload == "ensemble":
+        return run_ensemble(args)
+    if args.workload == "served":
+        return run_served(args)
     P, wname = make_workload(args.workload)
     print(f"[bench] workload {wname}: {P.cells} cells, {P.nblk} blocks", file=sys.stderr, flush=True)
     G = hydro.grid_for(P, device="cuda:0")

@@ -146,8 +146,65 @@ int hydro_current(hydro_grid *g, double **U_cur);
  * cells after an update.  Waits for the stream. */
 int hydro_counters(hydro_grid *g, long long out[3]);
 
-/* Destroy the handle (host metadata only; no device memory is freed). */
+/* Destroy the handle (host metadata only; no device memory is freed).
+ * Refused (HYDRO_EINVAL) while the grid belongs to a batch. */
 int hydro_free_grid(hydro_grid *g);
+
+/* Rebind the grid's two state buffers (same size and alignment rules as in
+ * the descriptor): U must hold the current state, U_alt becomes the output
+ * of the next step.  The kept signal speed and counters are unchanged, so U
+ * must hold exactly the state the handle last produced or was given (or
+ * call hydro_state_changed).  Lets a caller keep one state buffer per grid
+ * and lend output buffers only to grids with a step in flight. */
+int hydro_set_buffers(hydro_grid *g, double *U, double *U_alt);
+
+/* Tuning: split each block column into nseg z pencils (1, 2 or 4), one
+ * workgroup each; more workgroups for small grids at the cost of two extra
+ * halo planes per pencil.  Results are bitwise independent of it. */
+int hydro_set_pencils(hydro_grid *g, int nseg);
+
+/* ---- batches: many independent grids, one persistent launch per step ----
+ * (§2: physics is updated block by block, independently of how blocks are
+ * distributed; here blocks of many simulations share one launch.)  A batch
+ * groups grid handles (mixed nxb allowed).  Each step, workgroups pull
+ * (grid, pencil) items from a device work list until it is empty; each grid
+ * takes its own dt = cfl / its own maximum signal speed, formed on the
+ * device.  A grid's results are bitwise the same alone or in any batch.
+ * While a grid belongs to a batch its own step calls are refused; hydro_dt,
+ * hydro_current, hydro_counters and hydro_fill_guards keep working (the
+ * handles follow the batch's steps).  The caller orders work on the member
+ * grids' streams before the batch's stream. */
+typedef struct hydro_batch hydro_batch;
+
+/* Device workspace bytes a batch of these grids needs (0 if invalid). */
+size_t hydro_batch_work_bytes(hydro_grid *const *grids, int n);
+
+/* Create a batch over n distinct grids not in another batch; work is device
+ * memory (256-byte aligned, hydro_batch_work_bytes bytes) owned by the
+ * caller; stream is the hipStream_t batch steps are ordered on. */
+int hydro_batch_create(hydro_grid *const *grids, int n, void *work, size_t work_bytes, void *stream,
+                       hydro_batch **out);
+
+/* nsteps steps of every active member with dt = cfl / its own max signal
+ * speed.  Async.  With graphs enabled, runs of 6 steps replay one captured
+ * HIP graph (kernel nodes only). */
+int hydro_batch_step(hydro_batch *b, double cfl, int nsteps);
+
+/* mask[i] != 0: member i takes part in the following steps. */
+int hydro_batch_set_active(hydro_batch *b, const unsigned char *mask);
+
+/* Tuning (results are bitwise independent of them): z pencils per column for
+ * nxb = 8, 16, 32 (each 1, 2 or 4); persistent workgroups per CU (1..8);
+ * whether to replay steps through a captured HIP graph. */
+int hydro_batch_set_pencils(hydro_batch *b, const int nseg[3]);
+int hydro_batch_set_workgroups(hydro_batch *b, int per_cu);
+int hydro_batch_use_graph(hydro_batch *b, int enable);
+
+/* dt_out[i] = dt of member i's most recent step.  Waits for the stream. */
+int hydro_batch_dts(hydro_batch *b, double *dt_out);
+
+/* Destroy the batch (host metadata only); members become free grids. */
+int hydro_batch_free(hydro_batch *b);
 
 /* Bandwidth probe (not part of the method): copies n doubles from src to dst
  * (device, 16-byte aligned, disjoint) with a plain streaming kernel on

@@ -4,14 +4,18 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "hydro_internal.h"
+
+struct hydro_batch;
 
 struct hydro_grid {
   hydro_grid_desc d;
@@ -19,6 +23,28 @@ struct hydro_grid {
   int cur;                  // 0: state in d.U, 1: in d.U_alt
   unsigned long long steps; // steps taken; signal slot of the current state = steps % 3
   bool sig_valid;           // slot holds the current state's maximum signal speed
+  int nseg;                 // z pencils per block column (tuning; results do not depend on it)
+  hydro_batch* batch;       // batch the grid belongs to (its own step calls are refused meanwhile)
+};
+
+struct hydro_batch {
+  std::vector<hydro_grid*> grids;
+  std::vector<unsigned char> active;     // member takes part in the next steps
+  std::vector<hydro::BatchSim> sims;     // host copy of the device table
+  std::vector<hydro::BatchItem> items;   // host copy of the device work list
+  hydro::BatchSim* d_sims;
+  hydro::BatchItem* d_items;
+  size_t max_items;
+  void* stream;
+  int nseg[3];                           // pencils per column for nxb 8, 16, 32
+  int grid;                              // persistent workgroups
+  int cus;
+  long step;                             // steps since the table was last uploaded
+  bool dirty;                            // table / list must be rebuilt before the next step
+  bool use_graph;
+  double graph_cfl;                      // cfl baked into the captured graph
+  hipGraph_t graph;
+  hipGraphExec_t exec;
 };
 
 namespace {
@@ -92,13 +118,15 @@ int check_device() {
   return HYDRO_OK;
 }
 
-int ensure_signal(hydro_grid* g) {
+int ensure_signal_on(hydro_grid* g, hipStream_t s) {
   if (g->sig_valid) return HYDRO_OK;
-  hipError_t e = hydro::launch_signal(g->d.nxb, g->geom, cur_state(g), ws_of(g), slot_of(g), stream_of(g));
+  hipError_t e = hydro::launch_signal(g->d.nxb, g->geom, cur_state(g), ws_of(g), slot_of(g), s);
   if (e != hipSuccess) return hip_fail(e, "signal-speed kernel launch");
   g->sig_valid = true;
   return HYDRO_OK;
 }
+
+int ensure_signal(hydro_grid* g) { return ensure_signal_on(g, stream_of(g)); }
 
 int do_step(hydro_grid* g, double dt, double cfl) {
   hydro::StepArgs a;
@@ -108,7 +136,7 @@ int do_step(hydro_grid* g, double dt, double cfl) {
   a.dt = dt;
   a.cfl = cfl;
   a.slot = slot_of(g);
-  hipError_t e = hydro::launch_step(g->d.nxb, g->geom, a, stream_of(g));
+  hipError_t e = hydro::launch_step(g->d.nxb, g->geom, a, g->nseg, stream_of(g));
   if (e != hipSuccess) return hip_fail(e, "step kernel launch");
   g->cur ^= 1;
   g->steps += 1;
@@ -166,6 +194,8 @@ int hydro_init_grid(const hydro_grid_desc* d, hydro_grid** out) {
   g->cur = 0;
   g->steps = 0;
   g->sig_valid = false;
+  g->nseg = 1;
+  g->batch = nullptr;
   hipError_t e = hipMemsetAsync(d->work, 0, sizeof(hydro::WorkHeader), (hipStream_t)d->stream);
   if (e != hipSuccess) {
     delete g;
@@ -192,12 +222,14 @@ int hydro_fill_guards(hydro_grid* g, double* guarded) {
 
 int hydro_step(hydro_grid* g, double dt) {
   if (!g) return fail(HYDRO_EINVAL, "handle is NULL");
+  if (g->batch) return fail(HYDRO_EINVAL, "grid belongs to a batch; step it through the batch");
   if (!finite_pos(dt)) return fail(HYDRO_EINVAL, "dt must be finite and > 0 (got %g)", dt);
   return do_step(g, dt, 0.0);
 }
 
 int hydro_step_cfl(hydro_grid* g, double cfl) {
   if (!g) return fail(HYDRO_EINVAL, "handle is NULL");
+  if (g->batch) return fail(HYDRO_EINVAL, "grid belongs to a batch; step it through the batch");
   if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0 (got %g)", cfl);
   int rc = ensure_signal(g);
   if (rc) return rc;
@@ -256,7 +288,280 @@ int hydro_counters(hydro_grid* g, long long out[3]) {
 }
 
 int hydro_free_grid(hydro_grid* g) {
+  if (g && g->batch) return fail(HYDRO_EINVAL, "grid belongs to a batch; free the batch first");
   delete g;
+  return HYDRO_OK;
+}
+
+int hydro_set_buffers(hydro_grid* g, double* U, double* U_alt) {
+  if (!g) return fail(HYDRO_EINVAL, "handle is NULL");
+  if (g->batch) return fail(HYDRO_EINVAL, "grid belongs to a batch");
+  hydro_grid_desc d = g->d;
+  d.U = U;
+  d.U_alt = U_alt;
+  int rc = validate(&d);
+  if (rc) return rc;
+  g->d.U = U;
+  g->d.U_alt = U_alt;
+  g->cur = 0;
+  return HYDRO_OK;
+}
+
+int hydro_set_pencils(hydro_grid* g, int nseg) {
+  if (!g) return fail(HYDRO_EINVAL, "handle is NULL");
+  if (nseg != 1 && nseg != 2 && nseg != 4) return fail(HYDRO_EINVAL, "pencils per column must be 1, 2 or 4");
+  if (g->d.nxb / nseg < 2) return fail(HYDRO_EINVAL, "pencils shorter than 2 planes");
+  g->nseg = nseg;
+  return HYDRO_OK;
+}
+
+// ---- batches ---------------------------------------------------------------
+
+namespace {
+
+constexpr int kMaxPencils = 4;
+
+int tile_edge(int nxb) { return nxb == 8 ? 8 : 16; }
+int size_class(int nxb) { return nxb == 8 ? 0 : nxb == 16 ? 1 : 2; }
+
+long columns_of(const hydro_grid* g) {
+  const long per = (long)(g->d.nxb / tile_edge(g->d.nxb)) * (g->d.nxb / tile_edge(g->d.nxb));
+  return (long)g->d.nblk[0] * g->d.nblk[1] * g->d.nblk[2] * per;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BatchLayout {
+  size_t sims, items, total, max_items;
+};
+
+BatchLayout batch_layout(hydro_grid* const* grids, int n) {
+  BatchLayout L;
+  size_t maxi = 0;
+  for (int i = 0; i < n; ++i) maxi += (size_t)columns_of(grids[i]) * kMaxPencils;
+  L.max_items = maxi;
+  L.sims = 0;
+  L.items = align256(sizeof(hydro::BatchSim) * (size_t)n);
+  L.total = L.items + align256(sizeof(hydro::BatchItem) * maxi);
+  return L;
+}
+
+void drop_graph(hydro_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// Rebuild the member table and the work list from the grid handles (their
+// current buffer and signal slot) and upload both.
+int batch_upload(hydro_batch* b) {
+  hipStream_t s = (hipStream_t)b->stream;
+  const int n = (int)b->grids.size();
+  b->sims.resize(n);
+  b->items.clear();
+  // heaviest pencils first (32^3 columns, then 16^3, then 8^3): the strided
+  // assignment then hands every workgroup a similar mix
+  for (int cls = 2; cls >= 0; --cls) {
+    for (int i = 0; i < n; ++i) {
+      hydro_grid* g = b->grids[i];
+      if (!b->active[i] || size_class(g->d.nxb) != cls) continue;
+      const long cols = columns_of(g) * b->nseg[cls];
+      for (long c = 0; c < cols; ++c) b->items.push_back(hydro::BatchItem{i, (int)c});
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    hydro_grid* g = b->grids[i];
+    hydro::BatchSim& m = b->sims[i];
+    m.U0 = g->d.U;
+    m.U1 = g->d.U_alt;
+    m.ws = ws_of(g);
+    m.geom = g->geom;
+    m.nxb = g->d.nxb;
+    m.parity0 = g->cur;
+    m.slot0 = slot_of(g);
+    m.pad = 0;
+    if (b->active[i]) {
+      int rc = ensure_signal_on(g, s);
+      if (rc) return rc;
+    }
+  }
+  hipError_t e = hipMemcpyAsync(b->d_sims, b->sims.data(), sizeof(hydro::BatchSim) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !b->items.empty())
+    e = hipMemcpyAsync(b->d_items, b->items.data(), sizeof(hydro::BatchItem) * b->items.size(),
+                       hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "batch table upload");
+  b->step = 0;
+  b->dirty = false;
+  drop_graph(b);
+  return HYDRO_OK;
+}
+
+hipError_t batch_launch(hydro_batch* b, double cfl, long step) {
+  return hydro::launch_batch_step(b->d_sims, b->d_items, (int)b->items.size(), step % 6, cfl, b->nseg, b->grid,
+                                  (hipStream_t)b->stream);
+}
+
+void advance_members(hydro_batch* b, int nsteps) {
+  for (size_t i = 0; i < b->grids.size(); ++i) {
+    if (!b->active[i]) continue;
+    hydro_grid* g = b->grids[i];
+    g->cur ^= (nsteps & 1);
+    g->steps += (unsigned long long)nsteps;
+    g->sig_valid = true;
+  }
+}
+
+}  // namespace
+
+size_t hydro_batch_work_bytes(hydro_grid* const* grids, int n) {
+  if (!grids || n <= 0) return 0;
+  for (int i = 0; i < n; ++i)
+    if (!grids[i]) return 0;
+  return batch_layout(grids, n).total;
+}
+
+int hydro_batch_create(hydro_grid* const* grids, int n, void* work, size_t work_bytes, void* stream,
+                       hydro_batch** out) {
+  if (!out) return fail(HYDRO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grids || n <= 0) return fail(HYDRO_EINVAL, "a batch needs at least one grid");
+  for (int i = 0; i < n; ++i) {
+    if (!grids[i]) return fail(HYDRO_EINVAL, "grid %d is NULL", i);
+    if (grids[i]->batch) return fail(HYDRO_EINVAL, "grid %d already belongs to a batch", i);
+    for (int k = 0; k < i; ++k)
+      if (grids[k] == grids[i]) return fail(HYDRO_EINVAL, "grid %d appears twice", i);
+  }
+  if (!work || ((uintptr_t)work & 255)) return fail(HYDRO_EINVAL, "batch workspace must be non-NULL and 256-byte aligned");
+  const BatchLayout L = batch_layout(grids, n);
+  if (L.max_items > (size_t)0x7fffffff) return fail(HYDRO_EINVAL, "batch too large");
+  if (work_bytes < L.total) return fail(HYDRO_ESIZE, "batch workspace has %zu bytes, needs %zu", work_bytes, L.total);
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "device query");
+  hydro_batch* b = new (std::nothrow) hydro_batch;
+  if (!b) return fail(HYDRO_EINVAL, "out of host memory");
+  b->grids.assign(grids, grids + n);
+  b->active.assign(n, 1);
+  b->d_sims = (hydro::BatchSim*)((char*)work + L.sims);
+  b->d_items = (hydro::BatchItem*)((char*)work + L.items);
+  b->max_items = L.max_items;
+  b->stream = stream;
+  b->nseg[0] = b->nseg[1] = b->nseg[2] = 1;
+  b->cus = cus;
+  b->grid = 2 * cus;
+  b->step = 0;
+  b->dirty = true;
+  b->use_graph = false;
+  b->graph = nullptr;
+  b->exec = nullptr;
+  for (int i = 0; i < n; ++i) grids[i]->batch = b;
+  *out = b;
+  return HYDRO_OK;
+}
+
+int hydro_batch_set_active(hydro_batch* b, const unsigned char* mask) {
+  if (!b || !mask) return fail(HYDRO_EINVAL, "batch or mask is NULL");
+  for (size_t i = 0; i < b->grids.size(); ++i) b->active[i] = mask[i] ? 1 : 0;
+  b->dirty = true;
+  return HYDRO_OK;
+}
+
+int hydro_batch_set_pencils(hydro_batch* b, const int nseg[3]) {
+  if (!b || !nseg) return fail(HYDRO_EINVAL, "batch or nseg is NULL");
+  const int sizes[3] = {8, 16, 32};
+  for (int c = 0; c < 3; ++c) {
+    if (nseg[c] != 1 && nseg[c] != 2 && nseg[c] != 4) return fail(HYDRO_EINVAL, "pencils per column must be 1, 2 or 4");
+    if (sizes[c] / nseg[c] < 2) return fail(HYDRO_EINVAL, "pencils shorter than 2 planes");
+  }
+  for (int c = 0; c < 3; ++c) b->nseg[c] = nseg[c];
+  b->dirty = true;
+  return HYDRO_OK;
+}
+
+int hydro_batch_set_workgroups(hydro_batch* b, int per_cu) {
+  if (!b) return fail(HYDRO_EINVAL, "batch is NULL");
+  if (per_cu < 1 || per_cu > 8) return fail(HYDRO_EINVAL, "workgroups per CU must be 1..8");
+  b->grid = per_cu * b->cus;
+  drop_graph(b);
+  return HYDRO_OK;
+}
+
+int hydro_batch_use_graph(hydro_batch* b, int enable) {
+  if (!b) return fail(HYDRO_EINVAL, "batch is NULL");
+  b->use_graph = enable != 0;
+  if (!b->use_graph) drop_graph(b);
+  return HYDRO_OK;
+}
+
+int hydro_batch_step(hydro_batch* b, double cfl, int nsteps) {
+  if (!b) return fail(HYDRO_EINVAL, "batch is NULL");
+  if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0 (got %g)", cfl);
+  if (nsteps < 0) return fail(HYDRO_EINVAL, "nsteps must be >= 0");
+  if (b->dirty) {
+    int rc = batch_upload(b);
+    if (rc) return rc;
+  }
+  if (b->items.empty() || nsteps == 0) return HYDRO_OK;
+  hipStream_t s = (hipStream_t)b->stream;
+  int done = 0;
+  while (done < nsteps) {
+    const bool aligned = (b->step % 6) == 0;
+    if (b->use_graph && aligned && nsteps - done >= 6) {
+      if (!b->exec) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        for (int k = 0; k < 6 && e == hipSuccess; ++k) e = batch_launch(b, cfl, k);
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s, &gr);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+          if (gr) hipGraphDestroy(gr);
+          b->exec = nullptr;
+          return hip_fail(e, "batch graph capture");
+        }
+        b->graph = gr;
+        b->graph_cfl = cfl;
+      }
+      if (b->graph_cfl != cfl) {
+        drop_graph(b);
+        continue;
+      }
+      hipError_t e = hipGraphLaunch(b->exec, s);
+      if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+      b->step += 6;
+      done += 6;
+      advance_members(b, 6);
+      continue;
+    }
+    hipError_t e = batch_launch(b, cfl, b->step);
+    if (e != hipSuccess) return hip_fail(e, "batch step launch");
+    b->step += 1;
+    done += 1;
+    advance_members(b, 1);
+  }
+  return HYDRO_OK;
+}
+
+int hydro_batch_dts(hydro_batch* b, double* dt_out) {
+  if (!b || !dt_out) return fail(HYDRO_EINVAL, "batch or dt_out is NULL");
+  hipError_t e = hipStreamSynchronize((hipStream_t)b->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  for (size_t i = 0; i < b->grids.size(); ++i) {
+    hydro::WorkHeader h;
+    e = hipMemcpy(&h, b->grids[i]->d.work, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (member header)");
+    dt_out[i] = h.dt_last;
+  }
+  return HYDRO_OK;
+}
+
+int hydro_batch_free(hydro_batch* b) {
+  if (!b) return HYDRO_OK;
+  drop_graph(b);
+  for (hydro_grid* g : b->grids) g->batch = nullptr;
+  delete b;
   return HYDRO_OK;
 }
 

@@ -39,7 +39,27 @@ struct StepArgs {
   int slot;           // step number mod 3
 };
 
-hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, hipStream_t s);
+// One member grid of a batch (device table entry).
+struct BatchSim {
+  double* U0;         // state buffer 0
+  double* U1;         // state buffer 1
+  WorkHeader* ws;     // the grid's workspace header
+  GridGeom geom;
+  int nxb;
+  int parity0;        // buffer holding the state at batch step 0 (0: U0, 1: U1)
+  int slot0;          // signal slot of the state at batch step 0
+  int pad;
+};
+
+// One unit of batch work: a z pencil of a column tile of one grid.
+struct BatchItem {
+  int sim;
+  int tile;           // pencil index inside the grid (see tile_step)
+};
+
+hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, int nseg, hipStream_t s);
+hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,
+                             const int nseg[3], int grid, hipStream_t s);
 hipError_t launch_fill_guards(int nxb, const GridGeom& g, const double* U, double* out, hipStream_t s);
 hipError_t launch_signal(int nxb, const GridGeom& g, const double* U, WorkHeader* ws, int slot,
                          hipStream_t s);

@@ -78,7 +78,6 @@ __device__ __forceinline__ void load_cons(const double* __restrict__ U, long off
 
 // Maximum over a workgroup of a non-negative double, folded into *slot with
 // one atomicMax on the bit pattern.  red must hold one entry per wavefront.
-template <int NT>
 __device__ __forceinline__ void wg_max_to(double v, unsigned long long* red, unsigned long long* slot) {
   unsigned long long bits = __double_as_longlong(v);
 #pragma unroll
@@ -92,7 +91,7 @@ __device__ __forceinline__ void wg_max_to(double v, unsigned long long* red, uns
   if (threadIdx.x == 0) {
     unsigned long long m = red[0];
 #pragma unroll
-    for (int w = 1; w < (NT + 63) / 64; ++w) m = red[w] > m ? red[w] : m;
+    for (int w = 1; w < (int)(blockDim.x + 63) / 64; ++w) m = red[w] > m ? red[w] : m;
     atomicMax(slot, m);
   }
 }
@@ -300,42 +299,58 @@ __device__ __forceinline__ bool predict(const double (&wc)[5], double inv, const
   return ok;
 }
 
+// LDS of one tile step.
+template <int T>
+struct Smem {
+  static constexpr int NT = Tile<T>::NT, NR = Tile<T>::NR, WS = Tile<T>::WS, NQ = Tile<T>::NQ;
+  double sW[5][WS * WS];   // primitives of plane j, tile + 2-halo (index (y+2)*WS + x+2)
+  double sQx[5][NQ];       // high-x face state of cell (x, y), x = -1..T-1: index y*(T+1) + x+1
+  double sQy[5][NQ];       // high-y face state of cell (x, y), y = -1..T-1: index (y+1)*T + x
+  double sRx[5][T];        // low-x face state of ring cell (T, y)
+  double sRy[5][T];        // low-y face state of ring cell (x, T)
+  double sRing[3][5][NR];  // ring z windows (planes mod 3)
+  double sFx[5][NQ];       // x flux at face (x, y), x = 0..T: index y*(T+1) + x
+  double sFy[5][NQ];       // y flux at face (x, y), y = 0..T: index y*T + x
+  unsigned long long sRed[4];  // one per wavefront of a workgroup of up to 256 threads
+  int sCnt[3];
+};
+
+// One z pencil of one T x T column tile of an N^3 block, updated from Uin into
+// Uout.  tile_in_sim = (block * (N/T)^2 + in-plane tile) * nseg + segment;
+// the pencil covers planes [segment*N/nseg, (segment+1)*N/nseg).  dt is
+// cfl / max signal speed (ws->sig[slot]) when cfl > 0, else dt_host.  The
+// new state's signal speed goes to ws->sig[(slot+1)%3]; the first pencil of
+// the grid also records dt and clears ws->sig[(slot+2)%3].  Must be entered
+// by all NT threads of the workgroup.
 template <int N, int T>
-__global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepArgs a, long ntiles) {
+__device__ __forceinline__ void tile_step(const GridGeom& g, const double* __restrict__ Uin,
+                                          double* __restrict__ Uout, WorkHeader* ws, double dt_host,
+                                          double cfl, int slot, long tile_in_sim, int nseg, Smem<T>& sm) {
   using TL = Tile<T>;
-  constexpr int NT = TL::NT, NI = TL::NI, NR = TL::NR, NE = TL::NE, WS = TL::WS, NQ = TL::NQ;
+  constexpr int NT = TL::NT, NI = TL::NI, NR = TL::NR, NE = TL::NE, WS = TL::WS;
   constexpr int TPB = (N / T) * (N / T);
   constexpr long VS = Layout<N>::VS;
+  constexpr long PS = Layout<N>::PS;
 
-  __shared__ double sW[5][WS * WS];   // primitives of plane j, tile + 2-halo (index (y+2)*WS + x+2)
-  __shared__ double sQx[5][NQ];       // high-x face state of cell (x, y), x = -1..T-1: index y*(T+1) + x+1
-  __shared__ double sQy[5][NQ];       // high-y face state of cell (x, y), y = -1..T-1: index (y+1)*T + x
-  __shared__ double sRx[5][T];        // low-x face state of ring cell (T, y)
-  __shared__ double sRy[5][T];        // low-y face state of ring cell (x, T)
-  __shared__ double sRing[3][5][NR];  // ring z windows (planes mod 3)
-  __shared__ double sFx[5][NQ];       // x flux at face (x, y), x = 0..T: index y*(T+1) + x
-  __shared__ double sFy[5][NQ];       // y flux at face (x, y), y = 0..T: index y*T + x
-  __shared__ unsigned long long sRed[NT / 64];
-  __shared__ int sCnt[3];
-
-  const long tile_id = xcd_tile(blockIdx.x, ntiles);
-  if (tile_id >= ntiles) return;
   const int tid = threadIdx.x;
-  const long blk = tile_id / TPB;
-  const int tile = (int)(tile_id % TPB);
+  const long col = tile_in_sim / nseg;
+  const int seg = (int)(tile_in_sim % nseg);
+  const int L = N / nseg, z0 = seg * L, z1 = z0 + L;
+  const long blk = col / TPB;
+  const int tile = (int)(col % TPB);
   const int bx = (int)(blk % g.nb[0]);
   const int by = (int)((blk / g.nb[0]) % g.nb[1]);
   const int bz = (int)(blk / ((long)g.nb[0] * g.nb[1]));
   const int lx0 = (tile % (N / T)) * T, ly0 = (tile / (N / T)) * T;  // tile origin inside the block
   const int X0 = bx * N + lx0, Y0 = by * N + ly0, Z0 = bz * N;
 
-  if (tid < 3) sCnt[tid] = 0;
+  if (tid < 3) sm.sCnt[tid] = 0;
 
-  double dt = a.dt;
-  if (a.cfl > 0.0) dt = a.cfl / __longlong_as_double(a.ws->sig[a.slot]);
-  if (tile_id == 0 && tid == 0) {
-    a.ws->dt_last = dt;
-    a.ws->sig[(a.slot + 2) % 3] = 0ull;
+  double dt = dt_host;
+  if (cfl > 0.0) dt = cfl / __longlong_as_double(ws->sig[slot]);
+  if (tile_in_sim == 0 && tid == 0) {
+    ws->dt_last = dt;
+    ws->sig[(slot + 2) % 3] = 0ull;
   }
   const double lamx = dt * g.inv_dx[0], lamy = dt * g.inv_dx[1], lamz = dt * g.inv_dx[2];
   const double gamma = g.gamma, gm1inv = 1.0 / (g.gamma - 1.0);
@@ -343,7 +358,10 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
   // roles; the second items (ring, halo) and the boundary faces sit on the
   // wavefronts starting at (tile mod 4) so the busier wavefront moves
   // between SIMDs from one workgroup to the next
-  const int role = (tid + 64 * (int)(tile_id & 3)) % NT;
+  // (a workgroup may be wider than NT, e.g. 8^3 tiles in a 256-thread batch
+  // launch: the threads beyond NT only take part in the barriers)
+  const bool member = tid < NT;
+  const int role = member ? (tid + 64 * (int)(col & 3)) % NT : NT;
   const bool inner = tid < NI;
   const int cx = tid % T, cy = tid / T;                // valid when inner
   const int cidx = (cy + 2) * WS + (cx + 2);
@@ -359,6 +377,12 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
   // planes that lie inside the block (z halo planes go through the map)
   const long own0 = Layout<N>::at(blk, lx0 + cx, ly0 + cy, 0);
   const long sec0 = (is_ring || is_extra) ? cell_offset<N>(g, X0 + sx2, Y0 + sy2, Z0) : 0;
+  auto own_at = [&](int k) -> long {
+    return (k >= 0 && k < N) ? own0 + k * PS : cell_offset<N>(g, X0 + cx, Y0 + cy, Z0 + k);
+  };
+  auto sec_at = [&](int k) -> long {
+    return (k >= 0 && k < N) ? sec0 + k * PS : cell_offset<N>(g, X0 + sx2, Y0 + sy2, Z0 + k);
+  };
 
   double Wa[5], Wb[5], Wc[5];
   double un_next[5], u2_next[5];
@@ -372,39 +396,36 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
   int n_floor = 0, n_fb = 0, n_bad = 0;
   double smax = 0.0;
 
-  // prologue: planes -2, -1 of the own column, prefetch plane 0
+  // prologue: planes z0-2, z0-1 of the own column, prefetch plane z0
   if (inner) {
     double u[5], tmp;
-    load_cons<N>(a.Uin, cell_offset<N>(g, X0 + cx, Y0 + cy, Z0 - 2), u);
+    load_cons<N>(Uin, own_at(z0 - 2), u);
     prim(u, gamma, g.small_p, Wa, tmp);
-    load_cons<N>(a.Uin, cell_offset<N>(g, X0 + cx, Y0 + cy, Z0 - 1), u);
+    load_cons<N>(Uin, own_at(z0 - 1), u);
     prim(u, gamma, g.small_p, Wb, tmp);
-    load_cons<N>(a.Uin, own0, un_next);
+    load_cons<N>(Uin, own0 + z0 * PS, un_next);
   }
   if (is_ring) {
     double u[5], w[5], tmp;
-    load_cons<N>(a.Uin, cell_offset<N>(g, X0 + sx2, Y0 + sy2, Z0 - 1), u);
+    load_cons<N>(Uin, sec_at(z0 - 1), u);
     prim(u, gamma, g.small_p, w, tmp);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sRing[2][v][ring_id] = w[v];
-    load_cons<N>(a.Uin, sec0, u2_next);
+    for (int v = 0; v < 5; ++v) sm.sRing[(z0 + 2) % 3][v][ring_id] = w[v];
+    load_cons<N>(Uin, sec0 + z0 * PS, u2_next);
   }
-  if (is_extra) load_cons<N>(a.Uin, sec0, u2_next);
+  if (is_extra) load_cons<N>(Uin, sec0 + z0 * PS, u2_next);
 
-  for (int j = -1; j <= N; ++j) {
-    const bool mid = (j >= 0) && (j < N);
-    const int sm = (j + 5) % 3, s0 = (j + 3) % 3, sp = (j + 4) % 3;  // ring slots of planes j-1, j, j+1
+  for (int j = z0 - 1; j <= z1; ++j) {
+    const bool mid = (j >= z0) && (j < z1);
+    const int sl_m = (j + 5) % 3, sl_0 = (j + 3) % 3, sl_p = (j + 4) % 3;  // ring slots of planes j-1, j, j+1
     // -- own column: plane j+1 from the prefetch, prefetch plane j+2, publish plane j
     if (inner) {
       double inv_unused;
       const int fl = prim(un_next, gamma, g.small_p, Wc, inv_unused);
-      if (j + 1 >= 0 && j + 1 < N) n_floor += fl;
-      if (j + 2 < N)
-        load_cons<N>(a.Uin, own0 + (j + 2) * Layout<N>::PS, un_next);
-      else if (j + 2 <= N + 1)
-        load_cons<N>(a.Uin, cell_offset<N>(g, X0 + cx, Y0 + cy, Z0 + j + 2), un_next);
+      if (j + 1 >= z0 && j + 1 < z1) n_floor += fl;
+      if (j + 2 <= z1 + 1) load_cons<N>(Uin, own_at(j + 2), un_next);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sW[v][cidx] = Wb[v];
+      for (int v = 0; v < 5; ++v) sm.sW[v][cidx] = Wb[v];
     }
     // -- second item: ring cell window (planes j..j+1) or halo cell (plane j)
     if (is_ring) {
@@ -412,32 +433,29 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
       prim(u2_next, gamma, g.small_p, w, tmp);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        sRing[sp][v][ring_id] = w[v];
-        sW[v][sidx2] = sRing[s0][v][ring_id];
+        sm.sRing[sl_p][v][ring_id] = w[v];
+        sm.sW[v][sidx2] = sm.sRing[sl_0][v][ring_id];
       }
-      if (j + 2 < N)
-        load_cons<N>(a.Uin, sec0 + (j + 2) * Layout<N>::PS, u2_next);
-      else if (j + 2 <= N + 1)
-        load_cons<N>(a.Uin, cell_offset<N>(g, X0 + sx2, Y0 + sy2, Z0 + j + 2), u2_next);
+      if (j + 2 <= z1 + 1) load_cons<N>(Uin, sec_at(j + 2), u2_next);
     }
     if (is_extra && mid) {
       double w[5], tmp;
       prim(u2_next, gamma, g.small_p, w, tmp);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sW[v][sidx2] = w[v];
-      if (j + 1 < N) load_cons<N>(a.Uin, sec0 + (j + 1) * Layout<N>::PS, u2_next);
+      for (int v = 0; v < 5; ++v) sm.sW[v][sidx2] = w[v];
+      if (j + 1 < z1) load_cons<N>(Uin, sec0 + (j + 1) * PS, u2_next);
     }
     __syncthreads();
 
-    // -- predictor: own cell (every plane), ring cell (planes 0..N-1)
+    // -- predictor: own cell (every plane), ring cell (pencil planes)
     double xm[5], ym[5], zm[5], zp[5];
     if (inner) {
       double sx[5], sy[5], sz[5], wt[5], h;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const double c = Wb[v];
-        sx[v] = van_leer_sf(c - sW[v][cidx - 1], sW[v][cidx + 1] - c);
-        sy[v] = van_leer_sf(c - sW[v][cidx - WS], sW[v][cidx + WS] - c);
+        sx[v] = van_leer_sf(c - sm.sW[v][cidx - 1], sm.sW[v][cidx + 1] - c);
+        sy[v] = van_leer_sf(c - sm.sW[v][cidx - WS], sm.sW[v][cidx + WS] - c);
         sz[v] = van_leer_sf(c - Wa[v], Wc[v] - c);
       }
       const bool ok = predict(Wb, rcp_nr(Wb[0]), sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
@@ -452,8 +470,8 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
       if (mid) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          sQx[v][cy * (T + 1) + cx + 1] = fma(h, sx[v], wt[v]);
-          sQy[v][(cy + 1) * T + cx] = fma(h, sy[v], wt[v]);
+          sm.sQx[v][cy * (T + 1) + cx + 1] = fma(h, sx[v], wt[v]);
+          sm.sQy[v][(cy + 1) * T + cx] = fma(h, sy[v], wt[v]);
         }
       }
     }
@@ -461,10 +479,10 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
       double wc[5], sx[5], sy[5], sz[5], wt[5], h;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        wc[v] = sRing[s0][v][ring_id];
-        sx[v] = van_leer_sf(wc[v] - sW[v][sidx2 - 1], sW[v][sidx2 + 1] - wc[v]);
-        sy[v] = van_leer_sf(wc[v] - sW[v][sidx2 - WS], sW[v][sidx2 + WS] - wc[v]);
-        sz[v] = van_leer_sf(wc[v] - sRing[sm][v][ring_id], sRing[sp][v][ring_id] - wc[v]);
+        wc[v] = sm.sRing[sl_0][v][ring_id];
+        sx[v] = van_leer_sf(wc[v] - sm.sW[v][sidx2 - 1], sm.sW[v][sidx2 + 1] - wc[v]);
+        sy[v] = van_leer_sf(wc[v] - sm.sW[v][sidx2 - WS], sm.sW[v][sidx2 + WS] - wc[v]);
+        sz[v] = van_leer_sf(wc[v] - sm.sRing[sl_m][v][ring_id], sm.sRing[sl_p][v][ring_id] - wc[v]);
       }
       const double inv = rcp_nr(wc[0]);
       predict(wc, inv, sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
@@ -472,20 +490,20 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
       const int r = ring_id % T;
       if (rside == 0) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sQx[v][r * (T + 1)] = fma(h, sx[v], wt[v]);  // (-1, r) high x
+        for (int v = 0; v < 5; ++v) sm.sQx[v][r * (T + 1)] = fma(h, sx[v], wt[v]);  // (-1, r) high x
       } else if (rside == 1) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sRx[v][r] = fma(-h, sx[v], wt[v]);           // (T, r) low x
+        for (int v = 0; v < 5; ++v) sm.sRx[v][r] = fma(-h, sx[v], wt[v]);           // (T, r) low x
       } else if (rside == 2) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sQy[v][r] = fma(h, sy[v], wt[v]);            // (r, -1) high y
+        for (int v = 0; v < 5; ++v) sm.sQy[v][r] = fma(h, sy[v], wt[v]);            // (r, -1) high y
       } else {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sRy[v][r] = fma(-h, sy[v], wt[v]);           // (r, T) low y
+        for (int v = 0; v < 5; ++v) sm.sRy[v][r] = fma(-h, sy[v], wt[v]);           // (r, T) low y
       }
     }
     double fz[5];
-    if (inner && j >= 0) hllc<2>(zp_prev, zm, gamma, gm1inv, fz);
+    if (inner && j >= z0) hllc<2>(zp_prev, zm, gamma, gm1inv, fz);
     __syncthreads();
 
     // -- x and y fluxes: own low faces, plus the tile's high boundary faces
@@ -493,15 +511,15 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
       if (inner) {
         double WL[5], F[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) WL[v] = sQx[v][cy * (T + 1) + cx];
+        for (int v = 0; v < 5; ++v) WL[v] = sm.sQx[v][cy * (T + 1) + cx];
         hllc<0>(WL, xm, gamma, gm1inv, F);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sFx[v][cy * (T + 1) + cx] = F[v];
+        for (int v = 0; v < 5; ++v) sm.sFx[v][cy * (T + 1) + cx] = F[v];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) WL[v] = sQy[v][cy * T + cx];
+        for (int v = 0; v < 5; ++v) WL[v] = sm.sQy[v][cy * T + cx];
         hllc<1>(WL, ym, gamma, gm1inv, F);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sFy[v][cy * T + cx] = F[v];
+        for (int v = 0; v < 5; ++v) sm.sFy[v][cy * T + cx] = F[v];
       }
       if (role < 2 * T) {
         double WL[5], WR[5], F[5];
@@ -509,21 +527,21 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
         if (role < T) {  // x face at x = T, y = r
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            WL[v] = sQx[v][r * (T + 1) + T];
-            WR[v] = sRx[v][r];
+            WL[v] = sm.sQx[v][r * (T + 1) + T];
+            WR[v] = sm.sRx[v][r];
           }
           hllc<0>(WL, WR, gamma, gm1inv, F);
 #pragma unroll
-          for (int v = 0; v < 5; ++v) sFx[v][r * (T + 1) + T] = F[v];
+          for (int v = 0; v < 5; ++v) sm.sFx[v][r * (T + 1) + T] = F[v];
         } else {        // y face at y = T, x = r
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            WL[v] = sQy[v][T * T + r];
-            WR[v] = sRy[v][r];
+            WL[v] = sm.sQy[v][T * T + r];
+            WR[v] = sm.sRy[v][r];
           }
           hllc<1>(WL, WR, gamma, gm1inv, F);
 #pragma unroll
-          for (int v = 0; v < 5; ++v) sFy[v][T * T + r] = F[v];
+          for (int v = 0; v < 5; ++v) sm.sFy[v][T * T + r] = F[v];
         }
       }
     }
@@ -536,16 +554,16 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
         const int qx = cy * (T + 1) + cx, qy = cy * T + cx;
 #pragma unroll
         for (int v = 0; v < 5; ++v)
-          dxy[v] = lamx * (sFx[v][qx + 1] - sFx[v][qx]) + lamy * (sFy[v][qy + T] - sFy[v][qy]);
+          dxy[v] = lamx * (sm.sFx[v][qx + 1] - sm.sFx[v][qx]) + lamy * (sm.sFy[v][qy + T] - sm.sFy[v][qy]);
       }
-      if (j >= 1) {
-        const long off = own0 + (j - 1) * Layout<N>::PS;
+      if (j >= z0 + 1) {
+        const long off = own0 + (j - 1) * PS;
         double uold[5], un[5];
-        load_cons<N>(a.Uin, off, uold);
+        load_cons<N>(Uin, off, uold);
 #pragma unroll
         for (int v = 0; v < 5; ++v) un[v] = uold[v] - (dxy_prev[v] + lamz * (fz[v] - fz_prev[v]));
 #pragma unroll
-        for (int v = 0; v < 5; ++v) a.Uout[off + v * VS] = un[v];
+        for (int v = 0; v < 5; ++v) Uout[off + v * VS] = un[v];
         bool good = un[0] > 0.0 && un[4] > 0.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) good = good && isfinite(un[v]);
@@ -556,7 +574,7 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         if (mid) dxy_prev[v] = dxy[v];
-        if (j >= 0) fz_prev[v] = fz[v];
+        if (j >= z0) fz_prev[v] = fz[v];
         zp_prev[v] = zp[v];
         Wa[v] = Wb[v];
         Wb[v] = Wc[v];
@@ -564,13 +582,55 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
     }
   }
 
-  if (n_floor) atomicAdd(&sCnt[0], n_floor);
-  if (n_fb) atomicAdd(&sCnt[1], n_fb);
-  if (n_bad) atomicAdd(&sCnt[2], n_bad);
-  wg_max_to<NT>(smax, sRed, &a.ws->sig[(a.slot + 1) % 3]);
+  if (n_floor) atomicAdd(&sm.sCnt[0], n_floor);
+  if (n_fb) atomicAdd(&sm.sCnt[1], n_fb);
+  if (n_bad) atomicAdd(&sm.sCnt[2], n_bad);
+  wg_max_to(smax, sm.sRed, &ws->sig[(slot + 1) % 3]);
   if (tid == 0) {
     for (int c = 0; c < 3; ++c)
-      if (sCnt[c]) atomicAdd(&a.ws->cnt[c], (unsigned long long)sCnt[c]);
+      if (sm.sCnt[c]) atomicAdd(&ws->cnt[c], (unsigned long long)sm.sCnt[c]);
+  }
+}
+
+// One grid: one workgroup per pencil, XCD-aware order.
+template <int N, int T>
+__global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepArgs a, long ntiles, int nseg) {
+  __shared__ Smem<T> sm;
+  const long tile_id = xcd_tile(blockIdx.x, ntiles);
+  if (tile_id >= ntiles) return;
+  tile_step<N, T>(g, a.Uin, a.Uout, a.ws, a.dt, a.cfl, a.slot, tile_id, nseg, sm);
+}
+
+// Many grids in one persistent launch: workgroup w takes items w, w + G,
+// w + 2G, ... of the work list (G workgroups), which lists the heaviest
+// pencils first.  The item sequence depends only on the launch shape, so the
+// loop and every barrier in it are in uniform control flow.  (A shared
+// atomic counter broadcast through LDS was compiled into a loop whose lanes
+// reached the barrier without the fetching lane's store, and never ended.)
+// Every grid uses its own device dt (cfl / its own maximum signal speed).
+union BatchSmem {
+  Smem<8> s8;
+  Smem<16> s16;
+};
+
+__global__ __launch_bounds__(256, 2) void batch_step_kernel(const BatchSim* __restrict__ sims,
+                                                            const BatchItem* __restrict__ items, int nitems,
+                                                            long step, double cfl, int nseg8, int nseg16,
+                                                            int nseg32) {
+  __shared__ BatchSmem sm;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BatchItem w = items[it];
+    const BatchSim& d = sims[w.sim];
+    const int par = (int)((d.parity0 + step) & 1);
+    const int slot = (int)((d.slot0 + step) % 3);
+    const double* Uin = par ? d.U1 : d.U0;
+    double* Uout = par ? d.U0 : d.U1;
+    switch (d.nxb) {
+      case 8: tile_step<8, 8>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, nseg8, sm.s8); break;
+      case 16: tile_step<16, 16>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, nseg16, sm.s16); break;
+      default: tile_step<32, 16>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, nseg32, sm.s16); break;
+    }
+    __syncthreads();  // the next item reuses the LDS
   }
 }
 
@@ -618,7 +678,7 @@ __global__ __launch_bounds__(256) void signal_kernel(GridGeom g, const double* _
     const double s = signal_speed(u, g);
     smax = (s > smax || !(s == s)) ? s : smax;
   }
-  wg_max_to<256>(smax, sRed, slot);
+  wg_max_to(smax, sRed, slot);
 }
 
 __global__ void clear_slot_kernel(WorkHeader* ws, int slot) { ws->sig[slot] = 0ull; }
@@ -636,23 +696,31 @@ __global__ __launch_bounds__(256) void copy_kernel(const double* __restrict__ sr
 }
 
 template <int N, int T>
-hipError_t launch_step_t(const GridGeom& g, const StepArgs& a, hipStream_t s) {
+hipError_t launch_step_t(const GridGeom& g, const StepArgs& a, int nseg, hipStream_t s) {
   const long nblk = (long)g.nb[0] * g.nb[1] * g.nb[2];
-  const long ntiles = nblk * (N / T) * (N / T);
+  const long ntiles = nblk * (N / T) * (N / T) * nseg;
   const long grid = 8 * ((ntiles + 7) / 8);
-  hipLaunchKernelGGL((step_kernel<N, T>), dim3((unsigned)grid), dim3(Tile<T>::NT), 0, s, g, a, ntiles);
+  hipLaunchKernelGGL((step_kernel<N, T>), dim3((unsigned)grid), dim3(Tile<T>::NT), 0, s, g, a, ntiles, nseg);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, hipStream_t s) {
+hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, int nseg, hipStream_t s) {
+  if (nseg < 1 || nxb % nseg || nxb / nseg < 2) return hipErrorInvalidValue;
   switch (nxb) {
-    case 8: return launch_step_t<8, 8>(g, a, s);
-    case 16: return launch_step_t<16, 16>(g, a, s);
-    case 32: return launch_step_t<32, 16>(g, a, s);
+    case 8: return launch_step_t<8, 8>(g, a, nseg, s);
+    case 16: return launch_step_t<16, 16>(g, a, nseg, s);
+    case 32: return launch_step_t<32, 16>(g, a, nseg, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,
+                             const int nseg[3], int grid, hipStream_t s) {
+  hipLaunchKernelGGL(batch_step_kernel, dim3((unsigned)grid), dim3(256), 0, s, sims, items, nitems, step, cfl,
+                     nseg[0], nseg[1], nseg[2]);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_guards(int nxb, const GridGeom& g, const double* U, double* out, hipStream_t s) {

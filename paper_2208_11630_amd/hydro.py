@@ -66,6 +66,18 @@ SIGNATURES = {
     "hydro_current": ([_HP, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "hydro_counters": ([_HP, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
     "hydro_free_grid": ([_HP], ctypes.c_int),
+    "hydro_set_pencils": ([_HP, ctypes.c_int], ctypes.c_int),
+    "hydro_set_buffers": ([_HP, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "hydro_batch_work_bytes": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int], ctypes.c_size_t),
+    "hydro_batch_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "hydro_batch_step": ([_HP, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "hydro_batch_set_active": ([_HP, ctypes.POINTER(ctypes.c_ubyte)], ctypes.c_int),
+    "hydro_batch_set_pencils": ([_HP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "hydro_batch_set_workgroups": ([_HP, ctypes.c_int], ctypes.c_int),
+    "hydro_batch_use_graph": ([_HP, ctypes.c_int], ctypes.c_int),
+    "hydro_batch_dts": ([_HP, _dp], ctypes.c_int),
+    "hydro_batch_free": ([_HP], ctypes.c_int),
     "hydro_copy_probe": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "hydro_last_error": ([], ctypes.c_char_p),
 }
@@ -127,7 +139,7 @@ class Grid:
 
     def __init__(self, nxb: int, nblk: Sequence[int], lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
                  bc=(BC_PERIODIC,) * 3, gamma: float = 1.4, small_p: float = 1e-10,
-                 device: str = "cuda", stream=None, nguard: int = NGUARD):
+                 device: str = "cuda", stream=None, nguard: int = NGUARD, buffers=None):
         import torch
 
         L = lib()
@@ -143,7 +155,13 @@ class Grid:
         self.shape = (nb, 5, n, n, n)
         P = n + 2 * self.nguard
         self.guarded_shape = (nb, 5, P, P, P)
-        self.bufs = [torch.empty(self.shape, dtype=torch.float64, device=device) for _ in range(2)]
+        if buffers is None:
+            self.bufs = [torch.empty(self.shape, dtype=torch.float64, device=device) for _ in range(2)]
+        else:
+            self.bufs = list(buffers)
+            for t_ in self.bufs:
+                if tuple(t_.shape) != self.shape or t_.dtype != torch.float64 or not t_.is_contiguous():
+                    raise HydroError(HYDRO_EINVAL, "state buffers must be contiguous float64 of the grid shape")
         wb = L.hydro_work_bytes(ctypes.byref(d))
         self.work = torch.zeros(max(wb, 256), dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.bufs[0].device)
@@ -204,9 +222,84 @@ class Grid:
         _check(lib().hydro_counters(self.handle, out))
         return np.array(list(out), dtype=np.int64)
 
+    def set_pencils(self, nseg: int) -> None:
+        _check(lib().hydro_set_pencils(self.handle, int(nseg)))
+
+    def set_buffers(self, U, U_alt) -> None:
+        """Rebind the state buffers: U holds the current state, U_alt receives
+        the next step (torch float64 tensors of the grid shape)."""
+        for t_ in (U, U_alt):
+            if tuple(t_.shape) != self.shape or not t_.is_contiguous():
+                raise HydroError(HYDRO_EINVAL, "state buffers must be contiguous tensors of the grid shape")
+        _check(lib().hydro_set_buffers(self.handle, U.data_ptr(), U_alt.data_ptr()))
+        self.bufs = [U, U_alt]
+
     def close(self) -> None:
         if getattr(self, "handle", None) is not None:
             lib().hydro_free_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many grids stepped by one persistent launch per step (hydro_batch_*)."""
+
+    def __init__(self, grids, stream=None):
+        import torch
+
+        L = lib()
+        self.grids = list(grids)
+        n = len(self.grids)
+        arr = (ctypes.c_void_p * n)(*[g.handle.value for g in self.grids])
+        wb = L.hydro_batch_work_bytes(arr, n)
+        if wb == 0:
+            raise HydroError(HYDRO_EINVAL, "invalid batch")
+        dev = self.grids[0].bufs[0].device
+        self.work = torch.zeros(wb, dtype=torch.uint8, device=dev)
+        # a stream of its own (graph capture cannot use the null stream),
+        # ordered after the work already queued on the members' streams
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        for g in self.grids:
+            self.stream.wait_stream(g.stream)
+        h = ctypes.c_void_p()
+        _check(L.hydro_batch_create(arr, n, self.work.data_ptr(), wb, self.stream.cuda_stream, ctypes.byref(h)))
+        self.handle = h
+
+    def step(self, cfl: float, nsteps: int = 1) -> None:
+        _check(lib().hydro_batch_step(self.handle, float(cfl), int(nsteps)))
+
+    def synchronize(self) -> None:
+        """Wait for the batch's work; later work on the members' streams is
+        ordered after it too."""
+        self.stream.synchronize()
+
+    def set_active(self, mask) -> None:
+        m = (ctypes.c_ubyte * len(self.grids))(*[1 if x else 0 for x in mask])
+        _check(lib().hydro_batch_set_active(self.handle, m))
+
+    def set_pencils(self, nseg8: int, nseg16: int, nseg32: int) -> None:
+        a = (ctypes.c_int * 3)(int(nseg8), int(nseg16), int(nseg32))
+        _check(lib().hydro_batch_set_pencils(self.handle, a))
+
+    def set_workgroups(self, per_cu: int) -> None:
+        _check(lib().hydro_batch_set_workgroups(self.handle, int(per_cu)))
+
+    def use_graph(self, enable: bool = True) -> None:
+        _check(lib().hydro_batch_use_graph(self.handle, 1 if enable else 0))
+
+    def dts(self) -> np.ndarray:
+        out = (ctypes.c_double * len(self.grids))()
+        _check(lib().hydro_batch_dts(self.handle, out))
+        return np.array(list(out))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            lib().hydro_batch_free(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -317,3 +317,28 @@ def from_primitive(name: str, n: int, rho, u, v, w, p, gamma: float, dx, bc) -> 
     G = conserved(rho, u, v, w, p, gamma)
     Z, Y, X = G.shape[1:]
     return Problem(name, n, (X // n, Y // n, Z // n), tuple(dx), tuple(bc), gamma, to_compact(G, n))
+
+
+def served_state_device(sim: int, L: int, out, seed: int = 3, n: int = 16, gamma: float = 1.4):
+    """Initial state of served simulation ``sim`` drawn on the device into the
+    torch tensor ``out`` ([nblk, 5, n, n, n], compact blocked layout): the
+    ensemble's random state (rho, p log-normal with sigma 0.3; u, v, w normal
+    with sigma 0.2) from torch's device generator seeded with
+    seed * 1000003 + sim, so a served population of any size materialises on
+    first use without host-side generation or transfer."""
+    import torch
+
+    g = torch.Generator(device=out.device)
+    g.manual_seed(seed * 1000003 + sim)
+    shape = (L, L, L)
+    kw = dict(generator=g, device=out.device, dtype=torch.float64)
+    rho = torch.exp(0.3 * torch.randn(shape, **kw))
+    p = torch.exp(0.3 * torch.randn(shape, **kw))
+    u = 0.2 * torch.randn(shape, **kw)
+    v = 0.2 * torch.randn(shape, **kw)
+    w = 0.2 * torch.randn(shape, **kw)
+    G = torch.stack([rho, rho * u, rho * v, rho * w,
+                     p / (gamma - 1.0) + 0.5 * rho * ((u * u + v * v) + w * w)])
+    nb = L // n
+    out.copy_(G.reshape(5, nb, n, nb, n, nb, n).permute(1, 3, 5, 0, 2, 4, 6).reshape(nb ** 3, 5, n, n, n))
+    return out

@@ -1,0 +1,311 @@
+"""Serving loop: step requests for many resident simulations.
+
+Requests ``(sim, arrival time)`` ask for one step of one simulation.  The
+server keeps simulation states on the device within an HBM byte budget
+(admitting a simulation evicts least-recently-used idle ones to host memory),
+allows at most one in-flight step per simulation, and batches whatever is
+ready: all ready requests go into one batched launch (one persistent kernel
+over their blocks), and requests that arrive while launches are running are
+admitted into the next launch, which may start on a second stream while the
+first still runs (continuous batching).  Latency is arrival -> completion of
+the step; throughput is cells updated per second.
+
+The device side is an ``Executor``; ``GpuExecutor`` drives libhydro through
+the Python binding, and tests drive the scheduler with a fake executor.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    sim: int
+    t_arrival: float
+    t_launch: float = math.nan
+    t_done: float = math.nan
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+class Executor:
+    """What the server needs from the device."""
+
+    def bytes_of(self, sim: int) -> int: ...
+    def cells_of(self, sim: int) -> int: ...
+    def is_resident(self, sim: int) -> bool: ...
+    def make_resident(self, sim: int) -> None: ...
+    def evict(self, sim: int) -> None: ...
+    def launch(self, sims: Sequence[int]): ...
+    def done(self, handle) -> bool: ...
+    def finish(self, handle) -> None: ...
+
+
+@dataclass
+class Stats:
+    requests: List[Request] = field(default_factory=list)
+    launches: int = 0
+    cells: int = 0
+    evictions: int = 0
+    admissions: int = 0
+    refused: int = 0
+    wall: float = 0.0
+
+    def summary(self) -> Dict:
+        lat = np.array([r.latency for r in self.requests if not math.isnan(r.t_done)])
+        out = {"completed": int(lat.size), "launches": self.launches, "evictions": self.evictions,
+               "admissions": self.admissions, "wall_s": self.wall,
+               "cell_updates_per_s": self.cells / self.wall if self.wall > 0 else 0.0,
+               "requests_per_s": lat.size / self.wall if self.wall > 0 else 0.0}
+        if lat.size:
+            out.update({"p50_ms": float(np.percentile(lat, 50) * 1e3),
+                        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                        "mean_ms": float(lat.mean() * 1e3),
+                        "mean_batch": lat.size / max(self.launches, 1)})
+        return out
+
+
+class Server:
+    """Admission, continuous batching and completion tracking (host side)."""
+
+    def __init__(self, executor: Executor, budget_bytes: int, max_inflight: int = 2,
+                 max_cells_per_launch: Optional[int] = None, clock=time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_inflight = max_inflight
+        self.max_cells = max_cells_per_launch
+        self.clock = clock
+        self.used = 0
+        self.lru: "collections.OrderedDict[int, None]" = collections.OrderedDict()  # resident, oldest first
+        self.busy: set = set()
+
+    # -- residency ------------------------------------------------------------
+    def _admit(self, sim: int, pinned: set) -> bool:
+        if self.ex.is_resident(sim):
+            self.lru.move_to_end(sim)
+            return True
+        need = self.ex.bytes_of(sim)
+        if need > self.budget:
+            return False
+        victims = []
+        free = self.budget - self.used
+        for s in self.lru:
+            if free >= need:
+                break
+            if s in self.busy or s in pinned:
+                continue
+            victims.append(s)
+            free += self.ex.bytes_of(s)
+        if free < need:
+            return False
+        for s in victims:
+            self.ex.evict(s)
+            del self.lru[s]
+            self.used -= self.ex.bytes_of(s)
+            self.stats.evictions += 1
+        self.ex.make_resident(sim)
+        self.lru[sim] = None
+        self.used += need
+        self.stats.admissions += 1
+        return True
+
+    # -- the loop ---------------------------------------------------------------
+    def run(self, arrivals: Sequence[tuple], until_done: bool = True, horizon: Optional[float] = None) -> Stats:
+        """Serve arrivals [(t_offset_seconds, sim), ...] sorted by time."""
+        self.stats = Stats()
+        arrivals = sorted(arrivals)
+        pending: "collections.OrderedDict[int, collections.deque]" = collections.OrderedDict()
+        inflight: List = []  # (handle, [requests], [sims])
+        t0 = self.clock()
+        i = 0
+        n = len(arrivals)
+        while True:
+            now = self.clock() - t0
+            while i < n and arrivals[i][0] <= now:
+                t, s = arrivals[i]
+                r = Request(s, t0 + t)
+                self.stats.requests.append(r)
+                pending.setdefault(s, collections.deque()).append(r)
+                i += 1
+            # completions
+            still = []
+            for h, reqs, sims in inflight:
+                if self.ex.done(h):
+                    self.ex.finish(h)
+                    tdone = self.clock()
+                    for r in reqs:
+                        r.t_done = tdone
+                    for s in sims:
+                        self.busy.discard(s)
+                else:
+                    still.append((h, reqs, sims))
+            inflight = still
+            # form the next launch from whatever is ready
+            if len(inflight) < self.max_inflight:
+                chosen, reqs, cells = [], [], 0
+                pinned = set()
+                for s in list(pending.keys()):
+                    if s in self.busy:
+                        continue
+                    c = self.ex.cells_of(s)
+                    if self.max_cells and chosen and cells + c > self.max_cells:
+                        break
+                    if self.ex.bytes_of(s) > self.budget:
+                        # can never be resident: refuse its requests (left incomplete)
+                        self.stats.refused += len(pending.pop(s))
+                        continue
+                    pinned.add(s)
+                    if not self._admit(s, pinned):
+                        pinned.discard(s)  # wait for memory to free up
+                        continue
+                    chosen.append(s)
+                    cells += c
+                    q = pending[s]
+                    reqs.append(q.popleft())
+                    if not q:
+                        del pending[s]
+                if chosen:
+                    h = self.ex.launch(chosen)
+                    tl = self.clock()
+                    for r in reqs:
+                        r.t_launch = tl
+                    for s in chosen:
+                        self.busy.add(s)
+                    inflight.append((h, reqs, chosen))
+                    self.stats.launches += 1
+                    self.stats.cells += cells
+                    continue
+            if i >= n and not inflight and not pending:
+                break
+            if horizon is not None and now > horizon and not until_done:
+                break
+            # idle: wait a little for an arrival or a completion
+            if not inflight and i < n:
+                dt = arrivals[i][0] - (self.clock() - t0)
+                if dt > 2e-4:
+                    time.sleep(min(dt, 1e-3))
+            else:
+                time.sleep(2e-5)
+        self.stats.wall = self.clock() - t0
+        return self.stats
+
+
+def poisson_arrivals(rate: float, duration: float, nsims: int, seed: int = 4) -> List[tuple]:
+    """Poisson arrivals at `rate` per second for `duration` seconds, targets
+    uniform over the simulations."""
+    rng = np.random.default_rng(seed)
+    n = rng.poisson(rate * duration)
+    t = np.sort(rng.uniform(0.0, duration, size=n))
+    s = rng.integers(0, nsims, size=n)
+    return list(zip(t.tolist(), s.tolist()))
+
+
+class GpuExecutor(Executor):
+    """Simulations as libhydro grids on the device.
+
+    A resident simulation holds one state buffer (40 B per cell); each launch
+    lends its members an output buffer for the step in flight (from torch's
+    caching allocator, so no device allocation after warm-up), and on
+    completion the output becomes the state and the old buffer is returned.
+    Evicted states go to host memory.  The initial state of simulation s
+    (cubic L^3, 16^3 blocks, periodic) is drawn on the device on first
+    admission (``ics.served_state_device``).  Each launch is one batched step
+    on the next of `nstreams` streams."""
+
+    def __init__(self, sizes: Sequence[int], cfl: float = 0.8, nstreams: int = 2, device: str = "cuda",
+                 seed: int = 3, nxb: int = 16):
+        import torch
+
+        from . import hydro
+
+        self.torch = torch
+        self.hydro = hydro
+        self.sizes = list(sizes)
+        self.cfl = cfl
+        self.seed = seed
+        self.nxb = nxb
+        self.device = device
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(nstreams)]
+        self.next_stream = 0
+        self.state: Dict[int, "torch.Tensor"] = {}
+        self.grid: Dict[int, "hydro.Grid"] = {}
+        self.host: Dict[int, np.ndarray] = {}
+        self.steps_done = collections.Counter()
+
+    def shape_of(self, sim: int):
+        nb = self.sizes[sim] // self.nxb
+        return (nb ** 3, 5, self.nxb, self.nxb, self.nxb)
+
+    def cells_of(self, sim: int) -> int:
+        return self.sizes[sim] ** 3
+
+    def bytes_of(self, sim: int) -> int:
+        return 40 * self.cells_of(sim) + 256
+
+    def is_resident(self, sim: int) -> bool:
+        return sim in self.state
+
+    def make_resident(self, sim: int) -> None:
+        from . import ics
+
+        t = self.torch.empty(self.shape_of(sim), dtype=self.torch.float64, device=self.device)
+        if sim in self.host:
+            t.copy_(self.torch.from_numpy(self.host.pop(sim)))
+        else:
+            ics.served_state_device(sim, self.sizes[sim], out=t, seed=self.seed, n=self.nxb)
+        self.state[sim] = t
+
+    def evict(self, sim: int) -> None:
+        t = self.state.pop(sim)
+        self.host[sim] = t.cpu().numpy()
+
+    def current_state(self, sim: int) -> np.ndarray:
+        if sim in self.state:
+            return self.state[sim].cpu().numpy()
+        return self.host[sim]
+
+    def launch(self, sims: Sequence[int]):
+        torch = self.torch
+        s = self.streams[self.next_stream]
+        self.next_stream = (self.next_stream + 1) % len(self.streams)
+        grids, outs = [], []
+        for x in sims:
+            st = self.state[x]
+            out = torch.empty_like(st)
+            G = self.grid.get(x)
+            if G is None:
+                L = self.sizes[x]
+                nb = L // self.nxb
+                G = self.hydro.Grid(self.nxb, (nb, nb, nb), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (0, 0, 0), 1.4,
+                                    1e-10, device=self.device, buffers=(st, out))
+                self.grid[x] = G
+            else:
+                G.set_buffers(st, out)
+            grids.append(G)
+            outs.append(out)
+        s.wait_stream(torch.cuda.current_stream())
+        B = self.hydro.Batch(grids, stream=s)
+        B.step(self.cfl, 1)
+        ev = torch.cuda.Event()
+        ev.record(s)
+        B.close()  # host metadata; the device work list stays alive in the handle
+        for x in sims:
+            self.steps_done[x] += 1
+        return (ev, B.work, list(sims), outs)
+
+    def done(self, handle) -> bool:
+        return handle[0].query()
+
+    def finish(self, handle) -> None:
+        ev, _, sims, outs = handle
+        self.torch.cuda.current_stream().wait_event(ev)
+        for x, out in zip(sims, outs):
+            self.state[x] = out  # the old state buffer returns to the allocator

@@ -102,3 +102,20 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(hydro, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(hydro.HydroLibraryMissing):
         hydro.lib()
+
+
+def test_batch_null_arguments(L):
+    assert L.hydro_batch_work_bytes(None, 0) == 0
+    h = ctypes.c_void_p()
+    assert L.hydro_batch_create(None, 0, None, 0, None, ctypes.byref(h)) == hydro.HYDRO_EINVAL
+    assert L.hydro_batch_step(None, 0.8, 1) == hydro.HYDRO_EINVAL
+    assert L.hydro_batch_set_active(None, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_batch_set_pencils(None, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_batch_set_workgroups(None, 2) == hydro.HYDRO_EINVAL
+    assert L.hydro_batch_use_graph(None, 1) == hydro.HYDRO_EINVAL
+    assert L.hydro_batch_dts(None, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_batch_free(None) == hydro.HYDRO_OK
+    assert L.hydro_set_pencils(None, 2) == hydro.HYDRO_EINVAL
+    assert L.hydro_set_buffers(None, None, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_copy_probe(None, None, 0, None) == hydro.HYDRO_OK
+    assert L.hydro_copy_probe(None, None, 8, None) == hydro.HYDRO_EINVAL

@@ -1,0 +1,129 @@
+"""Batched mode: many grids in one persistent launch per step.
+
+Each member's state after k batch steps must be bitwise the state it reaches
+alone through the plain grid API (same kernels, same per-grid device dt),
+whatever the tuning (pencils, workgroups, graph replay) and whichever other
+members are active; and it must match the CPU oracle to the 1e-12 bar.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_11630_amd import ics
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hy():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2208_11630_amd import hydro
+
+    hydro.lib()
+    return hydro
+
+
+def members(count=14, seed=7):
+    # small mixed ensemble: every block size, 1..6 blocks each
+    rng = np.random.default_rng(seed)
+    shapes = [(int(rng.integers(1, 7)), [8, 16, 32][i % 3]) for i in range(count)]
+    return ics.ensemble(count=count, seed=seed, steps=4, shapes=shapes)
+
+
+def alone(hy, P, k, cfl=0.8, nseg=1):
+    G = hy.grid_for(P)
+    G.set_pencils(nseg)
+    for _ in range(k):
+        G.step_cfl(cfl)
+    return G.download(), G.last_dt()
+
+
+def batched(hy, sims, k, cfl=0.8, pencils=None, per_cu=None, graph=False, chunks=None):
+    grids = [hy.grid_for(P) for P in sims]
+    B = hy.Batch(grids)
+    if pencils:
+        B.set_pencils(*pencils)
+    if per_cu:
+        B.set_workgroups(per_cu)
+    B.use_graph(graph)
+    for c in (chunks or [k]):
+        B.step(cfl, c)
+        B.stream.synchronize()
+    out = [G.download() for G in grids]
+    dts = B.dts()
+    B.close()
+    return out, dts
+
+
+def test_batch_bitwise_equals_alone(hy):
+    sims = members()
+    k = 4
+    ref = [alone(hy, P, k) for P in sims]
+    out, dts = batched(hy, sims, k)
+    for i, (U, d) in enumerate(ref):
+        assert np.array_equal(out[i], U), f"member {i} (n={sims[i].n}, nblk={sims[i].nblk})"
+        assert dts[i] == d
+
+
+@pytest.mark.parametrize("pencils,per_cu", [((2, 2, 4), 2), ((4, 4, 2), 1), ((1, 4, 4), 3)])
+def test_batch_tuning_is_bitwise_invariant(hy, pencils, per_cu):
+    sims = members(count=9, seed=8)
+    base, _ = batched(hy, sims, 3)
+    out, _ = batched(hy, sims, 3, pencils=pencils, per_cu=per_cu)
+    for a, b in zip(base, out):
+        assert np.array_equal(a, b)
+
+
+def test_batch_graph_replays_match_direct_launches(hy):
+    sims = members(count=10, seed=9)
+    base, d0 = batched(hy, sims, 15)
+    # graph of 6 steps replayed twice (with host syncs between replays), then 3 direct steps
+    out, d1 = batched(hy, sims, 15, graph=True, chunks=[6, 6, 3])
+    for a, b in zip(base, out):
+        assert np.array_equal(a, b)
+    assert np.array_equal(d0, d1)
+
+
+@pytest.mark.parametrize("nseg", [2, 4])
+def test_grid_pencils_bitwise_invariant(hy, nseg):
+    P = ics.kelvin_helmholtz(shape=(64, 64, 64), n=16)
+    a, da = alone(hy, P, 3)
+    b, db = alone(hy, P, 3, nseg=nseg)
+    assert np.array_equal(a, b) and da == db
+
+
+def test_batch_active_mask(hy):
+    sims = members(count=8, seed=10)
+    grids = [hy.grid_for(P) for P in sims]
+    B = hy.Batch(grids)
+    mask = [i % 2 == 0 for i in range(len(sims))]
+    B.set_active(mask)
+    B.step(0.8, 3)
+    B.set_active([True] * len(sims))
+    B.step(0.8, 1)
+    B.stream.synchronize()
+    for i, P in enumerate(sims):
+        U, _ = alone(hy, P, 4 if mask[i] else 1)
+        assert np.array_equal(grids[i].download(), U), i
+    B.close()
+
+
+def test_batch_members_match_oracle(hy):
+    sims = members(count=6, seed=11)
+    k = 3
+    out, dts = batched(hy, sims, k)
+    for i, P in enumerate(sims):
+        g = oracle.Grid(P.n, P.nb, P.dx, P.bc, P.gamma, P.small_p)
+        U = P.U.copy()
+        for _ in range(k):
+            d = oracle.dt(g, U, 0.8)
+            U, _ = oracle.step(g, U, d)
+        assert abs(dts[i] / d - 1) <= 1e-14
+        a = out[i]
+        b = ics.interior(U, P.n)
+        for v in range(5):
+            den = np.abs(b[:, v]).max() if v in (0, 4) else np.sqrt((b[:, 1:4] ** 2).sum(axis=1)).max()
+            assert np.abs(a[:, v] - b[:, v]).max() <= 1e-12 * den, (i, v)

@@ -1,0 +1,135 @@
+"""Scheduler of the serving loop, driven by a fake executor on the CPU:
+admission under the byte budget with LRU eviction, at most one in-flight
+step per simulation, continuous batching (requests arriving during a launch
+go into the next launch, which may start before the first one ends), and the
+latency/throughput accounting."""
+import collections
+import time
+
+import numpy as np
+import pytest
+
+from paper_2208_11630_amd import serve
+
+
+class FakeExecutor(serve.Executor):
+    def __init__(self, sizes, cost_per_cell=1e-9, fail_sim=None):
+        self.sizes = sizes
+        self.res = set()
+        self.log = []            # (event, payload)
+        self.cost = cost_per_cell
+        self.inflight = {}       # handle -> (end time, sims)
+        self.active_sims = collections.Counter()
+        self.max_overlap = 0
+        self.overlapping_launches = 0
+        self.next = 0
+
+    def cells_of(self, s):
+        return self.sizes[s] ** 3
+
+    def bytes_of(self, s):
+        return 80 * self.cells_of(s)
+
+    def is_resident(self, s):
+        return s in self.res
+
+    def make_resident(self, s):
+        assert s not in self.res
+        self.res.add(s)
+        self.log.append(("admit", s))
+
+    def evict(self, s):
+        assert s in self.res
+        assert self.active_sims[s] == 0, "evicted a simulation with a step in flight"
+        self.res.discard(s)
+        self.log.append(("evict", s))
+
+    def launch(self, sims):
+        for s in sims:
+            assert s in self.res, "launched a non-resident simulation"
+            self.active_sims[s] += 1
+            assert self.active_sims[s] == 1, "two steps of one simulation in flight"
+        if self.inflight:
+            self.overlapping_launches += 1
+        h = self.next
+        self.next += 1
+        self.inflight[h] = (time.perf_counter() + self.cost * sum(self.cells_of(s) for s in sims), list(sims))
+        self.max_overlap = max(self.max_overlap, len(self.inflight))
+        self.log.append(("launch", tuple(sims)))
+        return h
+
+    def done(self, h):
+        return time.perf_counter() >= self.inflight[h][0]
+
+    def finish(self, h):
+        _, sims = self.inflight.pop(h)
+        for s in sims:
+            self.active_sims[s] -= 1
+
+
+def test_all_requests_served_once_in_order_per_sim():
+    sizes = [32, 48, 64, 32, 80]
+    ex = FakeExecutor(sizes)
+    srv = serve.Server(ex, budget_bytes=10 ** 12)
+    arr = serve.poisson_arrivals(rate=4000, duration=0.05, nsims=len(sizes), seed=1)
+    st = srv.run(arr)
+    assert len(st.requests) == len(arr)
+    assert all(not np.isnan(r.t_done) and r.t_done >= r.t_launch >= r.t_arrival for r in st.requests)
+    # per simulation, requests complete in arrival order (one step in flight at a time)
+    by = collections.defaultdict(list)
+    for r in st.requests:
+        by[r.sim].append(r)
+    for rs in by.values():
+        done = [r.t_done for r in sorted(rs, key=lambda r: r.t_arrival)]
+        assert done == sorted(done)
+    s = st.summary()
+    assert s["completed"] == len(arr) and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_budget_respected_with_lru_eviction():
+    sizes = [64] * 10                       # 80 B * 64^3 = 21 MB each
+    ex = FakeExecutor(sizes)
+    budget = 3 * 80 * 64 ** 3 + 10           # room for three
+    srv = serve.Server(ex, budget_bytes=budget)
+    arr = [(0.0001 * k, k % 10) for k in range(60)]
+    st = srv.run(arr)
+    assert st.summary()["completed"] == 60
+    assert st.evictions > 0
+    # replay the log: resident bytes never exceed the budget
+    res = set()
+    for ev, x in ex.log:
+        if ev == "admit":
+            res.add(x)
+        elif ev == "evict":
+            res.discard(x)
+        assert sum(80 * 64 ** 3 for _ in res) <= budget
+
+
+def test_request_larger_than_budget_is_refused_not_hung():
+    sizes = [32, 256]
+    ex = FakeExecutor(sizes)
+    srv = serve.Server(ex, budget_bytes=80 * 128 ** 3)
+    st = srv.run([(0.0, 0), (0.0, 1)])
+    assert st.refused > 0
+    done = [r for r in st.requests if not np.isnan(r.t_done)]
+    assert [r.sim for r in done] == [0]
+
+
+def test_continuous_batching_overlaps_launches():
+    sizes = [64] * 40
+    ex = FakeExecutor(sizes, cost_per_cell=2e-8)  # ~5 ms per 64^3 step: launches overlap arrivals
+    srv = serve.Server(ex, budget_bytes=10 ** 12, max_inflight=2)
+    arr = serve.poisson_arrivals(rate=3000, duration=0.1, nsims=40, seed=2)
+    st = srv.run(arr)
+    assert st.summary()["completed"] == len(arr)
+    assert ex.max_overlap == 2 and ex.overlapping_launches > 0
+    assert st.summary()["mean_batch"] > 1.0
+
+
+def test_poisson_arrivals_statistics():
+    arr = serve.poisson_arrivals(rate=2000.0, duration=2.0, nsims=100, seed=4)
+    assert abs(len(arr) - 4000) < 4 * np.sqrt(4000)
+    t = np.array([a[0] for a in arr])
+    assert np.all(np.diff(t) >= 0) and t.min() >= 0 and t.max() <= 2.0
+    gaps = np.diff(t)
+    assert abs(gaps.mean() * 2000.0 - 1.0) < 0.1

@@ -1,6 +1,6 @@
 // C-ABI host side of libhydro: descriptor validation, handles, launches.
 // The operation and the conventions are documented in include/hydro.h.
-#include "../../include/hydro.h"
+#include "hydro.h"
 
 #include <hip/hip_runtime.h>
 
@@ -347,8 +347,8 @@ BatchLayout batch_layout(hydro_grid* const* grids, int n) {
 }
 
 void drop_graph(hydro_batch* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
 }
@@ -517,7 +517,7 @@ int hydro_batch_step(hydro_batch* b, double cfl, int nsteps) {
         if (e == hipSuccess) e = e2;
         if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-          if (gr) hipGraphDestroy(gr);
+          if (gr) (void)hipGraphDestroy(gr);
           b->exec = nullptr;
           return hip_fail(e, "batch graph capture");
         }

@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # HYDRO_LIB points the binding at another build of the same library (kernel experiments)
-LIB_PATH = os.environ.get("HYDRO_LIB", os.path.join(HERE, "libhydro.so"))
+LIB_PATH = os.environ.get("HYDRO_LIB") or os.path.join(HERE, "libhydro.so")
 
 HYDRO_OK = 0
 HYDRO_EINVAL = -1

@@ -8,7 +8,8 @@ layout ``[nblk, 5, P, P, P]`` (P = n + 2*ng, x fastest).
 
 The method (paper §2 "Software Description": explicit shock-capturing methods
 with block-by-block update; §2.2 Hydrodynamics: the predictor-corrector
-unsplit compressible solver; §2.2 Equations of State: perfect gas) is
+unsplit compressible solver and the SSP Runge-Kutta one; §2.2 Equations of
+State: perfect gas) is
 documented function by function in hydro_oracle.h / hydro_oracle.c.
 """
 from __future__ import annotations
@@ -79,6 +80,11 @@ def lib():
         L.oracle_step_block_list.restype = None
         L.oracle_step.argtypes = [gp, dp, dp, ctypes.c_double, lp]
         L.oracle_step.restype = None
+        L.oracle_stage_block.argtypes = [gp, dp, ctypes.c_long, dp, ctypes.c_double, dp, ctypes.c_double,
+                                         ctypes.c_double, lp]
+        L.oracle_stage_block.restype = None
+        L.oracle_step_rk.argtypes = [gp, dp, dp, ctypes.c_double, ctypes.c_int, lp]
+        L.oracle_step_rk.restype = ctypes.c_int
         L.oracle_max_signal.argtypes = [gp, dp, ctypes.c_long, ctypes.c_long]
         L.oracle_max_signal.restype = ctypes.c_double
         L.oracle_dt.argtypes = [gp, dp, ctypes.c_double]
@@ -196,6 +202,38 @@ def step_blocks(g: Grid, U: np.ndarray, blocks: Sequence[int], dt: float):
     return np.ascontiguousarray(tmp[:, :, ng:ng + n, ng:ng + n, ng:ng + n]), np.array(list(cnt), dtype=np.int64)
 
 
+def step_rk(g: Grid, U: np.ndarray, dt: float, order: int):
+    """One SSP Runge-Kutta step (order 2 or 3) of method-of-lines stages:
+    returns (U_new, counters summed over the stages)."""
+    g.check(U)
+    out = U.copy()
+    cnt = (ctypes.c_long * 3)(0, 0, 0)
+    gc = g.c()
+    rc = lib().oracle_step_rk(ctypes.byref(gc), _dptr(U), _dptr(out), float(dt), int(order), cnt)
+    if rc == -1:
+        raise ValueError("SSP Runge-Kutta order must be 2 or 3 (got %r)" % (order,))
+    if rc != 0:
+        raise MemoryError("oracle stage buffers could not be allocated")
+    return out, np.array(list(cnt), dtype=np.int64)
+
+
+def stage_block(g: Grid, U: np.ndarray, b: int, dt: float, U0: np.ndarray = None, a0: float = 0.0,
+                a1: float = 0.0):
+    """One method-of-lines stage of block b (U's guards must be filled):
+    returns block b's new storage (interior updated, guards copied from U)."""
+    g.check(U)
+    gc = g.c()
+    out = np.ascontiguousarray(U[b]).copy()
+    cnt = (ctypes.c_long * 3)(0, 0, 0)
+    base = None
+    if U0 is not None:
+        g.check(U0)
+        base = np.ascontiguousarray(U0[b])
+    lib().oracle_stage_block(ctypes.byref(gc), _dptr(U), int(b), _dptr(out), float(dt),
+                             _dptr(base) if base is not None else None, float(a0), float(a1), cnt)
+    return out, np.array(list(cnt), dtype=np.int64)
+
+
 def max_signal(g: Grid, U: np.ndarray) -> float:
     g.check(U)
     gc = g.c()
@@ -208,15 +246,16 @@ def dt(g: Grid, U: np.ndarray, cfl: float) -> float:
     return lib().oracle_dt(ctypes.byref(gc), _dptr(U), float(cfl))
 
 
-def run(g: Grid, U: np.ndarray, nsteps: int, cfl: float = 0.8, callback=None):
-    """n repetitions of (dt = CFL/max signal; step(dt)); returns (U, dts, counters)."""
+def run(g: Grid, U: np.ndarray, nsteps: int, cfl: float = 0.8, callback=None, rk: int = 0):
+    """n repetitions of (dt = CFL/max signal; step(dt)); returns (U, dts, counters).
+    rk = 2 or 3 takes SSP Runge-Kutta steps instead of predictor-corrector ones."""
     dts = []
     cnt = np.zeros(3, dtype=np.int64)
     for s in range(nsteps):
         d = dt(g, U, cfl)
         if not d > 0:
             raise FloatingPointError("non-positive or non-finite dt at step %d" % s)
-        U, c = step(g, U, d)
+        U, c = step_rk(g, U, d, rk) if rk else step(g, U, d)
         cnt += c
         dts.append(d)
         if callback is not None:

@@ -183,10 +183,16 @@ static void jacobian_times(const double W[5], int d, double gamma, const double 
   out[4] = gamma * p * dW[1 + d] + un * dW[4];
 }
 
-/* ---- one block: a2..a5 (§2.2 Hydrodynamics: predictor, then corrector) --- */
+/* ---- one block: a2..a5 -------------------------------------------------
+ * hancock = 1: the predictor-corrector step (§2.2 Hydrodynamics: predictor,
+ * then corrector), face states extrapolated from the half-step predicted
+ * centre.  hancock = 0: one method-of-lines stage of the SSP Runge-Kutta
+ * solver (§2.2 Hydrodynamics), face states extrapolated from the cell centre
+ * itself, and the result combined with a base state U0b when U0b != NULL:
+ * Uo = a0*U0 + a1*(U - div F). */
 
-void oracle_step_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
-                       long cnt[ORACLE_NCNT]) {
+static void update_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt, int hancock,
+                         const double *U0b, double a0, double a1, long cnt[ORACLE_NCNT]) {
   const int n = g->n, ng = g->ng, P = edge(g);
   const double gamma = g->gamma;
   const double lam[3] = {dt / g->dx[0], dt / g->dx[1], dt / g->dx[2]};
@@ -229,11 +235,15 @@ void oracle_step_block(const oracle_grid *g, const double *U, long b, double *Uo
           const double *Wq = WI(i + off[d][0], j + off[d][1], k + off[d][2]);
           for (int v = 0; v < 5; ++v) Sc[5 * d + v] = oracle_van_leer(Wc[v] - Wm[v], Wq[v] - Wc[v]);
         }
-        double A[3][5];
-        for (int d = 0; d < 3; ++d) jacobian_times(Wc, d, gamma, Sc + 5 * d, A[d]);
         double *Wt = Wp + 5 * MI(i, j, k);
-        for (int v = 0; v < 5; ++v)
-          Wt[v] = Wc[v] - 0.5 * ((lam[0] * A[0][v] + lam[1] * A[1][v]) + lam[2] * A[2][v]);
+        if (hancock) {
+          double A[3][5];
+          for (int d = 0; d < 3; ++d) jacobian_times(Wc, d, gamma, Sc + 5 * d, A[d]);
+          for (int v = 0; v < 5; ++v)
+            Wt[v] = Wc[v] - 0.5 * ((lam[0] * A[0][v] + lam[1] * A[1][v]) + lam[2] * A[2][v]);
+        } else {
+          for (int v = 0; v < 5; ++v) Wt[v] = Wc[v];
+        }
         int bad = 0;
         for (int d = 0; d < 3; ++d)
           for (int s = -1; s <= 1; s += 2) {
@@ -278,6 +288,7 @@ void oracle_step_block(const oracle_grid *g, const double *U, long b, double *Uo
                         lam[1] * (F[1][5 * fy1 + v] - F[1][5 * fy0 + v])) +
                        lam[2] * (F[2][5 * fz1 + v] - F[2][5 * fz0 + v]);
           Un[v] = Ub[at(g, v, i, j, k)] - div;
+          if (U0b) Un[v] = a0 * U0b[at(g, v, i, j, k)] + a1 * Un[v];
           Uo[at(g, v, i, j, k)] = Un[v];
         }
         int ok = Un[0] > 0.0 && Un[4] > 0.0;
@@ -291,6 +302,16 @@ void oracle_step_block(const oracle_grid *g, const double *U, long b, double *Uo
   free(Wp);
   free(fb);
   for (int d = 0; d < 3; ++d) free(F[d]);
+}
+
+void oracle_step_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+                       long cnt[ORACLE_NCNT]) {
+  update_block(g, U, b, Uo, dt, 1, NULL, 0.0, 0.0, cnt);
+}
+
+void oracle_stage_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+                        const double *U0b, double a0, double a1, long cnt[ORACLE_NCNT]) {
+  update_block(g, U, b, Uo, dt, 0, U0b, a0, a1, cnt);
 }
 
 void oracle_step(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]) {
@@ -329,6 +350,57 @@ void oracle_step_block_list(const oracle_grid *g, double *U, const long *blocks,
   cnt[ORACLE_CNT_FLOOR] += c0;
   cnt[ORACLE_CNT_FALLBACK] += c1;
   cnt[ORACLE_CNT_NONPHYS] += c2;
+}
+
+/* ---- f1: SSP Runge-Kutta method-of-lines step (§2.2 Hydrodynamics: the
+ *      compressible solver with second- or third-order strong-stability-
+ *      preserving Runge-Kutta time integration).  Shu-Osher form with
+ *      L(U) = -div F(U) from the stage operator above:
+ *        order 2: U1 = U + dt L(U);  U' = 1/2 U + 1/2 (U1 + dt L(U1))
+ *        order 3: U1 = U + dt L(U);  U2 = 3/4 U + 1/4 (U1 + dt L(U1));
+ *                 U' = 1/3 U + 2/3 (U2 + dt L(U2))
+ *      Each stage fills the guards of its input first. ------------------- */
+
+static void stage_all(const oracle_grid *g, double *Us, const double *U0, double a0, double a1, double *Uo,
+                      double dt, long cnt[ORACLE_NCNT]) {
+  long nblk = (long)g->nb[0] * g->nb[1] * g->nb[2];
+  const size_t bd = oracle_block_doubles(g);
+  oracle_fill_guards(g, Us);
+  long c0 = 0, c1 = 0, c2 = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : c0, c1, c2)
+  for (long b = 0; b < nblk; ++b) {
+    long c[ORACLE_NCNT] = {0, 0, 0};
+    update_block(g, Us, b, Uo + (size_t)b * bd, dt, 0, U0 ? U0 + (size_t)b * bd : NULL, a0, a1, c);
+    c0 += c[0];
+    c1 += c[1];
+    c2 += c[2];
+  }
+  cnt[ORACLE_CNT_FLOOR] += c0;
+  cnt[ORACLE_CNT_FALLBACK] += c1;
+  cnt[ORACLE_CNT_NONPHYS] += c2;
+}
+
+int oracle_step_rk(const oracle_grid *g, double *U, double *Unew, double dt, int order, long cnt[ORACLE_NCNT]) {
+  if (order != 2 && order != 3) return -1;
+  long nblk = (long)g->nb[0] * g->nb[1] * g->nb[2];
+  size_t total = (size_t)nblk * oracle_block_doubles(g);
+  double *U1 = (double *)calloc(total, sizeof(double));
+  double *U2 = order == 3 ? (double *)calloc(total, sizeof(double)) : NULL;
+  if (!U1 || (order == 3 && !U2)) {
+    free(U1);
+    free(U2);
+    return -2;
+  }
+  stage_all(g, U, NULL, 0.0, 0.0, U1, dt, cnt);
+  if (order == 2) {
+    stage_all(g, U1, U, 0.5, 0.5, Unew, dt, cnt);
+  } else {
+    stage_all(g, U1, U, 0.75, 0.25, U2, dt, cnt);
+    stage_all(g, U2, U, 1.0 / 3.0, 2.0 / 3.0, Unew, dt, cnt);
+  }
+  free(U1);
+  free(U2);
+  return 0;
 }
 
 /* ---- a6: CFL signal speed and dt ---------------------------------------- */

@@ -20,7 +20,10 @@
  *     directions at once (fully unsplit, no transverse corner coupling);
  *   - HLLC fluxes with Davis wave speeds and the Batten contact speed;
  *   - the conservative flux-difference update;
- *   - dt = CFL / max over cells of sum_d (|u_d| + c) / dx_d.
+ *   - dt = CFL / max over cells of sum_d (|u_d| + c) / dx_d;
+ *   - the SSP Runge-Kutta variant (§2.2 Hydrodynamics, the other compressible
+ *     solver): method-of-lines stages with face states from the cell centre,
+ *     combined in Shu-Osher form (second and third order).
  *
  * Layout: a grid of nb[0]*nb[1]*nb[2] cubic blocks, block id
  * b = bx + nb0*(by + nb1*bz).  Each block stores 5 conserved variables
@@ -87,6 +90,19 @@ void oracle_step_block_list(const oracle_grid *g, double *U, const long *blocks,
 
 /* One full step: fills U's guards, then updates every block into Unew. */
 void oracle_step(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]);
+
+/* One method-of-lines stage of block b (the SSP Runge-Kutta solver of §2.2):
+ * face states are the cell-centred primitives plus or minus half the van Leer
+ * slope (no predictor half step; the same first-order fallback), fluxes by
+ * HLLC, and Uo's interior = U - div F when U0b is NULL, else
+ * a0*U0b + a1*(U - div F) (U0b: block b's storage of the base state). */
+void oracle_stage_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+                        const double *U0b, double a0, double a1, long cnt[ORACLE_NCNT]);
+
+/* One SSP Runge-Kutta step of order 2 or 3 (Shu-Osher form) from U into
+ * Unew; U's guards are refilled in place.  Returns 0, -1 for another order,
+ * -2 when the stage buffers cannot be allocated. */
+int oracle_step_rk(const oracle_grid *g, double *U, double *Unew, double dt, int order, long cnt[ORACLE_NCNT]);
 
 /* max over interior cells of sum_d (|u_d| + c)/dx_d; the block range [b0,b1). */
 double oracle_max_signal(const oracle_grid *g, const double *U, long b0, long b1);

@@ -210,13 +210,16 @@ __device__ __forceinline__ long xcd_tile(long w, long total) {
 // ---------------------------------------------------------------------------
 // Fused step.  Workgroups of whole wavefront quartets (256 threads for T =
 // 16) so that two of them share a CU evenly across its four SIMDs (a 320-
-// thread workgroup, one thread per predictor cell, packed only one per CU).  Thread t owns tile cell (t % T, t / T) and keeps that column's
-// primitives for planes j-1, j, j+1 in registers.  The one-cell ring around
-// the tile (4T cells) is a second item of threads 0..4T-1 whose z windows
-// live in LDS; the two-deep halo cells that only feed ring slopes (4T+4
-// cells) are a second item of the next threads.  Each thread computes the x
-// and y fluxes of its own low faces and its z flux; threads 0..2T-1 also
-// take the tile's high x and y boundary faces.
+// thread workgroup, one thread per predictor cell, packed only one per CU).
+// Thread t owns tile cell (t % T, t / T) and keeps that column's primitives
+// for planes j-1, j, j+1 in registers.  The one-cell ring around the tile
+// (4T cells) is a second item of roles 0..4T-1 whose z windows live in LDS;
+// the two-deep halo cells that only feed ring slopes (4T+4 cells) are a
+// second item of the next roles.  Each thread computes the x
+// and y fluxes of its own low faces and its z flux; the last 2T roles also
+// take the tile's high x and y boundary faces.  The ring is on the first
+// wavefront of the role order and the boundary faces on the last, so no
+// wavefront carries both extra items.
 template <int T>
 struct Tile {
   static constexpr int NI = T * T;   // tile cells
@@ -521,10 +524,10 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
 #pragma unroll
         for (int v = 0; v < 5; ++v) sm.sFy[v][cy * T + cx] = F[v];
       }
-      if (role < 2 * T) {
+      if (role >= NT - 2 * T) {  // on the last wavefront, away from the ring's
         double WL[5], WR[5], F[5];
-        const int r = role % T;
-        if (role < T) {  // x face at x = T, y = r
+        const int r = (role - (NT - 2 * T)) % T;
+        if (role < NT - T) {  // x face at x = T, y = r
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
             WL[v] = sm.sQx[v][r * (T + 1) + T];

@@ -34,6 +34,14 @@ MUTATIONS = {
     "periodic_wrap_off_by_one": ("return r < 0 ? r + N : r;", "return r < 0 ? r + N - 1 : r;"),
     "dt_drops_sound_speed_in_z": ("(fabs(W[3]) + c) / g->dx[2]", "fabs(W[3]) / g->dx[2]"),
     "fallback_never_applies": ("if (!(r > 0.0) || !(p > 0.0)) bad = 1;", ""),
+    "rk2_final_weights": ("stage_all(g, U1, U, 0.5, 0.5, Unew, dt, cnt);", "stage_all(g, U1, U, 0.0, 1.0, Unew, dt, cnt);"),
+    "rk3_middle_weights": ("stage_all(g, U1, U, 0.75, 0.25, U2, dt, cnt);", "stage_all(g, U1, U, 0.25, 0.75, U2, dt, cnt);"),
+    "rk3_final_input": ("stage_all(g, U2, U, 1.0 / 3.0, 2.0 / 3.0, Unew, dt, cnt);",
+                        "stage_all(g, U1, U, 1.0 / 3.0, 2.0 / 3.0, Unew, dt, cnt);"),
+    "stage_weights_swapped": ("Un[v] = a0 * U0b[at(g, v, i, j, k)] + a1 * Un[v];",
+                              "Un[v] = a1 * U0b[at(g, v, i, j, k)] + a0 * Un[v];"),
+    "stage_uses_predictor": ("Uo + (size_t)b * bd, dt, 0,", "Uo + (size_t)b * bd, dt, 1,"),
+    "stage_skips_guard_fill": ("oracle_fill_guards(g, Us);", ""),
 }
 
 
@@ -53,6 +61,6 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     env = dict(os.environ, HYDRO_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         "tests/test_oracle_units.py", "tests/test_oracle_step.py",
-                        "tests/test_oracle_fallback.py"],
+                        "tests/test_oracle_fallback.py", "tests/test_oracle_rk.py"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutation {name} survived all pins:\n{r.stdout[-2000:]}"

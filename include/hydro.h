@@ -70,6 +70,11 @@ extern "C" {
 
 #define HYDRO_NGUARD 4
 
+/* Time integration (hydro_set_scheme). */
+#define HYDRO_SCHEME_MH 0  /* predictor-corrector (MUSCL-Hancock) step, the default */
+#define HYDRO_SCHEME_RK2 2 /* second-order SSP Runge-Kutta, method-of-lines stages */
+#define HYDRO_SCHEME_RK3 3 /* third-order SSP Runge-Kutta, method-of-lines stages */
+
 typedef struct hydro_grid hydro_grid;
 
 typedef struct {
@@ -163,11 +168,34 @@ int hydro_set_buffers(hydro_grid *g, double *U, double *U_alt);
  * halo planes per pencil.  Results are bitwise independent of it. */
 int hydro_set_pencils(hydro_grid *g, int nseg);
 
+/* Time integration of the grid's steps (§2.2 Hydrodynamics names two
+ * compressible solvers: the predictor-corrector one and one with second- or
+ * third-order strong-stability-preserving Runge-Kutta time integration).
+ *   HYDRO_SCHEME_MH  (default): the predictor-corrector step above.
+ *   HYDRO_SCHEME_RK2 / _RK3: Shu-Osher SSP Runge-Kutta of order 2 / 3 over
+ *     method-of-lines stages.  A stage uses the same guard fill, EOS,
+ *     van Leer slopes, positivity fallback, HLLC and flux difference, with
+ *     face states W +- Delta/2 from the cell centre (no predictor half step):
+ *       order 2: U1 = U + dt L(U);  U' = U/2 + (U1 + dt L(U1))/2
+ *       order 3: U1 = U + dt L(U);  U2 = 3U/4 + (U1 + dt L(U1))/4;
+ *                U' = U/3 + 2(U2 + dt L(U2))/3
+ *     dt is the step's (host value, or cfl / the maximum signal speed of
+ *     U); the signal speed of U' is reduced for the next dt.  The state
+ *     stays in the current buffer (the other one holds U1; the last stage
+ *     overwrites U cell by cell), so hydro_current does not change.
+ * U_stage: caller-owned device buffer of hydro_state_doubles values,
+ * 256-byte aligned, not overlapping U or U_alt; required by RK3 (holds U2),
+ * ignored otherwise (may be NULL).  Counters sum over stages.
+ * Errors: HYDRO_EINVAL (unknown scheme, RK3 without a valid stage buffer,
+ * grid in a batch).  Batches take HYDRO_SCHEME_MH grids only. */
+int hydro_set_scheme(hydro_grid *g, int scheme, double *U_stage);
+
 /* ---- batches: many independent grids, one persistent launch per step ----
  * (§2: physics is updated block by block, independently of how blocks are
  * distributed; here blocks of many simulations share one launch.)  A batch
- * groups grid handles (mixed nxb allowed).  Each step, workgroups pull
- * (grid, pencil) items from a device work list until it is empty; each grid
+ * groups grid handles (mixed nxb allowed).  Each step, a persistent grid
+ * of G workgroups walks a device work list of (grid, pencil) items, the
+ * heaviest first, workgroup w taking items w, w+G, w+2G, ...; each grid
  * takes its own dt = cfl / its own maximum signal speed, formed on the
  * device.  A grid's results are bitwise the same alone or in any batch.
  * While a grid belongs to a batch its own step calls are refused; hydro_dt,

@@ -25,6 +25,8 @@ struct hydro_grid {
   bool sig_valid;           // slot holds the current state's maximum signal speed
   int nseg;                 // z pencils per block column (tuning; results do not depend on it)
   hydro_batch* batch;       // batch the grid belongs to (its own step calls are refused meanwhile)
+  int scheme;               // HYDRO_SCHEME_*
+  double* U_stage;          // third state buffer (third-order Runge-Kutta only)
 };
 
 struct hydro_batch {
@@ -128,7 +130,50 @@ int ensure_signal_on(hydro_grid* g, hipStream_t s) {
 
 int ensure_signal(hydro_grid* g) { return ensure_signal_on(g, stream_of(g)); }
 
+// SSP Runge-Kutta step in Shu-Osher form from the current buffer A, with
+// B = the other buffer and C = the stage buffer:
+//   order 2: A -> B (U1 = U + dt L(U)); (B, A) -> A (1/2 U + 1/2 (U1 + dt L(U1)))
+//   order 3: A -> B; (B, A) -> C (3/4 U + 1/4 (...)); (C, A) -> A (1/3 U + 2/3 (...))
+// The last stage writes over the base state cell by cell, so the state stays
+// in A.
+int do_rk_step(hydro_grid* g, double dt, double cfl) {
+  double* A = cur_state(g);
+  double* B = other_state(g);
+  const int order = g->scheme == HYDRO_SCHEME_RK3 ? 3 : 2;
+  struct Stage {
+    const double* in;
+    double* out;
+    const double* base;
+    double a0, a1;
+  };
+  const Stage rk2[2] = {{A, B, nullptr, 0.0, 0.0}, {B, A, A, 0.5, 0.5}};
+  const Stage rk3[3] = {{A, B, nullptr, 0.0, 0.0}, {B, g->U_stage, A, 0.75, 0.25},
+                        {g->U_stage, A, A, 1.0 / 3.0, 2.0 / 3.0}};
+  const Stage* stages = order == 3 ? rk3 : rk2;
+  for (int k = 0; k < order; ++k) {
+    hydro::StepArgs a;
+    a.Uin = stages[k].in;
+    a.Uout = stages[k].out;
+    a.ws = ws_of(g);
+    a.dt = dt;
+    a.cfl = cfl;
+    a.slot = slot_of(g);
+    hydro::StageArgs st;
+    st.U0 = stages[k].base;
+    st.a0 = stages[k].a0;
+    st.a1 = stages[k].a1;
+    st.stage = k;
+    st.last = k == order - 1;
+    hipError_t e = hydro::launch_step(g->d.nxb, g->geom, a, &st, g->nseg, stream_of(g));
+    if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
+  }
+  g->steps += 1;
+  g->sig_valid = true;
+  return HYDRO_OK;
+}
+
 int do_step(hydro_grid* g, double dt, double cfl) {
+  if (g->scheme != HYDRO_SCHEME_MH) return do_rk_step(g, dt, cfl);
   hydro::StepArgs a;
   a.Uin = cur_state(g);
   a.Uout = other_state(g);
@@ -136,12 +181,17 @@ int do_step(hydro_grid* g, double dt, double cfl) {
   a.dt = dt;
   a.cfl = cfl;
   a.slot = slot_of(g);
-  hipError_t e = hydro::launch_step(g->d.nxb, g->geom, a, g->nseg, stream_of(g));
+  hipError_t e = hydro::launch_step(g->d.nxb, g->geom, a, nullptr, g->nseg, stream_of(g));
   if (e != hipSuccess) return hip_fail(e, "step kernel launch");
   g->cur ^= 1;
   g->steps += 1;
   g->sig_valid = true;
   return HYDRO_OK;
+}
+
+bool overlaps(const void* p, size_t pb, const void* q, size_t qb) {
+  const uintptr_t a0 = (uintptr_t)p, a1 = a0 + pb, b0 = (uintptr_t)q, b1 = b0 + qb;
+  return a0 < b1 && b0 < a1;
 }
 
 int read_header(hydro_grid* g, hydro::WorkHeader* h) {
@@ -196,6 +246,8 @@ int hydro_init_grid(const hydro_grid_desc* d, hydro_grid** out) {
   g->sig_valid = false;
   g->nseg = 1;
   g->batch = nullptr;
+  g->scheme = HYDRO_SCHEME_MH;
+  g->U_stage = nullptr;
   hipError_t e = hipMemsetAsync(d->work, 0, sizeof(hydro::WorkHeader), (hipStream_t)d->stream);
   if (e != hipSuccess) {
     delete g;
@@ -211,7 +263,9 @@ int hydro_fill_guards(hydro_grid* g, double* guarded) {
   if ((uintptr_t)guarded & 7) return fail(HYDRO_EINVAL, "guarded output buffer must be 8-byte aligned");
   const uintptr_t o0 = (uintptr_t)guarded, o1 = o0 + hydro_guarded_doubles(&g->d) * sizeof(double);
   const size_t sb = hydro_state_doubles(&g->d) * sizeof(double);
-  for (const double* st : {g->d.U, g->d.U_alt}) {
+  const double* states[3] = {g->d.U, g->d.U_alt, g->U_stage};
+  for (const double* st : states) {
+    if (!st) continue;
     const uintptr_t s0 = (uintptr_t)st, s1 = s0 + sb;
     if (o0 < s1 && s0 < o1) return fail(HYDRO_EINVAL, "guarded output overlaps a state buffer");
   }
@@ -301,9 +355,31 @@ int hydro_set_buffers(hydro_grid* g, double* U, double* U_alt) {
   d.U_alt = U_alt;
   int rc = validate(&d);
   if (rc) return rc;
+  const size_t sb = hydro_state_doubles(&d) * sizeof(double);
+  if (g->U_stage && (overlaps(g->U_stage, sb, U, sb) || overlaps(g->U_stage, sb, U_alt, sb)))
+    return fail(HYDRO_EINVAL, "state buffers overlap the stage buffer");
   g->d.U = U;
   g->d.U_alt = U_alt;
   g->cur = 0;
+  return HYDRO_OK;
+}
+
+int hydro_set_scheme(hydro_grid* g, int scheme, double* U_stage) {
+  if (!g) return fail(HYDRO_EINVAL, "handle is NULL");
+  if (g->batch) return fail(HYDRO_EINVAL, "grid belongs to a batch");
+  if (scheme != HYDRO_SCHEME_MH && scheme != HYDRO_SCHEME_RK2 && scheme != HYDRO_SCHEME_RK3)
+    return fail(HYDRO_EINVAL, "unknown scheme %d", scheme);
+  if (scheme == HYDRO_SCHEME_RK3) {
+    if (!U_stage) return fail(HYDRO_EINVAL, "the third-order scheme needs a stage buffer");
+    if ((uintptr_t)U_stage & 255) return fail(HYDRO_EINVAL, "stage buffer must be 256-byte aligned");
+    const size_t sb = hydro_state_doubles(&g->d) * sizeof(double);
+    if (overlaps(U_stage, sb, g->d.U, sb) || overlaps(U_stage, sb, g->d.U_alt, sb))
+      return fail(HYDRO_EINVAL, "stage buffer overlaps a state buffer");
+  } else {
+    U_stage = nullptr;
+  }
+  g->scheme = scheme;
+  g->U_stage = U_stage;
   return HYDRO_OK;
 }
 
@@ -429,6 +505,8 @@ int hydro_batch_create(hydro_grid* const* grids, int n, void* work, size_t work_
   for (int i = 0; i < n; ++i) {
     if (!grids[i]) return fail(HYDRO_EINVAL, "grid %d is NULL", i);
     if (grids[i]->batch) return fail(HYDRO_EINVAL, "grid %d already belongs to a batch", i);
+    if (grids[i]->scheme != HYDRO_SCHEME_MH)
+      return fail(HYDRO_EINVAL, "grid %d uses a Runge-Kutta scheme; batches take predictor-corrector grids", i);
     for (int k = 0; k < i; ++k)
       if (grids[k] == grids[i]) return fail(HYDRO_EINVAL, "grid %d appears twice", i);
   }

@@ -39,6 +39,15 @@ struct StepArgs {
   int slot;           // step number mod 3
 };
 
+// One method-of-lines stage of an SSP Runge-Kutta step: the result is
+// a0*U0 + a1*(Uin - dt div F), or Uin - dt div F when U0 is NULL.
+struct StageArgs {
+  const double* U0;   // base state of the step (may be the stage's output buffer)
+  double a0, a1;
+  int stage;          // 0: first stage (takes and records dt); > 0: uses the recorded dt
+  int last;           // nonzero: reduce the result's signal speed for the next dt
+};
+
 // One member grid of a batch (device table entry).
 struct BatchSim {
   double* U0;         // state buffer 0
@@ -57,7 +66,9 @@ struct BatchItem {
   int tile;           // pencil index inside the grid (see tile_step)
 };
 
-hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, int nseg, hipStream_t s);
+// st == NULL: predictor-corrector step; else one method-of-lines stage.
+hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const StageArgs* st, int nseg,
+                       hipStream_t s);
 hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,
                              const int nseg[3], int grid, hipStream_t s);
 hipError_t launch_fill_guards(int nxb, const GridGeom& g, const double* U, double* out, hipStream_t s);

@@ -256,10 +256,24 @@ __device__ __forceinline__ double van_leer_sf(double a, double b) {
   return div_nr(num, den);
 }
 
-// Predictor of one cell: half step with all three directions, positivity
-// check of the six face states.  On exit wt is the state the face states
-// extrapolate from and h the half-slope factor: (predicted centre, 0.5) or,
-// for the first-order fallback, (cell centre, 0).
+// Positivity check of the six face states t +- s_d/2 of one cell: their
+// densities and pressures are all positive exactly when t > |s_d|/2 for every
+// d.  On exit wt is the state the face states extrapolate from and h the
+// half-slope factor: (t, 0.5), or for the first-order fallback (wc, 0).
+__device__ __forceinline__ bool face_check(const double (&t)[5], const double (&wc)[5], const double (&sx)[5],
+                                           const double (&sy)[5], const double (&sz)[5], double (&wt)[5],
+                                           double& h) {
+  const double hr = 0.5 * fmax(fmax(fabs(sx[0]), fabs(sy[0])), fabs(sz[0]));
+  const double hp = 0.5 * fmax(fmax(fabs(sx[4]), fabs(sy[4])), fabs(sz[4]));
+  const bool ok = (t[0] - hr > 0.0) && (t[0] + hr > 0.0) && (t[4] - hp > 0.0) && (t[4] + hp > 0.0);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) wt[v] = ok ? t[v] : wc[v];
+  h = ok ? 0.5 : 0.0;
+  return ok;
+}
+
+// Predictor of one cell: half step with all three directions, then the
+// positivity check of the six face states (face_check).
 __device__ __forceinline__ bool predict(const double (&wc)[5], double inv, const double (&sx)[5],
                                         const double (&sy)[5], const double (&sz)[5], double gamma,
                                         double lamx, double lamy, double lamz, double (&wt)[5], double& h) {
@@ -292,14 +306,7 @@ __device__ __forceinline__ bool predict(const double (&wc)[5], double inv, const
   double t[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) t[v] = fma(-0.5, acc[v], wc[v]);
-  // face densities and pressures are t +- s/2; all six positive <=> t > |s|/2 for each
-  const double hr = 0.5 * fmax(fmax(fabs(sx[0]), fabs(sy[0])), fabs(sz[0]));
-  const double hp = 0.5 * fmax(fmax(fabs(sx[4]), fabs(sy[4])), fabs(sz[4]));
-  const bool ok = (t[0] - hr > 0.0) && (t[0] + hr > 0.0) && (t[4] - hp > 0.0) && (t[4] + hp > 0.0);
-#pragma unroll
-  for (int v = 0; v < 5; ++v) wt[v] = ok ? t[v] : wc[v];
-  h = ok ? 0.5 : 0.0;
-  return ok;
+  return face_check(t, wc, sx, sy, sz, wt, h);
 }
 
 // LDS of one tile step.
@@ -325,10 +332,19 @@ struct Smem {
 // new state's signal speed goes to ws->sig[(slot+1)%3]; the first pencil of
 // the grid also records dt and clears ws->sig[(slot+2)%3].  Must be entered
 // by all NT threads of the workgroup.
-template <int N, int T>
-__device__ __forceinline__ void tile_step(const GridGeom& g, const double* __restrict__ Uin,
-                                          double* __restrict__ Uout, WorkHeader* ws, double dt_host,
-                                          double cfl, int slot, long tile_in_sim, int nseg, Smem<T>& sm) {
+//
+// MOL = false: the predictor-corrector step (face states from the half-step
+// predicted centre).  MOL = true: one method-of-lines stage of an SSP
+// Runge-Kutta step (face states from the cell centre; result
+// a0*U0 + a1*(Uin - dt div F) when st.U0 is set).  A later stage (st.stage
+// > 0) takes the dt its first stage recorded; only the last stage reduces
+// the signal speed.  Uout may be st.U0 (each cell of U0 is read only by the
+// thread that then writes it), never Uin.
+template <int N, int T, bool MOL = false>
+__device__ __forceinline__ void tile_step(const GridGeom& g, const double* __restrict__ Uin, double* Uout,
+                                          WorkHeader* ws, double dt_host, double cfl, int slot,
+                                          long tile_in_sim, int nseg, Smem<T>& sm,
+                                          const StageArgs& st = StageArgs{nullptr, 0.0, 0.0, 0, 1}) {
   using TL = Tile<T>;
   constexpr int NT = TL::NT, NI = TL::NI, NR = TL::NR, NE = TL::NE, WS = TL::WS;
   constexpr int TPB = (N / T) * (N / T);
@@ -350,11 +366,16 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   if (tid < 3) sm.sCnt[tid] = 0;
 
   double dt = dt_host;
-  if (cfl > 0.0) dt = cfl / __longlong_as_double(ws->sig[slot]);
-  if (tile_in_sim == 0 && tid == 0) {
-    ws->dt_last = dt;
-    ws->sig[(slot + 2) % 3] = 0ull;
+  if (MOL && st.stage > 0) {
+    if (cfl > 0.0) dt = ws->dt_last;
+  } else {
+    if (cfl > 0.0) dt = cfl / __longlong_as_double(ws->sig[slot]);
+    if (tile_in_sim == 0 && tid == 0) {
+      ws->dt_last = dt;
+      ws->sig[(slot + 2) % 3] = 0ull;
+    }
   }
+  const bool emit = !MOL || st.last;
   const double lamx = dt * g.inv_dx[0], lamy = dt * g.inv_dx[1], lamz = dt * g.inv_dx[2];
   const double gamma = g.gamma, gm1inv = 1.0 / (g.gamma - 1.0);
 
@@ -461,7 +482,11 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         sy[v] = van_leer_sf(c - sm.sW[v][cidx - WS], sm.sW[v][cidx + WS] - c);
         sz[v] = van_leer_sf(c - Wa[v], Wc[v] - c);
       }
-      const bool ok = predict(Wb, rcp_nr(Wb[0]), sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
+      bool ok;
+      if constexpr (MOL)
+        ok = face_check(Wb, Wb, sx, sy, sz, wt, h);
+      else
+        ok = predict(Wb, rcp_nr(Wb[0]), sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
       if (mid && !ok) ++n_fb;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -487,8 +512,10 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         sy[v] = van_leer_sf(wc[v] - sm.sW[v][sidx2 - WS], sm.sW[v][sidx2 + WS] - wc[v]);
         sz[v] = van_leer_sf(wc[v] - sm.sRing[sl_m][v][ring_id], sm.sRing[sl_p][v][ring_id] - wc[v]);
       }
-      const double inv = rcp_nr(wc[0]);
-      predict(wc, inv, sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
+      if constexpr (MOL)
+        face_check(wc, wc, sx, sy, sz, wt, h);
+      else
+        predict(wc, rcp_nr(wc[0]), sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
       // the one face state of this ring cell that a tile face uses
       const int r = ring_id % T;
       if (rside == 0) {
@@ -565,14 +592,24 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         load_cons<N>(Uin, off, uold);
 #pragma unroll
         for (int v = 0; v < 5; ++v) un[v] = uold[v] - (dxy_prev[v] + lamz * (fz[v] - fz_prev[v]));
+        if constexpr (MOL) {
+          if (st.U0) {
+            double base[5];
+            load_cons<N>(st.U0, off, base);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) un[v] = st.a0 * base[v] + st.a1 * un[v];
+          }
+        }
 #pragma unroll
         for (int v = 0; v < 5; ++v) Uout[off + v * VS] = un[v];
         bool good = un[0] > 0.0 && un[4] > 0.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) good = good && isfinite(un[v]);
         if (!good) ++n_bad;
-        const double s = signal_speed(un, g);
-        smax = (s > smax || !(s == s)) ? s : smax;
+        if (emit) {
+          const double s = signal_speed(un, g);
+          smax = (s > smax || !(s == s)) ? s : smax;
+        }
       }
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -588,7 +625,8 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   if (n_floor) atomicAdd(&sm.sCnt[0], n_floor);
   if (n_fb) atomicAdd(&sm.sCnt[1], n_fb);
   if (n_bad) atomicAdd(&sm.sCnt[2], n_bad);
-  wg_max_to(smax, sm.sRed, &ws->sig[(slot + 1) % 3]);
+  if (emit) wg_max_to(smax, sm.sRed, &ws->sig[(slot + 1) % 3]);
+  else __syncthreads();  // sCnt is complete
   if (tid == 0) {
     for (int c = 0; c < 3; ++c)
       if (sm.sCnt[c]) atomicAdd(&ws->cnt[c], (unsigned long long)sm.sCnt[c]);
@@ -602,6 +640,16 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepAr
   const long tile_id = xcd_tile(blockIdx.x, ntiles);
   if (tile_id >= ntiles) return;
   tile_step<N, T>(g, a.Uin, a.Uout, a.ws, a.dt, a.cfl, a.slot, tile_id, nseg, sm);
+}
+
+// One method-of-lines stage of one grid (same launch shape as step_kernel).
+template <int N, int T>
+__global__ __launch_bounds__(Tile<T>::NT, 2) void stage_kernel(GridGeom g, StepArgs a, StageArgs st, long ntiles,
+                                                               int nseg) {
+  __shared__ Smem<T> sm;
+  const long tile_id = xcd_tile(blockIdx.x, ntiles);
+  if (tile_id >= ntiles) return;
+  tile_step<N, T, true>(g, a.Uin, a.Uout, a.ws, a.dt, a.cfl, a.slot, tile_id, nseg, sm, st);
 }
 
 // Many grids in one persistent launch: workgroup w takes items w, w + G,
@@ -699,22 +747,27 @@ __global__ __launch_bounds__(256) void copy_kernel(const double* __restrict__ sr
 }
 
 template <int N, int T>
-hipError_t launch_step_t(const GridGeom& g, const StepArgs& a, int nseg, hipStream_t s) {
+hipError_t launch_step_t(const GridGeom& g, const StepArgs& a, const StageArgs* st, int nseg, hipStream_t s) {
   const long nblk = (long)g.nb[0] * g.nb[1] * g.nb[2];
   const long ntiles = nblk * (N / T) * (N / T) * nseg;
   const long grid = 8 * ((ntiles + 7) / 8);
-  hipLaunchKernelGGL((step_kernel<N, T>), dim3((unsigned)grid), dim3(Tile<T>::NT), 0, s, g, a, ntiles, nseg);
+  if (st)
+    hipLaunchKernelGGL((stage_kernel<N, T>), dim3((unsigned)grid), dim3(Tile<T>::NT), 0, s, g, a, *st, ntiles,
+                       nseg);
+  else
+    hipLaunchKernelGGL((step_kernel<N, T>), dim3((unsigned)grid), dim3(Tile<T>::NT), 0, s, g, a, ntiles, nseg);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, int nseg, hipStream_t s) {
+hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const StageArgs* st, int nseg,
+                       hipStream_t s) {
   if (nseg < 1 || nxb % nseg || nxb / nseg < 2) return hipErrorInvalidValue;
   switch (nxb) {
-    case 8: return launch_step_t<8, 8>(g, a, nseg, s);
-    case 16: return launch_step_t<16, 16>(g, a, nseg, s);
-    case 32: return launch_step_t<32, 16>(g, a, nseg, s);
+    case 8: return launch_step_t<8, 8>(g, a, st, nseg, s);
+    case 16: return launch_step_t<16, 16>(g, a, st, nseg, s);
+    case 32: return launch_step_t<32, 16>(g, a, st, nseg, s);
   }
   return hipErrorInvalidValue;
 }

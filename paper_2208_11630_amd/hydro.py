@@ -25,6 +25,7 @@ HYDRO_ENONPHYS = -4
 BC_PERIODIC = 0
 BC_OUTFLOW = 1
 NGUARD = 4
+SCHEME_MH, SCHEME_RK2, SCHEME_RK3 = 0, 2, 3
 
 # Every entry point include/hydro.h declares, with its ctypes signature.
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -67,6 +68,7 @@ SIGNATURES = {
     "hydro_counters": ([_HP, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
     "hydro_free_grid": ([_HP], ctypes.c_int),
     "hydro_set_pencils": ([_HP, ctypes.c_int], ctypes.c_int),
+    "hydro_set_scheme": ([_HP, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "hydro_set_buffers": ([_HP, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "hydro_batch_work_bytes": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int], ctypes.c_size_t),
     "hydro_batch_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
@@ -224,6 +226,19 @@ class Grid:
 
     def set_pencils(self, nseg: int) -> None:
         _check(lib().hydro_set_pencils(self.handle, int(nseg)))
+
+    def set_scheme(self, scheme: int, stage=None) -> None:
+        """Time integration: SCHEME_MH (predictor-corrector), SCHEME_RK2 or
+        SCHEME_RK3 (SSP Runge-Kutta over method-of-lines stages).  RK3 needs a
+        third state tensor; one is allocated when `stage` is None."""
+        if scheme == SCHEME_RK3 and stage is None:
+            stage = self._torch.empty(self.shape, dtype=self._torch.float64, device=self.bufs[0].device)
+        if stage is not None and (tuple(stage.shape) != self.shape or not stage.is_contiguous()):
+            raise HydroError(HYDRO_EINVAL, "stage buffer must be a contiguous tensor of the grid shape")
+        ptr = stage.data_ptr() if (stage is not None and scheme == SCHEME_RK3) else None
+        _check(lib().hydro_set_scheme(self.handle, int(scheme), ptr))
+        self.stage_buf = stage if scheme == SCHEME_RK3 else None
+        self.scheme = int(scheme)
 
     def set_buffers(self, U, U_alt) -> None:
         """Rebind the state buffers: U holds the current state, U_alt receives

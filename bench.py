@@ -22,6 +22,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_CELL = 80.0          # read 5 doubles of U, write 5 doubles of U'
+# SSP Runge-Kutta steps: the first stage reads U and writes U1 (80 B); every
+# later stage reads its input and the base state and writes its result (120 B)
+RK_BYTES_PER_CELL = {"rk2": 80.0 + 120.0, "rk3": 80.0 + 2 * 120.0}
 
 
 def make_workload(name):
@@ -259,6 +262,8 @@ def main():
     ap.add_argument("--cfl", type=float, default=0.8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--scheme", default="mh", choices=["mh", "rk2", "rk3"],
+                    help="grid workloads: predictor-corrector step (default) or SSP Runge-Kutta steps")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="also run the streaming copy probe on this many GiB (roofline calibration)")
     args = ap.parse_args()
@@ -279,6 +284,9 @@ def main():
     P, wname = make_workload(args.workload)
     print(f"[bench] workload {wname}: {P.cells} cells, {P.nblk} blocks", file=sys.stderr, flush=True)
     G = hydro.grid_for(P, device="cuda:0")
+    if args.scheme != "mh":
+        G.set_scheme(hydro.SCHEME_RK2 if args.scheme == "rk2" else hydro.SCHEME_RK3)
+    bpc = BYTES_PER_CELL if args.scheme == "mh" else RK_BYTES_PER_CELL[args.scheme]
     stream = G.stream
     for _ in range(args.warmup):
         G.step_cfl(args.cfl)
@@ -296,11 +304,18 @@ def main():
     cnt = G.counters().tolist()
     print(f"[bench] {args.steps} steps in {ms:.3f} ms ({ms_step:.4f} ms/step), counters {cnt}",
           file=sys.stderr, flush=True)
-    achieved = BYTES_PER_CELL * P.cells / (ms_step * 1e-3) / 1e9
-    tag = f"step_kernel_nxb{P.n}_{args.workload}"
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(tag),
-            "kernel": tag, "algorithmic_bytes_per_launch": BYTES_PER_CELL * P.cells}
+    achieved = bpc * P.cells / (ms_step * 1e-3) / 1e9
+    if args.scheme == "mh":
+        tag = f"step_kernel_nxb{P.n}_{args.workload}"
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(tag),
+                "kernel": tag, "algorithmic_bytes_per_launch": BYTES_PER_CELL * P.cells}
+    else:  # several stage launches per step: bytes and time are per step
+        tag = f"stage_kernel_nxb{P.n}_{args.workload}_{args.scheme}"
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": tag,
+                "algorithmic_bytes_per_step": bpc * P.cells,
+                "launches_per_step": 2 if args.scheme == "rk2" else 3}
     out = {
         "metric": "FP64 cell-updates/s",
         "value": rate,
@@ -315,6 +330,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wname, "cells": P.cells, "nxb": P.n, "blocks": P.nblk, "cfl": args.cfl,
+                   "scheme": {"mh": "predictor-corrector", "rk2": "ssp-rk2", "rk3": "ssp-rk3"}[args.scheme],
                    "parallelism": "single-gpu"},
         "roofline": roof,
     }
@@ -335,7 +351,7 @@ def main():
         out["copy_probe"] = {"bytes_read": 8 * n, "bytes_written": 8 * n, "ms": cms,
                              "GB/s": 16 * n / (cms * 1e-3) / 1e9}
         del src, dst
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.scheme == "mh":
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_seconds)
     print(json.dumps(out), flush=True)

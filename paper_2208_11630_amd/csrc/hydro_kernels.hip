@@ -390,6 +390,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   const int cx = tid % T, cy = tid / T;                // valid when inner
   const int cidx = (cy + 2) * WS + (cx + 2);
   const bool is_ring = role < NR;
+  const bool ring_wave = role < 64;                     // uniform over a wavefront
   const bool is_extra = role >= NR && role < NR + NE;
   const int ring_id = role;                             // valid when is_ring
   int sx2 = 0, sy2 = 0;                                 // second item position
@@ -504,6 +505,9 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
       }
     }
     if (is_ring && mid) {
+      // the ring's wavefront is the last to reach the next barrier: let it
+      // issue ahead of the other workgroup's wavefront on its SIMD
+      __builtin_amdgcn_s_setprio(2);
       double wc[5], sx[5], sy[5], sz[5], wt[5], h;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -532,11 +536,15 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         for (int v = 0; v < 5; ++v) sm.sRy[v][r] = fma(-h, sy[v], wt[v]);           // (r, T) low y
       }
     }
+    // z faces of the own column; the ring's wavefront, which predicted a
+    // second cell, takes its z faces after the barrier
     double fz[5];
-    if (inner && j >= z0) hllc<2>(zp_prev, zm, gamma, gm1inv, fz);
+    if (inner && j >= z0 && !ring_wave) hllc<2>(zp_prev, zm, gamma, gm1inv, fz);
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
 
     // -- x and y fluxes: own low faces, plus the tile's high boundary faces
+    if (inner && j >= z0 && ring_wave) hllc<2>(zp_prev, zm, gamma, gm1inv, fz);
     if (mid) {
       if (inner) {
         double WL[5], F[5];
@@ -552,27 +560,35 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         for (int v = 0; v < 5; ++v) sm.sFy[v][cy * T + cx] = F[v];
       }
       if (role >= NT - 2 * T) {  // on the last wavefront, away from the ring's
-        double WL[5], WR[5], F[5];
+        // x faces at (T, r) and y faces at (r, T) in one HLLC call: a y face
+        // is an x face of the state with u and v exchanged (the flux is
+        // exchanged back), which gives the same operations in the same order
         const int r = (role - (NT - 2 * T)) % T;
-        if (role < NT - T) {  // x face at x = T, y = r
+        const bool yface = role >= NT - T;
+        const double* qL = yface ? (const double*)sm.sQy + (T * T + r) : (const double*)sm.sQx + (r * (T + 1) + T);
+        const double* qR = yface ? (const double*)sm.sRy + r : (const double*)sm.sRx + r;
+        double* fo = yface ? (double*)sm.sFy + (T * T + r) : (double*)sm.sFx + (r * (T + 1) + T);
+        double WL[5], WR[5], F[5];
 #pragma unroll
-          for (int v = 0; v < 5; ++v) {
-            WL[v] = sm.sQx[v][r * (T + 1) + T];
-            WR[v] = sm.sRx[v][r];
-          }
-          hllc<0>(WL, WR, gamma, gm1inv, F);
-#pragma unroll
-          for (int v = 0; v < 5; ++v) sm.sFx[v][r * (T + 1) + T] = F[v];
-        } else {        // y face at y = T, x = r
-#pragma unroll
-          for (int v = 0; v < 5; ++v) {
-            WL[v] = sm.sQy[v][T * T + r];
-            WR[v] = sm.sRy[v][r];
-          }
-          hllc<1>(WL, WR, gamma, gm1inv, F);
-#pragma unroll
-          for (int v = 0; v < 5; ++v) sm.sFy[v][T * T + r] = F[v];
+        for (int v = 0; v < 5; ++v) {
+          WL[v] = qL[v * TL::NQ];
+          WR[v] = qR[v * T];
         }
+        if (yface) {
+          const double a = WL[1], b = WR[1];
+          WL[1] = WL[2];
+          WL[2] = a;
+          WR[1] = WR[2];
+          WR[2] = b;
+        }
+        hllc<0>(WL, WR, gamma, gm1inv, F);
+        if (yface) {
+          const double a = F[1];
+          F[1] = F[2];
+          F[2] = a;
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fo[v * TL::NQ] = F[v];
       }
     }
     __syncthreads();

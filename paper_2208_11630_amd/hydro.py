@@ -105,6 +105,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise HydroLibraryMissing(
                 f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded (one runtime per process), whatever the import order.
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -180,6 +184,8 @@ class Grid:
     # -- state access ---------------------------------------------------------
     @property
     def state(self):
+        if not self.bufs:
+            raise HydroError(HYDRO_EINVAL, "state buffers were released; rebind them with set_buffers")
         p = ctypes.c_void_p()
         _check(lib().hydro_current(self.handle, ctypes.byref(p)))
         return self.bufs[0] if p.value == self.bufs[0].data_ptr() else self.bufs[1]
@@ -248,6 +254,12 @@ class Grid:
                 raise HydroError(HYDRO_EINVAL, "state buffers must be contiguous tensors of the grid shape")
         _check(lib().hydro_set_buffers(self.handle, U.data_ptr(), U_alt.data_ptr()))
         self.bufs = [U, U_alt]
+
+    def release_buffers(self) -> None:
+        """Drop this object's references to the state tensors (a caller that
+        owns them elsewhere, e.g. a serving loop, lets them go back to the
+        allocator).  Rebind with set_buffers before the next step."""
+        self.bufs = []
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None:

@@ -308,4 +308,5 @@ class GpuExecutor(Executor):
         ev, _, sims, outs = handle
         self.torch.cuda.current_stream().wait_event(ev)
         for x, out in zip(sims, outs):
-            self.state[x] = out  # the old state buffer returns to the allocator
+            self.state[x] = out  # the old state buffer returns to the allocator ...
+            self.grid[x].release_buffers()  # ... once the handle's wrapper lets go of it too

@@ -252,7 +252,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="kh", choices=["kh", "sedov", "sod", "ensemble", "served"])
     ap.add_argument("--served-sims", type=int, default=2000)
     ap.add_argument("--served-budget-gb", type=float, default=200.0)

@@ -42,6 +42,10 @@ class Executor:
     def bytes_of(self, sim: int) -> int: ...
     def cells_of(self, sim: int) -> int: ...
     def is_resident(self, sim: int) -> bool: ...
+    def is_ready(self, sim: int) -> bool:
+        """Resident with its state in place (an admission copy may still be
+        in flight after make_resident returns)."""
+        return self.is_resident(sim)
     def make_resident(self, sim: int) -> None: ...
     def evict(self, sim: int) -> None: ...
     def launch(self, sims: Sequence[int]): ...
@@ -166,6 +170,8 @@ class Server:
                     if not self._admit(s, pinned):
                         pinned.discard(s)  # wait for memory to free up
                         continue
+                    if not self.ex.is_ready(s):
+                        continue  # its state is still being copied in: a later launch takes it
                     chosen.append(s)
                     cells += c
                     q = pending[s]
@@ -208,6 +214,41 @@ def poisson_arrivals(rate: float, duration: float, nsims: int, seed: int = 4) ->
     return list(zip(t.tolist(), s.tolist()))
 
 
+class PinnedPool:
+    """Pinned host buffers for evicted states, carved from a few large pinned
+    chunks and recycled per exact size (the served sizes take a handful of
+    values), so the pinned footprint tracks the evicted bytes instead of
+    growing with every eviction.  get() returns None once `cap_bytes` of
+    chunks are in use (the caller then falls back to pageable memory)."""
+
+    def __init__(self, torch, chunk_bytes: int = 4 << 30, cap_bytes: int = 96 << 30):
+        self.torch = torch
+        self.chunk_bytes = int(chunk_bytes)
+        self.cap_bytes = int(cap_bytes)
+        self.chunks: List = []
+        self.free: Dict[int, List] = collections.defaultdict(list)
+        self.off = 0
+
+    def get(self, nbytes: int):
+        lst = self.free.get(nbytes)
+        if lst:
+            return lst.pop()
+        size = (nbytes + 4095) // 4096 * 4096
+        if size > self.chunk_bytes:
+            return None
+        if not self.chunks or self.off + size > self.chunk_bytes:
+            if (len(self.chunks) + 1) * self.chunk_bytes > self.cap_bytes:
+                return None
+            self.chunks.append(self.torch.empty(self.chunk_bytes, dtype=self.torch.uint8, pin_memory=True))
+            self.off = 0
+        buf = self.chunks[-1][self.off:self.off + nbytes]
+        self.off += size
+        return buf
+
+    def put(self, buf) -> None:
+        self.free[buf.numel()].append(buf)
+
+
 class GpuExecutor(Executor):
     """Simulations as libhydro grids on the device.
 
@@ -215,10 +256,13 @@ class GpuExecutor(Executor):
     lends its members an output buffer for the step in flight (from torch's
     caching allocator, so no device allocation after warm-up), and on
     completion the output becomes the state and the old buffer is returned.
-    Evicted states go to host memory.  The initial state of simulation s
-    (cubic L^3, 16^3 blocks, periodic) is drawn on the device on first
-    admission (``ics.served_state_device``).  Each launch is one batched step
-    on the next of `nstreams` streams."""
+    Evicted states go to pinned host memory and come back through
+    asynchronous copies on a copy stream of their own, overlapped with the
+    steps of resident simulations; a simulation joins a launch once its
+    state is in place.  The initial state of simulation s (cubic L^3, 16^3
+    blocks, periodic) is drawn on the device on first admission
+    (``ics.served_state_device``).  Each launch is one batched step on the
+    next of `nstreams` streams."""
 
     def __init__(self, sizes: Sequence[int], cfl: float = 0.8, nstreams: int = 2, device: str = "cuda",
                  seed: int = 3, nxb: int = 16):
@@ -234,10 +278,13 @@ class GpuExecutor(Executor):
         self.nxb = nxb
         self.device = device
         self.streams = [torch.cuda.Stream(device=device) for _ in range(nstreams)]
+        self.copy_stream = torch.cuda.Stream(device=device)
         self.next_stream = 0
         self.state: Dict[int, "torch.Tensor"] = {}
         self.grid: Dict[int, "hydro.Grid"] = {}
-        self.host: Dict[int, np.ndarray] = {}
+        self.host: Dict[int, tuple] = {}       # evicted: (host tensor, event of its copy or None, pool buffer)
+        self.incoming: Dict[int, tuple] = {}   # admission copies in flight: (event, pool buffer)
+        self.pool = PinnedPool(torch)
         self.steps_done = collections.Counter()
 
     def shape_of(self, sim: int):
@@ -253,24 +300,70 @@ class GpuExecutor(Executor):
     def is_resident(self, sim: int) -> bool:
         return sim in self.state
 
+    def is_ready(self, sim: int) -> bool:
+        if sim not in self.state:
+            return False
+        inc = self.incoming.get(sim)
+        if inc is None:
+            return True
+        if inc[0].query():
+            del self.incoming[sim]
+            self.pool.put(inc[1])
+            return True
+        return False
+
     def make_resident(self, sim: int) -> None:
         from . import ics
 
-        t = self.torch.empty(self.shape_of(sim), dtype=self.torch.float64, device=self.device)
+        torch = self.torch
+        t = torch.empty(self.shape_of(sim), dtype=torch.float64, device=self.device)
         if sim in self.host:
-            t.copy_(self.torch.from_numpy(self.host.pop(sim)))
+            h, _, buf = self.host.pop(sim)
+            if buf is None:                            # pageable fallback: synchronous copy
+                t.copy_(h)
+            else:
+                cs = self.copy_stream
+                cs.wait_stream(torch.cuda.current_stream())  # t's memory may still be in use there
+                with torch.cuda.stream(cs):
+                    t.copy_(h, non_blocking=True)      # after its own eviction copy (same stream)
+                t.record_stream(cs)
+                ev = torch.cuda.Event()
+                ev.record(cs)
+                self.incoming[sim] = (ev, buf)
         else:
             ics.served_state_device(sim, self.sizes[sim], out=t, seed=self.seed, n=self.nxb)
         self.state[sim] = t
 
     def evict(self, sim: int) -> None:
+        torch = self.torch
         t = self.state.pop(sim)
-        self.host[sim] = t.cpu().numpy()
+        inc = self.incoming.pop(sim, None)
+        cs = self.copy_stream
+        if inc is not None:
+            inc[0].synchronize()                       # its admission copy has to land first
+            self.pool.put(inc[1])
+        buf = self.pool.get(t.numel() * t.element_size())
+        if buf is None:                                # pool exhausted: pageable, synchronous
+            torch.cuda.current_stream().synchronize()
+            self.host[sim] = (t.cpu(), None, None)
+            return
+        h = buf.view(t.dtype).view(t.shape)
+        cs.wait_stream(torch.cuda.current_stream())    # the state's last step has finished there
+        with torch.cuda.stream(cs):
+            h.copy_(t, non_blocking=True)
+        t.record_stream(cs)                            # the allocator reuses t after the copy
+        ev = torch.cuda.Event()
+        ev.record(cs)
+        self.host[sim] = (h, ev, buf)
 
     def current_state(self, sim: int) -> np.ndarray:
         if sim in self.state:
+            self.copy_stream.synchronize()
             return self.state[sim].cpu().numpy()
-        return self.host[sim]
+        h, ev, _ = self.host[sim]
+        if ev is not None:
+            ev.synchronize()
+        return h.numpy().copy()
 
     def launch(self, sims: Sequence[int]):
         torch = self.torch
@@ -278,6 +371,9 @@ class GpuExecutor(Executor):
         self.next_stream = (self.next_stream + 1) % len(self.streams)
         grids, outs = [], []
         for x in sims:
+            inc = self.incoming.pop(x, None)
+            if inc is not None:
+                s.wait_event(inc[0])
             st = self.state[x]
             out = torch.empty_like(st)
             G = self.grid.get(x)

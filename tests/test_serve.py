@@ -133,3 +133,29 @@ def test_poisson_arrivals_statistics():
     assert np.all(np.diff(t) >= 0) and t.min() >= 0 and t.max() <= 2.0
     gaps = np.diff(t)
     assert abs(gaps.mean() * 2000.0 - 1.0) < 0.1
+
+
+def test_pinned_pool_recycles_exact_sizes_and_respects_its_cap():
+    """Host bookkeeping of the pinned pool (plain host tensors stand in for
+    pinned ones): buffers come from large chunks, are recycled by exact size,
+    and get() refuses once the chunk cap is reached."""
+    import torch
+
+    class HostTorch:
+        uint8 = torch.uint8
+
+        @staticmethod
+        def empty(n, dtype, pin_memory):
+            return torch.empty(n, dtype=dtype)
+
+    p = serve.PinnedPool(HostTorch, chunk_bytes=1 << 20, cap_bytes=2 << 20)
+    a = p.get(300_000)
+    b = p.get(300_000)
+    assert a.numel() == b.numel() == 300_000
+    assert b.data_ptr() - a.data_ptr() == 303_104          # 4 KiB-aligned carving
+    c = p.get(500_000)                                       # does not fit the first chunk
+    assert len(p.chunks) == 2 and c.data_ptr() == p.chunks[1].data_ptr()
+    p.put(a)
+    assert p.get(300_000).data_ptr() == a.data_ptr()        # recycled, same size
+    assert p.get(600_000) is None                            # would need a third chunk
+    assert p.get(2 << 20) is None                            # larger than a chunk

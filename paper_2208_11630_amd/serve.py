@@ -227,7 +227,14 @@ class PinnedPool:
         self.cap_bytes = int(cap_bytes)
         self.chunks: List = []
         self.free: Dict[int, List] = collections.defaultdict(list)
+        self.spare: List = []          # reserved chunks not carved yet
         self.off = 0
+
+    def reserve(self, nbytes: int) -> None:
+        """Pin up to `nbytes` (within the cap) up front, so that serving does
+        not page-lock host memory on its critical path."""
+        while (len(self.chunks) + len(self.spare)) * self.chunk_bytes < min(int(nbytes), self.cap_bytes):
+            self.spare.append(self.torch.empty(self.chunk_bytes, dtype=self.torch.uint8, pin_memory=True))
 
     def get(self, nbytes: int):
         lst = self.free.get(nbytes)
@@ -237,9 +244,12 @@ class PinnedPool:
         if size > self.chunk_bytes:
             return None
         if not self.chunks or self.off + size > self.chunk_bytes:
-            if (len(self.chunks) + 1) * self.chunk_bytes > self.cap_bytes:
+            if self.spare:
+                self.chunks.append(self.spare.pop())
+            elif (len(self.chunks) + 1) * self.chunk_bytes > self.cap_bytes:
                 return None
-            self.chunks.append(self.torch.empty(self.chunk_bytes, dtype=self.torch.uint8, pin_memory=True))
+            else:
+                self.chunks.append(self.torch.empty(self.chunk_bytes, dtype=self.torch.uint8, pin_memory=True))
             self.off = 0
         buf = self.chunks[-1][self.off:self.off + nbytes]
         self.off += size
@@ -278,7 +288,8 @@ class GpuExecutor(Executor):
         self.nxb = nxb
         self.device = device
         self.streams = [torch.cuda.Stream(device=device) for _ in range(nstreams)]
-        self.copy_stream = torch.cuda.Stream(device=device)
+        self.copy_stream = torch.cuda.Stream(device=device)   # admissions, host -> device
+        self.evict_stream = torch.cuda.Stream(device=device)  # evictions, device -> host
         self.next_stream = 0
         self.state: Dict[int, "torch.Tensor"] = {}
         self.grid: Dict[int, "hydro.Grid"] = {}
@@ -318,14 +329,15 @@ class GpuExecutor(Executor):
         torch = self.torch
         t = torch.empty(self.shape_of(sim), dtype=torch.float64, device=self.device)
         if sim in self.host:
-            h, _, buf = self.host.pop(sim)
+            h, evicted, buf = self.host.pop(sim)
             if buf is None:                            # pageable fallback: synchronous copy
                 t.copy_(h)
             else:
                 cs = self.copy_stream
                 cs.wait_stream(torch.cuda.current_stream())  # t's memory may still be in use there
+                cs.wait_event(evicted)                 # the eviction copy has filled h
                 with torch.cuda.stream(cs):
-                    t.copy_(h, non_blocking=True)      # after its own eviction copy (same stream)
+                    t.copy_(h, non_blocking=True)
                 t.record_stream(cs)
                 ev = torch.cuda.Event()
                 ev.record(cs)
@@ -338,7 +350,7 @@ class GpuExecutor(Executor):
         torch = self.torch
         t = self.state.pop(sim)
         inc = self.incoming.pop(sim, None)
-        cs = self.copy_stream
+        cs = self.evict_stream
         if inc is not None:
             inc[0].synchronize()                       # its admission copy has to land first
             self.pool.put(inc[1])
@@ -359,6 +371,7 @@ class GpuExecutor(Executor):
     def current_state(self, sim: int) -> np.ndarray:
         if sim in self.state:
             self.copy_stream.synchronize()
+            self.evict_stream.synchronize()
             return self.state[sim].cpu().numpy()
         h, ev, _ = self.host[sim]
         if ev is not None:
@@ -369,11 +382,12 @@ class GpuExecutor(Executor):
         torch = self.torch
         s = self.streams[self.next_stream]
         self.next_stream = (self.next_stream + 1) % len(self.streams)
-        grids, outs = [], []
+        grids, outs, spent = [], [], []
         for x in sims:
             inc = self.incoming.pop(x, None)
             if inc is not None:
                 s.wait_event(inc[0])
+                spent.append(inc[1])  # back to the pool once this launch is done
             st = self.state[x]
             out = torch.empty_like(st)
             G = self.grid.get(x)
@@ -395,14 +409,16 @@ class GpuExecutor(Executor):
         B.close()  # host metadata; the device work list stays alive in the handle
         for x in sims:
             self.steps_done[x] += 1
-        return (ev, B.work, list(sims), outs)
+        return (ev, B.work, list(sims), outs, spent)
 
     def done(self, handle) -> bool:
         return handle[0].query()
 
     def finish(self, handle) -> None:
-        ev, _, sims, outs = handle
+        ev, _, sims, outs, spent = handle
         self.torch.cuda.current_stream().wait_event(ev)
+        for buf in spent:
+            self.pool.put(buf)
         for x, out in zip(sims, outs):
             self.state[x] = out  # the old state buffer returns to the allocator ...
             self.grid[x].release_buffers()  # ... once the handle's wrapper lets go of it too

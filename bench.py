@@ -298,6 +298,12 @@ def main():
     G = hydro.grid_for(P, device="cuda:0")
     if args.scheme != "mh":
         G.set_scheme(hydro.SCHEME_RK2 if args.scheme == "rk2" else hydro.SCHEME_RK3)
+    planes = P.n
+    if not args.no_tune:
+        from paper_2208_11630_amd import tune
+
+        planes = tune.tune_grid(G, args.cfl)
+        print(f"[bench] tuned: {planes} planes per z pencil", file=sys.stderr, flush=True)
     bpc = BYTES_PER_CELL if args.scheme == "mh" else RK_BYTES_PER_CELL[args.scheme]
     stream = G.stream
     for _ in range(args.warmup):
@@ -343,6 +349,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "cells": P.cells, "nxb": P.n, "blocks": P.nblk, "cfl": args.cfl,
                    "scheme": {"mh": "predictor-corrector", "rk2": "ssp-rk2", "rk3": "ssp-rk3"}[args.scheme],
+                   "pencil_planes": planes,
                    "parallelism": "single-gpu"},
         "roofline": roof,
     }

@@ -168,6 +168,13 @@ int hydro_set_buffers(hydro_grid *g, double *U, double *U_alt);
  * halo planes per pencil.  Results are bitwise independent of it. */
 int hydro_set_pencils(hydro_grid *g, int nseg);
 
+/* Tuning: z pencils of `planes` consecutive planes of the whole grid (a
+ * pencil may span several blocks along z: fewer re-read halo planes per
+ * updated plane on tall grids; or part of a block).  planes >= 2 and must
+ * divide nblk[2]*nxb; the default is nxb (one block).  Results are bitwise
+ * independent of it.  Errors: HYDRO_EINVAL. */
+int hydro_set_pencil_planes(hydro_grid *g, int planes);
+
 /* Time integration of the grid's steps (§2.2 Hydrodynamics names two
  * compressible solvers: the predictor-corrector one and one with second- or
  * third-order strong-stability-preserving Runge-Kutta time integration).

@@ -23,7 +23,7 @@ struct hydro_grid {
   int cur;                  // 0: state in d.U, 1: in d.U_alt
   unsigned long long steps; // steps taken; signal slot of the current state = steps % 3
   bool sig_valid;           // slot holds the current state's maximum signal speed
-  int nseg;                 // z pencils per block column (tuning; results do not depend on it)
+  int plen;                 // planes per z pencil (tuning; results do not depend on it)
   hydro_batch* batch;       // batch the grid belongs to (its own step calls are refused meanwhile)
   int scheme;               // HYDRO_SCHEME_*
   double* U_stage;          // third state buffer (third-order Runge-Kutta only)
@@ -164,7 +164,7 @@ int do_rk_step(hydro_grid* g, double dt, double cfl) {
     st.a1 = stages[k].a1;
     st.stage = k;
     st.last = k == order - 1;
-    hipError_t e = hydro::launch_step(g->d.nxb, g->geom, a, &st, g->nseg, stream_of(g));
+    hipError_t e = hydro::launch_step(g->d.nxb, g->geom, a, &st, g->plen, stream_of(g));
     if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
   }
   g->steps += 1;
@@ -181,7 +181,7 @@ int do_step(hydro_grid* g, double dt, double cfl) {
   a.dt = dt;
   a.cfl = cfl;
   a.slot = slot_of(g);
-  hipError_t e = hydro::launch_step(g->d.nxb, g->geom, a, nullptr, g->nseg, stream_of(g));
+  hipError_t e = hydro::launch_step(g->d.nxb, g->geom, a, nullptr, g->plen, stream_of(g));
   if (e != hipSuccess) return hip_fail(e, "step kernel launch");
   g->cur ^= 1;
   g->steps += 1;
@@ -244,7 +244,7 @@ int hydro_init_grid(const hydro_grid_desc* d, hydro_grid** out) {
   g->cur = 0;
   g->steps = 0;
   g->sig_valid = false;
-  g->nseg = 1;
+  g->plen = d->nxb;
   g->batch = nullptr;
   g->scheme = HYDRO_SCHEME_MH;
   g->U_stage = nullptr;
@@ -387,7 +387,16 @@ int hydro_set_pencils(hydro_grid* g, int nseg) {
   if (!g) return fail(HYDRO_EINVAL, "handle is NULL");
   if (nseg != 1 && nseg != 2 && nseg != 4) return fail(HYDRO_EINVAL, "pencils per column must be 1, 2 or 4");
   if (g->d.nxb / nseg < 2) return fail(HYDRO_EINVAL, "pencils shorter than 2 planes");
-  g->nseg = nseg;
+  g->plen = g->d.nxb / nseg;
+  return HYDRO_OK;
+}
+
+int hydro_set_pencil_planes(hydro_grid* g, int planes) {
+  if (!g) return fail(HYDRO_EINVAL, "handle is NULL");
+  const long nz = (long)g->d.nblk[2] * g->d.nxb;
+  if (planes < 2 || planes > nz || nz % planes)
+    return fail(HYDRO_EINVAL, "planes per pencil must be >= 2 and divide the %ld planes along z", nz);
+  g->plen = planes;
   return HYDRO_OK;
 }
 

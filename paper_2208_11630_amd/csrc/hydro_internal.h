@@ -67,7 +67,8 @@ struct BatchItem {
 };
 
 // st == NULL: predictor-corrector step; else one method-of-lines stage.
-hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const StageArgs* st, int nseg,
+// plen: planes per z pencil (>= 2, divides the grid's z extent).
+hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const StageArgs* st, int plen,
                        hipStream_t s);
 hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,
                              const int nseg[3], int grid, hipStream_t s);

@@ -326,8 +326,10 @@ struct Smem {
 };
 
 // One z pencil of one T x T column tile of an N^3 block, updated from Uin into
-// Uout.  tile_in_sim = (block * (N/T)^2 + in-plane tile) * nseg + segment;
-// the pencil covers planes [segment*N/nseg, (segment+1)*N/nseg).  dt is
+// Uout.  A pencil is plen consecutive planes of the global z axis (part of
+// a block, or several blocks); tile_in_sim = layer * (column tiles of one
+// z layer) + (block_xy * (N/T)^2 + in-plane tile), block_xy = bx + nb0*by,
+// so the pencil covers global planes [layer*plen, (layer+1)*plen).  dt is
 // cfl / max signal speed (ws->sig[slot]) when cfl > 0, else dt_host.  The
 // new state's signal speed goes to ws->sig[(slot+1)%3]; the first pencil of
 // the grid also records dt and clears ws->sig[(slot+2)%3].  Must be entered
@@ -343,7 +345,7 @@ struct Smem {
 template <int N, int T, bool MOL = false>
 __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __restrict__ Uin, double* Uout,
                                           WorkHeader* ws, double dt_host, double cfl, int slot,
-                                          long tile_in_sim, int nseg, Smem<T>& sm,
+                                          long tile_in_sim, int plen, Smem<T>& sm,
                                           const StageArgs& st = StageArgs{nullptr, 0.0, 0.0, 0, 1}) {
   using TL = Tile<T>;
   constexpr int NT = TL::NT, NI = TL::NI, NR = TL::NR, NE = TL::NE, WS = TL::WS;
@@ -352,16 +354,17 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   constexpr long PS = Layout<N>::PS;
 
   const int tid = threadIdx.x;
-  const long col = tile_in_sim / nseg;
-  const int seg = (int)(tile_in_sim % nseg);
-  const int L = N / nseg, z0 = seg * L, z1 = z0 + L;
-  const long blk = col / TPB;
-  const int tile = (int)(col % TPB);
-  const int bx = (int)(blk % g.nb[0]);
-  const int by = (int)((blk / g.nb[0]) % g.nb[1]);
-  const int bz = (int)(blk / ((long)g.nb[0] * g.nb[1]));
+  const long nxy = (long)g.nb[0] * g.nb[1] * TPB;  // column tiles of one z layer
+  const int NZ = g.nb[2] * N;
+  const long layer = tile_in_sim / nxy;
+  const long cxy = tile_in_sim % nxy;
+  const int z0 = (int)(layer * plen), z1 = z0 + plen;  // global planes of the pencil
+  const long bxy = cxy / TPB;                          // block (bx, by, 0)
+  const int tile = (int)(cxy % TPB);
+  const int bx = (int)(bxy % g.nb[0]);
+  const int by = (int)(bxy / g.nb[0]);
   const int lx0 = (tile % (N / T)) * T, ly0 = (tile / (N / T)) * T;  // tile origin inside the block
-  const int X0 = bx * N + lx0, Y0 = by * N + ly0, Z0 = bz * N;
+  const int X0 = bx * N + lx0, Y0 = by * N + ly0;
 
   if (tid < 3) sm.sCnt[tid] = 0;
 
@@ -385,7 +388,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   // (a workgroup may be wider than NT, e.g. 8^3 tiles in a 256-thread batch
   // launch: the threads beyond NT only take part in the barriers)
   const bool member = tid < NT;
-  const int role = member ? (tid + 64 * (int)(col & 3)) % NT : NT;
+  const int role = member ? (tid + 64 * (int)(tile_in_sim & 3)) % NT : NT;
   const bool inner = tid < NI;
   const int cx = tid % T, cy = tid / T;                // valid when inner
   const int cidx = (cy + 2) * WS + (cx + 2);
@@ -400,23 +403,30 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   const int rside = role / T;                           // ring side (valid when is_ring)
   // offsets of plane 0 of the own column and of the second item, for the
   // planes that lie inside the block (z halo planes go through the map)
-  const long own0 = Layout<N>::at(blk, lx0 + cx, ly0 + cy, 0);
-  const long sec0 = (is_ring || is_extra) ? cell_offset<N>(g, X0 + sx2, Y0 + sy2, Z0) : 0;
+  // offsets (variable 0) at global plane 0 of the own column and of the
+  // second item; a plane k inside the domain adds zoff(k), planes beyond the
+  // z boundaries go through the boundary map
+  const long BZS = (long)g.nb[0] * g.nb[1] * Layout<N>::BS;  // block stride along z
+  auto zoff = [&](int k) -> long { return (long)((unsigned)k / N) * BZS + (long)((unsigned)k % N) * PS; };
+  const long own0 = Layout<N>::at(bxy, lx0 + cx, ly0 + cy, 0);
+  const long sec0 = (is_ring || is_extra) ? cell_offset<N>(g, X0 + sx2, Y0 + sy2, 0) : 0;
   auto own_at = [&](int k) -> long {
-    return (k >= 0 && k < N) ? own0 + k * PS : cell_offset<N>(g, X0 + cx, Y0 + cy, Z0 + k);
+    return (k >= 0 && k < NZ) ? own0 + zoff(k) : cell_offset<N>(g, X0 + cx, Y0 + cy, k);
   };
   auto sec_at = [&](int k) -> long {
-    return (k >= 0 && k < N) ? sec0 + k * PS : cell_offset<N>(g, X0 + sx2, Y0 + sy2, Z0 + k);
+    return (k >= 0 && k < NZ) ? sec0 + zoff(k) : cell_offset<N>(g, X0 + sx2, Y0 + sy2, k);
   };
 
   double Wa[5], Wb[5], Wc[5];
   double un_next[5], u2_next[5];
-  double zp_prev[5], fz_prev[5], dxy_prev[5];
+  // acc: plane j-1's x/y flux divergence minus its lower z flux, carried to
+  // the next plane, whose z flux completes the update of plane j-1
+  double zp_prev[5], acc[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     Wa[v] = Wb[v] = Wc[v] = 0.0;
     un_next[v] = u2_next[v] = 0.0;
-    zp_prev[v] = fz_prev[v] = dxy_prev[v] = 0.0;
+    zp_prev[v] = acc[v] = 0.0;
   }
   int n_floor = 0, n_fb = 0, n_bad = 0;
   double smax = 0.0;
@@ -428,7 +438,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     prim(u, gamma, g.small_p, Wa, tmp);
     load_cons<N>(Uin, own_at(z0 - 1), u);
     prim(u, gamma, g.small_p, Wb, tmp);
-    load_cons<N>(Uin, own0 + z0 * PS, un_next);
+    load_cons<N>(Uin, own0 + zoff(z0), un_next);
   }
   if (is_ring) {
     double u[5], w[5], tmp;
@@ -436,9 +446,9 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     prim(u, gamma, g.small_p, w, tmp);
 #pragma unroll
     for (int v = 0; v < 5; ++v) sm.sRing[(z0 + 2) % 3][v][ring_id] = w[v];
-    load_cons<N>(Uin, sec0 + z0 * PS, u2_next);
+    load_cons<N>(Uin, sec0 + zoff(z0), u2_next);
   }
-  if (is_extra) load_cons<N>(Uin, sec0 + z0 * PS, u2_next);
+  if (is_extra) load_cons<N>(Uin, sec0 + zoff(z0), u2_next);
 
   for (int j = z0 - 1; j <= z1; ++j) {
     const bool mid = (j >= z0) && (j < z1);
@@ -468,7 +478,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
       prim(u2_next, gamma, g.small_p, w, tmp);
 #pragma unroll
       for (int v = 0; v < 5; ++v) sm.sW[v][sidx2] = w[v];
-      if (j + 1 < z1) load_cons<N>(Uin, sec0 + (j + 1) * PS, u2_next);
+      if (j + 1 < z1) load_cons<N>(Uin, sec0 + zoff(j + 1), u2_next);
     }
     __syncthreads();
 
@@ -593,7 +603,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     }
     __syncthreads();
 
-    // -- update plane j-1, keep plane j's x/y divergence
+    // -- update plane j-1, carry plane j's divergence
     if (inner) {
       double dxy[5];
       if (mid) {
@@ -603,11 +613,11 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
           dxy[v] = lamx * (sm.sFx[v][qx + 1] - sm.sFx[v][qx]) + lamy * (sm.sFy[v][qy + T] - sm.sFy[v][qy]);
       }
       if (j >= z0 + 1) {
-        const long off = own0 + (j - 1) * PS;
+        const long off = own0 + zoff(j - 1);
         double uold[5], un[5];
         load_cons<N>(Uin, off, uold);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) un[v] = uold[v] - (dxy_prev[v] + lamz * (fz[v] - fz_prev[v]));
+        for (int v = 0; v < 5; ++v) un[v] = uold[v] - fma(lamz, fz[v], acc[v]);
         if constexpr (MOL) {
           if (st.U0) {
             double base[5];
@@ -629,8 +639,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
       }
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        if (mid) dxy_prev[v] = dxy[v];
-        if (j >= z0) fz_prev[v] = fz[v];
+        if (mid) acc[v] = fma(-lamz, fz[v], dxy[v]);
         zp_prev[v] = zp[v];
         Wa[v] = Wb[v];
         Wb[v] = Wc[v];
@@ -651,21 +660,21 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
 
 // One grid: one workgroup per pencil, XCD-aware order.
 template <int N, int T>
-__global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepArgs a, long ntiles, int nseg) {
+__global__ __launch_bounds__(Tile<T>::NT, 2) void step_kernel(GridGeom g, StepArgs a, long ntiles, int plen) {
   __shared__ Smem<T> sm;
   const long tile_id = xcd_tile(blockIdx.x, ntiles);
   if (tile_id >= ntiles) return;
-  tile_step<N, T>(g, a.Uin, a.Uout, a.ws, a.dt, a.cfl, a.slot, tile_id, nseg, sm);
+  tile_step<N, T>(g, a.Uin, a.Uout, a.ws, a.dt, a.cfl, a.slot, tile_id, plen, sm);
 }
 
 // One method-of-lines stage of one grid (same launch shape as step_kernel).
 template <int N, int T>
 __global__ __launch_bounds__(Tile<T>::NT, 2) void stage_kernel(GridGeom g, StepArgs a, StageArgs st, long ntiles,
-                                                               int nseg) {
+                                                               int plen) {
   __shared__ Smem<T> sm;
   const long tile_id = xcd_tile(blockIdx.x, ntiles);
   if (tile_id >= ntiles) return;
-  tile_step<N, T, true>(g, a.Uin, a.Uout, a.ws, a.dt, a.cfl, a.slot, tile_id, nseg, sm, st);
+  tile_step<N, T, true>(g, a.Uin, a.Uout, a.ws, a.dt, a.cfl, a.slot, tile_id, plen, sm, st);
 }
 
 // Many grids in one persistent launch: workgroup w takes items w, w + G,
@@ -693,9 +702,9 @@ __global__ __launch_bounds__(256, 2) void batch_step_kernel(const BatchSim* __re
     const double* Uin = par ? d.U1 : d.U0;
     double* Uout = par ? d.U0 : d.U1;
     switch (d.nxb) {
-      case 8: tile_step<8, 8>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, nseg8, sm.s8); break;
-      case 16: tile_step<16, 16>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, nseg16, sm.s16); break;
-      default: tile_step<32, 16>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, nseg32, sm.s16); break;
+      case 8: tile_step<8, 8>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, 8 / nseg8, sm.s8); break;
+      case 16: tile_step<16, 16>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, 16 / nseg16, sm.s16); break;
+      default: tile_step<32, 16>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, 32 / nseg32, sm.s16); break;
     }
     __syncthreads();  // the next item reuses the LDS
   }
@@ -763,27 +772,28 @@ __global__ __launch_bounds__(256) void copy_kernel(const double* __restrict__ sr
 }
 
 template <int N, int T>
-hipError_t launch_step_t(const GridGeom& g, const StepArgs& a, const StageArgs* st, int nseg, hipStream_t s) {
-  const long nblk = (long)g.nb[0] * g.nb[1] * g.nb[2];
-  const long ntiles = nblk * (N / T) * (N / T) * nseg;
+hipError_t launch_step_t(const GridGeom& g, const StepArgs& a, const StageArgs* st, int plen, hipStream_t s) {
+  const long layers = (long)g.nb[2] * N / plen;
+  const long ntiles = (long)g.nb[0] * g.nb[1] * (N / T) * (N / T) * layers;
   const long grid = 8 * ((ntiles + 7) / 8);
   if (st)
     hipLaunchKernelGGL((stage_kernel<N, T>), dim3((unsigned)grid), dim3(Tile<T>::NT), 0, s, g, a, *st, ntiles,
-                       nseg);
+                       plen);
   else
-    hipLaunchKernelGGL((step_kernel<N, T>), dim3((unsigned)grid), dim3(Tile<T>::NT), 0, s, g, a, ntiles, nseg);
+    hipLaunchKernelGGL((step_kernel<N, T>), dim3((unsigned)grid), dim3(Tile<T>::NT), 0, s, g, a, ntiles, plen);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const StageArgs* st, int nseg,
+hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const StageArgs* st, int plen,
                        hipStream_t s) {
-  if (nseg < 1 || nxb % nseg || nxb / nseg < 2) return hipErrorInvalidValue;
+  const long nz = (long)g.nb[2] * nxb;
+  if (plen < 2 || plen > nz || nz % plen) return hipErrorInvalidValue;
   switch (nxb) {
-    case 8: return launch_step_t<8, 8>(g, a, st, nseg, s);
-    case 16: return launch_step_t<16, 16>(g, a, st, nseg, s);
-    case 32: return launch_step_t<32, 16>(g, a, st, nseg, s);
+    case 8: return launch_step_t<8, 8>(g, a, st, plen, s);
+    case 16: return launch_step_t<16, 16>(g, a, st, plen, s);
+    case 32: return launch_step_t<32, 16>(g, a, st, plen, s);
   }
   return hipErrorInvalidValue;
 }

@@ -68,6 +68,7 @@ SIGNATURES = {
     "hydro_counters": ([_HP, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
     "hydro_free_grid": ([_HP], ctypes.c_int),
     "hydro_set_pencils": ([_HP, ctypes.c_int], ctypes.c_int),
+    "hydro_set_pencil_planes": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_set_scheme": ([_HP, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "hydro_set_buffers": ([_HP, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "hydro_batch_work_bytes": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int], ctypes.c_size_t),
@@ -232,6 +233,9 @@ class Grid:
 
     def set_pencils(self, nseg: int) -> None:
         _check(lib().hydro_set_pencils(self.handle, int(nseg)))
+
+    def set_pencil_planes(self, planes: int) -> None:
+        _check(lib().hydro_set_pencil_planes(self.handle, int(planes)))
 
     def set_scheme(self, scheme: int, stage=None) -> None:
         """Time integration: SCHEME_MH (predictor-corrector), SCHEME_RK2 or

@@ -9,9 +9,11 @@ advanced).  Results are cached as JSON (``HYDRO_TUNE_CACHE``, default
 signature.
 
 Tunables:
-  * pencils per block column (1, 2 or 4 z pencils, one workgroup each) per
-    block size: more, shorter pencils fill the 256 CUs on small grids at the
-    cost of two extra halo planes per pencil;
+  * planes per z pencil (one workgroup each): for a single grid any divisor
+    of its z extent from nxb/4 to 8*nxb (pencils may span several blocks:
+    fewer halo planes re-read per updated plane on tall grids; shorter
+    pencils fill the 256 CUs on small grids); for batches 1, 2 or 4 pencils
+    per block column per block size;
   * persistent workgroups per CU for batches (1..3).
 """
 from __future__ import annotations
@@ -78,32 +80,36 @@ def _time(run, warm: int = 1, reps: int = 3, stream=None) -> float:
 
 
 def grid_signature(G: "hydro.Grid") -> str:
-    nb = G.nblk[0] * G.nblk[1] * G.nblk[2]
-    return f"grid|n{G.nxb}|blk{2 ** int(math.log2(nb))}"
+    nbxy = G.nblk[0] * G.nblk[1]
+    return f"grid|n{G.nxb}|bxy{2 ** int(math.log2(nbxy))}|bz{G.nblk[2]}"
+
+
+def pencil_candidates(G: "hydro.Grid") -> List[int]:
+    nz = G.nblk[2] * G.nxb
+    return [p for p in (G.nxb // 4, G.nxb // 2, G.nxb, 2 * G.nxb, 4 * G.nxb, 8 * G.nxb)
+            if p >= 2 and p <= nz and nz % p == 0]
 
 
 def tune_grid(G: "hydro.Grid", cfl: float = 0.8, apply: bool = True, use_cache: bool = True) -> int:
-    """Best pencils-per-column for this grid; applied to G unless apply=False."""
+    """Best planes per z pencil for this grid; applied to G unless apply=False."""
     key = f"{_arch()}|{grid_signature(G)}"
     cache = _load() if use_cache else {}
-    if key in cache:
-        best = int(cache[key]["nseg"])
+    if key in cache and "planes" in cache[key]:
+        best = int(cache[key]["planes"])
     else:
         C = _clone(G)
         times = {}
-        for nseg in (1, 2, 4):
-            if G.nxb // nseg < 2:
-                continue
-            C.set_pencils(nseg)
-            times[nseg] = _time(lambda: C.step_cfl(cfl), stream=C.stream)
+        for planes in pencil_candidates(G):
+            C.set_pencil_planes(planes)
+            times[planes] = _time(lambda: C.step_cfl(cfl), warm=2, reps=3, stream=C.stream)
         C.close()
         best = min(times, key=times.get)
         cache = _load()
-        cache[key] = {"nseg": best, "ms": times}
+        cache[key] = {"planes": best, "ms": {str(k): v for k, v in times.items()}}
         if use_cache:
             _store(cache)
     if apply:
-        G.set_pencils(best)
+        G.set_pencil_planes(best)
     return best
 
 

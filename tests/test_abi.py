@@ -116,6 +116,7 @@ def test_batch_null_arguments(L):
     assert L.hydro_batch_dts(None, None) == hydro.HYDRO_EINVAL
     assert L.hydro_batch_free(None) == hydro.HYDRO_OK
     assert L.hydro_set_pencils(None, 2) == hydro.HYDRO_EINVAL
+    assert L.hydro_set_pencil_planes(None, 16) == hydro.HYDRO_EINVAL
     assert L.hydro_set_buffers(None, None, None) == hydro.HYDRO_EINVAL
     assert L.hydro_set_scheme(None, hydro.SCHEME_RK2, None) == hydro.HYDRO_EINVAL
     assert L.hydro_copy_probe(None, None, 0, None) == hydro.HYDRO_OK

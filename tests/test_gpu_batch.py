@@ -95,6 +95,35 @@ def test_grid_pencils_bitwise_invariant(hy, nseg):
     assert np.array_equal(a, b) and da == db
 
 
+@pytest.mark.parametrize("planes", [8, 32, 64, 128])
+@pytest.mark.parametrize("case", ["kh", "outflow_n8"])
+def test_grid_pencil_planes_bitwise_invariant(hy, planes, case):
+    """Pencils spanning several blocks along z (or part of one) give the same
+    bits as one pencil per block, with periodic and outflow z boundaries."""
+    if case == "kh":
+        P = ics.kelvin_helmholtz(shape=(32, 32, 128), n=16)
+    else:
+        P = ics.sod(N=16, n=8, axis=2, shape=(16, 8, 128))
+    nz = P.nb[2] * P.n
+    if nz % planes:
+        pytest.skip("planes must divide the z extent")
+    a, da = alone(hy, P, 3)
+    G = hy.grid_for(P)
+    G.set_pencil_planes(planes)
+    for _ in range(3):
+        G.step_cfl(0.8)
+    assert np.array_equal(G.download(), a) and G.last_dt() == da
+
+
+def test_pencil_planes_argument_errors(hy):
+    P = ics.kelvin_helmholtz(shape=(32, 32, 48), n=16)
+    G = hy.grid_for(P)
+    for bad in (0, 1, 5, 96):
+        with pytest.raises(hy.HydroError):
+            G.set_pencil_planes(bad)
+    G.set_pencil_planes(48)
+
+
 def test_batch_active_mask(hy):
     sims = members(count=8, seed=10)
     grids = [hy.grid_for(P) for P in sims]

@@ -105,7 +105,9 @@ size_t hydro_work_bytes(const hydro_grid_desc *d);
 /* Validate the descriptor and create a handle.  The current state starts in
  * U.  Clears the workspace (stream-ordered).  Errors: HYDRO_EINVAL for any
  * invalid field (including nguard != 4, nxb not in {8,16,32}, NULL or
- * misaligned buffers, U == U_alt), HYDRO_ESIZE for a short workspace,
+ * misaligned buffers, U == U_alt, a z layer of blocks -- nblk[0]*nblk[1]
+ * blocks, 40*nxb^3 bytes each -- of 4 GiB or more: kernels address a layer
+ * with 32-bit byte offsets), HYDRO_ESIZE for a short workspace,
  * HYDRO_EDEVICE when the device is not gfx950 or a HIP call fails. */
 int hydro_init_grid(const hydro_grid_desc *d, hydro_grid **out);
 

@@ -87,6 +87,9 @@ int validate(const hydro_grid_desc* d) {
       return fail(HYDRO_EINVAL, "bc[%d] must be HYDRO_BC_PERIODIC or HYDRO_BC_OUTFLOW", a);
   }
   if (nblk > (1LL << 31) / 16) return fail(HYDRO_EINVAL, "too many blocks (%lld)", nblk);
+  const long long layer_bytes = (long long)d->nblk[0] * d->nblk[1] * 5 * d->nxb * d->nxb * d->nxb * 8;
+  if (layer_bytes >= (1LL << 32))
+    return fail(HYDRO_EINVAL, "a z layer of blocks (nblk[0]*nblk[1] blocks) must hold less than 4 GiB");
   if (!(std::isfinite(d->gamma) && d->gamma > 1.0)) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
   if (!(std::isfinite(d->small_p) && d->small_p >= 0.0)) return fail(HYDRO_EINVAL, "small_p must be finite and >= 0");
   if (!d->U || !d->U_alt) return fail(HYDRO_EINVAL, "state buffers must be non-NULL");

@@ -76,6 +76,14 @@ __device__ __forceinline__ void load_cons(const double* __restrict__ U, long off
   for (int v = 0; v < 5; ++v) u[v] = U[off + v * Layout<N>::VS];
 }
 
+// Same, from a workgroup-uniform base P and a 32-bit per-cell byte offset
+// (a scalar base plus a vector offset in the load itself).
+template <int N>
+__device__ __forceinline__ void load_cons_at(const double* P, unsigned xyb, double (&u)[5]) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) u[v] = *(const double*)((const char*)(P + v * Layout<N>::VS) + xyb);
+}
+
 // Maximum over a workgroup of a non-negative double, folded into *slot with
 // one atomicMax on the bit pattern.  red must hold one entry per wavefront.
 __device__ __forceinline__ void wg_max_to(double v, unsigned long long* red, unsigned long long* slot) {
@@ -403,19 +411,19 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   const int rside = role / T;                           // ring side (valid when is_ring)
   // offsets of plane 0 of the own column and of the second item, for the
   // planes that lie inside the block (z halo planes go through the map)
-  // offsets (variable 0) at global plane 0 of the own column and of the
-  // second item; a plane k inside the domain adds zoff(k), planes beyond the
-  // z boundaries go through the boundary map
-  const long BZS = (long)g.nb[0] * g.nb[1] * Layout<N>::BS;  // block stride along z
-  auto zoff = [&](int k) -> long { return (long)((unsigned)k / N) * BZS + (long)((unsigned)k % N) * PS; };
-  const long own0 = Layout<N>::at(bxy, lx0 + cx, ly0 + cy, 0);
-  const long sec0 = (is_ring || is_extra) ? cell_offset<N>(g, X0 + sx2, Y0 + sy2, 0) : 0;
-  auto own_at = [&](int k) -> long {
-    return (k >= 0 && k < NZ) ? own0 + zoff(k) : cell_offset<N>(g, X0 + cx, Y0 + cy, k);
+  // Addressing: a cell of global plane k sits at plane(U, k)[xy + v*VS],
+  // where plane(U, k) is uniform over the workgroup (the plane's offset in
+  // the z layer of blocks that holds it, after the z boundary map) and xy is
+  // the cell's 32-bit offset inside its z layer (x/y boundary map applied
+  // once, below).  Loads then take a scalar base and a vector offset.
+  const long BZS = (long)g.nb[0] * g.nb[1] * Layout<N>::BS;  // size of a z layer of blocks
+  auto plane_off = [&](int k) -> long {
+    const int K = map_axis(k, NZ, g.bc[2]);
+    return (long)((unsigned)K / N) * BZS + (long)((unsigned)K % N) * PS;
   };
-  auto sec_at = [&](int k) -> long {
-    return (k >= 0 && k < NZ) ? sec0 + zoff(k) : cell_offset<N>(g, X0 + sx2, Y0 + sy2, k);
-  };
+  // (byte offsets: a z layer of blocks is below 4 GiB, checked on the host)
+  const unsigned own_xy = 8u * (unsigned)Layout<N>::at(bxy, lx0 + cx, ly0 + cy, 0);
+  const unsigned sec_xy = (is_ring || is_extra) ? 8u * (unsigned)cell_offset<N>(g, X0 + sx2, Y0 + sy2, 0) : 0u;
 
   double Wa[5], Wb[5], Wc[5];
   double un_next[5], u2_next[5];
@@ -434,21 +442,21 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   // prologue: planes z0-2, z0-1 of the own column, prefetch plane z0
   if (inner) {
     double u[5], tmp;
-    load_cons<N>(Uin, own_at(z0 - 2), u);
+    load_cons_at<N>(Uin + plane_off(z0 - 2), own_xy, u);
     prim(u, gamma, g.small_p, Wa, tmp);
-    load_cons<N>(Uin, own_at(z0 - 1), u);
+    load_cons_at<N>(Uin + plane_off(z0 - 1), own_xy, u);
     prim(u, gamma, g.small_p, Wb, tmp);
-    load_cons<N>(Uin, own0 + zoff(z0), un_next);
+    load_cons_at<N>(Uin + plane_off(z0), own_xy, un_next);
   }
   if (is_ring) {
     double u[5], w[5], tmp;
-    load_cons<N>(Uin, sec_at(z0 - 1), u);
+    load_cons_at<N>(Uin + plane_off(z0 - 1), sec_xy, u);
     prim(u, gamma, g.small_p, w, tmp);
 #pragma unroll
     for (int v = 0; v < 5; ++v) sm.sRing[(z0 + 2) % 3][v][ring_id] = w[v];
-    load_cons<N>(Uin, sec0 + zoff(z0), u2_next);
+    load_cons_at<N>(Uin + plane_off(z0), sec_xy, u2_next);
   }
-  if (is_extra) load_cons<N>(Uin, sec0 + zoff(z0), u2_next);
+  if (is_extra) load_cons_at<N>(Uin + plane_off(z0), sec_xy, u2_next);
 
   for (int j = z0 - 1; j <= z1; ++j) {
     const bool mid = (j >= z0) && (j < z1);
@@ -458,7 +466,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
       double inv_unused;
       const int fl = prim(un_next, gamma, g.small_p, Wc, inv_unused);
       if (j + 1 >= z0 && j + 1 < z1) n_floor += fl;
-      if (j + 2 <= z1 + 1) load_cons<N>(Uin, own_at(j + 2), un_next);
+      if (j + 2 <= z1 + 1) load_cons_at<N>(Uin + plane_off(j + 2), own_xy, un_next);
 #pragma unroll
       for (int v = 0; v < 5; ++v) sm.sW[v][cidx] = Wb[v];
     }
@@ -471,14 +479,14 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         sm.sRing[sl_p][v][ring_id] = w[v];
         sm.sW[v][sidx2] = sm.sRing[sl_0][v][ring_id];
       }
-      if (j + 2 <= z1 + 1) load_cons<N>(Uin, sec_at(j + 2), u2_next);
+      if (j + 2 <= z1 + 1) load_cons_at<N>(Uin + plane_off(j + 2), sec_xy, u2_next);
     }
     if (is_extra && mid) {
       double w[5], tmp;
       prim(u2_next, gamma, g.small_p, w, tmp);
 #pragma unroll
       for (int v = 0; v < 5; ++v) sm.sW[v][sidx2] = w[v];
-      if (j + 1 < z1) load_cons<N>(Uin, sec0 + zoff(j + 1), u2_next);
+      if (j + 1 < z1) load_cons_at<N>(Uin + plane_off(j + 1), sec_xy, u2_next);
     }
     __syncthreads();
 
@@ -613,21 +621,21 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
           dxy[v] = lamx * (sm.sFx[v][qx + 1] - sm.sFx[v][qx]) + lamy * (sm.sFy[v][qy + T] - sm.sFy[v][qy]);
       }
       if (j >= z0 + 1) {
-        const long off = own0 + zoff(j - 1);
+        const long off = plane_off(j - 1);
         double uold[5], un[5];
-        load_cons<N>(Uin, off, uold);
+        load_cons_at<N>(Uin + off, own_xy, uold);
 #pragma unroll
         for (int v = 0; v < 5; ++v) un[v] = uold[v] - fma(lamz, fz[v], acc[v]);
         if constexpr (MOL) {
           if (st.U0) {
             double base[5];
-            load_cons<N>(st.U0, off, base);
+            load_cons_at<N>(st.U0 + off, own_xy, base);
 #pragma unroll
             for (int v = 0; v < 5; ++v) un[v] = st.a0 * base[v] + st.a1 * un[v];
           }
         }
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Uout[off + v * VS] = un[v];
+        for (int v = 0; v < 5; ++v) *(double*)((char*)(Uout + off + v * VS) + own_xy) = un[v];
         bool good = un[0] > 0.0 && un[4] > 0.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) good = good && isfinite(un[v]);

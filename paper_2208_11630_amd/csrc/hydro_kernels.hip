@@ -430,11 +430,13 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   // acc: plane j-1's x/y flux divergence minus its lower z flux, carried to
   // the next plane, whose z flux completes the update of plane j-1
   double zp_prev[5], acc[5];
+  double pend[5];     // the last updated plane, stored in the next plane's predictor phase
+  long pend_off = -1;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     Wa[v] = Wb[v] = Wc[v] = 0.0;
     un_next[v] = u2_next[v] = 0.0;
-    zp_prev[v] = acc[v] = 0.0;
+    zp_prev[v] = acc[v] = pend[v] = 0.0;
   }
   int n_floor = 0, n_fb = 0, n_bad = 0;
   double smax = 0.0;
@@ -461,16 +463,15 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   for (int j = z0 - 1; j <= z1; ++j) {
     const bool mid = (j >= z0) && (j < z1);
     const int sl_m = (j + 5) % 3, sl_0 = (j + 3) % 3, sl_p = (j + 4) % 3;  // ring slots of planes j-1, j, j+1
-    // -- own column: plane j+1 from the prefetch, prefetch plane j+2, publish plane j
+    // -- own column: plane j+1 from the prefetch, publish plane j; second
+    // item: ring cell window (planes j..j+1) or halo cell (plane j)
     if (inner) {
       double inv_unused;
       const int fl = prim(un_next, gamma, g.small_p, Wc, inv_unused);
       if (j + 1 >= z0 && j + 1 < z1) n_floor += fl;
-      if (j + 2 <= z1 + 1) load_cons_at<N>(Uin + plane_off(j + 2), own_xy, un_next);
 #pragma unroll
       for (int v = 0; v < 5; ++v) sm.sW[v][cidx] = Wb[v];
     }
-    // -- second item: ring cell window (planes j..j+1) or halo cell (plane j)
     if (is_ring) {
       double w[5], tmp;
       prim(u2_next, gamma, g.small_p, w, tmp);
@@ -479,16 +480,27 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         sm.sRing[sl_p][v][ring_id] = w[v];
         sm.sW[v][sidx2] = sm.sRing[sl_0][v][ring_id];
       }
-      if (j + 2 <= z1 + 1) load_cons_at<N>(Uin + plane_off(j + 2), sec_xy, u2_next);
     }
     if (is_extra && mid) {
       double w[5], tmp;
       prim(u2_next, gamma, g.small_p, w, tmp);
 #pragma unroll
       for (int v = 0; v < 5; ++v) sm.sW[v][sidx2] = w[v];
-      if (j + 1 < z1) load_cons_at<N>(Uin + plane_off(j + 1), sec_xy, u2_next);
     }
+    // -- prefetches for the next planes, issued only after the current
+    // values are consumed: they then land in the same registers, and nothing
+    // waits for them until the next plane
+    __builtin_amdgcn_sched_barrier(0);
+    if (inner && j + 2 <= z1 + 1) load_cons_at<N>(Uin + plane_off(j + 2), own_xy, un_next);
+    if (is_ring && j + 2 <= z1 + 1) load_cons_at<N>(Uin + plane_off(j + 2), sec_xy, u2_next);
+    if (is_extra && mid && j + 1 < z1) load_cons_at<N>(Uin + plane_off(j + 1), sec_xy, u2_next);
     __syncthreads();
+
+    // -- the previous plane's update goes out now
+    if (inner && pend_off >= 0) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) *(double*)((char*)(Uout + pend_off + v * VS) + own_xy) = pend[v];
+    }
 
     // -- predictor: own cell (every plane), ring cell (pencil planes)
     double xm[5], ym[5], zm[5], zp[5];
@@ -609,6 +621,16 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         for (int v = 0; v < 5; ++v) fo[v * TL::NQ] = F[v];
       }
     }
+    // the old state of plane j-1 (and the base state of a stage) is fetched
+    // before the barrier, so its latency overlaps the wait
+    const long off_u = plane_off(j - 1);
+    double uold[5], base[5];
+    if (inner && j >= z0 + 1) {
+      load_cons_at<N>(Uin + off_u, own_xy, uold);
+      if constexpr (MOL) {
+        if (st.U0) load_cons_at<N>(st.U0 + off_u, own_xy, base);
+      }
+    }
     __syncthreads();
 
     // -- update plane j-1, carry plane j's divergence
@@ -621,21 +643,19 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
           dxy[v] = lamx * (sm.sFx[v][qx + 1] - sm.sFx[v][qx]) + lamy * (sm.sFy[v][qy + T] - sm.sFy[v][qy]);
       }
       if (j >= z0 + 1) {
-        const long off = plane_off(j - 1);
-        double uold[5], un[5];
-        load_cons_at<N>(Uin + off, own_xy, uold);
+        double un[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) un[v] = uold[v] - fma(lamz, fz[v], acc[v]);
         if constexpr (MOL) {
           if (st.U0) {
-            double base[5];
-            load_cons_at<N>(st.U0 + off, own_xy, base);
 #pragma unroll
             for (int v = 0; v < 5; ++v) un[v] = st.a0 * base[v] + st.a1 * un[v];
           }
         }
+        // stored early in the next plane (after its loads are awaited), so
+        // the wait at the top of the plane does not cover these stores
 #pragma unroll
-        for (int v = 0; v < 5; ++v) *(double*)((char*)(Uout + off + v * VS) + own_xy) = un[v];
+        for (int v = 0; v < 5; ++v) pend[v] = un[v];
         bool good = un[0] > 0.0 && un[4] > 0.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) good = good && isfinite(un[v]);
@@ -653,6 +673,11 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         Wb[v] = Wc[v];
       }
     }
+    pend_off = (j >= z0 + 1) ? off_u : -1;
+  }
+  if (inner && pend_off >= 0) {  // the pencil's last plane
+#pragma unroll
+    for (int v = 0; v < 5; ++v) *(double*)((char*)(Uout + pend_off + v * VS) + own_xy) = pend[v];
   }
 
   if (n_floor) atomicAdd(&sm.sCnt[0], n_floor);

@@ -85,6 +85,14 @@ def lib():
         L.oracle_stage_block.restype = None
         L.oracle_step_rk.argtypes = [gp, dp, dp, ctypes.c_double, ctypes.c_int, lp]
         L.oracle_step_rk.restype = ctypes.c_int
+        L.oracle_ctu_block.argtypes = [gp, dp, ctypes.c_long, dp, ctypes.c_double, lp]
+        L.oracle_ctu_block.restype = None
+        L.oracle_step_ctu.argtypes = [gp, dp, dp, ctypes.c_double, lp]
+        L.oracle_step_ctu.restype = None
+        L.oracle_max_signal_dir.argtypes = [gp, dp, ctypes.c_long, ctypes.c_long]
+        L.oracle_max_signal_dir.restype = ctypes.c_double
+        L.oracle_dt_ctu.argtypes = [gp, dp, ctypes.c_double]
+        L.oracle_dt_ctu.restype = ctypes.c_double
         L.oracle_max_signal.argtypes = [gp, dp, ctypes.c_long, ctypes.c_long]
         L.oracle_max_signal.restype = ctypes.c_double
         L.oracle_dt.argtypes = [gp, dp, ctypes.c_double]
@@ -234,6 +242,23 @@ def stage_block(g: Grid, U: np.ndarray, b: int, dt: float, U0: np.ndarray = None
     return out, np.array(list(cnt), dtype=np.int64)
 
 
+def step_ctu(g: Grid, U: np.ndarray, dt: float):
+    """One corner-transport-upwind step: returns (U_new, counters)."""
+    g.check(U)
+    out = U.copy()
+    cnt = (ctypes.c_long * 3)(0, 0, 0)
+    gc = g.c()
+    lib().oracle_step_ctu(ctypes.byref(gc), _dptr(U), _dptr(out), float(dt), cnt)
+    return out, np.array(list(cnt), dtype=np.int64)
+
+
+def dt_ctu(g: Grid, U: np.ndarray, cfl: float) -> float:
+    """dt of the per-direction CFL rule: cfl / max over cells and d of (|u_d|+c)/dx_d."""
+    g.check(U)
+    gc = g.c()
+    return lib().oracle_dt_ctu(ctypes.byref(gc), _dptr(U), float(cfl))
+
+
 def max_signal(g: Grid, U: np.ndarray) -> float:
     g.check(U)
     gc = g.c()
@@ -246,16 +271,17 @@ def dt(g: Grid, U: np.ndarray, cfl: float) -> float:
     return lib().oracle_dt(ctypes.byref(gc), _dptr(U), float(cfl))
 
 
-def run(g: Grid, U: np.ndarray, nsteps: int, cfl: float = 0.8, callback=None, rk: int = 0):
+def run(g: Grid, U: np.ndarray, nsteps: int, cfl: float = 0.8, callback=None, rk: int = 0, ctu: bool = False):
     """n repetitions of (dt = CFL/max signal; step(dt)); returns (U, dts, counters).
-    rk = 2 or 3 takes SSP Runge-Kutta steps instead of predictor-corrector ones."""
+    rk = 2 or 3 takes SSP Runge-Kutta steps instead of predictor-corrector
+    ones; ctu takes corner-transport-upwind steps with the per-direction rule."""
     dts = []
     cnt = np.zeros(3, dtype=np.int64)
     for s in range(nsteps):
-        d = dt(g, U, cfl)
+        d = dt_ctu(g, U, cfl) if ctu else dt(g, U, cfl)
         if not d > 0:
             raise FloatingPointError("non-positive or non-finite dt at step %d" % s)
-        U, c = step_rk(g, U, d, rk) if rk else step(g, U, d)
+        U, c = step_ctu(g, U, d) if ctu else (step_rk(g, U, d, rk) if rk else step(g, U, d))
         cnt += c
         dts.append(d)
         if callback is not None:

@@ -403,6 +403,215 @@ int oracle_step_rk(const oracle_grid *g, double *U, double *Unew, double dt, int
   return 0;
 }
 
+/* ---- f2: corner-transport-upwind (CTU) unsplit step ----------------------
+ * §2.2 Hydrodynamics names the unsplit predictor-corrector solver; its
+ * corner-coupled form is taken here: the three-dimensional corner transport
+ * upwind scheme with twelve Riemann solves per cell (Colella 1990; Saltzman
+ * 1994; the hydrodynamic part of Gardiner & Stone 2008), on the same
+ * ingredients (EOS, van Leer slopes on primitives, HLLC):
+ *   1. normal predictor, each direction d alone: W_d = W - (lam_d/2) A_d D_d,
+ *      face states W_d -+ D_d/2 (low / high face of the cell); first-order
+ *      fallback when any of the six has rho <= 0 or p <= 0;
+ *   2. 1-D fluxes F1_d at every d-face from the normal face states;
+ *   3. corner states: the conserved normal face state of direction d minus
+ *      lam_t/3 times the difference of F1_t over the cell, for each
+ *      transverse t; corner fluxes F_{d|t} from them;
+ *   4. final states: the conserved normal face state minus lam_t/2 times the
+ *      difference of F_{t|u} and lam_u/2 times that of F_{u|t} over the cell
+ *      ({t, u} the transverse pair); final fluxes;
+ *   5. the conservative update.
+ * A corrected state with rho <= 0 or p <= 0 falls back to the normal face
+ * state it came from (counted as a fallback).  dt uses the per-direction
+ * CFL rule (oracle_dt_ctu). */
+
+/* Primitive of a corrected conserved state; 0 when it is not physical. */
+static int corrected_prim(const double U[5], double gamma, double W[5]) {
+  double rho = U[0];
+  if (!(rho > 0.0)) return 0;
+  double u = U[1] / rho, v = U[2] / rho, w = U[3] / rho;
+  double p = (gamma - 1.0) * (U[4] - 0.5 * rho * ((u * u + v * v) + w * w));
+  if (!(p > 0.0)) return 0;
+  W[0] = rho;
+  W[1] = u;
+  W[2] = v;
+  W[3] = w;
+  W[4] = p;
+  return 1;
+}
+
+void oracle_ctu_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+                      long cnt[ORACLE_NCNT]) {
+  const int n = g->n;
+  const double gamma = g->gamma;
+  const double lam[3] = {dt / g->dx[0], dt / g->dx[1], dt / g->dx[2]};
+  const size_t bd = oracle_block_doubles(g);
+  const double *Ub = U + (size_t)b * bd;
+  const int m = n + 2;                 /* cells -1..n per axis */
+  const size_t nm = (size_t)m * m * m;
+  /* transverse pairs: for direction d, t = tr[d][0], u = tr[d][1] */
+  const int tr[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+  double *Wf = (double *)malloc(sizeof(double) * 30 * nm);   /* normal face states [d][side][v], side 0 low 1 high */
+  double *Uf = (double *)malloc(sizeof(double) * 30 * nm);   /* the same, conserved */
+  double *F1 = (double *)malloc(sizeof(double) * 15 * nm);   /* 1-D flux at the low d-face of a cell [d][v] */
+  double *Fc = (double *)malloc(sizeof(double) * 30 * nm);   /* corner flux F_{d|t} at the low d-face [d][k][v], t = tr[d][k] */
+
+#define CI(i, j, k) ((((size_t)((k) + 1) * m + (size_t)((j) + 1)) * m + (size_t)((i) + 1)))
+  /* 1. normal predictor on cells -1..n */
+  for (int k = -1; k <= n; ++k)
+    for (int j = -1; j <= n; ++j)
+      for (int i = -1; i <= n; ++i) {
+        const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        double W[5], Wm[5], Wq[5], Sl[3][5];
+        double Uc[5];
+        for (int v = 0; v < 5; ++v) Uc[v] = Ub[at(g, v, i, j, k)];
+        int fl = oracle_cons_to_prim(Uc, gamma, g->small_p, W);
+        int interior = i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n;
+        if (fl && interior) cnt[ORACLE_CNT_FLOOR]++;
+        for (int d = 0; d < 3; ++d) {
+          double Um_[5], Uq_[5];
+          for (int v = 0; v < 5; ++v) {
+            Um_[v] = Ub[at(g, v, i - off[d][0], j - off[d][1], k - off[d][2])];
+            Uq_[v] = Ub[at(g, v, i + off[d][0], j + off[d][1], k + off[d][2])];
+          }
+          oracle_cons_to_prim(Um_, gamma, g->small_p, Wm);
+          oracle_cons_to_prim(Uq_, gamma, g->small_p, Wq);
+          for (int v = 0; v < 5; ++v) Sl[d][v] = oracle_van_leer(W[v] - Wm[v], Wq[v] - W[v]);
+        }
+        double *wf = Wf + 30 * CI(i, j, k);
+        int bad = 0;
+        for (int d = 0; d < 3; ++d) {
+          double A[5], Wt[5];
+          jacobian_times(W, d, gamma, Sl[d], A);
+          for (int v = 0; v < 5; ++v) Wt[v] = W[v] - 0.5 * lam[d] * A[v];
+          for (int v = 0; v < 5; ++v) {
+            wf[(2 * d + 0) * 5 + v] = Wt[v] - 0.5 * Sl[d][v];
+            wf[(2 * d + 1) * 5 + v] = Wt[v] + 0.5 * Sl[d][v];
+          }
+          for (int sd = 0; sd < 2; ++sd)
+            if (!(wf[(2 * d + sd) * 5 + 0] > 0.0) || !(wf[(2 * d + sd) * 5 + 4] > 0.0)) bad = 1;
+        }
+        if (bad) {
+          for (int q = 0; q < 6; ++q)
+            for (int v = 0; v < 5; ++v) wf[q * 5 + v] = W[v];
+          if (interior) cnt[ORACLE_CNT_FALLBACK]++;
+        }
+        for (int q = 0; q < 6; ++q) prim_to_cons(wf + q * 5, gamma, Uf + 30 * CI(i, j, k) + q * 5);
+      }
+
+  /* 2. 1-D fluxes at d-faces between cells c - e_d and c, c_d in 0..n */
+  for (int d = 0; d < 3; ++d)
+    for (int k = -1; k <= n; ++k)
+      for (int j = -1; j <= n; ++j)
+        for (int i = -1; i <= n; ++i) {
+          const int c[3] = {i, j, k};
+          if (c[d] < 0) continue;
+          const int li = i - (d == 0), lj = j - (d == 1), lk = k - (d == 2);
+          oracle_hllc(Wf + 30 * CI(li, lj, lk) + (2 * d + 1) * 5, Wf + 30 * CI(i, j, k) + (2 * d + 0) * 5, d, gamma,
+                      F1 + 15 * CI(i, j, k) + 5 * d);
+        }
+
+  /* 3. corner states and corner fluxes F_{d|t} at d-faces with c_t in 0..n-1 */
+  for (int d = 0; d < 3; ++d)
+    for (int q = 0; q < 2; ++q) {
+      const int t = tr[d][q];
+      for (int k = -1; k <= n; ++k)
+        for (int j = -1; j <= n; ++j)
+          for (int i = -1; i <= n; ++i) {
+            const int c[3] = {i, j, k};
+            if (c[d] < 0 || c[t] < 0 || c[t] > n - 1) continue;
+            double Wside[2][5];
+            for (int sd = 0; sd < 2; ++sd) {   /* sd 0: the low cell's high face, 1: this cell's low face */
+              const int ci = i - (sd == 0 && d == 0), cj = j - (sd == 0 && d == 1), ck = k - (sd == 0 && d == 2);
+              const int face = sd == 0 ? 1 : 0;
+              const size_t cc = CI(ci, cj, ck);
+              const size_t ch = CI(ci + (t == 0), cj + (t == 1), ck + (t == 2)); /* cell above in t */
+              double Ucor[5];
+              for (int v = 0; v < 5; ++v)
+                Ucor[v] = Uf[30 * cc + (2 * d + face) * 5 + v] -
+                          (lam[t] / 3.0) * (F1[15 * ch + 5 * t + v] - F1[15 * cc + 5 * t + v]);
+              if (!corrected_prim(Ucor, gamma, Wside[sd])) {
+                for (int v = 0; v < 5; ++v) Wside[sd][v] = Wf[30 * cc + (2 * d + face) * 5 + v];
+                cnt[ORACLE_CNT_FALLBACK]++;
+              }
+            }
+            oracle_hllc(Wside[0], Wside[1], d, gamma, Fc + 30 * CI(i, j, k) + (2 * d + q) * 5);
+          }
+    }
+
+  /* 4. final states and fluxes at the interior faces; 5. update */
+  double *Ff = (double *)malloc(sizeof(double) * 15 * nm);
+  for (int d = 0; d < 3; ++d) {
+    const int t = tr[d][0], u = tr[d][1];
+    for (int k = 0; k <= n; ++k)
+      for (int j = 0; j <= n; ++j)
+        for (int i = 0; i <= n; ++i) {
+          const int c[3] = {i, j, k};
+          if (c[t] > n - 1 || c[u] > n - 1) continue;
+          double Wside[2][5];
+          for (int sd = 0; sd < 2; ++sd) {
+            const int ci = i - (sd == 0 && d == 0), cj = j - (sd == 0 && d == 1), ck = k - (sd == 0 && d == 2);
+            const int face = sd == 0 ? 1 : 0;
+            const size_t cc = CI(ci, cj, ck);
+            const size_t ct = CI(ci + (t == 0), cj + (t == 1), ck + (t == 2));
+            const size_t cu = CI(ci + (u == 0), cj + (u == 1), ck + (u == 2));
+            /* index of u among t's transverse pair, and of t among u's */
+            const int kt = tr[t][0] == u ? 0 : 1;
+            const int ku = tr[u][0] == t ? 0 : 1;
+            double Ufin[5];
+            for (int v = 0; v < 5; ++v)
+              Ufin[v] = Uf[30 * cc + (2 * d + face) * 5 + v] -
+                        0.5 * (lam[t] * (Fc[30 * ct + (2 * t + kt) * 5 + v] - Fc[30 * cc + (2 * t + kt) * 5 + v]) +
+                               lam[u] * (Fc[30 * cu + (2 * u + ku) * 5 + v] - Fc[30 * cc + (2 * u + ku) * 5 + v]));
+            if (!corrected_prim(Ufin, gamma, Wside[sd])) {
+              for (int v = 0; v < 5; ++v) Wside[sd][v] = Wf[30 * cc + (2 * d + face) * 5 + v];
+              cnt[ORACLE_CNT_FALLBACK]++;
+            }
+          }
+          oracle_hllc(Wside[0], Wside[1], d, gamma, Ff + 15 * CI(i, j, k) + 5 * d);
+        }
+  }
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        const size_t c0 = CI(i, j, k);
+        const size_t cx = CI(i + 1, j, k), cy = CI(i, j + 1, k), cz = CI(i, j, k + 1);
+        double Un[5];
+        for (int v = 0; v < 5; ++v) {
+          double div = (lam[0] * (Ff[15 * cx + v] - Ff[15 * c0 + v]) +
+                        lam[1] * (Ff[15 * cy + 5 + v] - Ff[15 * c0 + 5 + v])) +
+                       lam[2] * (Ff[15 * cz + 10 + v] - Ff[15 * c0 + 10 + v]);
+          Un[v] = Ub[at(g, v, i, j, k)] - div;
+          Uo[at(g, v, i, j, k)] = Un[v];
+        }
+        int ok = Un[0] > 0.0 && Un[4] > 0.0;
+        for (int v = 0; v < 5; ++v) ok = ok && isfinite(Un[v]);
+        if (!ok) cnt[ORACLE_CNT_NONPHYS]++;
+      }
+#undef CI
+  free(Wf);
+  free(Uf);
+  free(F1);
+  free(Fc);
+  free(Ff);
+}
+
+void oracle_step_ctu(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]) {
+  long nblk = (long)g->nb[0] * g->nb[1] * g->nb[2];
+  oracle_fill_guards(g, U);
+  long c0 = 0, c1 = 0, c2 = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : c0, c1, c2)
+  for (long b = 0; b < nblk; ++b) {
+    long c[ORACLE_NCNT] = {0, 0, 0};
+    oracle_ctu_block(g, U, b, Unew + (size_t)b * oracle_block_doubles(g), dt, c);
+    c0 += c[0];
+    c1 += c[1];
+    c2 += c[2];
+  }
+  cnt[ORACLE_CNT_FLOOR] += c0;
+  cnt[ORACLE_CNT_FALLBACK] += c1;
+  cnt[ORACLE_CNT_NONPHYS] += c2;
+}
+
 /* ---- a6: CFL signal speed and dt ---------------------------------------- */
 
 double oracle_max_signal(const oracle_grid *g, const double *U, long b0, long b1) {
@@ -426,6 +635,40 @@ double oracle_max_signal(const oracle_grid *g, const double *U, long b0, long b1
         }
   }
   return bad ? NAN : smax;
+}
+
+/* max over interior cells and directions of (|u_d| + c)/dx_d: the
+ * per-direction CFL rule of the CTU step. */
+double oracle_max_signal_dir(const oracle_grid *g, const double *U, long b0, long b1) {
+  const int n = g->n;
+  const size_t bd = oracle_block_doubles(g);
+  double smax = 0.0;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(max : smax) reduction(| : bad)
+  for (long b = b0; b < b1; ++b) {
+    const double *Ub = U + (size_t)b * bd;
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double Uc[5], W[5];
+          for (int v = 0; v < 5; ++v) Uc[v] = Ub[at(g, v, i, j, k)];
+          oracle_cons_to_prim(Uc, g->gamma, g->small_p, W);
+          double c = sqrt(g->gamma * W[4] / W[0]);
+          for (int d = 0; d < 3; ++d) {
+            double s = (fabs(W[1 + d]) + c) / g->dx[d];
+            if (!isfinite(s)) bad = 1;
+            else if (s > smax) smax = s;
+          }
+        }
+  }
+  return bad ? NAN : smax;
+}
+
+double oracle_dt_ctu(const oracle_grid *g, const double *U, double cfl) {
+  long nblk = (long)g->nb[0] * g->nb[1] * g->nb[2];
+  double s = oracle_max_signal_dir(g, U, 0, nblk);
+  if (!(s > 0.0) || !isfinite(s)) return -1.0;
+  return cfl / s;
 }
 
 double oracle_dt(const oracle_grid *g, const double *U, double cfl) {

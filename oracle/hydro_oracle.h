@@ -104,10 +104,24 @@ void oracle_stage_block(const oracle_grid *g, const double *U, long b, double *U
  * -2 when the stage buffers cannot be allocated. */
 int oracle_step_rk(const oracle_grid *g, double *U, double *Unew, double dt, int order, long cnt[ORACLE_NCNT]);
 
+/* One corner-transport-upwind step of block b (U's guards filled; Uo is
+ * block b's storage): normal predictor, 1-D fluxes, corner states with
+ * lam/3 transverse corrections and their fluxes, final states with lam/2
+ * cross corrections, final fluxes, update (twelve HLLC solves per cell).
+ * Counters: floors and normal-state fallbacks on interior cells, plus every
+ * corrected state that fell back to its normal state. */
+void oracle_ctu_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+                      long cnt[ORACLE_NCNT]);
+/* One CTU step of the whole grid (fills U's guards first). */
+void oracle_step_ctu(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]);
+
 /* max over interior cells of sum_d (|u_d| + c)/dx_d; the block range [b0,b1). */
 double oracle_max_signal(const oracle_grid *g, const double *U, long b0, long b1);
 /* dt = cfl / max signal over all blocks; returns -1 when the maximum is not positive and finite. */
 double oracle_dt(const oracle_grid *g, const double *U, double cfl);
+/* Per-direction rule of the CTU step: max over cells and d of (|u_d| + c)/dx_d, and cfl / that. */
+double oracle_max_signal_dir(const oracle_grid *g, const double *U, long b0, long b1);
+double oracle_dt_ctu(const oracle_grid *g, const double *U, double cfl);
 
 #ifdef __cplusplus
 }

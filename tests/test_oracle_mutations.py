@@ -28,8 +28,14 @@ MUTATIONS = {
     "star_energy_sign": ("(Sstar + p / (rho * (S - un)))", "(Sstar - p / (rho * (S - un)))"),
     "star_tangential_dropped": ("Us[2] = factor * W[2];", "Us[2] = factor;"),
     "energy_flux_drops_p": ("F[4] = un * (E + W[4]);", "F[4] = un * E;"),
-    "update_sign": ("Un[v] = Ub[at(g, v, i, j, k)] - div;", "Un[v] = Ub[at(g, v, i, j, k)] + div;"),
-    "lambda_z_uses_dy": ("dt / g->dx[2]}", "dt / g->dx[1]}"),
+    "update_sign": ("Un[v] = Ub[at(g, v, i, j, k)] - div;\n          if (U0b)",
+                    "Un[v] = Ub[at(g, v, i, j, k)] + div;\n          if (U0b)"),
+    "ctu_update_sign": ("Un[v] = Ub[at(g, v, i, j, k)] - div;\n          Uo[at(g, v, i, j, k)] = Un[v];\n        }\n        int ok",
+                        "Un[v] = Ub[at(g, v, i, j, k)] + div;\n          Uo[at(g, v, i, j, k)] = Un[v];\n        }\n        int ok"),
+    "lambda_z_uses_dy": ("dt / g->dx[2]};\n  const size_t bd = oracle_block_doubles(g);\n  const double *Ub = U + (size_t)b * bd;\n  /* Cells that need",
+                         "dt / g->dx[1]};\n  const size_t bd = oracle_block_doubles(g);\n  const double *Ub = U + (size_t)b * bd;\n  /* Cells that need"),
+    "ctu_lambda_z_uses_dy": ("dt / g->dx[2]};\n  const size_t bd = oracle_block_doubles(g);\n  const double *Ub = U + (size_t)b * bd;\n  const int m",
+                             "dt / g->dx[1]};\n  const size_t bd = oracle_block_doubles(g);\n  const double *Ub = U + (size_t)b * bd;\n  const int m"),
     "outflow_clamp_wrong_end": ("if (I > N - 1) return N - 1;", "if (I > N - 1) return N - 2;"),
     "periodic_wrap_off_by_one": ("return r < 0 ? r + N : r;", "return r < 0 ? r + N - 1 : r;"),
     "dt_drops_sound_speed_in_z": ("(fabs(W[3]) + c) / g->dx[2]", "fabs(W[3]) / g->dx[2]"),
@@ -42,6 +48,13 @@ MUTATIONS = {
                               "Un[v] = a1 * U0b[at(g, v, i, j, k)] + a0 * Un[v];"),
     "stage_uses_predictor": ("Uo + (size_t)b * bd, dt, 0,", "Uo + (size_t)b * bd, dt, 1,"),
     "stage_skips_guard_fill": ("oracle_fill_guards(g, Us);", ""),
+    "ctu_corner_weight_half": ("(lam[t] / 3.0)", "(lam[t] / 2.0)"),
+    "ctu_final_weight_one": ("0.5 * (lam[t] * (Fc[", "1.0 * (lam[t] * (Fc["),
+    "ctu_final_cross_index": ("const int kt = tr[t][0] == u ? 0 : 1;", "const int kt = tr[t][0] == u ? 1 : 0;"),
+    "ctu_corner_uses_own_direction": ("(F1[15 * ch + 5 * t + v] - F1[15 * cc + 5 * t + v])",
+                                      "(F1[15 * ch + 5 * d + v] - F1[15 * cc + 5 * d + v])"),
+    "ctu_dt_sums_directions": ("else if (s > smax) smax = s;\n          }\n        }\n  }\n  return bad ? NAN : smax;\n}\n\ndouble oracle_dt_ctu",
+                               "else if (s > smax) smax = s;\n          }\n        }\n  }\n  return bad ? NAN : 3.0 * smax;\n}\n\ndouble oracle_dt_ctu"),
 }
 
 
@@ -59,8 +72,15 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     subprocess.run(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
                     "-shared", "-std=c99", "-o", str(lib), str(mut), "-lm"], check=True)
     env = dict(os.environ, HYDRO_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        "tests/test_oracle_units.py", "tests/test_oracle_step.py",
-                        "tests/test_oracle_fallback.py", "tests/test_oracle_rk.py"],
+    # a mistake in a scheme-specific path is looked for by that scheme's pins
+    # first (the suite stops at the first failure either way)
+    files = ["tests/test_oracle_units.py", "tests/test_oracle_step.py", "tests/test_oracle_fallback.py",
+             "tests/test_oracle_rk.py", "tests/test_oracle_ctu.py"]
+    first = {"ctu": "tests/test_oracle_ctu.py", "rk": "tests/test_oracle_rk.py",
+             "stage": "tests/test_oracle_rk.py"}.get(name.split("_")[0])
+    if first:
+        files.remove(first)
+        files.insert(0, first)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *files],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutation {name} survived all pins:\n{r.stdout[-2000:]}"

@@ -74,6 +74,7 @@ extern "C" {
 #define HYDRO_SCHEME_MH 0  /* predictor-corrector (MUSCL-Hancock) step, the default */
 #define HYDRO_SCHEME_RK2 2 /* second-order SSP Runge-Kutta, method-of-lines stages */
 #define HYDRO_SCHEME_RK3 3 /* third-order SSP Runge-Kutta, method-of-lines stages */
+#define HYDRO_SCHEME_CTU 4 /* corner-transport-upwind unsplit step, per-direction CFL rule */
 
 typedef struct hydro_grid hydro_grid;
 
@@ -195,9 +196,26 @@ int hydro_set_pencil_planes(hydro_grid *g, int planes);
  * U_stage: caller-owned device buffer of hydro_state_doubles values,
  * 256-byte aligned, not overlapping U or U_alt; required by RK3 (holds U2),
  * ignored otherwise (may be NULL).  Counters sum over stages.
- * Errors: HYDRO_EINVAL (unknown scheme, RK3 without a valid stage buffer,
+ *   HYDRO_SCHEME_CTU: the corner-coupled form of the unsplit predictor-
+ *     corrector step (corner transport upwind, twelve HLLC solves per
+ *     cell): normal predictor per direction (W_d = W - (dt/2dx_d) A_d D_d,
+ *     face states W_d -+ D_d/2, first-order fallback); 1-D fluxes F1_d;
+ *     corner states U_d - (dt/3dx_t) dF1_t over the cell for each
+ *     transverse t and their fluxes F_{d|t}; final states
+ *     U_d - (dt/2dx_t) dF_{t|u} - (dt/2dx_u) dF_{u|t} and their fluxes;
+ *     update.  A corrected state with rho <= 0 or p <= 0 falls back to the
+ *     normal face state (counted).  Its CFL rule is per direction:
+ *     dt = cfl / max over cells and d of (|u_d|+c)/dx_d (hydro_dt and
+ *     hydro_step_cfl follow it for a CTU grid).  U_stage is then a scratch
+ *     buffer of hydro_ctu_scratch_bytes bytes (caller-owned, device,
+ *     256-byte aligned, not overlapping U or U_alt).
+ * Errors: HYDRO_EINVAL (unknown scheme, RK3 or CTU without a valid buffer,
  * grid in a batch).  Batches take HYDRO_SCHEME_MH grids only. */
 int hydro_set_scheme(hydro_grid *g, int scheme, double *U_stage);
+
+/* Scratch bytes the CTU scheme needs for this grid (0 for an invalid
+ * descriptor): stage slices of up to 8 GiB worth of blocks per launch. */
+size_t hydro_ctu_scratch_bytes(const hydro_grid_desc *d);
 
 /* ---- batches: many independent grids, one persistent launch per step ----
  * (§2: physics is updated block by block, independently of how blocks are

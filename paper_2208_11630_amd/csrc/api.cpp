@@ -26,7 +26,7 @@ struct hydro_grid {
   int plen;                 // planes per z pencil (tuning; results do not depend on it)
   hydro_batch* batch;       // batch the grid belongs to (its own step calls are refused meanwhile)
   int scheme;               // HYDRO_SCHEME_*
-  double* U_stage;          // third state buffer (third-order Runge-Kutta only)
+  double* U_stage;          // third state buffer (third-order Runge-Kutta) or CTU scratch
 };
 
 struct hydro_batch {
@@ -125,7 +125,8 @@ int check_device() {
 
 int ensure_signal_on(hydro_grid* g, hipStream_t s) {
   if (g->sig_valid) return HYDRO_OK;
-  hipError_t e = hydro::launch_signal(g->d.nxb, g->geom, cur_state(g), ws_of(g), slot_of(g), s);
+  hipError_t e = hydro::launch_signal(g->d.nxb, g->geom, cur_state(g), ws_of(g), slot_of(g),
+                                      g->scheme == HYDRO_SCHEME_CTU, s);
   if (e != hipSuccess) return hip_fail(e, "signal-speed kernel launch");
   g->sig_valid = true;
   return HYDRO_OK;
@@ -175,7 +176,32 @@ int do_rk_step(hydro_grid* g, double dt, double cfl) {
   return HYDRO_OK;
 }
 
+// CTU scratch: blocks per launch so that one launch's slices fit 8 GiB.
+long ctu_chunk(const hydro_grid_desc* d) {
+  const long nblk = (long)d->nblk[0] * d->nblk[1] * d->nblk[2];
+  const long per = hydro::ctu_block_doubles(d->nxb) * (long)sizeof(double);
+  const long fit = per > 0 ? (8L << 30) / per : 1;
+  return std::max(1L, std::min(nblk, fit));
+}
+
+int do_ctu_step(hydro_grid* g, double dt, double cfl) {
+  hydro::StepArgs a;
+  a.Uin = cur_state(g);
+  a.Uout = other_state(g);
+  a.ws = ws_of(g);
+  a.dt = dt;
+  a.cfl = cfl;
+  a.slot = slot_of(g);
+  hipError_t e = hydro::launch_ctu(g->d.nxb, g->geom, a, g->U_stage, ctu_chunk(&g->d), stream_of(g));
+  if (e != hipSuccess) return hip_fail(e, "CTU kernel launch");
+  g->cur ^= 1;
+  g->steps += 1;
+  g->sig_valid = true;
+  return HYDRO_OK;
+}
+
 int do_step(hydro_grid* g, double dt, double cfl) {
+  if (g->scheme == HYDRO_SCHEME_CTU) return do_ctu_step(g, dt, cfl);
   if (g->scheme != HYDRO_SCHEME_MH) return do_rk_step(g, dt, cfl);
   hydro::StepArgs a;
   a.Uin = cur_state(g);
@@ -370,20 +396,31 @@ int hydro_set_buffers(hydro_grid* g, double* U, double* U_alt) {
 int hydro_set_scheme(hydro_grid* g, int scheme, double* U_stage) {
   if (!g) return fail(HYDRO_EINVAL, "handle is NULL");
   if (g->batch) return fail(HYDRO_EINVAL, "grid belongs to a batch");
-  if (scheme != HYDRO_SCHEME_MH && scheme != HYDRO_SCHEME_RK2 && scheme != HYDRO_SCHEME_RK3)
+  if (scheme != HYDRO_SCHEME_MH && scheme != HYDRO_SCHEME_RK2 && scheme != HYDRO_SCHEME_RK3 &&
+      scheme != HYDRO_SCHEME_CTU)
     return fail(HYDRO_EINVAL, "unknown scheme %d", scheme);
-  if (scheme == HYDRO_SCHEME_RK3) {
-    if (!U_stage) return fail(HYDRO_EINVAL, "the third-order scheme needs a stage buffer");
-    if ((uintptr_t)U_stage & 255) return fail(HYDRO_EINVAL, "stage buffer must be 256-byte aligned");
+  if (scheme == HYDRO_SCHEME_RK3 || scheme == HYDRO_SCHEME_CTU) {
+    const bool ctu = scheme == HYDRO_SCHEME_CTU;
+    if (!U_stage) return fail(HYDRO_EINVAL, ctu ? "the CTU scheme needs a scratch buffer" : "the third-order scheme needs a stage buffer");
+    if ((uintptr_t)U_stage & 255) return fail(HYDRO_EINVAL, "stage / scratch buffer must be 256-byte aligned");
     const size_t sb = hydro_state_doubles(&g->d) * sizeof(double);
-    if (overlaps(U_stage, sb, g->d.U, sb) || overlaps(U_stage, sb, g->d.U_alt, sb))
-      return fail(HYDRO_EINVAL, "stage buffer overlaps a state buffer");
+    const size_t need = ctu ? hydro_ctu_scratch_bytes(&g->d) : sb;
+    if (overlaps(U_stage, need, g->d.U, sb) || overlaps(U_stage, need, g->d.U_alt, sb))
+      return fail(HYDRO_EINVAL, "stage / scratch buffer overlaps a state buffer");
   } else {
     U_stage = nullptr;
   }
+  if ((scheme == HYDRO_SCHEME_CTU) != (g->scheme == HYDRO_SCHEME_CTU))
+    g->sig_valid = false;  // the kept signal speed follows the other CFL rule
   g->scheme = scheme;
   g->U_stage = U_stage;
   return HYDRO_OK;
+}
+
+size_t hydro_ctu_scratch_bytes(const hydro_grid_desc* d) {
+  if (!d || (d->nxb != 8 && d->nxb != 16 && d->nxb != 32) || d->nblk[0] < 1 || d->nblk[1] < 1 || d->nblk[2] < 1)
+    return 0;
+  return (size_t)ctu_chunk(d) * (size_t)hydro::ctu_block_doubles(d->nxb) * sizeof(double);
 }
 
 int hydro_set_pencils(hydro_grid* g, int nseg) {

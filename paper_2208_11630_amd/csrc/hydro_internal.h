@@ -73,8 +73,14 @@ hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const Stag
 hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,
                              const int nseg[3], int grid, hipStream_t s);
 hipError_t launch_fill_guards(int nxb, const GridGeom& g, const double* U, double* out, hipStream_t s);
-hipError_t launch_signal(int nxb, const GridGeom& g, const double* U, WorkHeader* ws, int slot,
+// dir: the per-direction signal max_d (|u_d|+c)/dx_d of the CTU step
+// instead of the summed one.
+hipError_t launch_signal(int nxb, const GridGeom& g, const double* U, WorkHeader* ws, int slot, bool dir,
                          hipStream_t s);
+// Corner-transport-upwind step: blocks in launches of `chunk` workgroups,
+// each using ctu_block_doubles(nxb) doubles of scratch.
+long ctu_block_doubles(int nxb);
+hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, double* scratch, long chunk, hipStream_t s);
 hipError_t launch_clear_slot(WorkHeader* ws, int slot, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, long n, hipStream_t s);
 

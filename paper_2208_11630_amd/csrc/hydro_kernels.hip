@@ -199,6 +199,16 @@ __device__ __forceinline__ void hllc(const double (&L)[5], const double (&R)[5],
   }
 }
 
+// Per-direction CFL signal of the corner-transport-upwind step:
+// max_d (|u_d| + c)/dx_d.
+__device__ __forceinline__ double signal_speed_dir(const double (&u)[5], const GridGeom& g) {
+  double w[5], inv;
+  prim(u, g.gamma, g.small_p, w, inv);
+  const double gp = g.gamma * w[4];
+  const double c = gp * rsq_nr(gp * w[0]);
+  return fmax(fmax((fabs(w[1]) + c) * g.inv_dx[0], (fabs(w[2]) + c) * g.inv_dx[1]), (fabs(w[3]) + c) * g.inv_dx[2]);
+}
+
 __device__ __forceinline__ double signal_speed(const double (&u)[5], const GridGeom& g) {
   double w[5], inv;
   prim(u, g.gamma, g.small_p, w, inv);
@@ -744,6 +754,279 @@ __global__ __launch_bounds__(256, 2) void batch_step_kernel(const BatchSim* __re
 }
 
 // ---------------------------------------------------------------------------
+// Corner-transport-upwind (CTU) step: the corner-coupled form of the unsplit
+// predictor-corrector solver (§2.2 Hydrodynamics), twelve HLLC solves per
+// cell: normal predictor per direction, 1-D fluxes, corner states with
+// lam_t/3 transverse corrections and their fluxes, final states with lam/2
+// cross corrections and their fluxes, update.  One workgroup per block; the
+// stages pass through a per-workgroup slice of a caller-provided scratch
+// (global memory, one barrier between stages).  The halo is gathered
+// through the boundary index map, as in the fused step.
+template <int N>
+struct Ctu {
+  static constexpr int M = N + 4;            // primitives on cells -2..N+1
+  static constexpr int m = N + 2;            // face states on cells -1..N
+  static constexpr long M3 = (long)M * M * M, m3 = (long)m * m * m;
+  static constexpr long oW = 0, oWf = 5 * M3, oF1 = oWf + 30 * m3, oFc = oF1 + 15 * m3, oFf = oFc + 30 * m3;
+  static constexpr long doubles = oFf + 15 * m3;   // scratch doubles per block
+  __device__ static int ci(int i, int j, int k) { return ((k + 1) * m + (j + 1)) * m + (i + 1); }
+  __device__ static int cW(int i, int j, int k) { return ((k + 2) * M + (j + 2)) * M + (i + 2); }
+};
+
+// HLLC along a runtime direction (the solver is specialised per direction).
+__device__ __forceinline__ void hllc_dir(int d, const double (&L)[5], const double (&R)[5], double gamma,
+                                         double gm1inv, double (&F)[5]) {
+  if (d == 0)
+    hllc<0>(L, R, gamma, gm1inv, F);
+  else if (d == 1)
+    hllc<1>(L, R, gamma, gm1inv, F);
+  else
+    hllc<2>(L, R, gamma, gm1inv, F);
+}
+
+__device__ __forceinline__ void to_cons(const double* w, double gm1inv, double (&u)[5]) {
+  u[0] = w[0];
+  u[1] = w[0] * w[1];
+  u[2] = w[0] * w[2];
+  u[3] = w[0] * w[3];
+  u[4] = w[4] * gm1inv + 0.5 * w[0] * ((w[1] * w[1] + w[2] * w[2]) + w[3] * w[3]);
+}
+
+// Primitive of a corrected conserved state; false when rho <= 0 or p <= 0.
+__device__ __forceinline__ bool corrected_prim(const double (&u)[5], double gamma, double (&w)[5]) {
+  if (!(u[0] > 0.0)) return false;
+  const double inv = rcp_nr(u[0]);
+  w[0] = u[0];
+  w[1] = u[1] * inv;
+  w[2] = u[2] * inv;
+  w[3] = u[3] * inv;
+  w[4] = (gamma - 1.0) * (u[4] - 0.5 * u[0] * ((w[1] * w[1] + w[2] * w[2]) + w[3] * w[3]));
+  return w[4] > 0.0;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void ctu_kernel(GridGeom g, StepArgs a, double* __restrict__ scratch, long b0) {
+  using C = Ctu<N>;
+  constexpr int m = C::m, M = C::M;
+  __shared__ unsigned long long sRed[4];
+  __shared__ int sCnt[3];
+  const long blk = b0 + blockIdx.x;
+  const int tid = threadIdx.x;
+  double* sc = scratch + (long)blockIdx.x * C::doubles;
+  double* W = sc + C::oW;
+  double* Wf = sc + C::oWf;
+  double* F1 = sc + C::oF1;
+  double* Fc = sc + C::oFc;
+  double* Ff = sc + C::oFf;
+  WorkHeader* ws = a.ws;
+  const int slot = a.slot;
+  if (tid < 3) sCnt[tid] = 0;
+  double dt = a.dt;
+  if (a.cfl > 0.0) dt = a.cfl / __longlong_as_double(ws->sig[slot]);
+  if (blk == 0 && tid == 0) {
+    ws->dt_last = dt;
+    ws->sig[(slot + 2) % 3] = 0ull;
+  }
+  const double lam[3] = {dt * g.inv_dx[0], dt * g.inv_dx[1], dt * g.inv_dx[2]};
+  const double gamma = g.gamma, gm1inv = 1.0 / (g.gamma - 1.0);
+  const int bx = (int)(blk % g.nb[0]), by = (int)((blk / g.nb[0]) % g.nb[1]);
+  const int bz = (int)(blk / ((long)g.nb[0] * g.nb[1]));
+  const int X0 = bx * N, Y0 = by * N, Z0 = bz * N;
+  const int tr[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+  int n_floor = 0, n_fb = 0, n_bad = 0;
+
+  // primitives on cells -2..N+1 (halo through the boundary map)
+  for (int it = tid; it < M * M * M; it += 256) {
+    const int i = it % M - 2, j = (it / M) % M - 2, k = it / (M * M) - 2;
+    double u[5], w[5], inv;
+    load_cons<N>(a.Uin, cell_offset<N>(g, X0 + i, Y0 + j, Z0 + k), u);
+    const int fl = prim(u, gamma, g.small_p, w, inv);
+    if (fl && i >= 0 && i < N && j >= 0 && j < N && k >= 0 && k < N) ++n_floor;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) W[v * C::M3 + it] = w[v];
+  }
+  __syncthreads();
+
+  // 1. normal predictor on cells -1..N: face states [d][side][v], side 0 low, 1 high
+  for (int it = tid; it < m * m * m; it += 256) {
+    const int i = it % m - 1, j = (it / m) % m - 1, k = it / (m * m) - 1;
+    const int c = C::cW(i, j, k);
+    const int step[3] = {1, M, M * M};
+    double w[5], fs[6][5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[v] = W[v * C::M3 + c];
+    const double inv = rcp_nr(w[0]);
+    const double gp = gamma * w[4];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double sl[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        sl[v] = van_leer_sf(w[v] - W[v * C::M3 + c - step[d]], W[v * C::M3 + c + step[d]] - w[v]);
+      const double un = w[1 + d];
+      double A[5];
+      A[0] = un * sl[0] + w[0] * sl[1 + d];
+      A[1] = un * sl[1];
+      A[2] = un * sl[2];
+      A[3] = un * sl[3];
+      A[1 + d] += sl[4] * inv;
+      A[4] = gp * sl[1 + d] + un * sl[4];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double wt = w[v] - 0.5 * lam[d] * A[v];
+        fs[2 * d][v] = wt - 0.5 * sl[v];
+        fs[2 * d + 1][v] = wt + 0.5 * sl[v];
+      }
+      ok = ok && fs[2 * d][0] > 0.0 && fs[2 * d][4] > 0.0 && fs[2 * d + 1][0] > 0.0 && fs[2 * d + 1][4] > 0.0;
+    }
+    if (!ok && i >= 0 && i < N && j >= 0 && j < N && k >= 0 && k < N) ++n_fb;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Wf[(q * 5 + v) * C::m3 + it] = ok ? fs[q][v] : w[v];
+  }
+  __syncthreads();
+
+  // 2. 1-D fluxes at the low d-face of cells with c_d in 0..N (others -1..N)
+  for (int d = 0; d < 3; ++d) {
+    const int cnt = (N + 1) * m * m;
+    for (int it = tid; it < cnt; it += 256) {
+      int c3[3];
+      const int a0 = it % m, a1 = (it / m) % m, a2 = it / (m * m);  // a2 runs 0..N along d
+      // map (a0, a1) to the two transverse axes and a2 to d
+      const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      c3[t0] = a0 - 1;
+      c3[t1] = a1 - 1;
+      c3[d] = a2;
+      const int hi = C::ci(c3[0], c3[1], c3[2]);
+      const int lo = C::ci(c3[0] - (d == 0), c3[1] - (d == 1), c3[2] - (d == 2));
+      double L[5], R[5], F[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        L[v] = Wf[((2 * d + 1) * 5 + v) * C::m3 + lo];
+        R[v] = Wf[((2 * d + 0) * 5 + v) * C::m3 + hi];
+      }
+      hllc_dir(d, L, R, gamma, gm1inv, F);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) F1[(d * 5 + v) * C::m3 + hi] = F[v];
+    }
+  }
+  __syncthreads();
+
+  // 3. corner fluxes F_{d|t} at d-faces with c_d in 0..N, c_t in 0..N-1, the
+  //    remaining axis in -1..N
+  for (int d = 0; d < 3; ++d)
+    for (int q = 0; q < 2; ++q) {
+      const int t = tr[d][q], r = 3 - d - t;
+      const int cnt = (N + 1) * N * m;
+      for (int it = tid; it < cnt; it += 256) {
+        int c3[3];
+        c3[r] = it % m - 1;
+        c3[t] = (it / m) % N;
+        c3[d] = it / (m * N);
+        double side[2][5];
+        for (int sd = 0; sd < 2; ++sd) {
+          const int ci = c3[0] - (sd == 0 && d == 0), cj = c3[1] - (sd == 0 && d == 1), ck = c3[2] - (sd == 0 && d == 2);
+          const int face = sd == 0 ? 1 : 0;
+          const int cc = C::ci(ci, cj, ck);
+          const int ch = C::ci(ci + (t == 0), cj + (t == 1), ck + (t == 2));
+          double wn[5], u[5], w[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) wn[v] = Wf[((2 * d + face) * 5 + v) * C::m3 + cc];
+          to_cons(wn, gm1inv, u);
+#pragma unroll
+          for (int v = 0; v < 5; ++v)
+            u[v] -= (lam[t] * (1.0 / 3.0)) * (F1[(t * 5 + v) * C::m3 + ch] - F1[(t * 5 + v) * C::m3 + cc]);
+          const bool good = corrected_prim(u, gamma, w);
+          if (!good) ++n_fb;
+#pragma unroll
+          for (int v = 0; v < 5; ++v) side[sd][v] = good ? w[v] : wn[v];
+        }
+        double F[5];
+        hllc_dir(d, side[0], side[1], gamma, gm1inv, F);
+        const int hi = C::ci(c3[0], c3[1], c3[2]);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fc[((2 * d + q) * 5 + v) * C::m3 + hi] = F[v];
+      }
+    }
+  __syncthreads();
+
+  // 4. final fluxes at the interior faces
+  for (int d = 0; d < 3; ++d) {
+    const int t = tr[d][0], u_ = tr[d][1];
+    const int kt = tr[t][0] == u_ ? 0 : 1;   // F_{t|u} index among t's pair
+    const int ku = tr[u_][0] == t ? 0 : 1;   // F_{u|t} index among u's pair
+    const int cnt = (N + 1) * N * N;
+    for (int it = tid; it < cnt; it += 256) {
+      int c3[3];
+      c3[t] = it % N;
+      c3[u_] = (it / N) % N;
+      c3[d] = it / (N * N);
+      double side[2][5];
+      for (int sd = 0; sd < 2; ++sd) {
+        const int ci = c3[0] - (sd == 0 && d == 0), cj = c3[1] - (sd == 0 && d == 1), ck = c3[2] - (sd == 0 && d == 2);
+        const int face = sd == 0 ? 1 : 0;
+        const int cc = C::ci(ci, cj, ck);
+        const int ct = C::ci(ci + (t == 0), cj + (t == 1), ck + (t == 2));
+        const int cu = C::ci(ci + (u_ == 0), cj + (u_ == 1), ck + (u_ == 2));
+        double wn[5], u[5], w[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) wn[v] = Wf[((2 * d + face) * 5 + v) * C::m3 + cc];
+        to_cons(wn, gm1inv, u);
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          u[v] -= 0.5 * (lam[t] * (Fc[((2 * t + kt) * 5 + v) * C::m3 + ct] - Fc[((2 * t + kt) * 5 + v) * C::m3 + cc]) +
+                         lam[u_] * (Fc[((2 * u_ + ku) * 5 + v) * C::m3 + cu] - Fc[((2 * u_ + ku) * 5 + v) * C::m3 + cc]));
+        const bool good = corrected_prim(u, gamma, w);
+        if (!good) ++n_fb;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) side[sd][v] = good ? w[v] : wn[v];
+      }
+      double F[5];
+      hllc_dir(d, side[0], side[1], gamma, gm1inv, F);
+      const int hi = C::ci(c3[0], c3[1], c3[2]);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Ff[(d * 5 + v) * C::m3 + hi] = F[v];
+    }
+  }
+  __syncthreads();
+
+  // 5. update and the per-direction signal of the new state
+  double smax = 0.0;
+  for (int it = tid; it < N * N * N; it += 256) {
+    const int i = it % N, j = (it / N) % N, k = it / (N * N);
+    const int c0 = C::ci(i, j, k);
+    const int cx = C::ci(i + 1, j, k), cy = C::ci(i, j + 1, k), cz = C::ci(i, j, k + 1);
+    const long off = Layout<N>::at(blk, i, j, k);
+    double u[5], un[5];
+    load_cons<N>(a.Uin, off, u);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double div = (lam[0] * (Ff[(0 * 5 + v) * C::m3 + cx] - Ff[(0 * 5 + v) * C::m3 + c0]) +
+                          lam[1] * (Ff[(1 * 5 + v) * C::m3 + cy] - Ff[(1 * 5 + v) * C::m3 + c0])) +
+                         lam[2] * (Ff[(2 * 5 + v) * C::m3 + cz] - Ff[(2 * 5 + v) * C::m3 + c0]);
+      un[v] = u[v] - div;
+      a.Uout[off + v * Layout<N>::VS] = un[v];
+    }
+    bool good = un[0] > 0.0 && un[4] > 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) good = good && isfinite(un[v]);
+    if (!good) ++n_bad;
+    const double s = signal_speed_dir(un, g);
+    smax = (s > smax || !(s == s)) ? s : smax;
+  }
+  if (n_floor) atomicAdd(&sCnt[0], n_floor);
+  if (n_fb) atomicAdd(&sCnt[1], n_fb);
+  if (n_bad) atomicAdd(&sCnt[2], n_bad);
+  wg_max_to(smax, sRed, &ws->sig[(slot + 1) % 3]);
+  if (tid == 0) {
+    for (int q = 0; q < 3; ++q)
+      if (sCnt[q]) atomicAdd(&ws->cnt[q], (unsigned long long)sCnt[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Guard fill: one workgroup per (block, plane of the guarded view); every
 // cell of the guarded view (interior and guard layers, faces, edges and
 // corners) receives the state value at its mapped global index.
@@ -774,7 +1057,7 @@ __global__ __launch_bounds__(256) void fill_guards_kernel(GridGeom g, const doub
 }
 
 // Standalone CFL signal-speed reduction: one workgroup per block.
-template <int N>
+template <int N, bool DIR>
 __global__ __launch_bounds__(256) void signal_kernel(GridGeom g, const double* __restrict__ U,
                                                      unsigned long long* slot) {
   __shared__ unsigned long long sRed[4];
@@ -784,7 +1067,7 @@ __global__ __launch_bounds__(256) void signal_kernel(GridGeom g, const double* _
     const int i = t % N, j = (t / N) % N, k = t / (N * N);
     double u[5];
     load_cons<N>(U, Layout<N>::at(blk, i, j, k), u);
-    const double s = signal_speed(u, g);
+    const double s = DIR ? signal_speed_dir(u, g) : signal_speed(u, g);
     smax = (s > smax || !(s == s)) ? s : smax;
   }
   wg_max_to(smax, sRed, slot);
@@ -831,6 +1114,32 @@ hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const Stag
   return hipErrorInvalidValue;
 }
 
+long ctu_block_doubles(int nxb) {
+  switch (nxb) {
+    case 8: return Ctu<8>::doubles;
+    case 16: return Ctu<16>::doubles;
+    case 32: return Ctu<32>::doubles;
+  }
+  return 0;
+}
+
+hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, double* scratch, long chunk, hipStream_t s) {
+  const long nblk = (long)g.nb[0] * g.nb[1] * g.nb[2];
+  if (chunk < 1) return hipErrorInvalidValue;
+  for (long b0 = 0; b0 < nblk; b0 += chunk) {
+    const unsigned grid = (unsigned)(nblk - b0 < chunk ? nblk - b0 : chunk);
+    switch (nxb) {
+      case 8: hipLaunchKernelGGL(ctu_kernel<8>, dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
+      case 16: hipLaunchKernelGGL(ctu_kernel<16>, dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
+      case 32: hipLaunchKernelGGL(ctu_kernel<32>, dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
+      default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,
                              const int nseg[3], int grid, hipStream_t s) {
   hipLaunchKernelGGL(batch_step_kernel, dim3((unsigned)grid), dim3(256), 0, s, sims, items, nitems, step, cfl,
@@ -856,15 +1165,23 @@ hipError_t launch_fill_guards(int nxb, const GridGeom& g, const double* U, doubl
   return hipGetLastError();
 }
 
-hipError_t launch_signal(int nxb, const GridGeom& g, const double* U, WorkHeader* ws, int slot,
-                         hipStream_t s) {
+template <int N>
+void launch_signal_t(const GridGeom& g, const double* U, unsigned long long* dst, bool dir, hipStream_t s) {
   const long nblk = (long)g.nb[0] * g.nb[1] * g.nb[2];
+  if (dir)
+    hipLaunchKernelGGL((signal_kernel<N, true>), dim3((unsigned)nblk), dim3(256), 0, s, g, U, dst);
+  else
+    hipLaunchKernelGGL((signal_kernel<N, false>), dim3((unsigned)nblk), dim3(256), 0, s, g, U, dst);
+}
+
+hipError_t launch_signal(int nxb, const GridGeom& g, const double* U, WorkHeader* ws, int slot, bool dir,
+                         hipStream_t s) {
   unsigned long long* dst = &ws->sig[slot];
   hipLaunchKernelGGL(clear_slot_kernel, dim3(1), dim3(1), 0, s, ws, slot);
   switch (nxb) {
-    case 8: hipLaunchKernelGGL(signal_kernel<8>, dim3((unsigned)nblk), dim3(256), 0, s, g, U, dst); break;
-    case 16: hipLaunchKernelGGL(signal_kernel<16>, dim3((unsigned)nblk), dim3(256), 0, s, g, U, dst); break;
-    case 32: hipLaunchKernelGGL(signal_kernel<32>, dim3((unsigned)nblk), dim3(256), 0, s, g, U, dst); break;
+    case 8: launch_signal_t<8>(g, U, dst, dir, s); break;
+    case 16: launch_signal_t<16>(g, U, dst, dir, s); break;
+    case 32: launch_signal_t<32>(g, U, dst, dir, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

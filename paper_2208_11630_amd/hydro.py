@@ -25,7 +25,7 @@ HYDRO_ENONPHYS = -4
 BC_PERIODIC = 0
 BC_OUTFLOW = 1
 NGUARD = 4
-SCHEME_MH, SCHEME_RK2, SCHEME_RK3 = 0, 2, 3
+SCHEME_MH, SCHEME_RK2, SCHEME_RK3, SCHEME_CTU = 0, 2, 3, 4
 
 # Every entry point include/hydro.h declares, with its ctypes signature.
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -70,6 +70,7 @@ SIGNATURES = {
     "hydro_set_pencils": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_set_pencil_planes": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_set_scheme": ([_HP, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "hydro_ctu_scratch_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
     "hydro_set_buffers": ([_HP, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "hydro_batch_work_bytes": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int], ctypes.c_size_t),
     "hydro_batch_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
@@ -239,15 +240,25 @@ class Grid:
 
     def set_scheme(self, scheme: int, stage=None) -> None:
         """Time integration: SCHEME_MH (predictor-corrector), SCHEME_RK2 or
-        SCHEME_RK3 (SSP Runge-Kutta over method-of-lines stages).  RK3 needs a
-        third state tensor; one is allocated when `stage` is None."""
-        if scheme == SCHEME_RK3 and stage is None:
-            stage = self._torch.empty(self.shape, dtype=self._torch.float64, device=self.bufs[0].device)
-        if stage is not None and (tuple(stage.shape) != self.shape or not stage.is_contiguous()):
-            raise HydroError(HYDRO_EINVAL, "stage buffer must be a contiguous tensor of the grid shape")
-        ptr = stage.data_ptr() if (stage is not None and scheme == SCHEME_RK3) else None
+        SCHEME_RK3 (SSP Runge-Kutta over method-of-lines stages), SCHEME_CTU
+        (corner transport upwind).  RK3 needs a third state tensor and CTU a
+        scratch tensor; one is allocated when `stage` is None."""
+        torch = self._torch
+        if scheme == SCHEME_CTU:
+            nbytes = lib().hydro_ctu_scratch_bytes(ctypes.byref(self.desc))
+            if stage is None:
+                stage = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=self.bufs[0].device)
+            elif stage.numel() * stage.element_size() < nbytes or not stage.is_contiguous():
+                raise HydroError(HYDRO_EINVAL, f"CTU scratch must be a contiguous tensor of >= {nbytes} bytes")
+        elif scheme == SCHEME_RK3:
+            if stage is None:
+                stage = torch.empty(self.shape, dtype=torch.float64, device=self.bufs[0].device)
+            if tuple(stage.shape) != self.shape or not stage.is_contiguous():
+                raise HydroError(HYDRO_EINVAL, "stage buffer must be a contiguous tensor of the grid shape")
+        keep = scheme in (SCHEME_RK3, SCHEME_CTU)
+        ptr = stage.data_ptr() if (stage is not None and keep) else None
         _check(lib().hydro_set_scheme(self.handle, int(scheme), ptr))
-        self.stage_buf = stage if scheme == SCHEME_RK3 else None
+        self.stage_buf = stage if keep else None
         self.scheme = int(scheme)
 
     def set_buffers(self, U, U_alt) -> None:

@@ -41,28 +41,58 @@ def make_workload(name):
 
 def cpu_baseline(P, seconds_target=15.0):
     """The oracle (plain FP64 C, OpenMP over blocks) on a bounded sample of the
-    same workload: one step of the first nb blocks of the grid, nb doubling
-    until one timing takes at least half the target (or covers the grid)."""
+    same workload, on the host cores: one step of the first nb blocks of the
+    grid, nb doubling until one timing takes at least half the target (or
+    covers the grid), whole-grid steps repeated up to the target; then the
+    same on one thread, on a sample of a few seconds."""
+    import platform
+
     import numpy as np
 
     import oracle
 
     g = oracle.Grid(P.n, P.nb, P.dx, P.bc, P.gamma, P.small_p, P.ng)
     dt = oracle.dt(g, P.U, P.cfl) if P.nblk <= 4096 else 1e-4
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    nb = min(64, P.nblk)
-    while True:
-        blocks = np.arange(nb)
-        t1 = time.perf_counter()
-        oracle.step_blocks(g, P.U, blocks, dt)
-        elapsed = time.perf_counter() - t1
-        if elapsed >= seconds_target / 2 or nb == P.nblk:
-            break
-        nb = min(2 * nb, P.nblk)
-    cells = nb * P.n ** 3
+    cores = oracle.lib().oracle_max_threads()
+
+    def timed_sample(target):
+        nb = min(64, P.nblk)
+        while True:
+            blocks = np.arange(nb)
+            t1 = time.perf_counter()
+            oracle.step_blocks(g, P.U, blocks, dt)
+            elapsed = time.perf_counter() - t1
+            if elapsed >= target / 2 or nb == P.nblk:
+                break
+            nb = min(2 * nb, P.nblk)
+        reps = 1
+        while elapsed < target * 2 / 3 and nb == P.nblk:   # the whole grid: repeat the step
+            t1 = time.perf_counter()
+            oracle.step_blocks(g, P.U, np.arange(nb), dt)
+            elapsed += time.perf_counter() - t1
+            reps += 1
+        return nb, reps, elapsed
+
+    nb, reps, elapsed = timed_sample(seconds_target)
+    cells = nb * P.n ** 3 * reps
+    prev = oracle.set_threads(1)
+    nb1, reps1, el1 = timed_sample(4.0)
+    oracle.set_threads(prev)
+    cells1 = nb1 * P.n ** 3 * reps1
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": cells / elapsed, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"one step of the first {nb} of {P.nblk} blocks ({cells} cells), "
-                      f"{elapsed:.2f} s on {cores} host threads"}
+            "sample": f"{reps} step(s) of the first {nb} of {P.nblk} blocks ({cells} cell updates), "
+                      f"{elapsed:.2f} s on {cores} host threads",
+            "single_thread": {"value": cells1 / el1, "unit": "cell-updates/s",
+                              "sample": f"{reps1} step(s) of the first {nb1} blocks, {el1:.2f} s on 1 thread"},
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def traffic_from_profiles(kernel_tag):

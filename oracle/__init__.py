@@ -60,6 +60,10 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         gp = ctypes.POINTER(_Grid)
         lp = ctypes.POINTER(ctypes.c_long)
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = ctypes.c_int
         L.oracle_block_doubles.argtypes = [gp]
         L.oracle_block_doubles.restype = ctypes.c_size_t
         L.oracle_cons_to_prim.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
@@ -141,6 +145,13 @@ class Grid:
     def check(self, U: np.ndarray) -> None:
         if U.shape != self.shape():
             raise ValueError(f"state shape {U.shape} != {self.shape()}")
+
+
+def set_threads(n: int) -> int:
+    """Host threads for the loops over blocks; returns the previous count."""
+    prev = lib().oracle_max_threads()
+    lib().oracle_set_threads(int(n))
+    return prev
 
 
 def cons_to_prim(U: Sequence[float], gamma: float, small_p: float = 1e-10):

@@ -9,8 +9,16 @@
 #include "hydro_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Host threads of the OpenMP loops over blocks (timing of the baseline). */
+void oracle_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
+int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 /* ---- layout ------------------------------------------------------------ */
 

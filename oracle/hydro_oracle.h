@@ -63,6 +63,10 @@ enum { ORACLE_CNT_FLOOR = 0, ORACLE_CNT_FALLBACK = 1, ORACLE_CNT_NONPHYS = 2, OR
 
 size_t oracle_block_doubles(const oracle_grid *g);
 
+/* Host threads used by the loops over blocks (timing only; no effect on results). */
+void oracle_set_threads(int n);
+int oracle_max_threads(void);
+
 /* Primitive recovery of one cell; returns 1 when the pressure floor was hit. */
 int oracle_cons_to_prim(const double U[5], double gamma, double small_p, double W[5]);
 /* van Leer harmonic slope. */

@@ -84,6 +84,8 @@ def lib():
         L.oracle_step_block_list.restype = None
         L.oracle_step.argtypes = [gp, dp, dp, ctypes.c_double, lp]
         L.oracle_step.restype = None
+        L.oracle_step_block_fluxes.argtypes = [gp, dp, ctypes.c_long, dp, ctypes.c_double, dp, dp, dp, lp]
+        L.oracle_step_block_fluxes.restype = None
         L.oracle_stage_block.argtypes = [gp, dp, ctypes.c_long, dp, ctypes.c_double, dp, ctypes.c_double,
                                          ctypes.c_double, lp]
         L.oracle_stage_block.restype = None

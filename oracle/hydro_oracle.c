@@ -200,7 +200,7 @@ static void jacobian_times(const double W[5], int d, double gamma, const double 
  * Uo = a0*U0 + a1*(U - div F). */
 
 static void update_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt, int hancock,
-                         const double *U0b, double a0, double a1, long cnt[ORACLE_NCNT]) {
+                         const double *U0b, double a0, double a1, long cnt[ORACLE_NCNT], double *Fout[3]) {
   const int n = g->n, ng = g->ng, P = edge(g);
   const double gamma = g->gamma;
   const double lam[3] = {dt / g->dx[0], dt / g->dx[1], dt / g->dx[2]};
@@ -303,6 +303,9 @@ static void update_block(const oracle_grid *g, const double *U, long b, double *
         for (int v = 0; v < 5; ++v) ok = ok && isfinite(Un[v]);
         if (!ok) cnt[ORACLE_CNT_NONPHYS]++;
       }
+  if (Fout)
+    for (int d = 0; d < 3; ++d)
+      if (Fout[d]) memcpy(Fout[d], F[d], sizeof(double) * 5 * nf);
 #undef WI
 #undef MI
   free(W);
@@ -314,12 +317,18 @@ static void update_block(const oracle_grid *g, const double *U, long b, double *
 
 void oracle_step_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
                        long cnt[ORACLE_NCNT]) {
-  update_block(g, U, b, Uo, dt, 1, NULL, 0.0, 0.0, cnt);
+  update_block(g, U, b, Uo, dt, 1, NULL, 0.0, 0.0, cnt, NULL);
+}
+
+void oracle_step_block_fluxes(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+                              double *Fx, double *Fy, double *Fz, long cnt[ORACLE_NCNT]) {
+  double *Fout[3] = {Fx, Fy, Fz};
+  update_block(g, U, b, Uo, dt, 1, NULL, 0.0, 0.0, cnt, Fout);
 }
 
 void oracle_stage_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
                         const double *U0b, double a0, double a1, long cnt[ORACLE_NCNT]) {
-  update_block(g, U, b, Uo, dt, 0, U0b, a0, a1, cnt);
+  update_block(g, U, b, Uo, dt, 0, U0b, a0, a1, cnt, NULL);
 }
 
 void oracle_step(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]) {
@@ -378,7 +387,7 @@ static void stage_all(const oracle_grid *g, double *Us, const double *U0, double
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : c0, c1, c2)
   for (long b = 0; b < nblk; ++b) {
     long c[ORACLE_NCNT] = {0, 0, 0};
-    update_block(g, Us, b, Uo + (size_t)b * bd, dt, 0, U0 ? U0 + (size_t)b * bd : NULL, a0, a1, c);
+    update_block(g, Us, b, Uo + (size_t)b * bd, dt, 0, U0 ? U0 + (size_t)b * bd : NULL, a0, a1, c, NULL);
     c0 += c[0];
     c1 += c[1];
     c2 += c[2];

@@ -86,6 +86,14 @@ void oracle_fill_guards(const oracle_grid *g, double *U);
 void oracle_step_block(const oracle_grid *g, const double *U, long b, double *Uo,
                        double dt, long cnt[ORACLE_NCNT]);
 
+/* The same step of block b, also returning every face flux of the block:
+ * Fx[(k*n + j)*(n+1) + i][v] at the low x face of cell (i, j, k), i = 0..n
+ * (i = n: the high face of cell n-1); Fy[(k*(n+1) + j)*n + i][v], j = 0..n;
+ * Fz[(k*n + j)*n + i][v], k = 0..n.  Each array holds 5*(n+1)*n*n values.
+ * (For refluxing at refinement jumps.) */
+void oracle_step_block_fluxes(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+                              double *Fx, double *Fy, double *Fz, long cnt[ORACLE_NCNT]);
+
 /* Step a list of blocks (guards of each filled first, then updated); block
  * t's result goes to out + t*oracle_block_doubles(g).  Guards are written
  * only from interiors, so the blocks are independent. */

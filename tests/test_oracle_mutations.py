@@ -84,3 +84,44 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *files],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutation {name} survived all pins:\n{r.stdout[-2000:]}"
+
+
+# Mistakes planted in the two-level AMR step (oracle/amr.py, numpy).
+AMR_MUTATIONS = {
+    "amr_no_reflux": ("corr = lam0[d] * (Fc - Ff) * (1.0 if side else -1.0)",
+                      "corr = 0.0 * lam0[d] * (Fc - Ff) * (1.0 if side else -1.0)"),
+    "amr_reflux_sign": ("corr = lam0[d] * (Fc - Ff) * (1.0 if side else -1.0)",
+                        "corr = lam0[d] * (Fc - Ff) * (-1.0 if side else 1.0)"),
+    "amr_reflux_wrong_face": ("Fc = _face(flux0[b][d], d, n, n if side else 0)",
+                              "Fc = _face(flux0[b][d], d, n, 0 if side else n)"),
+    "amr_prolong_slope_sign": ("val = val + S * (0.25 * offs[d])", "val = val - S * (0.25 * offs[d])"),
+    "amr_prolong_half_weight": ("val = val + S * (0.25 * offs[d])", "val = val + S * (0.5 * offs[d])"),
+    "amr_restrict_wrong_child": ("cx, cy, cz = c & 1, (c >> 1) & 1, (c >> 2) & 1\n            ch = Uf[8 * q + c]",
+                                 "cx, cy, cz = (c >> 1) & 1, c & 1, (c >> 2) & 1\n            ch = Uf[8 * q + c]"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(AMR_MUTATIONS))
+def test_amr_pins_catch_planted_mistake(name, tmp_path):
+    import shutil
+
+    old, new = AMR_MUTATIONS[name]
+    pkg = tmp_path / "oracle"
+    shutil.copytree(os.path.join(ROOT, "oracle"), pkg, ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    src = (pkg / "amr.py").read_text()
+    assert src.count(old) == 1, f"mutation anchor not unique/found: {old!r}"
+    (pkg / "amr.py").write_text(src.replace(old, new))
+    import oracle
+
+    # run the pins from a directory of their own so that `import oracle`
+    # finds the mutated copy first (the rest comes from the repository)
+    shutil.copy(os.path.join(ROOT, "tests", "test_oracle_amr.py"), tmp_path / "test_oracle_amr.py")
+    env = dict(os.environ, HYDRO_ORACLE_LIB=oracle.LIB_PATH, OMP_NUM_THREADS="4",
+               PYTHONPATH=os.pathsep.join([str(tmp_path), ROOT, os.environ.get("PYTHONPATH", "")]))
+    probe = subprocess.run([sys.executable, "-c", "import oracle.amr as a; print(a.__file__)"], cwd=tmp_path,
+                           env=env, capture_output=True, text=True, timeout=120)
+    assert probe.stdout.strip().startswith(str(tmp_path)), probe.stdout + probe.stderr
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "test_oracle_amr.py"], cwd=tmp_path, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1 and " failed" in r.stdout, f"mutation {name} survived the AMR pins:\n{r.stdout[-2000:]}"

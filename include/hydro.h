@@ -270,6 +270,65 @@ int hydro_copy_probe(const double *src, double *dst, size_t n, void *stream);
 /* Message of the last failed call on this thread ("" if none). */
 const char *hydro_last_error(void);
 
+/* ---- two-level static AMR ------------------------------------------------
+ * (§2: the Grid unit's block-structured mesh with adaptive refinement:
+ * blocks of nxb^3 cells, guard cells across refinement jumps, conservative
+ * fluxes at fine-coarse faces.)  A root grid of nblk blocks (level 0) whose
+ * flagged blocks are each covered by eight children at half the cell size
+ * (level 1), refinement fixed at creation; every leaf takes the
+ * predictor-corrector step with the same dt:
+ *   1. guard fill: root blocks by the same-level map over the root state
+ *      (refined root blocks hold the restriction of their children); fine
+ *      blocks copy fine cells where their guard positions lie in refined
+ *      root blocks and are otherwise prolonged from the root cell under
+ *      them: U_c + sum_d S_d (+-1/4), S_d the van Leer slope of the conserved
+ *      variable over root cells d-1, d, d+1, keeping U_c if the result has
+ *      rho <= 0 or p <= 0 (positions beyond the domain mapped at their own
+ *      level: periodic or outflow per axis);
+ *   2. the step of each leaf from its guarded view (lam = dt/dx of its
+ *      level), keeping its boundary fluxes;
+ *   3. refluxing: a root leaf's cell next to a face shared with a refined
+ *      root block replaces its face flux by the mean of the four fine fluxes
+ *      over it;
+ *   4. restriction: each refined root block takes the mean of its children.
+ * Layouts (device, caller-owned, 256-byte aligned): Ur [nroot][5][nxb^3]
+ * (block id bx + nb0*(by + nb1*bz)); Uf [8*nrefined][5][nxb^3], the
+ * children of the refined root blocks in increasing root id, child
+ * cx + 2*cy + 4*cz covering cells (cx*nxb/2.., cy*nxb/2.., cz*nxb/2..) of its
+ * parent; nxb^3 cells per child at half the parent's cell width.  The step
+ * updates Ur and Uf in place (new states are formed in the workspace and
+ * copied back).  refine: host flags, one per root block, copied at creation. */
+typedef struct hydro_amr hydro_amr;
+typedef struct {
+  int nxb;                     /* 8, 16 or 32 */
+  int nguard;                  /* must be HYDRO_NGUARD */
+  int nblk[3];                 /* root blocks per axis */
+  double lo[3], hi[3];         /* domain; root dx_d = (hi - lo)/(nblk_d*nxb) */
+  int bc[3];                   /* HYDRO_BC_* per axis */
+  double gamma, small_p;
+  const unsigned char *refine; /* host, nblk[0]*nblk[1]*nblk[2] flags */
+  double *Ur;                  /* device root state */
+  double *Uf;                  /* device fine state (may be NULL without refinement) */
+  void *work;                  /* device workspace, hydro_amr_work_bytes */
+  size_t work_bytes;
+  void *stream;                /* hipStream_t */
+} hydro_amr_desc;
+
+/* Number of fine blocks (8 per flagged root block); 0 for an invalid descriptor. */
+size_t hydro_amr_fine_blocks(const hydro_amr_desc *d);
+/* Workspace bytes: guarded views, new states, boundary fluxes, step scratch, tables. */
+size_t hydro_amr_work_bytes(const hydro_amr_desc *d);
+/* Validate and build the mesh tables (uploaded to the workspace; waits for
+ * the upload).  Errors: HYDRO_EINVAL, HYDRO_ESIZE, HYDRO_EDEVICE. */
+int hydro_amr_create(const hydro_amr_desc *d, hydro_amr **out);
+/* One step of size dt (stream-ordered). */
+int hydro_amr_step(hydro_amr *a, double dt);
+/* dt = cfl / max over leaves of sum_d (|u_d|+c)/dx_d of their level (waits). */
+int hydro_amr_dt(hydro_amr *a, double cfl, double *dt_out);
+/* Event counters summed since creation: floors, fallbacks, nonphysical cells (waits). */
+int hydro_amr_counters(hydro_amr *a, long long out[3]);
+int hydro_amr_free(hydro_amr *a);
+
 #ifdef __cplusplus
 }
 #endif

@@ -707,3 +707,234 @@ int hydro_copy_probe(const double* src, double* dst, size_t n, void* stream) {
 const char* hydro_last_error(void) { return g_err; }
 
 }  // extern "C"
+
+// ---- two-level static AMR ---------------------------------------------------
+
+struct hydro_amr {
+  hydro_amr_desc d;
+  hydro::AmrLaunch L;
+  std::vector<unsigned char> refine;
+};
+
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct AmrLayout {
+  long nroot, nfine, nleaf0, nrefined, nreflux, ngroups, chunk;
+  size_t o_tab, o_G0, o_G1, o_Urn, o_Ufn, o_f0, o_f1, o_sc, total;
+  std::vector<int> leaf0, child_base, fine_root, refined;
+  std::vector<int> reflux;  // 4 ints per entry, grouped by coarse leaf
+  std::vector<int> first;   // ngroups + 1 entry offsets
+};
+
+int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
+  if (!d) return fail(HYDRO_EINVAL, "descriptor is NULL");
+  if (d->nxb != 8 && d->nxb != 16 && d->nxb != 32) return fail(HYDRO_EINVAL, "nxb must be 8, 16 or 32");
+  if (d->nguard != HYDRO_NGUARD) return fail(HYDRO_EINVAL, "nguard must be %d", HYDRO_NGUARD);
+  for (int a = 0; a < 3; ++a) {
+    if (d->nblk[a] < 1) return fail(HYDRO_EINVAL, "nblk[%d] must be >= 1", a);
+    if (!(std::isfinite(d->lo[a]) && std::isfinite(d->hi[a]) && d->hi[a] > d->lo[a]))
+      return fail(HYDRO_EINVAL, "domain axis %d needs finite lo < hi", a);
+    if (d->bc[a] != HYDRO_BC_PERIODIC && d->bc[a] != HYDRO_BC_OUTFLOW) return fail(HYDRO_EINVAL, "bad bc[%d]", a);
+  }
+  if (!(std::isfinite(d->gamma) && d->gamma > 1.0)) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
+  if (!d->refine) return fail(HYDRO_EINVAL, "refine flags are NULL");
+  const int N = d->nxb;
+  const long nb0 = d->nblk[0], nb1 = d->nblk[1], nb2 = d->nblk[2];
+  A.nroot = nb0 * nb1 * nb2;
+  if (A.nroot > (1L << 24)) return fail(HYDRO_EINVAL, "too many root blocks");
+  A.leaf0.clear();
+  A.refined.clear();
+  A.child_base.assign(A.nroot, -1);
+  for (long b = 0; b < A.nroot; ++b) {
+    if (d->refine[b]) {
+      A.child_base[b] = (int)(8 * A.refined.size());
+      A.refined.push_back((int)b);
+    } else {
+      A.leaf0.push_back((int)b);
+    }
+  }
+  A.nrefined = (long)A.refined.size();
+  A.nfine = 8 * A.nrefined;
+  A.nleaf0 = (long)A.leaf0.size();
+  A.fine_root.assign(A.nfine, 0);
+  for (long q = 0; q < A.nrefined; ++q)
+    for (int c = 0; c < 8; ++c) A.fine_root[8 * q + c] = A.refined[q];
+  A.reflux.clear();
+  A.first.assign(1, 0);
+  for (int b : A.leaf0) {
+    const long bx = b % nb0, by = (b / nb0) % nb1, bz = b / (nb0 * nb1);
+    for (int dd = 0; dd < 3; ++dd)
+      for (int side = 0; side < 2; ++side) {
+        long pos[3] = {bx, by, bz};
+        const long nb[3] = {nb0, nb1, nb2};
+        pos[dd] += side ? 1 : -1;
+        if (d->bc[dd] == HYDRO_BC_PERIODIC) pos[dd] = (pos[dd] + nb[dd]) % nb[dd];
+        else if (pos[dd] < 0 || pos[dd] >= nb[dd]) continue;
+        const long nbr = pos[0] + nb0 * (pos[1] + nb1 * pos[2]);
+        if (!d->refine[nbr]) continue;
+        A.reflux.insert(A.reflux.end(), {b, dd, side, (int)nbr});
+      }
+    if ((int)A.reflux.size() / 4 > A.first.back()) A.first.push_back((int)A.reflux.size() / 4);
+  }
+  A.nreflux = (long)A.reflux.size() / 4;
+  A.ngroups = (long)A.first.size() - 1;
+  const long P = N + 2 * HYDRO_NGUARD;
+  const long per = hydro::amr_block_doubles(N) * (long)sizeof(double);
+  const long most = std::max(std::max(A.nleaf0, A.nfine), 1L);
+  A.chunk = std::max(1L, std::min(most, (4L << 30) / per));
+  const size_t tab = sizeof(int) * (size_t)(A.nleaf0 + A.nroot + A.nfine + A.nrefined + 4 * A.nreflux +
+                                             A.ngroups + 1);
+  A.o_tab = 256;
+  A.o_G0 = A.o_tab + al256(tab);
+  A.o_G1 = A.o_G0 + al256(sizeof(double) * 5 * P * P * P * A.nroot);
+  A.o_Urn = A.o_G1 + al256(sizeof(double) * 5 * P * P * P * A.nfine);
+  A.o_Ufn = A.o_Urn + al256(sizeof(double) * 5 * (size_t)N * N * N * A.nroot);
+  A.o_f0 = A.o_Ufn + al256(sizeof(double) * 5 * (size_t)N * N * N * A.nfine);
+  A.o_f1 = A.o_f0 + al256(sizeof(double) * 30 * (size_t)N * N * A.nroot);
+  A.o_sc = A.o_f1 + al256(sizeof(double) * 30 * (size_t)N * N * A.nfine);
+  A.total = A.o_sc + al256((size_t)per * A.chunk);
+  return HYDRO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hydro_amr_fine_blocks(const hydro_amr_desc* d) {
+  AmrLayout A;
+  if (amr_layout(d, A)) return 0;
+  return (size_t)A.nfine;
+}
+
+size_t hydro_amr_work_bytes(const hydro_amr_desc* d) {
+  AmrLayout A;
+  if (amr_layout(d, A)) return 0;
+  return A.total;
+}
+
+int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
+  if (!out) return fail(HYDRO_EINVAL, "out is NULL");
+  *out = nullptr;
+  AmrLayout A;
+  int rc = amr_layout(d, A);
+  if (rc) return rc;
+  if (!d->Ur || (A.nfine && !d->Uf)) return fail(HYDRO_EINVAL, "state buffers must be non-NULL");
+  if (!d->work || ((uintptr_t)d->work & 255)) return fail(HYDRO_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  if (d->work_bytes < A.total) return fail(HYDRO_ESIZE, "AMR workspace has %zu bytes, needs %zu", d->work_bytes, A.total);
+  rc = check_device();
+  if (rc) return rc;
+  hydro_amr* a = new (std::nothrow) hydro_amr;
+  if (!a) return fail(HYDRO_EINVAL, "out of host memory");
+  a->d = *d;
+  a->refine.assign(d->refine, d->refine + A.nroot);
+  a->d.refine = a->refine.data();
+  hydro::AmrLaunch& L = a->L;
+  const int N = d->nxb;
+  for (int ax = 0; ax < 3; ++ax) {
+    L.g0.nb[ax] = d->nblk[ax];
+    L.g0.bc[ax] = d->bc[ax];
+    L.g0.inv_dx[ax] = ((double)d->nblk[ax] * N) / (d->hi[ax] - d->lo[ax]);
+    L.g1.nb[ax] = 2 * d->nblk[ax];
+    L.g1.bc[ax] = d->bc[ax];
+    L.g1.inv_dx[ax] = 2.0 * L.g0.inv_dx[ax];
+  }
+  L.g0.gamma = L.g1.gamma = d->gamma;
+  L.g0.small_p = L.g1.small_p = d->small_p;
+  char* w = (char*)d->work;
+  int* tab = (int*)(w + A.o_tab);
+  // table order: reflux entries first (int4, 16-byte aligned at the table start)
+  std::vector<int> host;
+  host.insert(host.end(), A.reflux.begin(), A.reflux.end());
+  host.insert(host.end(), A.leaf0.begin(), A.leaf0.end());
+  host.insert(host.end(), A.child_base.begin(), A.child_base.end());
+  host.insert(host.end(), A.fine_root.begin(), A.fine_root.end());
+  host.insert(host.end(), A.refined.begin(), A.refined.end());
+  host.insert(host.end(), A.first.begin(), A.first.end());
+  L.reflux = (const int4*)tab;
+  L.leaf0 = tab + 4 * A.nreflux;
+  L.child_base = L.leaf0 + A.nleaf0;
+  L.fine_root = L.child_base + A.nroot;
+  L.refined = L.fine_root + A.nfine;
+  L.reflux_first = L.refined + A.nrefined;
+  L.Ur = d->Ur;
+  L.Uf = d->Uf;
+  L.G0 = (double*)(w + A.o_G0);
+  L.G1 = (double*)(w + A.o_G1);
+  L.Ur_new = (double*)(w + A.o_Urn);
+  L.Uf_new = (double*)(w + A.o_Ufn);
+  L.flux0 = (double*)(w + A.o_f0);
+  L.flux1 = (double*)(w + A.o_f1);
+  L.scratch = (double*)(w + A.o_sc);
+  L.ws = (hydro::WorkHeader*)w;
+  L.nroot = A.nroot;
+  L.nleaf0 = A.nleaf0;
+  L.nfine = A.nfine;
+  L.nrefined = A.nrefined;
+  L.nreflux = A.nreflux;
+  L.nreflux_groups = A.ngroups;
+  L.chunk = A.chunk;
+  L.dt = 0.0;
+  hipStream_t s = (hipStream_t)d->stream;
+  hipError_t e = hipMemsetAsync(w, 0, 256, s);
+  if (e == hipSuccess && !host.empty())
+    e = hipMemcpyAsync(tab, host.data(), sizeof(int) * host.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host table is temporary
+  if (e != hipSuccess) {
+    delete a;
+    return hip_fail(e, "AMR table upload");
+  }
+  *out = a;
+  return HYDRO_OK;
+}
+
+int hydro_amr_step(hydro_amr* a, double dt) {
+  if (!a) return fail(HYDRO_EINVAL, "handle is NULL");
+  if (!finite_pos(dt)) return fail(HYDRO_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+  a->L.dt = dt;
+  hipStream_t s = (hipStream_t)a->d.stream;
+  hipError_t e = hydro::launch_amr_step(a->d.nxb, a->L, s);
+  if (e != hipSuccess) return hip_fail(e, "AMR step launch");
+  const size_t N3 = (size_t)a->d.nxb * a->d.nxb * a->d.nxb;
+  e = hipMemcpyAsync(a->d.Ur, a->L.Ur_new, sizeof(double) * 5 * N3 * a->L.nroot, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && a->L.nfine)
+    e = hipMemcpyAsync(a->d.Uf, a->L.Uf_new, sizeof(double) * 5 * N3 * a->L.nfine, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "AMR state copy");
+  return HYDRO_OK;
+}
+
+int hydro_amr_dt(hydro_amr* a, double cfl, double* dt_out) {
+  if (!a || !dt_out) return fail(HYDRO_EINVAL, "handle or dt_out is NULL");
+  if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
+  hipStream_t s = (hipStream_t)a->d.stream;
+  hipError_t e = hydro::launch_amr_signal(a->d.nxb, a->L, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "AMR signal launch");
+  hydro::WorkHeader h;
+  e = hipMemcpyAsync(&h, a->d.work, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "AMR header read");
+  double sig;
+  memcpy(&sig, &h.sig[0], sizeof sig);
+  if (!(std::isfinite(sig) && sig > 0.0)) return fail(HYDRO_EINVAL, "maximum signal speed %g is not positive and finite", sig);
+  *dt_out = cfl / sig;
+  return HYDRO_OK;
+}
+
+int hydro_amr_counters(hydro_amr* a, long long out[3]) {
+  if (!a || !out) return fail(HYDRO_EINVAL, "handle or out is NULL");
+  hipStream_t s = (hipStream_t)a->d.stream;
+  hydro::WorkHeader h;
+  hipError_t e = hipMemcpyAsync(&h, a->d.work, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "AMR header read");
+  for (int c = 0; c < 3; ++c) out[c] = (long long)h.cnt[c];
+  return HYDRO_OK;
+}
+
+int hydro_amr_free(hydro_amr* a) {
+  delete a;
+  return HYDRO_OK;
+}
+
+}  // extern "C"

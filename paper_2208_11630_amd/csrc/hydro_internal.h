@@ -84,4 +84,31 @@ hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, double* scr
 hipError_t launch_clear_slot(WorkHeader* ws, int slot, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, long n, hipStream_t s);
 
+// Two-level static AMR step (see hydro_kernels.hip): everything one step
+// needs, device pointers into the caller's state and workspace.
+struct AmrLaunch {
+  GridGeom g0, g1;            // root and fine level geometry (inv_dx per level)
+  const double* Ur;           // root state (refined blocks hold the restriction)
+  const double* Uf;           // fine state
+  double* Ur_new;
+  double* Uf_new;
+  double* G0;                 // guarded views: root blocks, fine blocks
+  double* G1;
+  double* flux0;              // boundary fluxes per root block / fine block
+  double* flux1;
+  double* scratch;            // chunk * amr_block_doubles
+  const int* leaf0;           // unrefined root blocks
+  const int* child_base;      // per root block: first child, or -1
+  const int* fine_root;       // per fine block: its root block
+  const int* refined;         // refined root blocks
+  const int4* reflux;         // (coarse leaf, d, side, refined neighbour), grouped by coarse leaf
+  const int* reflux_first;    // nreflux_groups + 1 offsets into reflux
+  WorkHeader* ws;
+  long nroot, nleaf0, nfine, nrefined, nreflux, nreflux_groups, chunk;
+  double dt;
+};
+long amr_block_doubles(int nxb);
+hipError_t launch_amr_step(int nxb, const AmrLaunch& L, hipStream_t s);
+hipError_t launch_amr_signal(int nxb, const AmrLaunch& L, int slot, hipStream_t s);
+
 }  // namespace hydro

@@ -1027,6 +1027,299 @@ __global__ __launch_bounds__(256) void ctu_kernel(GridGeom g, StepArgs a, double
 }
 
 // ---------------------------------------------------------------------------
+// Two-level static AMR (the Grid unit's block-structured refinement): a root
+// grid (level 0) whose refined blocks are covered by eight children at half
+// the cell size (level 1).  Kernels: the guard fill of the fine blocks
+// (copies from fine neighbours, prolongation from the root cells elsewhere),
+// the predictor-corrector step of a leaf from its guarded view (also writing
+// its boundary fluxes), refluxing at fine-coarse faces and restriction.
+
+template <int N>
+struct AmrStep {
+  static constexpr int P = N + 2 * G;        // guarded edge
+  static constexpr long P3 = (long)P * P * P;
+  static constexpr int M = N + 4, m = N + 2;
+  static constexpr long M3 = (long)M * M * M, m3 = (long)m * m * m;
+  static constexpr long oW = 0, oWf = 5 * M3, oF = oWf + 30 * m3;
+  static constexpr long doubles = oF + 15 * m3;   // scratch per block
+  static constexpr long NF = 6L * 5 * N * N;      // boundary fluxes per block
+  __device__ static int ci(int i, int j, int k) { return ((k + 1) * m + (j + 1)) * m + (i + 1); }
+  __device__ static int cW(int i, int j, int k) { return ((k + 2) * M + (j + 2)) * M + (i + 2); }
+};
+
+// Fine guarded views: fine block f = child c of root block fine_root[f]
+// (children contiguous, c = f - child_base[root]); every cell of the view
+// either copies the fine cell at its level-1 position (when that position
+// lies in a refined root block) or is prolonged from the root cell under it:
+// U_c + sum_d S_d * (+-1/4), S_d the van Leer slope of the conserved variable
+// over the root cells (level-0 map), keeping U_c if the result has rho <= 0
+// or p <= 0.
+template <int N>
+__global__ __launch_bounds__(256) void amr_fill_fine_kernel(GridGeom g0, const double* __restrict__ Ur,
+                                                            const double* __restrict__ Uf,
+                                                            const int* __restrict__ child_base,
+                                                            const int* __restrict__ fine_root,
+                                                            double* __restrict__ G1) {
+  using A = AmrStep<N>;
+  constexpr int P = A::P;
+  const int f = blockIdx.x;
+  const int r = fine_root[f];
+  const int c = f - child_base[r];
+  const int bx = r % g0.nb[0], by = (r / g0.nb[0]) % g0.nb[1], bz = r / (g0.nb[0] * g0.nb[1]);
+  const int X0 = 2 * bx * N + (c & 1) * N, Y0 = 2 * by * N + ((c >> 1) & 1) * N, Z0 = 2 * bz * N + ((c >> 2) & 1) * N;
+  const int NF0 = 2 * g0.nb[0] * N, NF1 = 2 * g0.nb[1] * N, NF2 = 2 * g0.nb[2] * N;
+  double* out = G1 + (long)f * 5 * A::P3;
+  for (int t = threadIdx.x; t < P * P * P; t += blockDim.x) {
+    const int i = t % P - G, j = (t / P) % P - G, k = t / (P * P) - G;
+    int I = X0 + i, J = Y0 + j, K = Z0 + k;
+    I = g0.bc[0] == 0 ? (I < 0 ? I + NF0 : (I >= NF0 ? I - NF0 : I)) : min(max(I, 0), NF0 - 1);
+    J = g0.bc[1] == 0 ? (J < 0 ? J + NF1 : (J >= NF1 ? J - NF1 : J)) : min(max(J, 0), NF1 - 1);
+    K = g0.bc[2] == 0 ? (K < 0 ? K + NF2 : (K >= NF2 ? K - NF2 : K)) : min(max(K, 0), NF2 - 1);
+    const int rb = I / (2 * N) + g0.nb[0] * (J / (2 * N) + g0.nb[1] * (K / (2 * N)));
+    double val[5];
+    if (child_base[rb] >= 0) {
+      const int fb = child_base[rb] + (I / N) % 2 + 2 * ((J / N) % 2) + 4 * ((K / N) % 2);
+      load_cons<N>(Uf, Layout<N>::at(fb, I % N, J % N, K % N), val);
+    } else {
+      const int Ic = I / 2, Jc = J / 2, Kc = K / 2;
+      double uc[5];
+      load_cons<N>(Ur, cell_offset<N>(g0, Ic, Jc, Kc), uc);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) val[v] = uc[v];
+      const int off[3] = {(I & 1) * 2 - 1, (J & 1) * 2 - 1, (K & 1) * 2 - 1};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double um[5], up[5];
+        load_cons<N>(Ur, cell_offset<N>(g0, Ic - (d == 0), Jc - (d == 1), Kc - (d == 2)), um);
+        load_cons<N>(Ur, cell_offset<N>(g0, Ic + (d == 0), Jc + (d == 1), Kc + (d == 2)), up);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) val[v] += van_leer_sf(uc[v] - um[v], up[v] - uc[v]) * (0.25 * off[d]);
+      }
+      const double rho = val[0];
+      const double kin = 0.5 * ((val[1] * val[1] + val[2] * val[2]) + val[3] * val[3]) / (rho > 0.0 ? rho : 1.0);
+      const double p = (g0.gamma - 1.0) * (val[4] - kin);
+      if (!(rho > 0.0 && p > 0.0)) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) val[v] = uc[v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[v * A::P3 + t] = val[v];
+  }
+}
+
+// Predictor-corrector step of one leaf block from its guarded view (the
+// oracle's per-block formulation: primitives of the footprint, Hancock
+// predictor with the positivity fallback, HLLC at every face the update
+// uses, update), with a per-workgroup scratch slice; boundary fluxes go to
+// flux[block][face 2d+side][v][a][b] (a, b: the transverse indices, slower
+// axis first).  The block id of workgroup w is list[b0 + w] (or b0 + w).
+template <int N>
+__global__ __launch_bounds__(256) void amr_step_kernel(GridGeom g, const double* __restrict__ Gin,
+                                                       double* __restrict__ Uout, const int* __restrict__ list,
+                                                       double* __restrict__ flux, double* __restrict__ scratch,
+                                                       long b0, double dt, WorkHeader* ws) {
+  using A = AmrStep<N>;
+  constexpr int P = A::P, M = A::M, m = A::m;
+  __shared__ int sCnt[3];
+  const int tid = threadIdx.x;
+  const long w = b0 + blockIdx.x;
+  const long blk = list ? list[w] : w;
+  const double* gin = Gin + blk * 5 * A::P3;
+  double* sc = scratch + (long)blockIdx.x * A::doubles;
+  double* W = sc + A::oW;
+  double* Wf = sc + A::oWf;
+  double* F = sc + A::oF;
+  if (tid < 3) sCnt[tid] = 0;
+  const double lamx = dt * g.inv_dx[0], lamy = dt * g.inv_dx[1], lamz = dt * g.inv_dx[2];
+  const double gamma = g.gamma, gm1inv = 1.0 / (g.gamma - 1.0);
+  int n_floor = 0, n_fb = 0, n_bad = 0;
+  auto gat = [&](int i, int j, int k) -> long { return ((long)(k + G) * P + (j + G)) * P + (i + G); };
+
+  for (int it = tid; it < M * M * M; it += 256) {
+    const int i = it % M - 2, j = (it / M) % M - 2, k = it / (M * M) - 2;
+    double u[5], wv[5], inv;
+    const long o = gat(i, j, k);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = gin[v * A::P3 + o];
+    const int fl = prim(u, gamma, g.small_p, wv, inv);
+    if (fl && i >= 0 && i < N && j >= 0 && j < N && k >= 0 && k < N) ++n_floor;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) W[v * A::M3 + it] = wv[v];
+  }
+  __syncthreads();
+
+  for (int it = tid; it < m * m * m; it += 256) {
+    const int i = it % m - 1, j = (it / m) % m - 1, k = it / (m * m) - 1;
+    const int c = A::cW(i, j, k);
+    double wc[5], sx[5], sy[5], sz[5], wt[5], h;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      wc[v] = W[v * A::M3 + c];
+      sx[v] = van_leer_sf(wc[v] - W[v * A::M3 + c - 1], W[v * A::M3 + c + 1] - wc[v]);
+      sy[v] = van_leer_sf(wc[v] - W[v * A::M3 + c - M], W[v * A::M3 + c + M] - wc[v]);
+      sz[v] = van_leer_sf(wc[v] - W[v * A::M3 + c - M * M], W[v * A::M3 + c + M * M] - wc[v]);
+    }
+    const bool ok = predict(wc, rcp_nr(wc[0]), sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
+    if (!ok && i >= 0 && i < N && j >= 0 && j < N && k >= 0 && k < N) ++n_fb;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Wf[(0 * 5 + v) * A::m3 + it] = fma(-h, sx[v], wt[v]);
+      Wf[(1 * 5 + v) * A::m3 + it] = fma(h, sx[v], wt[v]);
+      Wf[(2 * 5 + v) * A::m3 + it] = fma(-h, sy[v], wt[v]);
+      Wf[(3 * 5 + v) * A::m3 + it] = fma(h, sy[v], wt[v]);
+      Wf[(4 * 5 + v) * A::m3 + it] = fma(-h, sz[v], wt[v]);
+      Wf[(5 * 5 + v) * A::m3 + it] = fma(h, sz[v], wt[v]);
+    }
+  }
+  __syncthreads();
+
+  // fluxes at the low d-face of cells with c_d in 0..N, the others in 0..N-1
+  for (int d = 0; d < 3; ++d) {
+    for (int it = tid; it < (N + 1) * N * N; it += 256) {
+      int c3[3];
+      const int a0 = it % N, a1 = (it / N) % N, a2 = it / (N * N);
+      const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      c3[t0] = a0;
+      c3[t1] = a1;
+      c3[d] = a2;
+      const int hi = A::ci(c3[0], c3[1], c3[2]);
+      const int lo = A::ci(c3[0] - (d == 0), c3[1] - (d == 1), c3[2] - (d == 2));
+      double L[5], R[5], Fv[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        L[v] = Wf[((2 * d + 1) * 5 + v) * A::m3 + lo];
+        R[v] = Wf[((2 * d + 0) * 5 + v) * A::m3 + hi];
+      }
+      hllc_dir(d, L, R, gamma, gm1inv, Fv);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) F[(d * 5 + v) * A::m3 + hi] = Fv[v];
+      // boundary faces of the block (c_d = 0: face 2d, c_d = N: face 2d+1)
+      if (a2 == 0 || a2 == N) {
+        // transverse indices, slower axis first: (t1, t0)
+        double* fo = flux + blk * A::NF + (long)(2 * d + (a2 == N)) * 5 * N * N;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fo[(long)v * N * N + a1 * N + a0] = Fv[v];
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int it = tid; it < N * N * N; it += 256) {
+    const int i = it % N, j = (it / N) % N, k = it / (N * N);
+    const int c0 = A::ci(i, j, k);
+    const int cx = A::ci(i + 1, j, k), cy = A::ci(i, j + 1, k), cz = A::ci(i, j, k + 1);
+    const long o = gat(i, j, k);
+    double un[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double div = (lamx * (F[(0 * 5 + v) * A::m3 + cx] - F[(0 * 5 + v) * A::m3 + c0]) +
+                          lamy * (F[(1 * 5 + v) * A::m3 + cy] - F[(1 * 5 + v) * A::m3 + c0])) +
+                         lamz * (F[(2 * 5 + v) * A::m3 + cz] - F[(2 * 5 + v) * A::m3 + c0]);
+      un[v] = gin[v * A::P3 + o] - div;
+      Uout[Layout<N>::at(blk, i, j, k) + v * Layout<N>::VS] = un[v];
+    }
+    bool good = un[0] > 0.0 && un[4] > 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) good = good && isfinite(un[v]);
+    if (!good) ++n_bad;
+  }
+  if (n_floor) atomicAdd(&sCnt[0], n_floor);
+  if (n_fb) atomicAdd(&sCnt[1], n_fb);
+  if (n_bad) atomicAdd(&sCnt[2], n_bad);
+  __syncthreads();
+  if (tid == 0) {
+    for (int q = 0; q < 3; ++q)
+      if (sCnt[q]) atomicAdd(&ws->cnt[q], (unsigned long long)sCnt[q]);
+  }
+}
+
+// Refluxing: entry e = (coarse leaf b, direction d, side, refined neighbour
+// r).  The root cell of b next to the face replaces its face flux by the mean
+// of the four fine fluxes over it: U += lam_d (F_c - <F_f>) on the high face
+// (side 1), U -= lam_d (F_c - <F_f>) on the low face.  Entries of one coarse
+// block are contiguous (first[w] .. first[w+1]) and one workgroup applies
+// them in order: faces of one block share their edge and corner cells.
+template <int N>
+__global__ __launch_bounds__(256) void amr_reflux_kernel(GridGeom g0, const int4* __restrict__ entries,
+                                                         const int* __restrict__ first,
+                                                         const double* __restrict__ flux0,
+                                                         const double* __restrict__ flux1,
+                                                         const int* __restrict__ child_base, double* Ur, double dt) {
+  using A = AmrStep<N>;
+  constexpr int H = N / 2;
+  const int e_end = first[blockIdx.x + 1];
+  for (int q = first[blockIdx.x]; q < e_end; ++q) {
+    const int4 e = entries[q];
+    const int b = e.x, d = e.y, side = e.z, r = e.w;
+    const double lam = dt * g0.inv_dx[d];
+    const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;   // faster, slower transverse axes
+    const double* fc = flux0 + (long)b * A::NF + (long)(2 * d + side) * 5 * N * N;
+    const int fside = side ? 0 : 1;                        // the refined block's face toward b
+    for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
+      const int a1 = t / N, a0 = t % N;                    // slower, faster transverse index
+      int co[3];
+      co[d] = fside;
+      co[t0] = a0 / H;
+      co[t1] = a1 / H;
+      const int fb = child_base[r] + co[0] + 2 * co[1] + 4 * co[2];
+      const double* ff = flux1 + (long)fb * A::NF + (long)(2 * d + fside) * 5 * N * N;
+      const int f1 = 2 * (a1 % H), f0 = 2 * (a0 % H);
+      int c3[3];
+      c3[d] = side ? N - 1 : 0;
+      c3[t0] = a0;
+      c3[t1] = a1;
+      const long off = Layout<N>::at(b, c3[0], c3[1], c3[2]);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double* fv = ff + (long)v * N * N;
+        const double mean =
+            0.25 * ((fv[f1 * N + f0] + fv[f1 * N + f0 + 1]) + (fv[(f1 + 1) * N + f0] + fv[(f1 + 1) * N + f0 + 1]));
+        const double corr = lam * (fc[(long)v * N * N + t] - mean);
+        Ur[off + v * Layout<N>::VS] += side ? corr : -corr;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Restriction: root block refined[w] takes the mean of its children.
+template <int N>
+__global__ __launch_bounds__(256) void amr_restrict_kernel(const int* __restrict__ refined,
+                                                           const int* __restrict__ child_base,
+                                                           const double* __restrict__ Uf, double* __restrict__ Ur) {
+  constexpr int H = N / 2;
+  const int r = refined[blockIdx.x];
+  for (int t = threadIdx.x; t < N * N * N; t += blockDim.x) {
+    const int i = t % N, j = (t / N) % N, k = t / (N * N);
+    const int fb = child_base[r] + (i / H) + 2 * (j / H) + 4 * (k / H);
+    const int fi = 2 * (i % H), fj = 2 * (j % H), fk = 2 * (k % H);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double s = 0.0;
+      for (int q = 0; q < 8; ++q) s += Uf[Layout<N>::at(fb, fi + (q & 1), fj + ((q >> 1) & 1), fk + ((q >> 2) & 1)) + v * Layout<N>::VS];
+      Ur[Layout<N>::at(r, i, j, k) + v * Layout<N>::VS] = s * 0.125;
+    }
+  }
+}
+
+// Summed signal speed over the listed blocks (all when list is null).
+template <int N>
+__global__ __launch_bounds__(256) void amr_signal_kernel(GridGeom g, const double* __restrict__ U,
+                                                         const int* __restrict__ list, unsigned long long* slot) {
+  __shared__ unsigned long long sRed[4];
+  const long blk = list ? list[blockIdx.x] : blockIdx.x;
+  double smax = 0.0;
+  for (int t = threadIdx.x; t < N * N * N; t += 256) {
+    double u[5];
+    load_cons<N>(U, Layout<N>::at(blk, t % N, (t / N) % N, t / (N * N)), u);
+    const double s = signal_speed(u, g);
+    smax = (s > smax || !(s == s)) ? s : smax;
+  }
+  wg_max_to(smax, sRed, slot);
+}
+
+// ---------------------------------------------------------------------------
 // Guard fill: one workgroup per (block, plane of the guarded view); every
 // cell of the guarded view (interior and guard layers, faces, edges and
 // corners) receives the state value at its mapped global index.
@@ -1112,6 +1405,76 @@ hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const Stag
     case 32: return launch_step_t<32, 16>(g, a, st, plen, s);
   }
   return hipErrorInvalidValue;
+}
+
+long amr_block_doubles(int nxb) {
+  switch (nxb) {
+    case 8: return AmrStep<8>::doubles;
+    case 16: return AmrStep<16>::doubles;
+    case 32: return AmrStep<32>::doubles;
+  }
+  return 0;
+}
+
+template <int N>
+hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
+  using A = AmrStep<N>;
+  (void)sizeof(A);
+  // 1. guard fill: root blocks (same-level map), fine blocks (copies / prolongation)
+  hipLaunchKernelGGL(fill_guards_kernel<N>, dim3((unsigned)(L.nroot * Guarded<N>::P)), dim3(256), 0, s, L.g0, L.Ur,
+                     L.G0);
+  if (L.nfine)
+    hipLaunchKernelGGL(amr_fill_fine_kernel<N>, dim3((unsigned)L.nfine), dim3(256), 0, s, L.g0, L.Ur, L.Uf,
+                       L.child_base, L.fine_root, L.G1);
+  // 2. leaf steps in chunks of workgroups sharing the scratch
+  for (long b0 = 0; b0 < L.nleaf0; b0 += L.chunk) {
+    const long n = L.nleaf0 - b0 < L.chunk ? L.nleaf0 - b0 : L.chunk;
+    hipLaunchKernelGGL(amr_step_kernel<N>, dim3((unsigned)n), dim3(256), 0, s, L.g0, L.G0, L.Ur_new, L.leaf0,
+                       L.flux0, L.scratch, b0, L.dt, L.ws);
+  }
+  for (long b0 = 0; b0 < L.nfine; b0 += L.chunk) {
+    const long n = L.nfine - b0 < L.chunk ? L.nfine - b0 : L.chunk;
+    hipLaunchKernelGGL(amr_step_kernel<N>, dim3((unsigned)n), dim3(256), 0, s, L.g1, L.G1, L.Uf_new,
+                       (const int*)nullptr, L.flux1, L.scratch, b0, L.dt, L.ws);
+  }
+  // 3. refluxing, 4. restriction
+  if (L.nreflux_groups)
+    hipLaunchKernelGGL(amr_reflux_kernel<N>, dim3((unsigned)L.nreflux_groups), dim3(256), 0, s, L.g0, L.reflux,
+                       L.reflux_first, L.flux0, L.flux1, L.child_base, L.Ur_new, L.dt);
+  if (L.nrefined)
+    hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)L.nrefined), dim3(256), 0, s, L.refined,
+                       L.child_base, L.Uf_new, L.Ur_new);
+  return hipGetLastError();
+}
+
+hipError_t launch_amr_step(int nxb, const AmrLaunch& L, hipStream_t s) {
+  switch (nxb) {
+    case 8: return launch_amr_t<8>(L, s);
+    case 16: return launch_amr_t<16>(L, s);
+    case 32: return launch_amr_t<32>(L, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int N>
+void launch_amr_signal_t(const AmrLaunch& L, unsigned long long* dst, hipStream_t s) {
+  if (L.nleaf0)
+    hipLaunchKernelGGL(amr_signal_kernel<N>, dim3((unsigned)L.nleaf0), dim3(256), 0, s, L.g0, L.Ur, L.leaf0, dst);
+  if (L.nfine)
+    hipLaunchKernelGGL(amr_signal_kernel<N>, dim3((unsigned)L.nfine), dim3(256), 0, s, L.g1, L.Uf,
+                       (const int*)nullptr, dst);
+}
+
+hipError_t launch_amr_signal(int nxb, const AmrLaunch& L, int slot, hipStream_t s) {
+  unsigned long long* dst = &L.ws->sig[slot];
+  hipLaunchKernelGGL(clear_slot_kernel, dim3(1), dim3(1), 0, s, L.ws, slot);
+  switch (nxb) {
+    case 8: launch_amr_signal_t<8>(L, dst, s); break;
+    case 16: launch_amr_signal_t<16>(L, dst, s); break;
+    case 32: launch_amr_signal_t<32>(L, dst, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 long ctu_block_doubles(int nxb) {

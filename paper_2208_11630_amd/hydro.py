@@ -68,6 +68,13 @@ SIGNATURES = {
     "hydro_counters": ([_HP, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
     "hydro_free_grid": ([_HP], ctypes.c_int),
     "hydro_set_pencils": ([_HP, ctypes.c_int], ctypes.c_int),
+    "hydro_amr_fine_blocks": ([ctypes.c_void_p], ctypes.c_size_t),
+    "hydro_amr_work_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
+    "hydro_amr_create": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "hydro_amr_step": ([ctypes.c_void_p, ctypes.c_double], ctypes.c_int),
+    "hydro_amr_dt": ([ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "hydro_amr_counters": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+    "hydro_amr_free": ([ctypes.c_void_p], ctypes.c_int),
     "hydro_set_pencil_planes": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_set_scheme": ([_HP, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "hydro_ctu_scratch_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
@@ -369,3 +376,98 @@ def grid_for(problem, device: str = "cuda", stream=None) -> Grid:
              device=device, stream=stream, nguard=problem.ng)
     g.upload(problem.Uc)
     return g
+
+
+class _AmrDesc(ctypes.Structure):
+    _fields_ = [
+        ("nxb", ctypes.c_int), ("nguard", ctypes.c_int), ("nblk", ctypes.c_int * 3),
+        ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3),
+        ("gamma", ctypes.c_double), ("small_p", ctypes.c_double),
+        ("refine", ctypes.POINTER(ctypes.c_ubyte)),
+        ("Ur", ctypes.c_void_p), ("Uf", ctypes.c_void_p),
+        ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p),
+    ]
+
+
+def make_amr_desc(nxb, nblk, refine, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(BC_PERIODIC,) * 3,
+                  gamma=1.4, small_p=1e-10, nguard=NGUARD):
+    d = _AmrDesc()
+    d.nxb, d.nguard = int(nxb), int(nguard)
+    d.nblk[:] = [int(x) for x in nblk]
+    d.lo[:] = [float(x) for x in lo]
+    d.hi[:] = [float(x) for x in hi]
+    d.bc[:] = [int(x) for x in bc]
+    d.gamma, d.small_p = float(gamma), float(small_p)
+    flags = (ctypes.c_ubyte * len(refine))(*[1 if f else 0 for f in refine])
+    d.refine = ctypes.cast(flags, ctypes.POINTER(ctypes.c_ubyte))
+    d._flags = flags  # keep the host array alive with the descriptor
+    return d
+
+
+class Amr:
+    """Two-level static AMR mesh over torch state tensors (hydro_amr_*).
+
+    Ur: root state [nroot, 5, n, n, n]; Uf: fine state [8*nrefined, 5, n, n, n]
+    (children of the refined root blocks in increasing root id)."""
+
+    def __init__(self, nxb, nblk, refine, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(BC_PERIODIC,) * 3,
+                 gamma=1.4, small_p=1e-10, device="cuda", stream=None):
+        import torch
+
+        L = lib()
+        self._torch = torch
+        d = make_amr_desc(nxb, nblk, refine, lo, hi, bc, gamma, small_p)
+        nfine = L.hydro_amr_fine_blocks(ctypes.byref(d))
+        n = int(nxb)
+        nroot = int(nblk[0]) * int(nblk[1]) * int(nblk[2])
+        self.Ur = torch.zeros((nroot, 5, n, n, n), dtype=torch.float64, device=device)
+        self.Uf = torch.zeros((max(nfine, 1), 5, n, n, n), dtype=torch.float64, device=device)
+        self.nfine = nfine
+        wb = L.hydro_amr_work_bytes(ctypes.byref(d))
+        if wb == 0:
+            raise HydroError(HYDRO_EINVAL, "invalid AMR descriptor")
+        self.work = torch.zeros(wb, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.Ur.device)
+        d.Ur, d.Uf = self.Ur.data_ptr(), self.Uf.data_ptr()
+        d.work, d.work_bytes = self.work.data_ptr(), self.work.numel()
+        d.stream = self.stream.cuda_stream
+        self.desc = d
+        h = ctypes.c_void_p()
+        _check(L.hydro_amr_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+
+    def upload(self, Ur, Uf=None) -> None:
+        t = self._torch
+        with t.cuda.stream(self.stream):
+            self.Ur.copy_(t.from_numpy(np.ascontiguousarray(Ur, dtype=np.float64)))
+            if Uf is not None and self.nfine:
+                self.Uf.copy_(t.from_numpy(np.ascontiguousarray(Uf, dtype=np.float64)))
+        self.stream.synchronize()
+
+    def download(self):
+        self.stream.synchronize()
+        return self.Ur.cpu().numpy(), self.Uf[:self.nfine].cpu().numpy()
+
+    def step(self, dt: float) -> None:
+        _check(lib().hydro_amr_step(self.handle, float(dt)))
+
+    def dt(self, cfl: float) -> float:
+        out = ctypes.c_double()
+        _check(lib().hydro_amr_dt(self.handle, float(cfl), ctypes.byref(out)))
+        return out.value
+
+    def counters(self) -> np.ndarray:
+        out = (ctypes.c_longlong * 3)()
+        _check(lib().hydro_amr_counters(self.handle, out))
+        return np.array(list(out), dtype=np.int64)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            lib().hydro_amr_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -130,3 +130,46 @@ def test_batch_null_arguments(L):
     assert L.hydro_set_scheme(None, hydro.SCHEME_RK2, None) == hydro.HYDRO_EINVAL
     assert L.hydro_copy_probe(None, None, 0, None) == hydro.HYDRO_OK
     assert L.hydro_copy_probe(None, None, 8, None) == hydro.HYDRO_EINVAL
+
+
+def test_amr_sizes_and_validation(L):
+    """Fine block count and workspace size of a two-level mesh; descriptor
+    errors before any device call."""
+    n, nb = 8, (2, 2, 1)
+    d = hydro.make_amr_desc(n, nb, [0, 1, 0, 1], bc=(0, 1, 0))
+    assert L.hydro_amr_fine_blocks(ctypes.byref(d)) == 16
+    P, m, M = n + 8, n + 2, n + 4
+    per = 8 * (5 * M ** 3 + 45 * m ** 3)
+    # reflux entries: leaves 0 and 2 face the refined blocks 1 and 3 across
+    # both x faces (periodic); their y neighbours are unrefined or outside
+    entries, groups = 4, 2
+    tab = 4 * (2 + 4 + 16 + 2 + 4 * entries + groups + 1)
+    al = lambda x: (x + 255) // 256 * 256
+    total = (256 + al(tab) + al(8 * 5 * P ** 3 * 4) + al(8 * 5 * P ** 3 * 16) + al(8 * 5 * n ** 3 * 4)
+             + al(8 * 5 * n ** 3 * 16) + al(8 * 30 * n * n * 4) + al(8 * 30 * n * n * 16) + al(per * 16))
+    assert L.hydro_amr_work_bytes(ctypes.byref(d)) == total
+    for field, value in [("nxb", 12), ("nguard", 2), ("gamma", 1.0)]:
+        bad = hydro.make_amr_desc(n, nb, [0, 1, 0, 1])
+        setattr(bad, field, value)
+        assert L.hydro_amr_work_bytes(ctypes.byref(bad)) == 0, field
+    bad = hydro.make_amr_desc(n, nb, [0, 1, 0, 1])
+    bad.bc[1] = 7
+    assert L.hydro_amr_fine_blocks(ctypes.byref(bad)) == 0
+    bad = hydro.make_amr_desc(n, nb, [0, 1, 0, 1])
+    bad.refine = None
+    assert L.hydro_amr_work_bytes(ctypes.byref(bad)) == 0
+    h = ctypes.c_void_p()
+    assert L.hydro_amr_create(None, ctypes.byref(h)) == hydro.HYDRO_EINVAL
+    d.Ur, d.Uf, d.work, d.work_bytes = 1 << 20, 1 << 30, (1 << 36) + 8, total
+    assert L.hydro_amr_create(ctypes.byref(d), ctypes.byref(h)) == hydro.HYDRO_EINVAL   # unaligned
+    d.work = 1 << 36
+    d.work_bytes = total - 1
+    assert L.hydro_amr_create(ctypes.byref(d), ctypes.byref(h)) == hydro.HYDRO_ESIZE
+    d.work_bytes = total
+    d.Uf = None
+    assert L.hydro_amr_create(ctypes.byref(d), ctypes.byref(h)) == hydro.HYDRO_EINVAL
+    assert L.hydro_amr_step(None, 1e-3) == hydro.HYDRO_EINVAL
+    out = ctypes.c_double()
+    assert L.hydro_amr_dt(None, 0.8, ctypes.byref(out)) == hydro.HYDRO_EINVAL
+    assert L.hydro_amr_counters(None, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_amr_free(None) == hydro.HYDRO_OK

@@ -1,0 +1,172 @@
+"""Parity of the two-level static AMR step of the HIP path (hydro_amr_*)
+with the CPU oracle's (oracle.amr), through the C ABI.
+
+Bar as for the uniform grid: after every step, per conserved variable, the
+normwise relative error over all leaf and restricted cells is at most 1e-12;
+the dt each side chooses agrees to 1e-14; the event counters match.  Inputs:
+a seeded field at the fine resolution (random per cell, or smooth with a
+pressure jump), the fine blocks cut from it and the root state its 2x2x2
+means, so the two levels start consistent.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import amr
+from paper_2208_11630_amd import ics
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+DT_TOL = 1e-14
+
+
+@pytest.fixture(scope="module")
+def hy():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2208_11630_amd import hydro
+
+    hydro.lib()
+    return hydro
+
+
+def fine_field(nb, n, kind, seed, gamma=1.4):
+    """Conserved field [5, Z, Y, X] at the fine resolution (2 n nb per axis)."""
+    shape = (2 * n * nb[2], 2 * n * nb[1], 2 * n * nb[0])
+    rng = np.random.default_rng(seed)
+    if kind == "random":
+        return ics.random_state(rng, shape, gamma)
+    z, y, x = np.meshgrid(*[(np.arange(s) + 0.5) / s for s in shape], indexing="ij")
+    rho = 1.0 + 0.5 * np.exp(-40.0 * ((x - 0.4) ** 2 + (y - 0.5) ** 2 + (z - 0.45) ** 2))
+    u = 0.6 * np.tanh(20.0 * (y - 0.5))
+    v = 0.05 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * z)
+    w = 0.1 * np.cos(2 * np.pi * y)
+    p = np.where((x - 0.3) ** 2 + (y - 0.6) ** 2 + (z - 0.5) ** 2 < 0.04, 10.0, 1.0)
+    return ics.conserved(rho, u, v, w, p, gamma)
+
+
+def mesh_state(mesh, F):
+    """Root state (2x2x2 means of the field) and the fine blocks cut from it."""
+    n = mesh.n
+    Z, Y, X = F.shape[1:]
+    coarse = F.reshape(5, Z // 2, 2, Y // 2, 2, X // 2, 2).mean(axis=(2, 4, 6))
+    Ur = ics.to_compact(coarse, n)
+    Uf = np.empty((mesh.nfine, 5, n, n, n))
+    for f in range(mesh.nfine):
+        x0, y0, z0 = mesh.fine_origin(f)
+        Uf[f] = F[:, z0:z0 + n, y0:y0 + n, x0:x0 + n]
+    amr.restrict(mesh, Ur, Uf)
+    return Ur, Uf
+
+
+def rel_errors(A, B):
+    """Per-variable normwise relative error over compact blocks [nb, 5, ...]."""
+    mom = np.sqrt((B[:, 1] ** 2 + B[:, 2] ** 2) + B[:, 3] ** 2).max()
+    out = []
+    for v in range(5):
+        den = mom if v in (1, 2, 3) else np.abs(B[:, v]).max()
+        out.append(np.abs(A[:, v] - B[:, v]).max() / (den if den > 0 else np.abs(B[:, 0]).max()))
+    return np.array(out)
+
+
+def assert_close(gpu, ref, what):
+    A = np.concatenate([gpu[0], gpu[1]]) if ref[1].size else gpu[0]
+    B = np.concatenate([ref[0], ref[1]]) if ref[1].size else ref[0]
+    e = rel_errors(A, B)
+    assert np.all(e <= TOL), f"{what}: relative errors {e}"
+
+
+# name: (n, nb, refined root blocks, bc, field kind, seed)
+CASES = {
+    "n8_2x2x2_one": (8, (2, 2, 2), [3], (0, 0, 0), "random", 51),
+    "n8_3x2x2_mixed_bc": (8, (3, 2, 2), [0, 5, 7], (1, 0, 1), "random", 52),
+    "n16_2x2x1_periodic_z1": (16, (2, 2, 1), [1, 2], (0, 0, 0), "smooth", 53),
+    "n8_4x1x1_outflow": (8, (4, 1, 1), [1, 2], (1, 1, 1), "smooth", 54),
+    "n8_all_refined": (8, (2, 1, 1), [0, 1], (0, 0, 0), "random", 55),
+    "n8_none_refined": (8, (2, 2, 1), [], (0, 1, 0), "random", 56),
+    "n32_2x1x1": (32, (2, 1, 1), [1], (0, 0, 0), "smooth", 57),
+}
+
+
+def make(hy, case):
+    n, nb, refined, bc, kind, seed = CASES[case]
+    flags = np.zeros(nb[0] * nb[1] * nb[2], bool)
+    flags[refined] = True
+    h = 1.0 / (nb[0] * n)
+    mesh = amr.Mesh(n, nb, (h, h, h), flags, bc=bc)
+    Ur, Uf = mesh_state(mesh, fine_field(nb, n, kind, seed))
+    hi = tuple(nb[d] * n * h for d in range(3))
+    A = hy.Amr(n, nb, flags.tolist(), hi=hi, bc=bc)
+    A.upload(Ur, Uf if mesh.nfine else None)
+    return mesh, Ur, Uf, A
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_amr_trajectory_parity(hy, case):
+    """Three steps, dt from the oracle's CFL rule; the device's dt agrees."""
+    print(f"\n[amr] {case}", flush=True)
+    mesh, Ur, Uf, A = make(hy, case)
+    cnt_ref = np.zeros(3, np.int64)
+    for s in range(3):
+        dt = amr.dt(mesh, Ur, Uf, 0.8)
+        d_gpu = A.dt(0.8)
+        assert abs(d_gpu / dt - 1.0) <= DT_TOL, (s, d_gpu, dt)
+        Ur, Uf, c = amr.step(mesh, Ur, Uf, dt)
+        cnt_ref += c
+        A.step(dt)
+        assert_close(A.download(), (Ur, Uf), f"{case} step {s}")
+    assert A.counters().tolist() == cnt_ref.tolist()
+    A.close()
+
+
+def test_amr_conserves_composite_totals(hy):
+    """Periodic mesh: leaf totals weighted by cell volume change by roundoff only."""
+    mesh, Ur, Uf, A = make(hy, "n8_2x2x2_one")
+    vol = [1.0, 1.0 / 8]
+
+    def totals(R, F):
+        leaves = np.flatnonzero(~mesh.refine)
+        return R[leaves].sum(axis=(0, 2, 3, 4)) * vol[0] + F.sum(axis=(0, 2, 3, 4)) * vol[1]
+
+    t0 = totals(Ur, Uf)
+    scale = totals(np.abs(Ur), np.abs(Uf))
+    for _ in range(3):
+        A.step(A.dt(0.8))
+    R, F = A.download()
+    assert np.all(np.abs(totals(R, F) - t0) <= 1e-13 * scale)
+    A.close()
+
+
+def test_amr_without_refinement_equals_uniform_step(hy):
+    """No flagged block: the AMR step is the uniform grid's step."""
+    n, nb = 16, (2, 1, 2)
+    rng = np.random.default_rng(58)
+    G = ics.random_state(rng, (nb[2] * n, nb[1] * n, nb[0] * n))
+    Ur = ics.to_compact(G, n)
+    h = 1.0 / 32
+    A = hy.Amr(n, nb, [0] * 4, hi=(nb[0] * n * h, nb[1] * n * h, nb[2] * n * h), bc=(1, 0, 1))
+    A.upload(Ur)
+    g = oracle.Grid(n, nb, (h, h, h), (1, 0, 1), 1.4, 1e-10, 4)
+    P = ics.Problem("r", n, nb, (h, h, h), (1, 0, 1), 1.4, Ur)
+    dt = oracle.dt(g, P.U, 0.8)
+    ref, _ = oracle.step(g, P.U.copy(), dt)
+    A.step(dt)
+    e = rel_errors(A.download()[0], ics.interior(ref, n))
+    assert np.all(e <= TOL), e
+    A.close()
+
+
+def test_amr_abi_rejects_bad_descriptors(hy):
+    with pytest.raises(hy.HydroError):
+        hy.Amr(12, (2, 1, 1), [0, 1])
+    with pytest.raises(hy.HydroError):
+        hy.Amr(8, (2, 1, 1), [0, 1], bc=(0, 5, 0))
+    A = hy.Amr(8, (2, 1, 1), [0, 1])
+    with pytest.raises(hy.HydroError):
+        A.step(float("nan"))
+    with pytest.raises(hy.HydroError):
+        A.step(-1.0)
+    A.close()

@@ -195,6 +195,72 @@ def run_ensemble(args):
     print(json.dumps(out), flush=True)
 
 
+def run_amr(args):
+    """Two-level static AMR: the Kelvin-Helmholtz shear layer on a 256 x 256
+    x 128 root grid of 16^3 blocks, the block rows at the two interfaces
+    refined once (fine cells 1/512).  A step: dt from the CFL rule over both
+    levels (one stream synchronization), then guard fill (same level,
+    prolongation), the step of every leaf, refluxing and restriction.
+    value = leaf cell-updates/s."""
+    import numpy as np
+    import torch
+
+    from paper_2208_11630_amd import hydro, ics
+
+    nb, flags, Ur, Uf, dx, gamma = ics.kelvin_helmholtz_amr(root=(256, 256, 128), n=16)
+    n = 16
+    nleaf = int((~flags).sum()) + Uf.shape[0]
+    cells = nleaf * n ** 3
+    print(f"[bench] amr: {flags.size} root blocks, {int(flags.sum())} refined, {nleaf} leaves, {cells} leaf cells",
+          file=sys.stderr, flush=True)
+    hi = tuple(nb[d] * n * dx[d] for d in range(3))
+    A = hydro.Amr(n, nb, flags.tolist(), hi=hi, gamma=gamma)
+    A.upload(Ur, Uf)
+    del Ur, Uf
+
+    def one():
+        A.step(A.dt(args.cfl))
+    for _ in range(args.warmup):
+        one()
+    A.stream.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(A.stream)
+    for _ in range(args.steps):
+        one()
+    t1.record(A.stream)
+    t1.synchronize()
+    ms = t0.elapsed_time(t1)
+    ms_step = ms / args.steps
+    rate = cells * args.steps / (ms * 1e-3)
+    cnt = A.counters().tolist()
+    print(f"[bench] {args.steps} steps in {ms:.3f} ms ({ms_step:.4f} ms/step), counters {cnt}", file=sys.stderr,
+          flush=True)
+    achieved = BYTES_PER_CELL * cells / (ms_step * 1e-3) / 1e9
+    out = {
+        "metric": "FP64 cell-updates/s",
+        "value": rate,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "amr_kelvin_helmholtz_root256x256x128_nxb16_two_levels", "cells": cells,
+                   "root_blocks": int(flags.size), "refined_blocks": int(flags.sum()), "leaf_blocks": nleaf,
+                   "cfl": args.cfl, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "amr_step_kernel",
+                     "algorithmic_bytes_per_step": BYTES_PER_CELL * cells},
+    }
+    A.close()
+    print(json.dumps(out), flush=True)
+
+
 def run_served(args):
     """Served stream: many resident cubic simulations (L log-uniform in
     32..256, 16^3 blocks, random initial states), one-step requests with
@@ -295,7 +361,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="kh", choices=["kh", "sedov", "sod", "ensemble", "served"])
+    ap.add_argument("--workload", default="kh", choices=["kh", "sedov", "sod", "ensemble", "served", "amr"])
     ap.add_argument("--served-sims", type=int, default=2000)
     ap.add_argument("--served-budget-gb", type=float, default=200.0)
     ap.add_argument("--served-seconds", type=float, default=2.0, help="served: seconds per rate point")
@@ -323,6 +389,8 @@ def main():
         return run_ensemble(args)
     if args.workload == "served":
         return run_served(args)
+    if args.workload == "amr":
+        return run_amr(args)
     P, wname = make_workload(args.workload)
     print(f"[bench] workload {wname}: {P.cells} cells, {P.nblk} blocks", file=sys.stderr, flush=True)
     G = hydro.grid_for(P, device="cuda:0")

@@ -93,6 +93,36 @@ class Problem:
 
 # ---- layout ---------------------------------------------------------------
 
+def kelvin_helmholtz_amr(root=(256, 256, 128), n: int = 16, seed_root: int = 1, seed_fine: int = 5):
+    """Two-level Kelvin-Helmholtz mesh: the shear layer of kelvin_helmholtz
+    on a root grid of ``root`` cells, the root blocks whose y range touches an
+    interface (y = 0.25, 0.75) refined once.  The root state samples the
+    problem at the root resolution, the fine blocks at twice it (independent
+    seeded perturbations; the first step's restriction makes the levels
+    agree).  Returns (nb, refine flags, Ur [nroot,5,n,n,n], Uf [nfine,5,n,n,n],
+    dx of the root level, gamma); fine blocks are the children of the refined
+    root blocks in increasing root id, child cx + 2 cy + 4 cz."""
+    X, Y, Z = root
+    nb = (X // n, Y // n, Z // n)
+    P0 = kelvin_helmholtz(shape=root, n=n, seed=seed_root)
+    # root block rows whose y range [by, by+1) * n/Y has 0.25 or 0.75 on an edge or inside
+    by = np.arange(nb[1])
+    y0, y1 = by * n / Y, (by + 1) * n / Y
+    touch = np.zeros(nb[1], bool)
+    for yi in (0.25, 0.75):
+        touch |= (y0 <= yi) & (y1 >= yi)
+    flags = np.broadcast_to(touch[None, :, None], (nb[2], nb[1], nb[0])).reshape(-1).copy()
+    refined = np.flatnonzero(flags)
+    Pf = kelvin_helmholtz(shape=(2 * X, 2 * Y, 2 * Z), n=n, seed=seed_fine)
+    fb = Pf.Uc.reshape(2 * nb[2], 2 * nb[1], 2 * nb[0], 5, n, n, n)
+    Uf = np.empty((8 * refined.size, 5, n, n, n))
+    for q, r in enumerate(refined):
+        bx, byy, bz = r % nb[0], (r // nb[0]) % nb[1], r // (nb[0] * nb[1])
+        for c in range(8):
+            Uf[8 * q + c] = fb[2 * bz + (c >> 2), 2 * byy + ((c >> 1) & 1), 2 * bx + (c & 1)]
+    return nb, flags, P0.Uc, Uf, P0.dx, P0.gamma
+
+
 def to_blocks(G: np.ndarray, n: int, ng: int = NGUARD, out: np.ndarray | None = None) -> np.ndarray:
     """Global ``[5, Z, Y, X]`` -> blocked ``[nblk, 5, P, P, P]`` (guards zero)."""
     _, Z, Y, X = G.shape

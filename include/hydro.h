@@ -296,8 +296,9 @@ const char *hydro_last_error(void);
  * children of the refined root blocks in increasing root id, child
  * cx + 2*cy + 4*cz covering cells (cx*nxb/2.., cy*nxb/2.., cz*nxb/2..) of its
  * parent; nxb^3 cells per child at half the parent's cell width.  The step
- * updates Ur and Uf in place (new states are formed in the workspace and
- * copied back).  refine: host flags, one per root block, copied at creation. */
+ * updates Ur and Uf in place (it reads the old state only through views
+ * with two guard layers, formed in the workspace first).  refine: host
+ * flags, one per root block, copied at creation. */
 typedef struct hydro_amr hydro_amr;
 typedef struct {
   int nxb;                     /* 8, 16 or 32 */
@@ -316,7 +317,8 @@ typedef struct {
 
 /* Number of fine blocks (8 per flagged root block); 0 for an invalid descriptor. */
 size_t hydro_amr_fine_blocks(const hydro_amr_desc *d);
-/* Workspace bytes: guarded views, new states, boundary fluxes, step scratch, tables. */
+/* Workspace bytes: header, mesh tables, views with two guard layers of every
+ * root and fine block, fluxes on block faces (used at fine-coarse faces). */
 size_t hydro_amr_work_bytes(const hydro_amr_desc *d);
 /* Validate and build the mesh tables (uploaded to the workspace; waits for
  * the upload).  Errors: HYDRO_EINVAL, HYDRO_ESIZE, HYDRO_EDEVICE. */

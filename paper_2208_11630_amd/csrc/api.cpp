@@ -721,8 +721,8 @@ namespace {
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct AmrLayout {
-  long nroot, nfine, nleaf0, nrefined, nreflux, ngroups, chunk;
-  size_t o_tab, o_G0, o_G1, o_Urn, o_Ufn, o_f0, o_f1, o_sc, total;
+  long nroot, nfine, nleaf0, nrefined, nreflux, ngroups;
+  size_t o_tab, o_G0, o_G1, o_f0, o_f1, total;
   std::vector<int> leaf0, child_base, fine_root, refined;
   std::vector<int> reflux;  // 4 ints per entry, grouped by coarse leaf
   std::vector<int> first;   // ngroups + 1 entry offsets
@@ -780,21 +780,15 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
   }
   A.nreflux = (long)A.reflux.size() / 4;
   A.ngroups = (long)A.first.size() - 1;
-  const long P = N + 2 * HYDRO_NGUARD;
-  const long per = hydro::amr_block_doubles(N) * (long)sizeof(double);
-  const long most = std::max(std::max(A.nleaf0, A.nfine), 1L);
-  A.chunk = std::max(1L, std::min(most, (4L << 30) / per));
+  const long P = N + 4;   // the step's internal views keep two guard layers
   const size_t tab = sizeof(int) * (size_t)(A.nleaf0 + A.nroot + A.nfine + A.nrefined + 4 * A.nreflux +
                                              A.ngroups + 1);
   A.o_tab = 256;
   A.o_G0 = A.o_tab + al256(tab);
   A.o_G1 = A.o_G0 + al256(sizeof(double) * 5 * P * P * P * A.nroot);
-  A.o_Urn = A.o_G1 + al256(sizeof(double) * 5 * P * P * P * A.nfine);
-  A.o_Ufn = A.o_Urn + al256(sizeof(double) * 5 * (size_t)N * N * N * A.nroot);
-  A.o_f0 = A.o_Ufn + al256(sizeof(double) * 5 * (size_t)N * N * N * A.nfine);
+  A.o_f0 = A.o_G1 + al256(sizeof(double) * 5 * P * P * P * A.nfine);
   A.o_f1 = A.o_f0 + al256(sizeof(double) * 30 * (size_t)N * N * A.nroot);
-  A.o_sc = A.o_f1 + al256(sizeof(double) * 30 * (size_t)N * N * A.nfine);
-  A.total = A.o_sc + al256((size_t)per * A.chunk);
+  A.total = A.o_f1 + al256(sizeof(double) * 30 * (size_t)N * N * A.nfine);
   return HYDRO_OK;
 }
 
@@ -862,11 +856,8 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
   L.Uf = d->Uf;
   L.G0 = (double*)(w + A.o_G0);
   L.G1 = (double*)(w + A.o_G1);
-  L.Ur_new = (double*)(w + A.o_Urn);
-  L.Uf_new = (double*)(w + A.o_Ufn);
   L.flux0 = (double*)(w + A.o_f0);
   L.flux1 = (double*)(w + A.o_f1);
-  L.scratch = (double*)(w + A.o_sc);
   L.ws = (hydro::WorkHeader*)w;
   L.nroot = A.nroot;
   L.nleaf0 = A.nleaf0;
@@ -874,7 +865,6 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
   L.nrefined = A.nrefined;
   L.nreflux = A.nreflux;
   L.nreflux_groups = A.ngroups;
-  L.chunk = A.chunk;
   L.dt = 0.0;
   hipStream_t s = (hipStream_t)d->stream;
   hipError_t e = hipMemsetAsync(w, 0, 256, s);
@@ -896,11 +886,6 @@ int hydro_amr_step(hydro_amr* a, double dt) {
   hipStream_t s = (hipStream_t)a->d.stream;
   hipError_t e = hydro::launch_amr_step(a->d.nxb, a->L, s);
   if (e != hipSuccess) return hip_fail(e, "AMR step launch");
-  const size_t N3 = (size_t)a->d.nxb * a->d.nxb * a->d.nxb;
-  e = hipMemcpyAsync(a->d.Ur, a->L.Ur_new, sizeof(double) * 5 * N3 * a->L.nroot, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess && a->L.nfine)
-    e = hipMemcpyAsync(a->d.Uf, a->L.Uf_new, sizeof(double) * 5 * N3 * a->L.nfine, hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return hip_fail(e, "AMR state copy");
   return HYDRO_OK;
 }
 

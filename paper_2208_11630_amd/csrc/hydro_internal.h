@@ -88,15 +88,12 @@ hipError_t launch_copy(const double* src, double* dst, long n, hipStream_t s);
 // needs, device pointers into the caller's state and workspace.
 struct AmrLaunch {
   GridGeom g0, g1;            // root and fine level geometry (inv_dx per level)
-  const double* Ur;           // root state (refined blocks hold the restriction)
-  const double* Uf;           // fine state
-  double* Ur_new;
-  double* Uf_new;
-  double* G0;                 // guarded views: root blocks, fine blocks
+  double* Ur;                 // root state (refined blocks hold the restriction), updated in place
+  double* Uf;                 // fine state, updated in place
+  double* G0;                 // views with two guard layers: root blocks, fine blocks
   double* G1;
-  double* flux0;              // boundary fluxes per root block / fine block
+  double* flux0;              // boundary fluxes per root block / fine block (fine-coarse faces only)
   double* flux1;
-  double* scratch;            // chunk * amr_block_doubles
   const int* leaf0;           // unrefined root blocks
   const int* child_base;      // per root block: first child, or -1
   const int* fine_root;       // per fine block: its root block
@@ -104,10 +101,9 @@ struct AmrLaunch {
   const int4* reflux;         // (coarse leaf, d, side, refined neighbour), grouped by coarse leaf
   const int* reflux_first;    // nreflux_groups + 1 offsets into reflux
   WorkHeader* ws;
-  long nroot, nleaf0, nfine, nrefined, nreflux, nreflux_groups, chunk;
+  long nroot, nleaf0, nfine, nrefined, nreflux, nreflux_groups;
   double dt;
 };
-long amr_block_doubles(int nxb);
 hipError_t launch_amr_step(int nxb, const AmrLaunch& L, hipStream_t s);
 hipError_t launch_amr_signal(int nxb, const AmrLaunch& L, int slot, hipStream_t s);
 

@@ -32,7 +32,8 @@
 namespace hydro {
 namespace {
 
-constexpr int G = 4;  // guard layers per side of the guarded view
+constexpr int G = 4;   // guard layers per side of the guarded view
+constexpr int VG = 2;  // guard layers of the internal views the AMR step fills (the stencil's depth)
 
 // Compact state layout: block b, variable v, cell (i, j, k).
 template <int N>
@@ -44,10 +45,10 @@ struct Layout {
   __device__ static long at(long b, int i, int j, int k) { return b * BS + (long)k * PS + (long)j * N + i; }
 };
 
-// Guarded view: [block][var][P][P][P], P = N + 2G, interior at offset G.
-template <int N>
+// Guarded view: [block][var][P][P][P], P = N + 2GW, interior at offset GW.
+template <int N, int GW = G>
 struct Guarded {
-  static constexpr int P = N + 2 * G;
+  static constexpr int P = N + 2 * GW;
   static constexpr long PS = (long)P * P;
   static constexpr long VS = PS * P;
   static constexpr long BS = 5 * VS;
@@ -78,10 +79,12 @@ __device__ __forceinline__ void load_cons(const double* __restrict__ U, long off
 
 // Same, from a workgroup-uniform base P and a 32-bit per-cell byte offset
 // (a scalar base plus a vector offset in the load itself).
-template <int N>
+// GVW: P points into an internal view (variable stride Guarded<N, VG>::VS).
+template <int N, bool GVW = false>
 __device__ __forceinline__ void load_cons_at(const double* P, unsigned xyb, double (&u)[5]) {
+  constexpr long VSX = GVW ? (long)(N + 2 * VG) * (N + 2 * VG) * (N + 2 * VG) : (long)N * N * N;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) u[v] = *(const double*)((const char*)(P + v * Layout<N>::VS) + xyb);
+  for (int v = 0; v < 5; ++v) u[v] = *(const double*)((const char*)(P + v * VSX) + xyb);
 }
 
 // Maximum over a workgroup of a non-negative double, folded into *slot with
@@ -360,24 +363,34 @@ struct Smem {
 // > 0) takes the dt its first stage recorded; only the last stage reduces
 // the signal speed.  Uout may be st.U0 (each cell of U0 is read only by the
 // thread that then writes it), never Uin.
-template <int N, int T, bool MOL = false>
+//
+// GV = true (predictor-corrector only): Uin holds guarded views
+// ([block][var][N+2VG]^3, the VG guard layers filled) and the pencil is the
+// whole z extent of block gv_list[tile_in_sim / (N/T)^2] (or that index
+// when gv_list is null): every read stays inside the block's own view, the
+// result goes to the block in compact layout in Uout, dt is dt_host and no
+// signal speed is reduced (event counters are).
+template <int N, int T, bool MOL = false, bool GV = false>
 __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __restrict__ Uin, double* Uout,
                                           WorkHeader* ws, double dt_host, double cfl, int slot,
                                           long tile_in_sim, int plen, Smem<T>& sm,
-                                          const StageArgs& st = StageArgs{nullptr, 0.0, 0.0, 0, 1}) {
+                                          const StageArgs& st = StageArgs{nullptr, 0.0, 0.0, 0, 1},
+                                          const int* gv_list = nullptr) {
+  static_assert(!(GV && MOL), "guarded-view input is for the predictor-corrector step");
   using TL = Tile<T>;
   constexpr int NT = TL::NT, NI = TL::NI, NR = TL::NR, NE = TL::NE, WS = TL::WS;
   constexpr int TPB = (N / T) * (N / T);
   constexpr long VS = Layout<N>::VS;
   constexpr long PS = Layout<N>::PS;
+  constexpr int GP = Guarded<N, VG>::P;
 
   const int tid = threadIdx.x;
-  const long nxy = (long)g.nb[0] * g.nb[1] * TPB;  // column tiles of one z layer
+  const long nxy = GV ? 1 : (long)g.nb[0] * g.nb[1] * TPB;  // column tiles of one z layer
   const int NZ = g.nb[2] * N;
-  const long layer = tile_in_sim / nxy;
-  const long cxy = tile_in_sim % nxy;
-  const int z0 = (int)(layer * plen), z1 = z0 + plen;  // global planes of the pencil
-  const long bxy = cxy / TPB;                          // block (bx, by, 0)
+  const long layer = GV ? 0 : tile_in_sim / nxy;
+  const long cxy = GV ? tile_in_sim : tile_in_sim % nxy;
+  const int z0 = GV ? 0 : (int)(layer * plen), z1 = GV ? N : z0 + plen;  // planes of the pencil
+  const long bxy = (GV && gv_list) ? (long)gv_list[cxy / TPB] : cxy / TPB;  // block (bx, by, 0), or the block
   const int tile = (int)(cxy % TPB);
   const int bx = (int)(bxy % g.nb[0]);
   const int by = (int)(bxy / g.nb[0]);
@@ -387,16 +400,18 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   if (tid < 3) sm.sCnt[tid] = 0;
 
   double dt = dt_host;
-  if (MOL && st.stage > 0) {
-    if (cfl > 0.0) dt = ws->dt_last;
-  } else {
-    if (cfl > 0.0) dt = cfl / __longlong_as_double(ws->sig[slot]);
-    if (tile_in_sim == 0 && tid == 0) {
-      ws->dt_last = dt;
-      ws->sig[(slot + 2) % 3] = 0ull;
+  if constexpr (!GV) {
+    if (MOL && st.stage > 0) {
+      if (cfl > 0.0) dt = ws->dt_last;
+    } else {
+      if (cfl > 0.0) dt = cfl / __longlong_as_double(ws->sig[slot]);
+      if (tile_in_sim == 0 && tid == 0) {
+        ws->dt_last = dt;
+        ws->sig[(slot + 2) % 3] = 0ull;
+      }
     }
   }
-  const bool emit = !MOL || st.last;
+  const bool emit = !GV && (!MOL || st.last);
   const double lamx = dt * g.inv_dx[0], lamy = dt * g.inv_dx[1], lamz = dt * g.inv_dx[2];
   const double gamma = g.gamma, gm1inv = 1.0 / (g.gamma - 1.0);
 
@@ -428,12 +443,25 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   // once, below).  Loads then take a scalar base and a vector offset.
   const long BZS = (long)g.nb[0] * g.nb[1] * Layout<N>::BS;  // size of a z layer of blocks
   auto plane_off = [&](int k) -> long {
-    const int K = map_axis(k, NZ, g.bc[2]);
-    return (long)((unsigned)K / N) * BZS + (long)((unsigned)K % N) * PS;
+    if constexpr (GV) {
+      return bxy * Guarded<N, VG>::BS + (long)(k + VG) * Guarded<N, VG>::PS;
+    } else {
+      const int K = map_axis(k, NZ, g.bc[2]);
+      return (long)((unsigned)K / N) * BZS + (long)((unsigned)K % N) * PS;
+    }
+  };
+  // output plane k (compact layout)
+  auto out_off = [&](int k) -> long {
+    if constexpr (GV) return bxy * Layout<N>::BS + (long)k * PS;
+    else return plane_off(k);
   };
   // (byte offsets: a z layer of blocks is below 4 GiB, checked on the host)
-  const unsigned own_xy = 8u * (unsigned)Layout<N>::at(bxy, lx0 + cx, ly0 + cy, 0);
-  const unsigned sec_xy = (is_ring || is_extra) ? 8u * (unsigned)cell_offset<N>(g, X0 + sx2, Y0 + sy2, 0) : 0u;
+  const unsigned own_xy = GV ? 8u * (unsigned)((ly0 + cy + VG) * GP + (lx0 + cx + VG))
+                             : 8u * (unsigned)Layout<N>::at(bxy, lx0 + cx, ly0 + cy, 0);
+  const unsigned own_out = GV ? 8u * (unsigned)((ly0 + cy) * N + (lx0 + cx)) : own_xy;
+  const unsigned sec_xy = !(is_ring || is_extra) ? 0u
+                          : GV ? 8u * (unsigned)((ly0 + sy2 + VG) * GP + (lx0 + sx2 + VG))
+                               : 8u * (unsigned)cell_offset<N>(g, X0 + sx2, Y0 + sy2, 0);
 
   double Wa[5], Wb[5], Wc[5];
   double un_next[5], u2_next[5];
@@ -454,21 +482,21 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   // prologue: planes z0-2, z0-1 of the own column, prefetch plane z0
   if (inner) {
     double u[5], tmp;
-    load_cons_at<N>(Uin + plane_off(z0 - 2), own_xy, u);
+    load_cons_at<N, GV>(Uin + plane_off(z0 - 2), own_xy, u);
     prim(u, gamma, g.small_p, Wa, tmp);
-    load_cons_at<N>(Uin + plane_off(z0 - 1), own_xy, u);
+    load_cons_at<N, GV>(Uin + plane_off(z0 - 1), own_xy, u);
     prim(u, gamma, g.small_p, Wb, tmp);
-    load_cons_at<N>(Uin + plane_off(z0), own_xy, un_next);
+    load_cons_at<N, GV>(Uin + plane_off(z0), own_xy, un_next);
   }
   if (is_ring) {
     double u[5], w[5], tmp;
-    load_cons_at<N>(Uin + plane_off(z0 - 1), sec_xy, u);
+    load_cons_at<N, GV>(Uin + plane_off(z0 - 1), sec_xy, u);
     prim(u, gamma, g.small_p, w, tmp);
 #pragma unroll
     for (int v = 0; v < 5; ++v) sm.sRing[(z0 + 2) % 3][v][ring_id] = w[v];
-    load_cons_at<N>(Uin + plane_off(z0), sec_xy, u2_next);
+    load_cons_at<N, GV>(Uin + plane_off(z0), sec_xy, u2_next);
   }
-  if (is_extra) load_cons_at<N>(Uin + plane_off(z0), sec_xy, u2_next);
+  if (is_extra) load_cons_at<N, GV>(Uin + plane_off(z0), sec_xy, u2_next);
 
   for (int j = z0 - 1; j <= z1; ++j) {
     const bool mid = (j >= z0) && (j < z1);
@@ -501,15 +529,15 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     // values are consumed: they then land in the same registers, and nothing
     // waits for them until the next plane
     __builtin_amdgcn_sched_barrier(0);
-    if (inner && j + 2 <= z1 + 1) load_cons_at<N>(Uin + plane_off(j + 2), own_xy, un_next);
-    if (is_ring && j + 2 <= z1 + 1) load_cons_at<N>(Uin + plane_off(j + 2), sec_xy, u2_next);
-    if (is_extra && mid && j + 1 < z1) load_cons_at<N>(Uin + plane_off(j + 1), sec_xy, u2_next);
+    if (inner && j + 2 <= z1 + 1) load_cons_at<N, GV>(Uin + plane_off(j + 2), own_xy, un_next);
+    if (is_ring && j + 2 <= z1 + 1) load_cons_at<N, GV>(Uin + plane_off(j + 2), sec_xy, u2_next);
+    if (is_extra && mid && j + 1 < z1) load_cons_at<N, GV>(Uin + plane_off(j + 1), sec_xy, u2_next);
     __syncthreads();
 
     // -- the previous plane's update goes out now
     if (inner && pend_off >= 0) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) *(double*)((char*)(Uout + pend_off + v * VS) + own_xy) = pend[v];
+      for (int v = 0; v < 5; ++v) *(double*)((char*)(Uout + pend_off + v * VS) + own_out) = pend[v];
     }
 
     // -- predictor: own cell (every plane), ring cell (pencil planes)
@@ -636,7 +664,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     const long off_u = plane_off(j - 1);
     double uold[5], base[5];
     if (inner && j >= z0 + 1) {
-      load_cons_at<N>(Uin + off_u, own_xy, uold);
+      load_cons_at<N, GV>(Uin + off_u, own_xy, uold);
       if constexpr (MOL) {
         if (st.U0) load_cons_at<N>(st.U0 + off_u, own_xy, base);
       }
@@ -683,11 +711,11 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         Wb[v] = Wc[v];
       }
     }
-    pend_off = (j >= z0 + 1) ? off_u : -1;
+    pend_off = (j >= z0 + 1) ? (GV ? out_off(j - 1) : off_u) : -1;
   }
   if (inner && pend_off >= 0) {  // the pencil's last plane
 #pragma unroll
-    for (int v = 0; v < 5; ++v) *(double*)((char*)(Uout + pend_off + v * VS) + own_xy) = pend[v];
+    for (int v = 0; v < 5; ++v) *(double*)((char*)(Uout + pend_off + v * VS) + own_out) = pend[v];
   }
 
   if (n_floor) atomicAdd(&sm.sCnt[0], n_floor);
@@ -1036,15 +1064,7 @@ __global__ __launch_bounds__(256) void ctu_kernel(GridGeom g, StepArgs a, double
 
 template <int N>
 struct AmrStep {
-  static constexpr int P = N + 2 * G;        // guarded edge
-  static constexpr long P3 = (long)P * P * P;
-  static constexpr int M = N + 4, m = N + 2;
-  static constexpr long M3 = (long)M * M * M, m3 = (long)m * m * m;
-  static constexpr long oW = 0, oWf = 5 * M3, oF = oWf + 30 * m3;
-  static constexpr long doubles = oF + 15 * m3;   // scratch per block
-  static constexpr long NF = 6L * 5 * N * N;      // boundary fluxes per block
-  __device__ static int ci(int i, int j, int k) { return ((k + 1) * m + (j + 1)) * m + (i + 1); }
-  __device__ static int cW(int i, int j, int k) { return ((k + 2) * M + (j + 2)) * M + (i + 2); }
+  static constexpr long NF = 6L * 5 * N * N;      // boundary fluxes per block: [face 2d+side][v][a1][a0]
 };
 
 // Fine guarded views: fine block f = child c of root block fine_root[f]
@@ -1060,17 +1080,16 @@ __global__ __launch_bounds__(256) void amr_fill_fine_kernel(GridGeom g0, const d
                                                             const int* __restrict__ child_base,
                                                             const int* __restrict__ fine_root,
                                                             double* __restrict__ G1) {
-  using A = AmrStep<N>;
-  constexpr int P = A::P;
+  constexpr int P = Guarded<N, VG>::P;
   const int f = blockIdx.x;
   const int r = fine_root[f];
   const int c = f - child_base[r];
   const int bx = r % g0.nb[0], by = (r / g0.nb[0]) % g0.nb[1], bz = r / (g0.nb[0] * g0.nb[1]);
   const int X0 = 2 * bx * N + (c & 1) * N, Y0 = 2 * by * N + ((c >> 1) & 1) * N, Z0 = 2 * bz * N + ((c >> 2) & 1) * N;
   const int NF0 = 2 * g0.nb[0] * N, NF1 = 2 * g0.nb[1] * N, NF2 = 2 * g0.nb[2] * N;
-  double* out = G1 + (long)f * 5 * A::P3;
+  double* out = G1 + (long)f * Guarded<N, VG>::BS;
   for (int t = threadIdx.x; t < P * P * P; t += blockDim.x) {
-    const int i = t % P - G, j = (t / P) % P - G, k = t / (P * P) - G;
+    const int i = t % P - VG, j = (t / P) % P - VG, k = t / (P * P) - VG;
     int I = X0 + i, J = Y0 + j, K = Z0 + k;
     I = g0.bc[0] == 0 ? (I < 0 ? I + NF0 : (I >= NF0 ? I - NF0 : I)) : min(max(I, 0), NF0 - 1);
     J = g0.bc[1] == 0 ? (J < 0 ? J + NF1 : (J >= NF1 ? J - NF1 : J)) : min(max(J, 0), NF1 - 1);
@@ -1104,133 +1123,107 @@ __global__ __launch_bounds__(256) void amr_fill_fine_kernel(GridGeom g0, const d
       }
     }
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out[v * A::P3 + t] = val[v];
+    for (int v = 0; v < 5; ++v) out[v * Guarded<N, VG>::VS + t] = val[v];
   }
 }
 
-// Predictor-corrector step of one leaf block from its guarded view (the
-// oracle's per-block formulation: primitives of the footprint, Hancock
-// predictor with the positivity fallback, HLLC at every face the update
-// uses, update), with a per-workgroup scratch slice; boundary fluxes go to
-// flux[block][face 2d+side][v][a][b] (a, b: the transverse indices, slower
-// axis first).  The block id of workgroup w is list[b0 + w] (or b0 + w).
+// Leaf step: the fused tile step over guarded views, one workgroup per
+// column tile (the whole z extent of the block), blocks list[0..nblk) (or
+// 0..nblk when list is null), XCD-aware order.
+template <int N, int T>
+__global__ __launch_bounds__(Tile<T>::NT, 2) void amr_tile_kernel(GridGeom g, const double* __restrict__ Gin,
+                                                                  double* Uout, const int* __restrict__ list,
+                                                                  long ntiles, double dt, WorkHeader* ws) {
+  __shared__ Smem<T> sm;
+  const long tile_id = xcd_tile(blockIdx.x, ntiles);
+  if (tile_id >= ntiles) return;
+  tile_step<N, T, false, true>(g, Gin, Uout, ws, dt, 0.0, 0, tile_id, N, sm,
+                               StageArgs{nullptr, 0.0, 0.0, 0, 1}, list);
+}
+
+// Face state of cell (i, j, k) of a guarded view V on its low (hi = 0) or
+// high (hi = 1) d face, formed as the leaf step forms it: primitives of the
+// cell and its six neighbours, van Leer slopes, predictor with fallback.
 template <int N>
-__global__ __launch_bounds__(256) void amr_step_kernel(GridGeom g, const double* __restrict__ Gin,
-                                                       double* __restrict__ Uout, const int* __restrict__ list,
-                                                       double* __restrict__ flux, double* __restrict__ scratch,
-                                                       long b0, double dt, WorkHeader* ws) {
+__device__ __forceinline__ void amr_face_state(const double* V, int i, int j, int k, int d, int hi,
+                                               const GridGeom& g, double lamx, double lamy, double lamz,
+                                               double (&out)[5]) {
+  constexpr int P = Guarded<N, VG>::P;
+  constexpr long VSg = Guarded<N, VG>::VS;
+  auto w_at = [&](int a, int b, int c, double (&w)[5]) {
+    const long o = ((long)(c + VG) * P + (b + VG)) * P + (a + VG);
+    double u[5], inv;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = V[o + v * VSg];
+    prim(u, g.gamma, g.small_p, w, inv);
+  };
+  double wc[5], wm[5], wp[5], sx[5], sy[5], sz[5], wt[5], h;
+  w_at(i, j, k, wc);
+  w_at(i - 1, j, k, wm);
+  w_at(i + 1, j, k, wp);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) sx[v] = van_leer_sf(wc[v] - wm[v], wp[v] - wc[v]);
+  w_at(i, j - 1, k, wm);
+  w_at(i, j + 1, k, wp);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) sy[v] = van_leer_sf(wc[v] - wm[v], wp[v] - wc[v]);
+  w_at(i, j, k - 1, wm);
+  w_at(i, j, k + 1, wp);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) sz[v] = van_leer_sf(wc[v] - wm[v], wp[v] - wc[v]);
+  predict(wc, rcp_nr(wc[0]), sx, sy, sz, g.gamma, lamx, lamy, lamz, wt, h);
+  const double hs = hi ? h : -h;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) out[v] = fma(hs, d == 0 ? sx[v] : (d == 1 ? sy[v] : sz[v]), wt[v]);
+}
+
+// Fluxes on the faces that refluxing uses, recomputed from the guarded
+// views with the leaf step's arithmetic: workgroup 5e + part of reflux
+// entry e = (coarse leaf b, d, side, refined r): part 0 is b's face 2d+side
+// (level 0), parts 1..4 the faces 2d+(1-side) of r's four children on the
+// side toward b (level 1).  Output flux[block][face][v][a1][a0], a0 / a1 the
+// faster / slower transverse index.
+template <int N>
+__global__ __launch_bounds__(256) void amr_face_flux_kernel(GridGeom g0, GridGeom g1,
+                                                            const int4* __restrict__ entries,
+                                                            const int* __restrict__ child_base,
+                                                            const double* __restrict__ G0,
+                                                            const double* __restrict__ G1, double* flux0,
+                                                            double* flux1, double dt) {
   using A = AmrStep<N>;
-  constexpr int P = A::P, M = A::M, m = A::m;
-  __shared__ int sCnt[3];
-  const int tid = threadIdx.x;
-  const long w = b0 + blockIdx.x;
-  const long blk = list ? list[w] : w;
-  const double* gin = Gin + blk * 5 * A::P3;
-  double* sc = scratch + (long)blockIdx.x * A::doubles;
-  double* W = sc + A::oW;
-  double* Wf = sc + A::oWf;
-  double* F = sc + A::oF;
-  if (tid < 3) sCnt[tid] = 0;
+  const int part = blockIdx.x % 5;
+  const int4 e = entries[blockIdx.x / 5];
+  const int d = e.y;
+  const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;   // faster, slower transverse axes
+  int blk, fs;
+  if (part == 0) {
+    blk = e.x;
+    fs = e.z;
+  } else {
+    fs = e.z ? 0 : 1;
+    int co[3];
+    co[d] = fs;
+    co[t0] = (part - 1) & 1;
+    co[t1] = (part - 1) >> 1;
+    blk = child_base[e.w] + co[0] + 2 * co[1] + 4 * co[2];
+  }
+  const GridGeom& g = part ? g1 : g0;
+  const double* V = (part ? G1 : G0) + (long)blk * Guarded<N, VG>::BS;
+  double* out = (part ? flux1 : flux0) + (long)blk * A::NF + (long)(2 * d + fs) * 5 * N * N;
   const double lamx = dt * g.inv_dx[0], lamy = dt * g.inv_dx[1], lamz = dt * g.inv_dx[2];
-  const double gamma = g.gamma, gm1inv = 1.0 / (g.gamma - 1.0);
-  int n_floor = 0, n_fb = 0, n_bad = 0;
-  auto gat = [&](int i, int j, int k) -> long { return ((long)(k + G) * P + (j + G)) * P + (i + G); };
-
-  for (int it = tid; it < M * M * M; it += 256) {
-    const int i = it % M - 2, j = (it / M) % M - 2, k = it / (M * M) - 2;
-    double u[5], wv[5], inv;
-    const long o = gat(i, j, k);
+  const double gm1inv = 1.0 / (g.gamma - 1.0);
+  for (int t = threadIdx.x; t < N * N; t += blockDim.x) {
+    const int a1 = t / N, a0 = t % N;
+    int c[3];
+    c[d] = fs ? N : 0;     // the cell on the face's high side
+    c[t0] = a0;
+    c[t1] = a1;
+    double L[5], R[5], F[5];
+    amr_face_state<N>(V, c[0] - (d == 0), c[1] - (d == 1), c[2] - (d == 2), d, 1, g, lamx, lamy, lamz, L);
+    amr_face_state<N>(V, c[0], c[1], c[2], d, 0, g, lamx, lamy, lamz, R);
+    hllc_dir(d, L, R, g.gamma, gm1inv, F);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) u[v] = gin[v * A::P3 + o];
-    const int fl = prim(u, gamma, g.small_p, wv, inv);
-    if (fl && i >= 0 && i < N && j >= 0 && j < N && k >= 0 && k < N) ++n_floor;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) W[v * A::M3 + it] = wv[v];
-  }
-  __syncthreads();
-
-  for (int it = tid; it < m * m * m; it += 256) {
-    const int i = it % m - 1, j = (it / m) % m - 1, k = it / (m * m) - 1;
-    const int c = A::cW(i, j, k);
-    double wc[5], sx[5], sy[5], sz[5], wt[5], h;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      wc[v] = W[v * A::M3 + c];
-      sx[v] = van_leer_sf(wc[v] - W[v * A::M3 + c - 1], W[v * A::M3 + c + 1] - wc[v]);
-      sy[v] = van_leer_sf(wc[v] - W[v * A::M3 + c - M], W[v * A::M3 + c + M] - wc[v]);
-      sz[v] = van_leer_sf(wc[v] - W[v * A::M3 + c - M * M], W[v * A::M3 + c + M * M] - wc[v]);
-    }
-    const bool ok = predict(wc, rcp_nr(wc[0]), sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
-    if (!ok && i >= 0 && i < N && j >= 0 && j < N && k >= 0 && k < N) ++n_fb;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      Wf[(0 * 5 + v) * A::m3 + it] = fma(-h, sx[v], wt[v]);
-      Wf[(1 * 5 + v) * A::m3 + it] = fma(h, sx[v], wt[v]);
-      Wf[(2 * 5 + v) * A::m3 + it] = fma(-h, sy[v], wt[v]);
-      Wf[(3 * 5 + v) * A::m3 + it] = fma(h, sy[v], wt[v]);
-      Wf[(4 * 5 + v) * A::m3 + it] = fma(-h, sz[v], wt[v]);
-      Wf[(5 * 5 + v) * A::m3 + it] = fma(h, sz[v], wt[v]);
-    }
-  }
-  __syncthreads();
-
-  // fluxes at the low d-face of cells with c_d in 0..N, the others in 0..N-1
-  for (int d = 0; d < 3; ++d) {
-    for (int it = tid; it < (N + 1) * N * N; it += 256) {
-      int c3[3];
-      const int a0 = it % N, a1 = (it / N) % N, a2 = it / (N * N);
-      const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-      c3[t0] = a0;
-      c3[t1] = a1;
-      c3[d] = a2;
-      const int hi = A::ci(c3[0], c3[1], c3[2]);
-      const int lo = A::ci(c3[0] - (d == 0), c3[1] - (d == 1), c3[2] - (d == 2));
-      double L[5], R[5], Fv[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        L[v] = Wf[((2 * d + 1) * 5 + v) * A::m3 + lo];
-        R[v] = Wf[((2 * d + 0) * 5 + v) * A::m3 + hi];
-      }
-      hllc_dir(d, L, R, gamma, gm1inv, Fv);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) F[(d * 5 + v) * A::m3 + hi] = Fv[v];
-      // boundary faces of the block (c_d = 0: face 2d, c_d = N: face 2d+1)
-      if (a2 == 0 || a2 == N) {
-        // transverse indices, slower axis first: (t1, t0)
-        double* fo = flux + blk * A::NF + (long)(2 * d + (a2 == N)) * 5 * N * N;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) fo[(long)v * N * N + a1 * N + a0] = Fv[v];
-      }
-    }
-  }
-  __syncthreads();
-
-  for (int it = tid; it < N * N * N; it += 256) {
-    const int i = it % N, j = (it / N) % N, k = it / (N * N);
-    const int c0 = A::ci(i, j, k);
-    const int cx = A::ci(i + 1, j, k), cy = A::ci(i, j + 1, k), cz = A::ci(i, j, k + 1);
-    const long o = gat(i, j, k);
-    double un[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const double div = (lamx * (F[(0 * 5 + v) * A::m3 + cx] - F[(0 * 5 + v) * A::m3 + c0]) +
-                          lamy * (F[(1 * 5 + v) * A::m3 + cy] - F[(1 * 5 + v) * A::m3 + c0])) +
-                         lamz * (F[(2 * 5 + v) * A::m3 + cz] - F[(2 * 5 + v) * A::m3 + c0]);
-      un[v] = gin[v * A::P3 + o] - div;
-      Uout[Layout<N>::at(blk, i, j, k) + v * Layout<N>::VS] = un[v];
-    }
-    bool good = un[0] > 0.0 && un[4] > 0.0;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) good = good && isfinite(un[v]);
-    if (!good) ++n_bad;
-  }
-  if (n_floor) atomicAdd(&sCnt[0], n_floor);
-  if (n_fb) atomicAdd(&sCnt[1], n_fb);
-  if (n_bad) atomicAdd(&sCnt[2], n_bad);
-  __syncthreads();
-  if (tid == 0) {
-    for (int q = 0; q < 3; ++q)
-      if (sCnt[q]) atomicAdd(&ws->cnt[q], (unsigned long long)sCnt[q]);
+    for (int v = 0; v < 5; ++v) out[(long)v * N * N + t] = F[v];
   }
 }
 
@@ -1323,19 +1316,19 @@ __global__ __launch_bounds__(256) void amr_signal_kernel(GridGeom g, const doubl
 // Guard fill: one workgroup per (block, plane of the guarded view); every
 // cell of the guarded view (interior and guard layers, faces, edges and
 // corners) receives the state value at its mapped global index.
-template <int N>
+template <int N, int GW = G>
 __global__ __launch_bounds__(256) void fill_guards_kernel(GridGeom g, const double* __restrict__ U,
                                                           double* __restrict__ out) {
-  constexpr int P = Guarded<N>::P;
+  constexpr int P = Guarded<N, GW>::P;
   constexpr long VS = Layout<N>::VS;
   const long blk = blockIdx.x / P;
-  const int k = (int)(blockIdx.x % P) - G;
+  const int k = (int)(blockIdx.x % P) - GW;
   const int bx = (int)(blk % g.nb[0]);
   const int by = (int)((blk / g.nb[0]) % g.nb[1]);
   const int bz = (int)(blk / ((long)g.nb[0] * g.nb[1]));
   const int nx = g.nb[0] * N, ny = g.nb[1] * N, nz = g.nb[2] * N;
   for (int t = threadIdx.x; t < P * P; t += blockDim.x) {
-    const int i = t % P - G, j = t / P - G;
+    const int i = t % P - GW, j = t / P - GW;
     // global index, mapped per axis (guards reach up to G cells out)
     int I = bx * N + i, J = by * N + j, K = bz * N + k;
     I = g.bc[0] == 0 ? ((I % nx) + nx) % nx : min(max(I, 0), nx - 1);
@@ -1343,9 +1336,9 @@ __global__ __launch_bounds__(256) void fill_guards_kernel(GridGeom g, const doub
     K = g.bc[2] == 0 ? ((K % nz) + nz) % nz : min(max(K, 0), nz - 1);
     const long sb = (long)(I / N) + (long)g.nb[0] * ((J / N) + (long)g.nb[1] * (K / N));
     const long src = Layout<N>::at(sb, I % N, J % N, K % N);
-    const long dst = blk * Guarded<N>::BS + (long)(k + G) * Guarded<N>::PS + (long)(j + G) * P + (i + G);
+    const long dst = blk * Guarded<N, GW>::BS + (long)(k + GW) * Guarded<N, GW>::PS + (long)(j + GW) * P + (i + GW);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out[dst + v * Guarded<N>::VS] = U[src + v * VS];
+    for (int v = 0; v < 5; ++v) out[dst + v * Guarded<N, GW>::VS] = U[src + v * VS];
   }
 }
 
@@ -1407,43 +1400,38 @@ hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const Stag
   return hipErrorInvalidValue;
 }
 
-long amr_block_doubles(int nxb) {
-  switch (nxb) {
-    case 8: return AmrStep<8>::doubles;
-    case 16: return AmrStep<16>::doubles;
-    case 32: return AmrStep<32>::doubles;
-  }
-  return 0;
-}
-
 template <int N>
 hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
-  using A = AmrStep<N>;
-  (void)sizeof(A);
+  constexpr int T = N == 8 ? 8 : 16;
+  constexpr long TPB = (N / T) * (N / T);
   // 1. guard fill: root blocks (same-level map), fine blocks (copies / prolongation)
-  hipLaunchKernelGGL(fill_guards_kernel<N>, dim3((unsigned)(L.nroot * Guarded<N>::P)), dim3(256), 0, s, L.g0, L.Ur,
-                     L.G0);
+  hipLaunchKernelGGL((fill_guards_kernel<N, VG>), dim3((unsigned)(L.nroot * Guarded<N, VG>::P)), dim3(256), 0, s,
+                     L.g0, L.Ur, L.G0);
   if (L.nfine)
     hipLaunchKernelGGL(amr_fill_fine_kernel<N>, dim3((unsigned)L.nfine), dim3(256), 0, s, L.g0, L.Ur, L.Uf,
                        L.child_base, L.fine_root, L.G1);
-  // 2. leaf steps in chunks of workgroups sharing the scratch
-  for (long b0 = 0; b0 < L.nleaf0; b0 += L.chunk) {
-    const long n = L.nleaf0 - b0 < L.chunk ? L.nleaf0 - b0 : L.chunk;
-    hipLaunchKernelGGL(amr_step_kernel<N>, dim3((unsigned)n), dim3(256), 0, s, L.g0, L.G0, L.Ur_new, L.leaf0,
-                       L.flux0, L.scratch, b0, L.dt, L.ws);
+  // 2. leaf steps (fused tile step over the views), written over the state:
+  //    every read of the old state went to the views
+  if (L.nleaf0) {
+    const long nt = L.nleaf0 * TPB;
+    hipLaunchKernelGGL((amr_tile_kernel<N, T>), dim3((unsigned)(8 * ((nt + 7) / 8))), dim3(Tile<T>::NT), 0, s, L.g0,
+                       L.G0, L.Ur, L.leaf0, nt, L.dt, L.ws);
   }
-  for (long b0 = 0; b0 < L.nfine; b0 += L.chunk) {
-    const long n = L.nfine - b0 < L.chunk ? L.nfine - b0 : L.chunk;
-    hipLaunchKernelGGL(amr_step_kernel<N>, dim3((unsigned)n), dim3(256), 0, s, L.g1, L.G1, L.Uf_new,
-                       (const int*)nullptr, L.flux1, L.scratch, b0, L.dt, L.ws);
+  if (L.nfine) {
+    const long nt = L.nfine * TPB;
+    hipLaunchKernelGGL((amr_tile_kernel<N, T>), dim3((unsigned)(8 * ((nt + 7) / 8))), dim3(Tile<T>::NT), 0, s, L.g1,
+                       L.G1, L.Uf, (const int*)nullptr, nt, L.dt, L.ws);
   }
-  // 3. refluxing, 4. restriction
-  if (L.nreflux_groups)
+  // 3. fluxes at the fine-coarse faces, refluxing, 4. restriction
+  if (L.nreflux) {
+    hipLaunchKernelGGL(amr_face_flux_kernel<N>, dim3((unsigned)(5 * L.nreflux)), dim3(256), 0, s, L.g0, L.g1,
+                       L.reflux, L.child_base, L.G0, L.G1, L.flux0, L.flux1, L.dt);
     hipLaunchKernelGGL(amr_reflux_kernel<N>, dim3((unsigned)L.nreflux_groups), dim3(256), 0, s, L.g0, L.reflux,
-                       L.reflux_first, L.flux0, L.flux1, L.child_base, L.Ur_new, L.dt);
+                       L.reflux_first, L.flux0, L.flux1, L.child_base, L.Ur, L.dt);
+  }
   if (L.nrefined)
     hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)L.nrefined), dim3(256), 0, s, L.refined,
-                       L.child_base, L.Uf_new, L.Ur_new);
+                       L.child_base, L.Uf, L.Ur);
   return hipGetLastError();
 }
 

@@ -138,15 +138,14 @@ def test_amr_sizes_and_validation(L):
     n, nb = 8, (2, 2, 1)
     d = hydro.make_amr_desc(n, nb, [0, 1, 0, 1], bc=(0, 1, 0))
     assert L.hydro_amr_fine_blocks(ctypes.byref(d)) == 16
-    P, m, M = n + 8, n + 2, n + 4
-    per = 8 * (5 * M ** 3 + 45 * m ** 3)
+    P = n + 4
     # reflux entries: leaves 0 and 2 face the refined blocks 1 and 3 across
     # both x faces (periodic); their y neighbours are unrefined or outside
     entries, groups = 4, 2
     tab = 4 * (2 + 4 + 16 + 2 + 4 * entries + groups + 1)
     al = lambda x: (x + 255) // 256 * 256
-    total = (256 + al(tab) + al(8 * 5 * P ** 3 * 4) + al(8 * 5 * P ** 3 * 16) + al(8 * 5 * n ** 3 * 4)
-             + al(8 * 5 * n ** 3 * 16) + al(8 * 30 * n * n * 4) + al(8 * 30 * n * n * 16) + al(per * 16))
+    total = (256 + al(tab) + al(8 * 5 * P ** 3 * 4) + al(8 * 5 * P ** 3 * 16) + al(8 * 30 * n * n * 4)
+             + al(8 * 30 * n * n * 16))
     assert L.hydro_amr_work_bytes(ctypes.byref(d)) == total
     for field, value in [("nxb", 12), ("nguard", 2), ("gamma", 1.0)]:
         bad = hydro.make_amr_desc(n, nb, [0, 1, 0, 1])

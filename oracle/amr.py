@@ -194,10 +194,49 @@ def dt(mesh: Mesh, Ur, Uf, cfl: float) -> float:
     return cfl / max_signal(mesh, Ur, Uf)
 
 
+def _leaf_step(grid: Grid, G, idx: int, dt: float):
+    """The predictor-corrector step of block idx of the guarded stack G
+    (oracle_step_block_fluxes): its new interior [5, n, n, n], its face
+    fluxes per direction and its event counters."""
+    n = grid.n
+    nf = 5 * (n + 1) * n * n
+    out = np.empty(G.shape[1:])
+    F = [np.empty(nf) for _ in range(3)]
+    c = (ctypes.c_long * 3)(0, 0, 0)
+    gc = grid.c()
+    lib().oracle_step_block_fluxes(ctypes.byref(gc), _dptr(G), int(idx), _dptr(out), float(dt),
+                                   _dptr(F[0]), _dptr(F[1]), _dptr(F[2]), c)
+    return out[:, NG:NG + n, NG:NG + n, NG:NG + n], F, np.array(list(c), dtype=np.int64)
+
+
+def _reflux_block(mesh: Mesh, b: int, Ub, flux0, flux1, lam0):
+    """Refluxing of unrefined root block b (new interior Ub, in place) on
+    each face it shares with a refined root block."""
+    n, nb = mesh.n, mesh.nb
+    bx, by, bz = b % nb[0], (b // nb[0]) % nb[1], b // (nb[0] * nb[1])
+    for d in range(3):
+        for side in (0, 1):            # 0: low face of the block, 1: high face
+            pos = [bx, by, bz]
+            pos[d] += 1 if side else -1
+            if mesh.bc[d] == BC_PERIODIC:
+                pos[d] %= nb[d]
+            elif not (0 <= pos[d] < nb[d]):
+                continue
+            nbr = pos[0] + nb[0] * (pos[1] + nb[1] * pos[2])
+            if not mesh.refine[nbr]:
+                continue
+            Fc = _face(flux0[b][d], d, n, n if side else 0)            # [5, n(t1), n(t0)]
+            Ff = _fine_face_mean(mesh, flux1, int(mesh.child_base[nbr]), d, side)
+            corr = lam0[d] * (Fc - Ff) * (1.0 if side else -1.0)
+            cell = n - 1 if side else 0
+            sl = [slice(None)] * 3
+            sl[2 - d] = cell                                          # array axes (z, y, x)
+            Ub[(slice(None),) + tuple(sl)] += corr
+
+
 def step(mesh: Mesh, Ur, Uf, dt: float):
     """One step; returns (Ur_new, Uf_new, counters)."""
     n = mesh.n
-    nf = 5 * (n + 1) * n * n
     cnt = np.zeros(3, dtype=np.int64)
     # 1. guard fill
     g0 = mesh.root_grid()
@@ -210,56 +249,80 @@ def step(mesh: Mesh, Ur, Uf, dt: float):
     Ur_new, Uf_new = Ur.copy(), Uf.copy()
     flux0 = {}
     for b in np.flatnonzero(~mesh.refine):
-        out = np.empty(G0.shape[1:])
-        F = [np.empty(nf) for _ in range(3)]
-        c = (ctypes.c_long * 3)(0, 0, 0)
-        gc = g0.c()
-        lib().oracle_step_block_fluxes(ctypes.byref(gc), _dptr(G0), int(b), _dptr(out), float(dt),
-                                       _dptr(F[0]), _dptr(F[1]), _dptr(F[2]), c)
-        cnt += np.array(list(c))
-        Ur_new[b] = out[:, NG:NG + n, NG:NG + n, NG:NG + n]
-        flux0[int(b)] = F
+        Ur_new[b], flux0[int(b)], c = _leaf_step(g0, G0, int(b), dt)
+        cnt += c
     flux1 = {}
     if mesh.nfine:
         g1 = mesh.fine_grid()
         G1 = np.ascontiguousarray(G1)
         for f in range(mesh.nfine):
-            out = np.empty(G1.shape[1:])
-            F = [np.empty(nf) for _ in range(3)]
-            c = (ctypes.c_long * 3)(0, 0, 0)
-            gc = g1.c()
-            lib().oracle_step_block_fluxes(ctypes.byref(gc), _dptr(G1), int(f), _dptr(out), float(dt),
-                                           _dptr(F[0]), _dptr(F[1]), _dptr(F[2]), c)
-            cnt += np.array(list(c))
-            Uf_new[f] = out[:, NG:NG + n, NG:NG + n, NG:NG + n]
-            flux1[f] = F
+            Uf_new[f], flux1[f], c = _leaf_step(g1, G1, f, dt)
+            cnt += c
     # 3. refluxing on faces between an unrefined and a refined root block
     lam0 = [dt / h for h in mesh.dx]
-    nb = mesh.nb
     for b in np.flatnonzero(~mesh.refine):
-        b = int(b)
-        bx, by, bz = b % nb[0], (b // nb[0]) % nb[1], b // (nb[0] * nb[1])
-        for d in range(3):
-            for side in (0, 1):            # 0: low face of the block, 1: high face
-                pos = [bx, by, bz]
-                pos[d] += 1 if side else -1
-                if mesh.bc[d] == BC_PERIODIC:
-                    pos[d] %= nb[d]
-                elif not (0 <= pos[d] < nb[d]):
-                    continue
-                nbr = pos[0] + nb[0] * (pos[1] + nb[1] * pos[2])
-                if not mesh.refine[nbr]:
-                    continue
-                Fc = _face(flux0[b][d], d, n, n if side else 0)            # [5, n(t1), n(t0)]
-                Ff = _fine_face_mean(mesh, flux1, int(mesh.child_base[nbr]), d, side)
-                corr = lam0[d] * (Fc - Ff) * (1.0 if side else -1.0)
-                cell = n - 1 if side else 0
-                sl = [slice(None)] * 3
-                sl[2 - d] = cell                                          # array axes (z, y, x)
-                Ur_new[b][(slice(None),) + tuple(sl)] += corr
+        _reflux_block(mesh, int(b), Ur_new[int(b)], flux0, flux1, lam0)
     # 4. restriction
     restrict(mesh, Ur_new, Uf_new)
     return Ur_new, Uf_new, cnt
+
+
+def root_guarded(mesh: Mesh, Ur, b: int):
+    """Guarded view [5, P, P, P] of root block b by the same-level map over
+    the root state (the values fill_guards gives it)."""
+    n = mesh.n
+    P = n + 2 * NG
+    bx, by, bz = b % mesh.nb[0], (b // mesh.nb[0]) % mesh.nb[1], b // (mesh.nb[0] * mesh.nb[1])
+    r = np.arange(-NG, n + NG)
+    K, J, I = np.meshgrid(r + bz * n, r + by * n, r + bx * n, indexing="ij")
+    return root_value(mesh, Ur, I.ravel(), J.ravel(), K.ravel()).reshape(5, P, P, P)
+
+
+def step_sampled(mesh: Mesh, Ur, Uf, dt: float, roots=(), fines=(), refined=()):
+    """What step() gives on chosen blocks, each formed the same way but
+    without stepping the rest of the mesh: ``roots`` unrefined root blocks
+    (leaf step and refluxing; the fine blocks on their fine-coarse faces are
+    stepped for their fluxes), ``fines`` fine blocks, ``refined`` refined
+    root blocks (the restriction of their stepped children).  Returns
+    ({root block: [5, n, n, n]}, {fine block: [5, n, n, n]})."""
+    n = mesh.n
+    h = mesh.dx
+    g0 = Grid(n, (1, 1, 1), h, mesh.bc, mesh.gamma, mesh.small_p, NG)
+    g1 = Grid(n, (1, 1, 1), tuple(x / 2 for x in h), mesh.bc, mesh.gamma, mesh.small_p, NG)
+    fine_new = {}
+
+    class _Fluxes(dict):
+        def __missing__(self, f):
+            V = np.ascontiguousarray(fine_guarded(mesh, Ur, Uf, f)[None])
+            fine_new[f], F, _ = _leaf_step(g1, V, 0, dt)
+            self[f] = F
+            return F
+
+    flux1 = _Fluxes()
+    lam0 = [dt / x for x in h]
+    out_r = {}
+    for b in roots:
+        b = int(b)
+        assert not mesh.refine[b]
+        V = np.ascontiguousarray(root_guarded(mesh, Ur, b)[None])
+        Ub, F, _ = _leaf_step(g0, V, 0, dt)
+        Ub = Ub.copy()
+        _reflux_block(mesh, b, Ub, {b: F}, flux1, lam0)
+        out_r[b] = Ub
+    for f in fines:
+        flux1[int(f)]
+    if len(refined):
+        Uf_part = np.zeros_like(Uf)
+        Ur_part = np.zeros_like(Ur)
+        for r in refined:
+            for c in range(8):
+                f = int(mesh.child_base[int(r)]) + c
+                flux1[f]
+                Uf_part[f] = fine_new[f]
+        restrict(mesh, Ur_part, Uf_part)
+        for r in refined:
+            out_r[int(r)] = Ur_part[int(r)].copy()
+    return out_r, {int(f): fine_new[int(f)].copy() for f in fines}
 
 
 def _face(F, d, n, idx):

@@ -170,3 +170,31 @@ def test_amr_abi_rejects_bad_descriptors(hy):
     with pytest.raises(hy.HydroError):
         A.step(-1.0)
     A.close()
+
+
+def test_amr_full_size_sampled_blocks(hy):
+    """The two-level Kelvin-Helmholtz mesh the benchmark times (root
+    256x256x128 in 16^3 blocks, the 512 blocks of the interface rows
+    refined): dt over the whole mesh, then one step checked on sampled root
+    leaves (inside a level, next to refined rows, at the periodic edges),
+    fine blocks and refined root blocks against the oracle's per-block step."""
+    nb, flags, Ur, Uf, dx, gamma = ics.kelvin_helmholtz_amr(root=(256, 256, 128), n=16)
+    n = 16
+    mesh = amr.Mesh(n, nb, dx, flags, gamma=gamma)
+    A = hy.Amr(n, nb, flags.tolist(), hi=tuple(nb[d] * n * dx[d] for d in range(3)), gamma=gamma)
+    A.upload(Ur, Uf)
+    dt = amr.dt(mesh, Ur, Uf, 0.8)
+    d_gpu = A.dt(0.8)
+    assert abs(d_gpu / dt - 1.0) <= DT_TOL, (d_gpu, dt)
+    A.step(dt)
+    R, F = A.download()
+    blk = lambda bx, by, bz: bx + nb[0] * (by + nb[1] * bz)
+    roots = [blk(5, 7, 3), blk(0, 2, 0), blk(15, 5, 7), blk(3, 10, 4), blk(9, 13, 7), blk(15, 15, 0)]
+    assert not flags[roots].any() and flags[[blk(0, 3, 0), blk(15, 4, 7), blk(3, 11, 4), blk(9, 12, 7)]].all()
+    refined = [int(mesh.refined[0]), int(mesh.refined[200]), int(mesh.refined[-1])]
+    fines = [0, 1, 777, 2048, mesh.nfine - 1]
+    out_r, out_f = amr.step_sampled(mesh, Ur, Uf, dt, roots=roots, fines=fines, refined=refined)
+    assert_close((np.stack([R[b] for b in out_r]), np.stack([F[f] for f in out_f])),
+                 (np.stack(list(out_r.values())), np.stack(list(out_f.values()))), "full-size sampled")
+    assert A.counters().tolist() == [0, 0, 0]
+    A.close()

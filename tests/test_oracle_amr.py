@@ -189,3 +189,33 @@ def test_smooth_wave_through_a_refined_block():
         e_amr += np.abs(Uf[f, 0, 0, 0, :] - (1.0 + 0.2 * np.sin(2 * np.pi * (xf - t)))).sum() * h / 2
     e_root = np.abs(ics.from_blocks(U0, n, nb, 4)[0, 0, 0] - exact).sum() * h
     assert e_amr <= 1.05 * e_root, (e_amr, e_root)
+
+
+def test_sampled_step_equals_full_step():
+    """The per-block sampled step (used to check the full-size mesh) gives
+    exactly what the whole-mesh step gives on the chosen blocks."""
+    n, nb = 8, (3, 2, 2)
+    Ur, _ = _random_root(nb, n, 45)
+    flags = np.zeros(12, bool)
+    flags[[0, 5, 7]] = True
+    mesh = amr.Mesh(n, nb, (1 / 24,) * 3, flags, bc=(1, 0, 1))
+    Uf = _fine_from_root(mesh, Ur)
+    rng = np.random.default_rng(46)
+    Uf *= 1.0 + 0.05 * rng.random(Uf.shape)            # fine detail beyond the injection
+    amr.restrict(mesh, Ur, Uf)
+    dt = amr.dt(mesh, Ur, Uf, 0.8)
+    R, F, _ = amr.step(mesh, Ur, Uf, dt)
+    roots = [1, 4, 6, 11]                                # 1, 4, 6: next to refined blocks
+    fines = [0, 9, mesh.nfine - 1]
+    out_r, out_f = amr.step_sampled(mesh, Ur, Uf, dt, roots=roots, fines=fines, refined=[5])
+    for b in roots + [5]:
+        assert np.array_equal(out_r[b], R[b]), b
+    for f in fines:
+        assert np.array_equal(out_f[f], F[f]), f
+    # block 1 meets refined block 0 across its low x face and refined block 7
+    # across its high z face: refluxing changes exactly those two layers
+    g = oracle.Grid(n, (1, 1, 1), mesh.dx, mesh.bc, 1.4, 1e-10, 4)
+    plain, _, _ = amr._leaf_step(g, np.ascontiguousarray(amr.root_guarded(mesh, Ur, 1)[None]), 0, dt)
+    assert not np.array_equal(plain[:, :, :, 0], R[1][:, :, :, 0])
+    assert not np.array_equal(plain[:, -1], R[1][:, -1])
+    assert np.array_equal(plain[:, :-1, :, 1:], R[1][:, :-1, :, 1:])

@@ -254,7 +254,7 @@ def run_amr(args):
                    "root_blocks": int(flags.size), "refined_blocks": int(flags.sum()), "leaf_blocks": nleaf,
                    "cfl": args.cfl, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "amr_step_kernel",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "amr_tile_kernel",
                      "algorithmic_bytes_per_step": BYTES_PER_CELL * cells},
     }
     A.close()

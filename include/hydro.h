@@ -325,7 +325,10 @@ size_t hydro_amr_work_bytes(const hydro_amr_desc *d);
 int hydro_amr_create(const hydro_amr_desc *d, hydro_amr **out);
 /* One step of size dt (stream-ordered). */
 int hydro_amr_step(hydro_amr *a, double dt);
-/* dt = cfl / max over leaves of sum_d (|u_d|+c)/dx_d of their level (waits). */
+/* dt = cfl / max over leaves of sum_d (|u_d|+c)/dx_d of their level (waits).
+ * Returns HYDRO_ENONPHYS (dt_out still written) if a step since creation
+ * left a nonphysical cell, HYDRO_EINVAL if the maximum is not positive and
+ * finite. */
 int hydro_amr_dt(hydro_amr *a, double cfl, double *dt_out);
 /* Event counters summed since creation: floors, fallbacks, nonphysical cells (waits). */
 int hydro_amr_counters(hydro_amr *a, long long out[3]);

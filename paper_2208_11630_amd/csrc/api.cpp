@@ -903,6 +903,8 @@ int hydro_amr_dt(hydro_amr* a, double cfl, double* dt_out) {
   memcpy(&sig, &h.sig[0], sizeof sig);
   if (!(std::isfinite(sig) && sig > 0.0)) return fail(HYDRO_EINVAL, "maximum signal speed %g is not positive and finite", sig);
   *dt_out = cfl / sig;
+  if (h.cnt[2] != 0)
+    return fail(HYDRO_ENONPHYS, "%llu nonphysical cells produced since creation", h.cnt[2]);
   return HYDRO_OK;
 }
 

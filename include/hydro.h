@@ -134,7 +134,7 @@ int hydro_step_cfl(hydro_grid *g, double cfl);
 /* dt = cfl / max over interior cells of sum_d (|u_d| + c)/dx_d of the current
  * state.  Waits for the stream.  Returns HYDRO_ENONPHYS (and still writes
  * dt_out when it is finite) if any step since init left a nonphysical cell,
- * HYDRO_EINVAL if the maximum is not positive and finite.  If the state was
+ * else HYDRO_EINVAL if the maximum is not positive and finite.  If the state was
  * modified outside the library after the last hydro_step, call
  * hydro_state_changed first. */
 int hydro_dt(hydro_grid *g, double cfl, double *dt_out);
@@ -326,9 +326,9 @@ int hydro_amr_create(const hydro_amr_desc *d, hydro_amr **out);
 /* One step of size dt (stream-ordered). */
 int hydro_amr_step(hydro_amr *a, double dt);
 /* dt = cfl / max over leaves of sum_d (|u_d|+c)/dx_d of their level (waits).
- * Returns HYDRO_ENONPHYS (dt_out still written) if a step since creation
- * left a nonphysical cell, HYDRO_EINVAL if the maximum is not positive and
- * finite. */
+ * Returns HYDRO_ENONPHYS (dt_out written when finite) if a step since
+ * creation left a nonphysical cell, else HYDRO_EINVAL if the maximum is not
+ * positive and finite. */
 int hydro_amr_dt(hydro_amr *a, double cfl, double *dt_out);
 /* Event counters summed since creation: floors, fallbacks, nonphysical cells (waits). */
 int hydro_amr_counters(hydro_amr *a, long long out[3]);

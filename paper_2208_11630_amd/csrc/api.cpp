@@ -331,11 +331,11 @@ int hydro_dt(hydro_grid* g, double cfl, double* dt_out) {
   const unsigned long long bits = h.sig[slot_of(g)];
   memcpy(&s, &bits, sizeof s);
   const double dt = cfl / s;
-  if (!(std::isfinite(s) && s > 0.0 && std::isfinite(dt) && dt > 0.0))
-    return fail(HYDRO_EINVAL, "maximum signal speed %g is not positive and finite", s);
-  *dt_out = dt;
-  if (h.cnt[2] != 0)
+  const bool ok = std::isfinite(s) && s > 0.0 && std::isfinite(dt) && dt > 0.0;
+  if (ok) *dt_out = dt;
+  if (h.cnt[2] != 0)  // takes precedence: a nonphysical state also spoils the signal speed
     return fail(HYDRO_ENONPHYS, "%llu nonphysical cells produced since init", h.cnt[2]);
+  if (!ok) return fail(HYDRO_EINVAL, "maximum signal speed %g is not positive and finite", s);
   return HYDRO_OK;
 }
 
@@ -901,10 +901,11 @@ int hydro_amr_dt(hydro_amr* a, double cfl, double* dt_out) {
   if (e != hipSuccess) return hip_fail(e, "AMR header read");
   double sig;
   memcpy(&sig, &h.sig[0], sizeof sig);
-  if (!(std::isfinite(sig) && sig > 0.0)) return fail(HYDRO_EINVAL, "maximum signal speed %g is not positive and finite", sig);
-  *dt_out = cfl / sig;
+  const bool ok = std::isfinite(sig) && sig > 0.0;
+  if (ok) *dt_out = cfl / sig;
   if (h.cnt[2] != 0)
     return fail(HYDRO_ENONPHYS, "%llu nonphysical cells produced since creation", h.cnt[2]);
+  if (!ok) return fail(HYDRO_EINVAL, "maximum signal speed %g is not positive and finite", sig);
   return HYDRO_OK;
 }
 

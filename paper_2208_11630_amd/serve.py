@@ -30,6 +30,7 @@ class Request:
     t_arrival: float
     t_launch: float = math.nan
     t_done: float = math.nan
+    error: Optional[str] = None   # set when the request failed (it then has no t_done)
 
     @property
     def latency(self) -> float:
@@ -50,7 +51,10 @@ class Executor:
     def evict(self, sim: int) -> None: ...
     def launch(self, sims: Sequence[int]): ...
     def done(self, handle) -> bool: ...
-    def finish(self, handle) -> None: ...
+    def finish(self, handle):
+        """Complete a launch; may return the sims whose step failed (e.g. a
+        nonphysical state): their requests fail and they take no more."""
+        ...
 
 
 @dataclass
@@ -61,12 +65,14 @@ class Stats:
     evictions: int = 0
     admissions: int = 0
     refused: int = 0
+    failed: int = 0
     wall: float = 0.0
 
     def summary(self) -> Dict:
         lat = np.array([r.latency for r in self.requests if not math.isnan(r.t_done)])
         out = {"completed": int(lat.size), "launches": self.launches, "evictions": self.evictions,
-               "admissions": self.admissions, "wall_s": self.wall,
+               "admissions": self.admissions, "refused": self.refused, "failed": self.failed,
+               "wall_s": self.wall,
                "cell_updates_per_s": self.cells / self.wall if self.wall > 0 else 0.0,
                "requests_per_s": lat.size / self.wall if self.wall > 0 else 0.0}
         if lat.size:
@@ -78,7 +84,11 @@ class Stats:
 
 
 class Server:
-    """Admission, continuous batching and completion tracking (host side)."""
+    """Admission, continuous batching and completion tracking (host side).
+
+    Failures stay local: a launch that raises fails the requests it carried
+    and nothing else; a sim that the executor reports as failed (or whose
+    launch raised) is quarantined, and its later requests fail at once."""
 
     def __init__(self, executor: Executor, budget_bytes: int, max_inflight: int = 2,
                  max_cells_per_launch: Optional[int] = None, clock=time.perf_counter):
@@ -90,6 +100,7 @@ class Server:
         self.used = 0
         self.lru: "collections.OrderedDict[int, None]" = collections.OrderedDict()  # resident, oldest first
         self.busy: set = set()
+        self.quarantined: Dict[int, str] = {}
 
     # -- residency ------------------------------------------------------------
     def _admit(self, sim: int, pinned: set) -> bool:
@@ -143,15 +154,28 @@ class Server:
             still = []
             for h, reqs, sims in inflight:
                 if self.ex.done(h):
-                    self.ex.finish(h)
+                    try:
+                        bad = set(self.ex.finish(h) or ())
+                        why = "step failed"
+                    except Exception as e:  # the whole launch is lost
+                        bad, why = set(sims), f"finish raised {type(e).__name__}: {e}"
                     tdone = self.clock()
                     for r in reqs:
-                        r.t_done = tdone
+                        if r.sim in bad:
+                            self._fail(r, why)
+                        else:
+                            r.t_done = tdone
                     for s in sims:
                         self.busy.discard(s)
+                        if s in bad:
+                            self.quarantined[s] = why
                 else:
                     still.append((h, reqs, sims))
             inflight = still
+            # requests of quarantined sims fail at once
+            for s in [s for s in pending if s in self.quarantined]:
+                for r in pending.pop(s):
+                    self._fail(r, self.quarantined[s])
             # form the next launch from whatever is ready
             if len(inflight) < self.max_inflight:
                 chosen, reqs, cells = [], [], 0
@@ -179,7 +203,15 @@ class Server:
                     if not q:
                         del pending[s]
                 if chosen:
-                    h = self.ex.launch(chosen)
+                    try:
+                        h = self.ex.launch(chosen)
+                    except Exception as e:
+                        why = f"launch raised {type(e).__name__}: {e}"
+                        for r in reqs:
+                            self._fail(r, why)
+                        for s_ in chosen:
+                            self.quarantined[s_] = why
+                        continue
                     tl = self.clock()
                     for r in reqs:
                         r.t_launch = tl
@@ -202,6 +234,10 @@ class Server:
                 time.sleep(2e-5)
         self.stats.wall = self.clock() - t0
         return self.stats
+
+    def _fail(self, r: Request, why: str) -> None:
+        r.error = why
+        self.stats.failed += 1
 
 
 def poisson_arrivals(rate: float, duration: float, nsims: int, seed: int = 4) -> List[tuple]:

@@ -159,3 +159,44 @@ def test_pinned_pool_recycles_exact_sizes_and_respects_its_cap():
     assert p.get(300_000).data_ptr() == a.data_ptr()        # recycled, same size
     assert p.get(600_000) is None                            # would need a third chunk
     assert p.get(2 << 20) is None                            # larger than a chunk
+
+
+class FailingExecutor(FakeExecutor):
+    """Raises at the launch that carries `raise_sim`; reports `bad_sim` as
+    failed when its step completes."""
+
+    def __init__(self, sizes, raise_sim, bad_sim):
+        super().__init__(sizes)
+        self.raise_sim, self.bad_sim = raise_sim, bad_sim
+
+    def launch(self, sims):
+        if self.raise_sim in sims:
+            raise RuntimeError("device error")
+        return super().launch(sims)
+
+    def finish(self, h):
+        sims = self.inflight[h][1]
+        super().finish(h)
+        return {self.bad_sim} & set(sims)
+
+
+def test_failures_stay_local_and_quarantine_the_sim():
+    sizes = [16] * 6
+    ex = FailingExecutor(sizes, raise_sim=1, bad_sim=4)
+    srv = serve.Server(ex, budget_bytes=10 ** 9, max_inflight=2, max_cells_per_launch=16 ** 3)
+    arrivals = [(0.0005 * i, i % 6) for i in range(60)]
+    stats = srv.run(arrivals)
+    by_sim = collections.defaultdict(list)
+    for r in stats.requests:
+        by_sim[r.sim].append(r)
+    for s in (0, 2, 3, 5):
+        assert all(r.error is None and not np.isnan(r.t_done) for r in by_sim[s]), s
+    assert all(r.error and "launch raised RuntimeError" in r.error for r in by_sim[1])
+    assert all(np.isnan(r.t_done) for r in by_sim[1])
+    # sim 4: its first step fails when it completes, every later request at once
+    assert all(r.error == "step failed" for r in by_sim[4])
+    assert sum(1 for ev, p in ex.log if ev == "launch" and 4 in p) == 1
+    assert stats.failed == len(by_sim[1]) + len(by_sim[4]) == 20
+    assert srv.quarantined.keys() == {1, 4}
+    summ = stats.summary()
+    assert summ["completed"] == 40 and summ["failed"] == 20

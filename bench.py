@@ -199,9 +199,9 @@ def run_amr(args):
     """Two-level static AMR: the Kelvin-Helmholtz shear layer on a 256 x 256
     x 128 root grid of 16^3 blocks, the block rows at the two interfaces
     refined once (fine cells 1/512).  A step: dt from the CFL rule over both
-    levels (one stream synchronization), then guard fill (same level,
-    prolongation), the step of every leaf, refluxing and restriction.
-    value = leaf cell-updates/s."""
+    levels formed on the device (the signal speed the previous step
+    reduced), views with guards (same level, prolongation), the step of
+    every leaf, refluxing and restriction.  value = leaf cell-updates/s."""
     import numpy as np
     import torch
 
@@ -219,7 +219,7 @@ def run_amr(args):
     del Ur, Uf
 
     def one():
-        A.step(A.dt(args.cfl))
+        A.step_cfl(args.cfl)
     for _ in range(args.warmup):
         one()
     A.stream.synchronize()

@@ -323,9 +323,21 @@ size_t hydro_amr_work_bytes(const hydro_amr_desc *d);
 /* Validate and build the mesh tables (uploaded to the workspace; waits for
  * the upload).  Errors: HYDRO_EINVAL, HYDRO_ESIZE, HYDRO_EDEVICE. */
 int hydro_amr_create(const hydro_amr_desc *d, hydro_amr **out);
-/* One step of size dt (stream-ordered). */
+/* One step of size dt (stream-ordered).  Every step also reduces the new
+ * state's signal speed (fused into the leaf steps and refluxing), so the
+ * next hydro_amr_step_cfl needs no extra pass. */
 int hydro_amr_step(hydro_amr *a, double dt);
-/* dt = cfl / max over leaves of sum_d (|u_d|+c)/dx_d of their level (waits).
+/* One step with dt = cfl / max over leaves of sum_d (|u_d|+c)/dx_d of the
+ * current state formed on the device (no host round trip); the dt used is
+ * kept for hydro_amr_last_dt.  Async. */
+int hydro_amr_step_cfl(hydro_amr *a, double cfl);
+/* dt of the most recent step (waits).  HYDRO_EINVAL before the first step. */
+int hydro_amr_last_dt(hydro_amr *a, double *dt_out);
+/* Call after writing Ur / Uf outside the library: the signal speed the
+ * last step reduced no longer describes the state. */
+int hydro_amr_state_changed(hydro_amr *a);
+/* dt = cfl / max over leaves of sum_d (|u_d|+c)/dx_d of their level (waits;
+ * reduces the current state first unless a step already did).
  * Returns HYDRO_ENONPHYS (dt_out written when finite) if a step since
  * creation left a nonphysical cell, else HYDRO_EINVAL if the maximum is not
  * positive and finite. */

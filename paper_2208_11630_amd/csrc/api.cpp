@@ -714,6 +714,8 @@ struct hydro_amr {
   hydro_amr_desc d;
   hydro::AmrLaunch L;
   std::vector<unsigned char> refine;
+  long steps = 0;          // signal slot of the current state: steps % 3
+  bool sig_valid = false;  // the slot holds the current state's signal speed
 };
 
 namespace {
@@ -723,7 +725,7 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct AmrLayout {
   long nroot, nfine, nleaf0, nrefined, nreflux, ngroups;
   size_t o_tab, o_G0, o_G1, o_f0, o_f1, total;
-  std::vector<int> leaf0, child_base, fine_root, refined;
+  std::vector<int> leaf0, leaf_plain, rx_blocks, child_base, fine_root, refined;
   std::vector<int> reflux;  // 4 ints per entry, grouped by coarse leaf
   std::vector<int> first;   // ngroups + 1 entry offsets
 };
@@ -763,6 +765,8 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
     for (int c = 0; c < 8; ++c) A.fine_root[8 * q + c] = A.refined[q];
   A.reflux.clear();
   A.first.assign(1, 0);
+  A.leaf_plain.clear();
+  A.rx_blocks.clear();
   for (int b : A.leaf0) {
     const long bx = b % nb0, by = (b / nb0) % nb1, bz = b / (nb0 * nb1);
     for (int dd = 0; dd < 3; ++dd)
@@ -776,13 +780,18 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
         if (!d->refine[nbr]) continue;
         A.reflux.insert(A.reflux.end(), {b, dd, side, (int)nbr});
       }
-    if ((int)A.reflux.size() / 4 > A.first.back()) A.first.push_back((int)A.reflux.size() / 4);
+    if ((int)A.reflux.size() / 4 > A.first.back()) {
+      A.first.push_back((int)A.reflux.size() / 4);
+      A.rx_blocks.push_back(b);
+    } else {
+      A.leaf_plain.push_back(b);
+    }
   }
   A.nreflux = (long)A.reflux.size() / 4;
   A.ngroups = (long)A.first.size() - 1;
   const long P = N + 4;   // the step's internal views keep two guard layers
   const size_t tab = sizeof(int) * (size_t)(A.nleaf0 + A.nroot + A.nfine + A.nrefined + 4 * A.nreflux +
-                                             A.ngroups + 1);
+                                             A.ngroups + 1 + A.nleaf0);
   A.o_tab = 256;
   A.o_G0 = A.o_tab + al256(tab);
   A.o_G1 = A.o_G0 + al256(sizeof(double) * 5 * P * P * P * A.nroot);
@@ -846,12 +855,17 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
   host.insert(host.end(), A.fine_root.begin(), A.fine_root.end());
   host.insert(host.end(), A.refined.begin(), A.refined.end());
   host.insert(host.end(), A.first.begin(), A.first.end());
+  host.insert(host.end(), A.leaf_plain.begin(), A.leaf_plain.end());
+  host.insert(host.end(), A.rx_blocks.begin(), A.rx_blocks.end());
   L.reflux = (const int4*)tab;
   L.leaf0 = tab + 4 * A.nreflux;
   L.child_base = L.leaf0 + A.nleaf0;
   L.fine_root = L.child_base + A.nroot;
   L.refined = L.fine_root + A.nfine;
   L.reflux_first = L.refined + A.nrefined;
+  L.leaf_plain = L.reflux_first + A.ngroups + 1;
+  L.rx_blocks = L.leaf_plain + A.leaf_plain.size();
+  L.nleaf_plain = (long)A.leaf_plain.size();
   L.Ur = d->Ur;
   L.Uf = d->Uf;
   L.G0 = (double*)(w + A.o_G0);
@@ -866,6 +880,8 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
   L.nreflux = A.nreflux;
   L.nreflux_groups = A.ngroups;
   L.dt = 0.0;
+  L.cfl = 0.0;
+  L.slot = 0;
   hipStream_t s = (hipStream_t)d->stream;
   hipError_t e = hipMemsetAsync(w, 0, 256, s);
   if (e == hipSuccess && !host.empty())
@@ -879,33 +895,86 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
   return HYDRO_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+int amr_ensure_signal(hydro_amr* a) {
+  if (a->sig_valid) return HYDRO_OK;
+  hipError_t e = hydro::launch_amr_signal(a->d.nxb, a->L, (int)(a->steps % 3), (hipStream_t)a->d.stream);
+  if (e != hipSuccess) return hip_fail(e, "AMR signal launch");
+  a->sig_valid = true;
+  return HYDRO_OK;
+}
+
+int amr_launch(hydro_amr* a, double dt, double cfl) {
+  a->L.dt = dt;
+  a->L.cfl = cfl;
+  a->L.slot = (int)(a->steps % 3);
+  hipError_t e = hydro::launch_amr_step(a->d.nxb, a->L, (hipStream_t)a->d.stream);
+  if (e != hipSuccess) return hip_fail(e, "AMR step launch");
+  ++a->steps;
+  a->sig_valid = true;  // the step reduced the new state's signal speed
+  return HYDRO_OK;
+}
+
+int amr_read_header(hydro_amr* a, hydro::WorkHeader* h) {
+  hipStream_t s = (hipStream_t)a->d.stream;
+  hipError_t e = hipMemcpyAsync(h, a->d.work, sizeof *h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "AMR header read");
+  return HYDRO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int hydro_amr_step(hydro_amr* a, double dt) {
   if (!a) return fail(HYDRO_EINVAL, "handle is NULL");
   if (!finite_pos(dt)) return fail(HYDRO_EINVAL, "dt must be finite and > 0 (got %g)", dt);
-  a->L.dt = dt;
-  hipStream_t s = (hipStream_t)a->d.stream;
-  hipError_t e = hydro::launch_amr_step(a->d.nxb, a->L, s);
-  if (e != hipSuccess) return hip_fail(e, "AMR step launch");
-  return HYDRO_OK;
+  return amr_launch(a, dt, 0.0);
+}
+
+int hydro_amr_step_cfl(hydro_amr* a, double cfl) {
+  if (!a) return fail(HYDRO_EINVAL, "handle is NULL");
+  if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
+  int rc = amr_ensure_signal(a);
+  if (rc) return rc;
+  return amr_launch(a, 0.0, cfl);
 }
 
 int hydro_amr_dt(hydro_amr* a, double cfl, double* dt_out) {
   if (!a || !dt_out) return fail(HYDRO_EINVAL, "handle or dt_out is NULL");
   if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
-  hipStream_t s = (hipStream_t)a->d.stream;
-  hipError_t e = hydro::launch_amr_signal(a->d.nxb, a->L, 0, s);
-  if (e != hipSuccess) return hip_fail(e, "AMR signal launch");
+  int rc = amr_ensure_signal(a);
+  if (rc) return rc;
   hydro::WorkHeader h;
-  e = hipMemcpyAsync(&h, a->d.work, sizeof h, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "AMR header read");
+  rc = amr_read_header(a, &h);
+  if (rc) return rc;
   double sig;
-  memcpy(&sig, &h.sig[0], sizeof sig);
+  memcpy(&sig, &h.sig[a->steps % 3], sizeof sig);
   const bool ok = std::isfinite(sig) && sig > 0.0;
   if (ok) *dt_out = cfl / sig;
   if (h.cnt[2] != 0)
     return fail(HYDRO_ENONPHYS, "%llu nonphysical cells produced since creation", h.cnt[2]);
   if (!ok) return fail(HYDRO_EINVAL, "maximum signal speed %g is not positive and finite", sig);
+  return HYDRO_OK;
+}
+
+int hydro_amr_last_dt(hydro_amr* a, double* dt_out) {
+  if (!a || !dt_out) return fail(HYDRO_EINVAL, "handle or dt_out is NULL");
+  if (a->steps == 0) return fail(HYDRO_EINVAL, "no step has been taken");
+  hydro::WorkHeader h;
+  int rc = amr_read_header(a, &h);
+  if (rc) return rc;
+  *dt_out = h.dt_last;
+  return HYDRO_OK;
+}
+
+int hydro_amr_state_changed(hydro_amr* a) {
+  if (!a) return fail(HYDRO_EINVAL, "handle is NULL");
+  a->sig_valid = false;
   return HYDRO_OK;
 }
 

@@ -95,14 +95,18 @@ struct AmrLaunch {
   double* flux0;              // boundary fluxes per root block / fine block (fine-coarse faces only)
   double* flux1;
   const int* leaf0;           // unrefined root blocks
+  const int* leaf_plain;      // unrefined root blocks without a refined neighbour
+  const int* rx_blocks;       // unrefined root blocks with one (the reflux groups' blocks, in group order)
   const int* child_base;      // per root block: first child, or -1
   const int* fine_root;       // per fine block: its root block
   const int* refined;         // refined root blocks
   const int4* reflux;         // (coarse leaf, d, side, refined neighbour), grouped by coarse leaf
   const int* reflux_first;    // nreflux_groups + 1 offsets into reflux
   WorkHeader* ws;
-  long nroot, nleaf0, nfine, nrefined, nreflux, nreflux_groups;
-  double dt;
+  long nroot, nleaf0, nleaf_plain, nfine, nrefined, nreflux, nreflux_groups;
+  double dt;                  // used when cfl <= 0
+  double cfl;                 // > 0: dt = cfl / ws->sig[slot]
+  int slot;                   // step number mod 3
 };
 hipError_t launch_amr_step(int nxb, const AmrLaunch& L, hipStream_t s);
 hipError_t launch_amr_signal(int nxb, const AmrLaunch& L, int slot, hipStream_t s);

@@ -368,14 +368,15 @@ struct Smem {
 // ([block][var][N+2VG]^3, the VG guard layers filled) and the pencil is the
 // whole z extent of block gv_list[tile_in_sim / (N/T)^2] (or that index
 // when gv_list is null): every read stays inside the block's own view, the
-// result goes to the block in compact layout in Uout, dt is dt_host and no
-// signal speed is reduced (event counters are).
+// result goes to the block in compact layout in Uout, dt is the one
+// recorded in ws->dt_last, and the new state's signal speed goes to
+// ws->sig[(slot+1)%3] only when gv_emit is set (event counters always).
 template <int N, int T, bool MOL = false, bool GV = false>
 __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __restrict__ Uin, double* Uout,
                                           WorkHeader* ws, double dt_host, double cfl, int slot,
                                           long tile_in_sim, int plen, Smem<T>& sm,
                                           const StageArgs& st = StageArgs{nullptr, 0.0, 0.0, 0, 1},
-                                          const int* gv_list = nullptr) {
+                                          const int* gv_list = nullptr, bool gv_emit = false) {
   static_assert(!(GV && MOL), "guarded-view input is for the predictor-corrector step");
   using TL = Tile<T>;
   constexpr int NT = TL::NT, NI = TL::NI, NR = TL::NR, NE = TL::NE, WS = TL::WS;
@@ -400,7 +401,9 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   if (tid < 3) sm.sCnt[tid] = 0;
 
   double dt = dt_host;
-  if constexpr (!GV) {
+  if constexpr (GV) {
+    dt = ws->dt_last;
+  } else {
     if (MOL && st.stage > 0) {
       if (cfl > 0.0) dt = ws->dt_last;
     } else {
@@ -411,7 +414,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
       }
     }
   }
-  const bool emit = !GV && (!MOL || st.last);
+  const bool emit = GV ? gv_emit : (!MOL || st.last);
   const double lamx = dt * g.inv_dx[0], lamy = dt * g.inv_dx[1], lamz = dt * g.inv_dx[2];
   const double gamma = g.gamma, gm1inv = 1.0 / (g.gamma - 1.0);
 
@@ -1127,18 +1130,27 @@ __global__ __launch_bounds__(256) void amr_fill_fine_kernel(GridGeom g0, const d
   }
 }
 
+// Start of an AMR step: dt = cfl / ws->sig[slot] (cfl > 0) or dt_host,
+// recorded in ws->dt_last for every later kernel of the step; the signal
+// slot of the step after next is cleared.
+__global__ void amr_begin_kernel(WorkHeader* ws, double dt_host, double cfl, int slot) {
+  ws->dt_last = cfl > 0.0 ? cfl / __longlong_as_double(ws->sig[slot]) : dt_host;
+  ws->sig[(slot + 2) % 3] = 0ull;
+}
+
 // Leaf step: the fused tile step over guarded views, one workgroup per
 // column tile (the whole z extent of the block), blocks list[0..nblk) (or
-// 0..nblk when list is null), XCD-aware order.
+// 0..nblk when list is null), XCD-aware order; emit: reduce the new state's
+// signal speed into ws->sig[(slot+1)%3].
 template <int N, int T>
 __global__ __launch_bounds__(Tile<T>::NT, 2) void amr_tile_kernel(GridGeom g, const double* __restrict__ Gin,
                                                                   double* Uout, const int* __restrict__ list,
-                                                                  long ntiles, double dt, WorkHeader* ws) {
+                                                                  long ntiles, int slot, int emit, WorkHeader* ws) {
   __shared__ Smem<T> sm;
   const long tile_id = xcd_tile(blockIdx.x, ntiles);
   if (tile_id >= ntiles) return;
-  tile_step<N, T, false, true>(g, Gin, Uout, ws, dt, 0.0, 0, tile_id, N, sm,
-                               StageArgs{nullptr, 0.0, 0.0, 0, 1}, list);
+  tile_step<N, T, false, true>(g, Gin, Uout, ws, 0.0, 0.0, slot, tile_id, N, sm,
+                               StageArgs{nullptr, 0.0, 0.0, 0, 1}, list, emit != 0);
 }
 
 // Face state of cell (i, j, k) of a guarded view V on its low (hi = 0) or
@@ -1189,8 +1201,9 @@ __global__ __launch_bounds__(256) void amr_face_flux_kernel(GridGeom g0, GridGeo
                                                             const int* __restrict__ child_base,
                                                             const double* __restrict__ G0,
                                                             const double* __restrict__ G1, double* flux0,
-                                                            double* flux1, double dt) {
+                                                            double* flux1, const WorkHeader* ws) {
   using A = AmrStep<N>;
+  const double dt = ws->dt_last;
   const int part = blockIdx.x % 5;
   const int4 e = entries[blockIdx.x / 5];
   const int d = e.y;
@@ -1233,14 +1246,19 @@ __global__ __launch_bounds__(256) void amr_face_flux_kernel(GridGeom g0, GridGeo
 // (side 1), U -= lam_d (F_c - <F_f>) on the low face.  Entries of one coarse
 // block are contiguous (first[w] .. first[w+1]) and one workgroup applies
 // them in order: faces of one block share their edge and corner cells.
+// Then it reduces the block's final signal speed into ws->sig[(slot+1)%3]
+// (the leaf step left these blocks out).
 template <int N>
 __global__ __launch_bounds__(256) void amr_reflux_kernel(GridGeom g0, const int4* __restrict__ entries,
                                                          const int* __restrict__ first,
                                                          const double* __restrict__ flux0,
                                                          const double* __restrict__ flux1,
-                                                         const int* __restrict__ child_base, double* Ur, double dt) {
+                                                         const int* __restrict__ child_base, double* Ur,
+                                                         WorkHeader* ws, int slot) {
   using A = AmrStep<N>;
   constexpr int H = N / 2;
+  __shared__ unsigned long long sRed[4];
+  const double dt = ws->dt_last;
   const int e_end = first[blockIdx.x + 1];
   for (int q = first[blockIdx.x]; q < e_end; ++q) {
     const int4 e = entries[q];
@@ -1274,6 +1292,15 @@ __global__ __launch_bounds__(256) void amr_reflux_kernel(GridGeom g0, const int4
     }
     __syncthreads();
   }
+  const int b = entries[first[blockIdx.x]].x;
+  double smax = 0.0;
+  for (int t = threadIdx.x; t < N * N * N; t += blockDim.x) {
+    double u[5];
+    load_cons<N>(Ur, Layout<N>::at(b, t % N, (t / N) % N, t / (N * N)), u);
+    const double sp = signal_speed(u, g0);
+    smax = (sp > smax || !(sp == sp)) ? sp : smax;
+  }
+  wg_max_to(smax, sRed, &ws->sig[(slot + 1) % 3]);
 }
 
 // Restriction: root block refined[w] takes the mean of its children.
@@ -1404,30 +1431,32 @@ template <int N>
 hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
   constexpr int T = N == 8 ? 8 : 16;
   constexpr long TPB = (N / T) * (N / T);
-  // 1. guard fill: root blocks (same-level map), fine blocks (copies / prolongation)
+  const int slot = L.slot;
+  hipLaunchKernelGGL(amr_begin_kernel, dim3(1), dim3(1), 0, s, L.ws, L.dt, L.cfl, slot);
+  // 1. views: root blocks (same-level map), fine blocks (copies / prolongation)
   hipLaunchKernelGGL((fill_guards_kernel<N, VG>), dim3((unsigned)(L.nroot * Guarded<N, VG>::P)), dim3(256), 0, s,
                      L.g0, L.Ur, L.G0);
   if (L.nfine)
     hipLaunchKernelGGL(amr_fill_fine_kernel<N>, dim3((unsigned)L.nfine), dim3(256), 0, s, L.g0, L.Ur, L.Uf,
                        L.child_base, L.fine_root, L.G1);
   // 2. leaf steps (fused tile step over the views), written over the state:
-  //    every read of the old state went to the views
-  if (L.nleaf0) {
-    const long nt = L.nleaf0 * TPB;
-    hipLaunchKernelGGL((amr_tile_kernel<N, T>), dim3((unsigned)(8 * ((nt + 7) / 8))), dim3(Tile<T>::NT), 0, s, L.g0,
-                       L.G0, L.Ur, L.leaf0, nt, L.dt, L.ws);
-  }
-  if (L.nfine) {
-    const long nt = L.nfine * TPB;
-    hipLaunchKernelGGL((amr_tile_kernel<N, T>), dim3((unsigned)(8 * ((nt + 7) / 8))), dim3(Tile<T>::NT), 0, s, L.g1,
-                       L.G1, L.Uf, (const int*)nullptr, nt, L.dt, L.ws);
-  }
+  //    every read of the old state went to the views.  Root leaves next to a
+  //    refined block reduce their signal speed after refluxing instead.
+  auto tiles = [&](const GridGeom& g, const double* Gv, double* U, const int* list, long nblk, int emit) {
+    if (!nblk) return;
+    const long nt = nblk * TPB;
+    hipLaunchKernelGGL((amr_tile_kernel<N, T>), dim3((unsigned)(8 * ((nt + 7) / 8))), dim3(Tile<T>::NT), 0, s, g, Gv,
+                       U, list, nt, slot, emit, L.ws);
+  };
+  tiles(L.g0, L.G0, L.Ur, L.leaf_plain, L.nleaf_plain, 1);
+  tiles(L.g0, L.G0, L.Ur, L.rx_blocks, L.nreflux_groups, 0);
+  tiles(L.g1, L.G1, L.Uf, (const int*)nullptr, L.nfine, 1);
   // 3. fluxes at the fine-coarse faces, refluxing, 4. restriction
   if (L.nreflux) {
     hipLaunchKernelGGL(amr_face_flux_kernel<N>, dim3((unsigned)(5 * L.nreflux)), dim3(256), 0, s, L.g0, L.g1,
-                       L.reflux, L.child_base, L.G0, L.G1, L.flux0, L.flux1, L.dt);
+                       L.reflux, L.child_base, L.G0, L.G1, L.flux0, L.flux1, (const WorkHeader*)L.ws);
     hipLaunchKernelGGL(amr_reflux_kernel<N>, dim3((unsigned)L.nreflux_groups), dim3(256), 0, s, L.g0, L.reflux,
-                       L.reflux_first, L.flux0, L.flux1, L.child_base, L.Ur, L.dt);
+                       L.reflux_first, L.flux0, L.flux1, L.child_base, L.Ur, L.ws, slot);
   }
   if (L.nrefined)
     hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)L.nrefined), dim3(256), 0, s, L.refined,

@@ -72,6 +72,9 @@ SIGNATURES = {
     "hydro_amr_work_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
     "hydro_amr_create": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "hydro_amr_step": ([ctypes.c_void_p, ctypes.c_double], ctypes.c_int),
+    "hydro_amr_step_cfl": ([ctypes.c_void_p, ctypes.c_double], ctypes.c_int),
+    "hydro_amr_last_dt": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "hydro_amr_state_changed": ([ctypes.c_void_p], ctypes.c_int),
     "hydro_amr_dt": ([ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "hydro_amr_counters": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
     "hydro_amr_free": ([ctypes.c_void_p], ctypes.c_int),
@@ -443,6 +446,7 @@ class Amr:
             if Uf is not None and self.nfine:
                 self.Uf.copy_(t.from_numpy(np.ascontiguousarray(Uf, dtype=np.float64)))
         self.stream.synchronize()
+        _check(lib().hydro_amr_state_changed(self.handle))
 
     def download(self):
         self.stream.synchronize()
@@ -450,6 +454,15 @@ class Amr:
 
     def step(self, dt: float) -> None:
         _check(lib().hydro_amr_step(self.handle, float(dt)))
+
+    def step_cfl(self, cfl: float) -> None:
+        """One step whose dt is formed on the device from the CFL rule."""
+        _check(lib().hydro_amr_step_cfl(self.handle, float(cfl)))
+
+    def last_dt(self) -> float:
+        out = ctypes.c_double()
+        _check(lib().hydro_amr_last_dt(self.handle, ctypes.byref(out)))
+        return out.value
 
     def dt(self, cfl: float) -> float:
         out = ctypes.c_double()

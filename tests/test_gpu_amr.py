@@ -122,6 +122,23 @@ def test_amr_trajectory_parity(hy, case):
     A.close()
 
 
+@pytest.mark.parametrize("case", ["n8_3x2x2_mixed_bc", "n16_2x2x1_periodic_z1", "n8_all_refined", "n32_2x1x1"])
+def test_amr_trajectory_with_device_dt(hy, case):
+    """Three steps whose dt the device forms from the signal speed the
+    previous step reduced (fused into the leaf steps and refluxing)."""
+    print(f"\n[amr] device dt {case}", flush=True)
+    mesh, Ur, Uf, A = make(hy, case)
+    for s in range(3):
+        dt = amr.dt(mesh, Ur, Uf, 0.8)
+        A.step_cfl(0.8)
+        assert abs(A.last_dt() / dt - 1.0) <= DT_TOL, (s, A.last_dt(), dt)
+        Ur, Uf, _ = amr.step(mesh, Ur, Uf, dt)
+        assert_close(A.download(), (Ur, Uf), f"{case} device-dt step {s}")
+    # the signal speed the last step reduced gives the next dt
+    assert abs(A.dt(0.8) / amr.dt(mesh, Ur, Uf, 0.8) - 1.0) <= DT_TOL
+    A.close()
+
+
 def test_amr_conserves_composite_totals(hy):
     """Periodic mesh: leaf totals weighted by cell volume change by roundoff only."""
     mesh, Ur, Uf, A = make(hy, "n8_2x2x2_one")

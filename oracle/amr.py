@@ -138,24 +138,34 @@ def fine_guarded(mesh: Mesh, Ur, Uf, f):
     # prolongation from the root cells under the others
     sel = ~fine_here
     if sel.any():
-        Ic, Jc, Kc = I[sel] // 2, J[sel] // 2, K[sel] // 2
-        Uc = root_value(mesh, Ur, Ic, Jc, Kc)
-        val = Uc.copy()
-        offs = [(I[sel] % 2) * 2 - 1, (J[sel] % 2) * 2 - 1, (K[sel] % 2) * 2 - 1]   # -1 / +1
-        for d in range(3):
-            e = [0, 0, 0]
-            e[d] = 1
-            Um = root_value(mesh, Ur, Ic - e[0], Jc - e[1], Kc - e[2])
-            Up = root_value(mesh, Ur, Ic + e[0], Jc + e[1], Kc + e[2])
-            S = _van_leer(Uc - Um, Up - Uc)
-            val = val + S * (0.25 * offs[d])
-        rho = val[0]
-        kin = 0.5 * ((val[1] ** 2 + val[2] ** 2) + val[3] ** 2) / np.where(rho > 0, rho, 1.0)
-        p = (mesh.gamma - 1.0) * (val[4] - kin)
-        bad = ~((rho > 0) & (p > 0))
-        val[:, bad] = Uc[:, bad]
-        out[:, sel] = val
+        out[:, sel] = prolong(mesh, Ur, I[sel], J[sel], K[sel])
     return out
+
+
+def prolong(mesh: Mesh, Ur, I, J, K):
+    """Conserved values [5, m] prolonged from the root state to level-1
+    global cells (I, J, K) (1-D arrays, inside the domain): the root cell
+    under each, U_c + sum_d S_d * (+-1/4), S_d the van Leer slope of the
+    conserved variable over root cells d-1, d, d+1 (level-0 map), the sign
+    that of the fine cell's offset from the root cell's centre; U_c itself
+    where that gives rho <= 0 or p <= 0."""
+    Ic, Jc, Kc = I // 2, J // 2, K // 2
+    Uc = root_value(mesh, Ur, Ic, Jc, Kc)
+    val = Uc.copy()
+    offs = [(I % 2) * 2 - 1, (J % 2) * 2 - 1, (K % 2) * 2 - 1]   # -1 / +1
+    for d in range(3):
+        e = [0, 0, 0]
+        e[d] = 1
+        Um = root_value(mesh, Ur, Ic - e[0], Jc - e[1], Kc - e[2])
+        Up = root_value(mesh, Ur, Ic + e[0], Jc + e[1], Kc + e[2])
+        S = _van_leer(Uc - Um, Up - Uc)
+        val = val + S * (0.25 * offs[d])
+    rho = val[0]
+    kin = 0.5 * ((val[1] ** 2 + val[2] ** 2) + val[3] ** 2) / np.where(rho > 0, rho, 1.0)
+    p = (mesh.gamma - 1.0) * (val[4] - kin)
+    bad = ~((rho > 0) & (p > 0))
+    val[:, bad] = Uc[:, bad]
+    return val
 
 
 def _to_guarded(U, n):
@@ -356,3 +366,88 @@ def _fine_face_mean(mesh, flux1, base, d, side):
         avg = F.reshape(5, h, 2, h, 2).mean(axis=(2, 4))
         out[:, o0:o0 + h, o1:o1 + h] = avg
     return out
+
+
+# ---- adaptivity: refinement estimator and regridding --------------------------
+
+def _root_global(mesh: Mesh, Ur):
+    """Root state as a global array [5, Z, Y, X]."""
+    n, nb = mesh.n, mesh.nb
+    A = Ur.reshape(nb[2], nb[1], nb[0], 5, n, n, n)
+    return np.ascontiguousarray(A.transpose(3, 0, 4, 1, 5, 2, 6)).reshape(5, nb[2] * n, nb[1] * n, nb[0] * n)
+
+
+def _second_difference_ratio(mesh: Mesh, f, eps: float):
+    """Squared Loehner indicator of field f [Z, Y, X] per cell: with
+    fL, f0, fR the cell and its neighbours along d (the root map),
+    num_d = (fR - f0) - (f0 - fL),
+    den_d = (|fR - f0| + |f0 - fL|) + eps ((|fR| + 2|f0|) + |fL|),
+    E^2 = sum_d num_d^2 / sum_d den_d^2 (0 where the denominator is 0)."""
+    num2 = None
+    den2 = None
+    for d in range(3):
+        ax = 2 - d                                      # array axis of direction d
+        N = f.shape[ax]
+        idx = np.arange(N)
+        lo = _map(idx - 1, N, mesh.bc[d])
+        hi = _map(idx + 1, N, mesh.bc[d])
+        fL = np.take(f, lo, axis=ax)
+        fR = np.take(f, hi, axis=ax)
+        num = (fR - f) - (f - fL)
+        den = (np.abs(fR - f) + np.abs(f - fL)) + eps * ((np.abs(fR) + 2.0 * np.abs(f)) + np.abs(fL))
+        num2 = num * num if num2 is None else num2 + num * num
+        den2 = den * den if den2 is None else den2 + den * den
+    out = np.zeros_like(f)
+    ok = den2 > 0
+    out[ok] = num2[ok] / den2[ok]
+    return out
+
+
+def indicator(mesh: Mesh, Ur, eps: float = 0.01):
+    """Refinement indicator per root block: the largest squared Loehner
+    second-derivative ratio over its cells, of density and of pressure,
+    evaluated on the root state (refined blocks hold their children's
+    restriction).  Values lie in [0, 1]."""
+    n, nb = mesh.n, mesh.nb
+    G = _root_global(mesh, Ur)
+    rho = G[0]
+    kin = 0.5 * ((G[1] * G[1] + G[2] * G[2]) + G[3] * G[3]) / rho
+    p = (mesh.gamma - 1.0) * (G[4] - kin)
+    E2 = np.maximum(_second_difference_ratio(mesh, rho, eps), _second_difference_ratio(mesh, p, eps))
+    B = E2.reshape(nb[2], n, nb[1], n, nb[0], n)
+    return B.max(axis=(1, 3, 5)).reshape(-1)
+
+
+def refine_flags(mesh: Mesh, E2, refine_cutoff: float = 0.8, derefine_cutoff: float = 0.2):
+    """New flags from the indicator: refine where E^2 > refine_cutoff^2,
+    derefine a refined block where E^2 < derefine_cutoff^2, keep the rest."""
+    new = mesh.refine.copy()
+    new[E2 > refine_cutoff * refine_cutoff] = True
+    new[mesh.refine & (E2 < derefine_cutoff * derefine_cutoff)] = False
+    return new
+
+
+def regrid(mesh: Mesh, Ur, Uf, flags):
+    """The mesh with refinement flags `flags` and its state: children of
+    blocks refined before are kept as they are; blocks refined now get
+    children prolonged from the root state (conservative: each 2x2x2 group
+    averages to its root cell); derefined blocks keep their root values
+    (the restriction of the children they lose); then every refined root
+    block takes the restriction of its children.  Returns (mesh, Ur, Uf)."""
+    n = mesh.n
+    new = Mesh(n, mesh.nb, mesh.dx, np.asarray(flags, dtype=bool), mesh.bc, mesh.gamma, mesh.small_p)
+    Uf2 = np.empty((new.nfine, 5, n, n, n))
+    r_ = np.arange(n)
+    for q, r in enumerate(new.refined):
+        for c in range(8):
+            f = 8 * q + c
+            if mesh.refine[r]:
+                Uf2[f] = Uf[int(mesh.child_base[r]) + c]
+                continue
+            X0, Y0, Z0 = new.fine_origin(f)
+            K, J, I = np.meshgrid(r_ + Z0, r_ + Y0, r_ + X0, indexing="ij")
+            Uf2[f] = prolong(new, Ur, I.ravel(), J.ravel(), K.ravel()).reshape(5, n, n, n)
+    Ur2 = Ur.copy()
+    restrict(new, Ur2, Uf2)
+    return new, Ur2, Uf2
+

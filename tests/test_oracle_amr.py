@@ -219,3 +219,111 @@ def test_sampled_step_equals_full_step():
     assert not np.array_equal(plain[:, :, :, 0], R[1][:, :, :, 0])
     assert not np.array_equal(plain[:, -1], R[1][:, -1])
     assert np.array_equal(plain[:, :-1, :, 1:], R[1][:, :-1, :, 1:])
+
+
+# ---- adaptivity -----------------------------------------------------------
+
+def _prim_state(rho, p, gamma):
+    z = np.zeros_like(rho)
+    return ics.conserved(rho, z, z, z, p, gamma)
+
+
+def test_indicator_lies_in_unit_interval():
+    n, nb = 8, (2, 2, 2)
+    Ur, _ = _random_root(nb, n, 47)
+    mesh = amr.Mesh(n, nb, (1 / 16,) * 3, np.zeros(8, bool))
+    E2 = amr.indicator(mesh, Ur)
+    assert E2.shape == (8,) and np.all(E2 >= 0.0) and np.all(E2 <= 1.0)
+    assert E2.max() > 0.1                          # a random field has curvature everywhere
+
+
+def test_indicator_vanishes_on_linear_fields():
+    """Integer-valued linear density and pressure (gamma = 2, at rest: the
+    pressure is recovered exactly): every second difference is exactly 0
+    away from the outflow boundaries."""
+    n, nb = 8, (4, 3, 3)
+    Z, Y, X = nb[2] * n, nb[1] * n, nb[0] * n
+    k, j, i = np.meshgrid(np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    rho = 2.0 + i + 2 * j + 3 * k
+    p = 5.0 + 3 * i + j + 2 * k
+    Ur = ics.to_compact(_prim_state(rho.astype(float), p.astype(float), 2.0), n)
+    mesh = amr.Mesh(n, nb, (1.0,) * 3, np.zeros(nb[0] * nb[1] * nb[2], bool), bc=(1, 1, 1), gamma=2.0)
+    E2 = amr.indicator(mesh, Ur).reshape(nb[2], nb[1], nb[0])
+    assert np.all(E2[1:-1, 1:-1, 1:-1] == 0.0)
+    assert E2[0, 0, 0] > 0.0                       # the clamped boundary is a kink
+
+
+@pytest.mark.parametrize("field", ["rho", "p"])
+def test_indicator_is_one_at_a_jump_without_the_filter(field):
+    """A jump along x and nothing else: with eps = 0 the ratio is exactly 1
+    in the two cells beside the jump and 0 (flat: 0/0 taken as 0) elsewhere."""
+    n, nb = 8, (4, 2, 1)
+    Z, Y, X = nb[2] * n, nb[1] * n, nb[0] * n
+    one = np.ones((Z, Y, X))
+    step = np.where(np.arange(X) < X // 2 + 3, 1.0, 3.5)[None, None, :] * one
+    rho, p = (step, 2.0 * one) if field == "rho" else (2.0 * one, step)
+    Ur = ics.to_compact(_prim_state(rho, p, 2.0), n)
+    mesh = amr.Mesh(n, nb, (1.0,) * 3, np.zeros(8, bool), bc=(1, 0, 0), gamma=2.0)
+    E2 = amr.indicator(mesh, Ur, eps=0.0).reshape(nb[2], nb[1], nb[0])
+    # the jump sits between cells X/2+2 and X/2+3: both in block bx = 2
+    assert np.all(E2[:, :, 2] == 1.0) and np.all(E2[:, :, [0, 1, 3]] == 0.0)
+    # the filter lowers it below 1
+    assert np.all(amr.indicator(mesh, Ur, eps=0.01).reshape(nb[2], nb[1], nb[0])[:, :, 2] < 1.0)
+
+
+def test_refine_flags_rule():
+    mesh = amr.Mesh(8, (3, 2, 1), (1.0,) * 3, np.array([1, 1, 1, 0, 0, 0], bool))
+    E2 = np.array([0.9, 0.01, 0.3, 0.65, 0.639, 0.039])
+    new = amr.refine_flags(mesh, E2, 0.8, 0.2)    # cutoffs squared: 0.64, 0.04
+    assert new.tolist() == [True, False, True, True, False, False]
+
+
+def test_regrid_is_conservative_and_derefinement_returns_the_root_state():
+    n, nb = 8, (2, 2, 2)
+    Ur, _ = _random_root(nb, n, 48)
+    m0 = amr.Mesh(n, nb, (1 / 16,) * 3, np.zeros(8, bool))
+    m1, Ur1, Uf1 = amr.regrid(m0, Ur, np.zeros((0, 5, n, n, n)), [0, 1, 0, 0, 1, 0, 0, 1])
+    assert m1.nfine == 24
+    scale = _totals(m0, np.abs(Ur), np.zeros((0, 5, n, n, n)))
+    assert np.all(np.abs(_totals(m1, Ur1, Uf1) - _totals(m0, Ur, np.zeros((0, 5, n, n, n)))) <= 1e-14 * scale)
+    # every group of eight children averages to its root cell (to rounding,
+    # relative to each variable's scale)
+    for v in range(5):
+        assert np.abs(Ur1[:, v] - Ur[:, v]).max() <= 2e-15 * np.abs(Ur[:, v]).max(), v
+    # derefining everything keeps the root values the children restricted to
+    m2, Ur2, Uf2 = amr.regrid(m1, Ur1, Uf1, np.zeros(8, bool))
+    assert Uf2.shape[0] == 0 and np.array_equal(Ur2, Ur1)
+
+
+def test_regrid_keeps_surviving_children_and_prolongs_new_ones():
+    n, nb = 8, (2, 2, 2)
+    Ur, _ = _random_root(nb, n, 49)
+    m0 = amr.Mesh(n, nb, (1 / 16,) * 3, np.array([1, 0, 0, 0, 0, 1, 0, 0], bool))
+    rng = np.random.default_rng(50)
+    Uf = _fine_from_root(m0, Ur) * (1.0 + 0.05 * rng.random((16, 5, n, n, n)))
+    amr.restrict(m0, Ur, Uf)
+    m1, Ur1, Uf1 = amr.regrid(m0, Ur, Uf, [0, 0, 0, 0, 0, 1, 0, 1])
+    assert np.array_equal(Uf1[0:8], Uf[8:16])                   # block 5's children, now first
+    assert np.array_equal(Ur1[0], Ur[0])                        # block 0 derefined: its restriction stays
+    # block 7's children are the prolongation of its root cells
+    X0, Y0, Z0 = m1.fine_origin(8)
+    r = np.arange(n)
+    K, J, I = np.meshgrid(r + Z0, r + Y0, r + X0, indexing="ij")
+    assert np.array_equal(Uf1[8], amr.prolong(m1, Ur, I.ravel(), J.ravel(), K.ravel()).reshape(5, n, n, n))
+
+
+def test_regrid_prolongs_linear_data_exactly():
+    n, nb = 8, (2, 2, 2)
+    X, Y, Z = nb[0] * n, nb[1] * n, nb[2] * n
+    z, y, x = np.meshgrid(np.arange(Z) + 0.5, np.arange(Y) + 0.5, np.arange(X) + 0.5, indexing="ij")
+    G = np.stack([2.0 + 0.01 * x + 0.02 * y - 0.01 * z, 0.1 + 0.003 * x, -0.2 + 0.004 * z,
+                  0.05 + 0.001 * y, 8.0 + 0.01 * (x + y + z)])
+    Ur = ics.to_compact(G, n)
+    m0 = amr.Mesh(n, nb, (1.0,) * 3, np.zeros(8, bool), bc=(1, 1, 1))
+    m1, _, Uf1 = amr.regrid(m0, Ur, np.zeros((0, 5, n, n, n)), [0, 0, 0, 0, 0, 0, 0, 1])
+    X0, Y0, Z0 = m1.fine_origin(0)
+    fz, fy, fx = np.meshgrid((Z0 + np.arange(n) + 0.5) / 2, (Y0 + np.arange(n) + 0.5) / 2,
+                             (X0 + np.arange(n) + 0.5) / 2, indexing="ij")
+    exact = np.stack([2.0 + 0.01 * fx + 0.02 * fy - 0.01 * fz, 0.1 + 0.003 * fx, -0.2 + 0.004 * fz,
+                      0.05 + 0.001 * fy, 8.0 + 0.01 * (fx + fy + fz)])
+    np.testing.assert_allclose(Uf1[0], exact, rtol=1e-14, atol=1e-15)

@@ -96,6 +96,19 @@ AMR_MUTATIONS = {
                               "Fc = _face(flux0[b][d], d, n, 0 if side else n)"),
     "amr_prolong_slope_sign": ("val = val + S * (0.25 * offs[d])", "val = val - S * (0.25 * offs[d])"),
     "amr_prolong_half_weight": ("val = val + S * (0.25 * offs[d])", "val = val + S * (0.5 * offs[d])"),
+    "amr_indicator_num_sign": ("num = (fR - f) - (f - fL)", "num = (fR - f) + (f - fL)"),
+    "amr_indicator_den_no_abs": ("den = (np.abs(fR - f) + np.abs(f - fL))", "den = ((fR - f) + (f - fL))"),
+    "amr_indicator_density_only": ("E2 = np.maximum(_second_difference_ratio(mesh, rho, eps), "
+                                   "_second_difference_ratio(mesh, p, eps))",
+                                   "E2 = np.maximum(_second_difference_ratio(mesh, rho, eps), "
+                                   "_second_difference_ratio(mesh, rho, eps))"),
+    "amr_flags_no_derefine": ("new[mesh.refine & (E2 < derefine_cutoff * derefine_cutoff)] = False",
+                              "new[mesh.refine & (E2 < derefine_cutoff * derefine_cutoff)] = True"),
+    "amr_regrid_injects": ("Uf2[f] = prolong(new, Ur, I.ravel(), J.ravel(), K.ravel()).reshape(5, n, n, n)",
+                           "Uf2[f] = root_value(new, Ur, I.ravel() // 2, J.ravel() // 2, K.ravel() // 2)"
+                           ".reshape(5, n, n, n)"),
+    "amr_regrid_wrong_child_kept": ("Uf2[f] = Uf[int(mesh.child_base[r]) + c]",
+                                    "Uf2[f] = Uf[int(mesh.child_base[r]) + (c ^ 1)]"),
     "amr_restrict_wrong_child": ("cx, cy, cz = c & 1, (c >> 1) & 1, (c >> 2) & 1\n            ch = Uf[8 * q + c]",
                                  "cx, cy, cz = (c >> 1) & 1, c & 1, (c >> 2) & 1\n            ch = Uf[8 * q + c]"),
 }

@@ -257,7 +257,23 @@ def run_amr(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "amr_tile_kernel",
                      "algorithmic_bytes_per_step": BYTES_PER_CELL * cells},
     }
-    A.close()
+    # adaptivity, timed apart from the steps: one estimate (indicator kernel,
+    # flags read back) and one regrid to its flags (new mesh: allocation,
+    # tables, transfer of the state)
+    A.stream.synchronize()
+    t = time.perf_counter()
+    flags_new, _ = A.estimate(eps=0.01, refine_cutoff=0.8, derefine_cutoff=0.2)
+    est_ms = (time.perf_counter() - t) * 1e3
+    t = time.perf_counter()
+    B = A.regrid(flags_new)
+    B.stream.synchronize()
+    regrid_ms = (time.perf_counter() - t) * 1e3
+    out["adapt"] = {"estimate_ms": est_ms, "regrid_ms": regrid_ms,
+                    "refined_after": int(flags_new.sum()), "refined_before": int(flags.sum()),
+                    "note": "host wall time; regrid includes allocating the new mesh"}
+    print(f"[bench] estimate {est_ms:.2f} ms, regrid {regrid_ms:.2f} ms "
+          f"({int(flags.sum())} -> {int(flags_new.sum())} refined root blocks)", file=sys.stderr, flush=True)
+    B.close()
     print(json.dumps(out), flush=True)
 
 

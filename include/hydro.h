@@ -318,7 +318,8 @@ typedef struct {
 /* Number of fine blocks (8 per flagged root block); 0 for an invalid descriptor. */
 size_t hydro_amr_fine_blocks(const hydro_amr_desc *d);
 /* Workspace bytes: header, mesh tables, views with two guard layers of every
- * root and fine block, fluxes on block faces (used at fine-coarse faces). */
+ * root and fine block, fluxes on block faces (used at fine-coarse faces),
+ * one refinement indicator per root block. */
 size_t hydro_amr_work_bytes(const hydro_amr_desc *d);
 /* Validate and build the mesh tables (uploaded to the workspace; waits for
  * the upload).  Errors: HYDRO_EINVAL, HYDRO_ESIZE, HYDRO_EDEVICE. */
@@ -342,6 +343,28 @@ int hydro_amr_state_changed(hydro_amr *a);
  * creation left a nonphysical cell, else HYDRO_EINVAL if the maximum is not
  * positive and finite. */
 int hydro_amr_dt(hydro_amr *a, double cfl, double *dt_out);
+/* Adaptivity (the Grid unit's refinement is adaptive; the paper names no
+ * criterion): per root block, the largest squared Loehner second-derivative
+ * ratio of density and of pressure over its cells (root state; refined
+ * blocks hold their children's restriction),
+ *   E^2 = sum_d num_d^2 / sum_d den_d^2,  num_d = (fR - f0) - (f0 - fL),
+ *   den_d = (|fR - f0| + |f0 - fL|) + eps ((|fR| + 2|f0|) + |fL|),
+ * neighbours along d by the root map, 0 where the denominator is 0, every
+ * operation rounded as written.  New flags: 1 where E^2 > refine_cutoff^2,
+ * 0 for a refined block where E^2 < derefine_cutoff^2, else the current
+ * flag.  flags_out: host, nroot; E2_out: host, nroot, may be NULL.  Waits.
+ * Errors: HYDRO_EINVAL (NULL, eps < 0, cutoffs not 0 <= derefine <= refine). */
+int hydro_amr_estimate(hydro_amr *a, double eps, double refine_cutoff, double derefine_cutoff, double *E2_out,
+                       unsigned char *flags_out);
+/* Regridding: fill the state of mesh `to` (created with the new flags over
+ * the same root grid, its own fine buffer) from mesh `from`: the root state
+ * is copied (unless both use one buffer), children of blocks refined in both
+ * are copied, children of newly refined blocks are prolonged from the root
+ * state (the guard-fill prolongation, conservative), and every refined root
+ * block of `to` takes its children's restriction; derefined blocks keep
+ * their root values (the restriction of the children they lose).  Waits for
+ * `from`'s stream, then runs on `to`'s.  `from` may be freed afterwards. */
+int hydro_amr_transfer(hydro_amr *from, hydro_amr *to);
 /* Event counters summed since creation: floors, fallbacks, nonphysical cells (waits). */
 int hydro_amr_counters(hydro_amr *a, long long out[3]);
 int hydro_amr_free(hydro_amr *a);

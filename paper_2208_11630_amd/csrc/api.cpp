@@ -716,6 +716,7 @@ struct hydro_amr {
   std::vector<unsigned char> refine;
   long steps = 0;          // signal slot of the current state: steps % 3
   bool sig_valid = false;  // the slot holds the current state's signal speed
+  double* E2 = nullptr;    // device, nroot refinement indicators
 };
 
 namespace {
@@ -724,7 +725,7 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct AmrLayout {
   long nroot, nfine, nleaf0, nrefined, nreflux, ngroups;
-  size_t o_tab, o_G0, o_G1, o_f0, o_f1, total;
+  size_t o_tab, o_G0, o_G1, o_f0, o_f1, o_E2, total;
   std::vector<int> leaf0, leaf_plain, rx_blocks, child_base, fine_root, refined;
   std::vector<int> reflux;  // 4 ints per entry, grouped by coarse leaf
   std::vector<int> first;   // ngroups + 1 entry offsets
@@ -797,7 +798,8 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
   A.o_G1 = A.o_G0 + al256(sizeof(double) * 5 * P * P * P * A.nroot);
   A.o_f0 = A.o_G1 + al256(sizeof(double) * 5 * P * P * P * A.nfine);
   A.o_f1 = A.o_f0 + al256(sizeof(double) * 30 * (size_t)N * N * A.nroot);
-  A.total = A.o_f1 + al256(sizeof(double) * 30 * (size_t)N * N * A.nfine);
+  A.o_E2 = A.o_f1 + al256(sizeof(double) * 30 * (size_t)N * N * A.nfine);
+  A.total = A.o_E2 + al256(sizeof(double) * (size_t)A.nroot);
   return HYDRO_OK;
 }
 
@@ -872,6 +874,7 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
   L.G1 = (double*)(w + A.o_G1);
   L.flux0 = (double*)(w + A.o_f0);
   L.flux1 = (double*)(w + A.o_f1);
+  a->E2 = (double*)(w + A.o_E2);
   L.ws = (hydro::WorkHeader*)w;
   L.nroot = A.nroot;
   L.nleaf0 = A.nleaf0;
@@ -975,6 +978,54 @@ int hydro_amr_last_dt(hydro_amr* a, double* dt_out) {
 int hydro_amr_state_changed(hydro_amr* a) {
   if (!a) return fail(HYDRO_EINVAL, "handle is NULL");
   a->sig_valid = false;
+  return HYDRO_OK;
+}
+
+int hydro_amr_estimate(hydro_amr* a, double eps, double refine_cutoff, double derefine_cutoff, double* E2_out,
+                       unsigned char* flags_out) {
+  if (!a || !flags_out) return fail(HYDRO_EINVAL, "handle or flags_out is NULL");
+  if (!(std::isfinite(eps) && eps >= 0.0)) return fail(HYDRO_EINVAL, "eps must be finite and >= 0");
+  if (!(std::isfinite(refine_cutoff) && std::isfinite(derefine_cutoff) && derefine_cutoff >= 0.0 &&
+        derefine_cutoff <= refine_cutoff))
+    return fail(HYDRO_EINVAL, "need finite cutoffs with 0 <= derefine_cutoff <= refine_cutoff");
+  hipStream_t s = (hipStream_t)a->d.stream;
+  hipError_t e = hydro::launch_amr_indicator(a->d.nxb, a->L, eps, a->E2, s);
+  if (e != hipSuccess) return hip_fail(e, "AMR indicator launch");
+  std::vector<double> E2((size_t)a->L.nroot);
+  e = hipMemcpyAsync(E2.data(), a->E2, sizeof(double) * E2.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "AMR indicator read");
+  const double rc2 = refine_cutoff * refine_cutoff, dc2 = derefine_cutoff * derefine_cutoff;
+  for (long b = 0; b < a->L.nroot; ++b) {
+    unsigned char f = a->refine[b] ? 1 : 0;
+    if (E2[b] > rc2) f = 1;
+    else if (f && E2[b] < dc2) f = 0;
+    flags_out[b] = f;
+    if (E2_out) E2_out[b] = E2[b];
+  }
+  return HYDRO_OK;
+}
+
+int hydro_amr_transfer(hydro_amr* from, hydro_amr* to) {
+  if (!from || !to || from == to) return fail(HYDRO_EINVAL, "need two distinct handles");
+  const hydro_amr_desc &x = from->d, &y = to->d;
+  bool same = x.nxb == y.nxb && x.gamma == y.gamma;
+  for (int ax = 0; ax < 3; ++ax)
+    same = same && x.nblk[ax] == y.nblk[ax] && x.bc[ax] == y.bc[ax] && x.lo[ax] == y.lo[ax] && x.hi[ax] == y.hi[ax];
+  if (!same) return fail(HYDRO_EINVAL, "the two meshes must share their root grid");
+  if (y.Uf == x.Uf && to->L.nfine && from->L.nfine)
+    return fail(HYDRO_EINVAL, "the new mesh needs a fine state buffer of its own");
+  hipError_t e = hipStreamSynchronize((hipStream_t)x.stream);  // the old mesh's last step has finished
+  if (e != hipSuccess) return hip_fail(e, "AMR transfer: waiting for the old mesh");
+  hipStream_t s = (hipStream_t)y.stream;
+  const size_t N3 = (size_t)x.nxb * x.nxb * x.nxb;
+  if (y.Ur != x.Ur) {
+    e = hipMemcpyAsync(y.Ur, x.Ur, sizeof(double) * 5 * N3 * (size_t)from->L.nroot, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "AMR transfer: root state copy");
+  }
+  e = hydro::launch_amr_transfer(y.nxb, from->L, to->L, s);
+  if (e != hipSuccess) return hip_fail(e, "AMR transfer launch");
+  to->sig_valid = false;
   return HYDRO_OK;
 }
 

@@ -110,5 +110,10 @@ struct AmrLaunch {
 };
 hipError_t launch_amr_step(int nxb, const AmrLaunch& L, hipStream_t s);
 hipError_t launch_amr_signal(int nxb, const AmrLaunch& L, int slot, hipStream_t s);
+// Refinement indicator per root block into E2[nroot] (device).
+hipError_t launch_amr_indicator(int nxb, const AmrLaunch& L, double eps, double* E2, hipStream_t s);
+// Fine state of mesh `to` from mesh `from` (same root grid; to.Ur holds the
+// root state), then the restriction of to's refined blocks.
+hipError_t launch_amr_transfer(int nxb, const AmrLaunch& from, const AmrLaunch& to, hipStream_t s);
 
 }  // namespace hydro

@@ -1070,6 +1070,36 @@ struct AmrStep {
   static constexpr long NF = 6L * 5 * N * N;      // boundary fluxes per block: [face 2d+side][v][a1][a0]
 };
 
+// Conserved state prolonged from the root level to the level-1 cell at
+// global index (I, J, K) (inside the domain): U_c + sum_d S_d * (+-1/4), S_d
+// the van Leer slope of the conserved variable over the root cells (level-0
+// map), keeping U_c if the result has rho <= 0 or p <= 0.
+template <int N>
+__device__ __forceinline__ void prolong_cell(const GridGeom& g0, const double* __restrict__ Ur, int I, int J, int K,
+                                             double (&val)[5]) {
+  const int Ic = I / 2, Jc = J / 2, Kc = K / 2;
+  double uc[5];
+  load_cons<N>(Ur, cell_offset<N>(g0, Ic, Jc, Kc), uc);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) val[v] = uc[v];
+  const int off[3] = {(I & 1) * 2 - 1, (J & 1) * 2 - 1, (K & 1) * 2 - 1};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double um[5], up[5];
+    load_cons<N>(Ur, cell_offset<N>(g0, Ic - (d == 0), Jc - (d == 1), Kc - (d == 2)), um);
+    load_cons<N>(Ur, cell_offset<N>(g0, Ic + (d == 0), Jc + (d == 1), Kc + (d == 2)), up);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) val[v] += van_leer_sf(uc[v] - um[v], up[v] - uc[v]) * (0.25 * off[d]);
+  }
+  const double rho = val[0];
+  const double kin = 0.5 * ((val[1] * val[1] + val[2] * val[2]) + val[3] * val[3]) / (rho > 0.0 ? rho : 1.0);
+  const double p = (g0.gamma - 1.0) * (val[4] - kin);
+  if (!(rho > 0.0 && p > 0.0)) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) val[v] = uc[v];
+  }
+}
+
 // Fine guarded views: fine block f = child c of root block fine_root[f]
 // (children contiguous, c = f - child_base[root]); every cell of the view
 // either copies the fine cell at its level-1 position (when that position
@@ -1103,27 +1133,7 @@ __global__ __launch_bounds__(256) void amr_fill_fine_kernel(GridGeom g0, const d
       const int fb = child_base[rb] + (I / N) % 2 + 2 * ((J / N) % 2) + 4 * ((K / N) % 2);
       load_cons<N>(Uf, Layout<N>::at(fb, I % N, J % N, K % N), val);
     } else {
-      const int Ic = I / 2, Jc = J / 2, Kc = K / 2;
-      double uc[5];
-      load_cons<N>(Ur, cell_offset<N>(g0, Ic, Jc, Kc), uc);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) val[v] = uc[v];
-      const int off[3] = {(I & 1) * 2 - 1, (J & 1) * 2 - 1, (K & 1) * 2 - 1};
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        double um[5], up[5];
-        load_cons<N>(Ur, cell_offset<N>(g0, Ic - (d == 0), Jc - (d == 1), Kc - (d == 2)), um);
-        load_cons<N>(Ur, cell_offset<N>(g0, Ic + (d == 0), Jc + (d == 1), Kc + (d == 2)), up);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) val[v] += van_leer_sf(uc[v] - um[v], up[v] - uc[v]) * (0.25 * off[d]);
-      }
-      const double rho = val[0];
-      const double kin = 0.5 * ((val[1] * val[1] + val[2] * val[2]) + val[3] * val[3]) / (rho > 0.0 ? rho : 1.0);
-      const double p = (g0.gamma - 1.0) * (val[4] - kin);
-      if (!(rho > 0.0 && p > 0.0)) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) val[v] = uc[v];
-      }
+      prolong_cell<N>(g0, Ur, I, J, K, val);
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[v * Guarded<N, VG>::VS + t] = val[v];
@@ -1303,6 +1313,102 @@ __global__ __launch_bounds__(256) void amr_reflux_kernel(GridGeom g0, const int4
   wg_max_to(smax, sRed, &ws->sig[(slot + 1) % 3]);
 }
 
+// Refinement indicator of root block b (one workgroup each): the largest,
+// over its cells, of Loehner's squared second-derivative ratio of density
+// and of pressure, E^2 = sum_d num_d^2 / sum_d den_d^2 with
+// num_d = (fR - f0) - (f0 - fL), den_d = (|fR - f0| + |f0 - fL|) +
+// eps ((|fR| + 2|f0|) + |fL|) over the cell and its neighbours along d (root
+// map); 0 where the denominator is 0.  Every operation is rounded as
+// written (no fused multiply-adds), so refinement decisions taken from it
+// are reproducible bit for bit.
+__device__ __forceinline__ double amr_pressure(const double (&u)[5], double gamma) {
+#pragma clang fp contract(off)
+  const double kin = 0.5 * ((u[1] * u[1] + u[2] * u[2]) + u[3] * u[3]) / u[0];
+  return (gamma - 1.0) * (u[4] - kin);
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void amr_indicator_kernel(GridGeom g0, const double* __restrict__ Ur, double eps,
+                                                            double* __restrict__ out) {
+#pragma clang fp contract(off)
+  __shared__ double sRed[4];
+  const int b = blockIdx.x;
+  const int bx = b % g0.nb[0], by = (b / g0.nb[0]) % g0.nb[1], bz = b / (g0.nb[0] * g0.nb[1]);
+  double emax = 0.0;
+  for (int t = threadIdx.x; t < N * N * N; t += blockDim.x) {
+    const int I = bx * N + t % N, J = by * N + (t / N) % N, K = bz * N + t / (N * N);
+    double u[5];
+    load_cons<N>(Ur, cell_offset<N>(g0, I, J, K), u);
+    const double r0 = u[0], p0 = amr_pressure(u, g0.gamma);
+    double nr = 0.0, dr = 0.0, np_ = 0.0, dp = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double um[5], up[5];
+      load_cons<N>(Ur, cell_offset<N>(g0, I - (d == 0), J - (d == 1), K - (d == 2)), um);
+      load_cons<N>(Ur, cell_offset<N>(g0, I + (d == 0), J + (d == 1), K + (d == 2)), up);
+      const double rL = um[0], rR = up[0], pL = amr_pressure(um, g0.gamma), pR = amr_pressure(up, g0.gamma);
+      const double an = (rR - r0) - (r0 - rL);
+      const double ad = (fabs(rR - r0) + fabs(r0 - rL)) + eps * ((fabs(rR) + 2.0 * fabs(r0)) + fabs(rL));
+      const double bn = (pR - p0) - (p0 - pL);
+      const double bd = (fabs(pR - p0) + fabs(p0 - pL)) + eps * ((fabs(pR) + 2.0 * fabs(p0)) + fabs(pL));
+      if (d == 0) {
+        nr = an * an;
+        dr = ad * ad;
+        np_ = bn * bn;
+        dp = bd * bd;
+      } else {
+        nr = nr + an * an;
+        dr = dr + ad * ad;
+        np_ = np_ + bn * bn;
+        dp = dp + bd * bd;
+      }
+    }
+    const double er = dr > 0.0 ? nr / dr : 0.0;
+    const double ep = dp > 0.0 ? np_ / dp : 0.0;
+    const double e = fmax(er, ep);
+    emax = fmax(emax, e);
+  }
+  // workgroup maximum (non-negative values; wavefront shuffles then LDS)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) emax = fmax(emax, __shfl_xor(emax, o, 64));
+  if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = emax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = sRed[0];
+    for (int w = 1; w < (int)(blockDim.x + 63) / 64; ++w) m = fmax(m, sRed[w]);
+    out[b] = m;
+  }
+}
+
+// Regridding: fine block f of the new mesh (root block fine_root[f], child
+// c = f - child_base[r]) copies child c of r from the old fine state when r
+// was refined before (old_base[r] >= 0), else is prolonged from the root
+// state cell by cell.
+template <int N>
+__global__ __launch_bounds__(256) void amr_transfer_kernel(GridGeom g0, const double* __restrict__ Ur,
+                                                           const double* __restrict__ Uf_old,
+                                                           const int* __restrict__ old_base,
+                                                           const int* __restrict__ child_base,
+                                                           const int* __restrict__ fine_root, double* __restrict__ Uf) {
+  const int f = blockIdx.x;
+  const int r = fine_root[f];
+  const int c = f - child_base[r];
+  double* out = Uf + (long)f * Layout<N>::BS;
+  if (old_base[r] >= 0) {
+    const double* src = Uf_old + (long)(old_base[r] + c) * Layout<N>::BS;
+    for (int t = threadIdx.x; t < 5 * N * N * N; t += blockDim.x) out[t] = src[t];
+    return;
+  }
+  const int bx = r % g0.nb[0], by = (r / g0.nb[0]) % g0.nb[1], bz = r / (g0.nb[0] * g0.nb[1]);
+  const int X0 = 2 * bx * N + (c & 1) * N, Y0 = 2 * by * N + ((c >> 1) & 1) * N, Z0 = 2 * bz * N + ((c >> 2) & 1) * N;
+  for (int t = threadIdx.x; t < N * N * N; t += blockDim.x) {
+    double val[5];
+    prolong_cell<N>(g0, Ur, X0 + t % N, Y0 + (t / N) % N, Z0 + t / (N * N), val);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[v * Layout<N>::VS + t] = val[v];
+  }
+}
+
 // Restriction: root block refined[w] takes the mean of its children.
 template <int N>
 __global__ __launch_bounds__(256) void amr_restrict_kernel(const int* __restrict__ refined,
@@ -1461,6 +1567,39 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
   if (L.nrefined)
     hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)L.nrefined), dim3(256), 0, s, L.refined,
                        L.child_base, L.Uf, L.Ur);
+  return hipGetLastError();
+}
+
+template <int N>
+void launch_amr_adapt_t(const AmrLaunch& L, double eps, double* E2, const AmrLaunch* from, hipStream_t s) {
+  if (E2) hipLaunchKernelGGL(amr_indicator_kernel<N>, dim3((unsigned)L.nroot), dim3(256), 0, s, L.g0, L.Ur, eps, E2);
+  if (from) {
+    if (L.nfine)
+      hipLaunchKernelGGL(amr_transfer_kernel<N>, dim3((unsigned)L.nfine), dim3(256), 0, s, L.g0, L.Ur, from->Uf,
+                         from->child_base, L.child_base, L.fine_root, L.Uf);
+    if (L.nrefined)
+      hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)L.nrefined), dim3(256), 0, s, L.refined,
+                         L.child_base, L.Uf, L.Ur);
+  }
+}
+
+hipError_t launch_amr_indicator(int nxb, const AmrLaunch& L, double eps, double* E2, hipStream_t s) {
+  switch (nxb) {
+    case 8: launch_amr_adapt_t<8>(L, eps, E2, nullptr, s); break;
+    case 16: launch_amr_adapt_t<16>(L, eps, E2, nullptr, s); break;
+    case 32: launch_amr_adapt_t<32>(L, eps, E2, nullptr, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_amr_transfer(int nxb, const AmrLaunch& from, const AmrLaunch& to, hipStream_t s) {
+  switch (nxb) {
+    case 8: launch_amr_adapt_t<8>(to, 0.0, nullptr, &from, s); break;
+    case 16: launch_amr_adapt_t<16>(to, 0.0, nullptr, &from, s); break;
+    case 32: launch_amr_adapt_t<32>(to, 0.0, nullptr, &from, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

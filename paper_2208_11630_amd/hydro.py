@@ -77,6 +77,9 @@ SIGNATURES = {
     "hydro_amr_state_changed": ([ctypes.c_void_p], ctypes.c_int),
     "hydro_amr_dt": ([ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "hydro_amr_counters": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+    "hydro_amr_estimate": ([ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_ubyte)], ctypes.c_int),
+    "hydro_amr_transfer": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "hydro_amr_free": ([ctypes.c_void_p], ctypes.c_int),
     "hydro_set_pencil_planes": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_set_scheme": ([_HP, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
@@ -420,6 +423,9 @@ class Amr:
         L = lib()
         self._torch = torch
         d = make_amr_desc(nxb, nblk, refine, lo, hi, bc, gamma, small_p)
+        self.nxb, self.nblk, self.refine = int(nxb), tuple(int(x) for x in nblk), [bool(f) for f in refine]
+        self.lo, self.hi, self.bc = tuple(lo), tuple(hi), tuple(bc)
+        self.gamma, self.small_p = float(gamma), float(small_p)
         nfine = L.hydro_amr_fine_blocks(ctypes.byref(d))
         n = int(nxb)
         nroot = int(nblk[0]) * int(nblk[1]) * int(nblk[2])
@@ -473,6 +479,26 @@ class Amr:
         out = (ctypes.c_longlong * 3)()
         _check(lib().hydro_amr_counters(self.handle, out))
         return np.array(list(out), dtype=np.int64)
+
+    def estimate(self, eps: float = 0.01, refine_cutoff: float = 0.8, derefine_cutoff: float = 0.2):
+        """(new refinement flags, per-root-block indicator E^2) from the
+        current state (hydro_amr_estimate)."""
+        n = len(self.refine)
+        E2 = (ctypes.c_double * n)()
+        flags = (ctypes.c_ubyte * n)()
+        _check(lib().hydro_amr_estimate(self.handle, float(eps), float(refine_cutoff), float(derefine_cutoff),
+                                        E2, flags))
+        return np.array(list(flags), dtype=bool), np.array(list(E2))
+
+    def regrid(self, flags) -> "Amr":
+        """A new mesh over the same root grid with refinement `flags`, its
+        state transferred from this one (hydro_amr_transfer); this mesh is
+        closed."""
+        new = Amr(self.nxb, self.nblk, [bool(f) for f in flags], self.lo, self.hi, self.bc, self.gamma,
+                  self.small_p, device=self.Ur.device, stream=self.stream)
+        _check(lib().hydro_amr_transfer(self.handle, new.handle))
+        self.close()
+        return new
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None:

@@ -145,7 +145,7 @@ def test_amr_sizes_and_validation(L):
     tab = 4 * (2 + 4 + 16 + 2 + 4 * entries + groups + 1)
     al = lambda x: (x + 255) // 256 * 256
     total = (256 + al(tab) + al(8 * 5 * P ** 3 * 4) + al(8 * 5 * P ** 3 * 16) + al(8 * 30 * n * n * 4)
-             + al(8 * 30 * n * n * 16))
+             + al(8 * 30 * n * n * 16) + al(8 * 4))
     assert L.hydro_amr_work_bytes(ctypes.byref(d)) == total
     for field, value in [("nxb", 12), ("nguard", 2), ("gamma", 1.0)]:
         bad = hydro.make_amr_desc(n, nb, [0, 1, 0, 1])
@@ -172,3 +172,5 @@ def test_amr_sizes_and_validation(L):
     assert L.hydro_amr_dt(None, 0.8, ctypes.byref(out)) == hydro.HYDRO_EINVAL
     assert L.hydro_amr_counters(None, None) == hydro.HYDRO_EINVAL
     assert L.hydro_amr_free(None) == hydro.HYDRO_OK
+    assert L.hydro_amr_estimate(None, 0.01, 0.8, 0.2, None, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_amr_transfer(None, None) == hydro.HYDRO_EINVAL

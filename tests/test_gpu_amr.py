@@ -215,3 +215,83 @@ def test_amr_full_size_sampled_blocks(hy):
                  (np.stack(list(out_r.values())), np.stack(list(out_f.values()))), "full-size sampled")
     assert A.counters().tolist() == [0, 0, 0]
     A.close()
+
+
+# ---- adaptivity --------------------------------------------------------------
+
+ADAPT_CASES = {
+    # name: (n, nb, refined, bc, field kind, seed)
+    "random_n8": (8, (3, 2, 2), [0, 5, 7], (1, 0, 1), "random", 61),
+    "smooth_n16": (16, (2, 2, 2), [1, 6], (0, 0, 0), "smooth", 62),
+    "smooth_n8_outflow": (8, (4, 2, 2), [2, 9], (1, 1, 1), "smooth", 63),
+}
+
+
+def _adapt_mesh(hy, case):
+    n, nb, refined, bc, kind, seed = ADAPT_CASES[case]
+    CASES[case] = ADAPT_CASES[case]
+    try:
+        return make(hy, case)
+    finally:
+        del CASES[case]
+
+
+@pytest.mark.parametrize("case", list(ADAPT_CASES))
+@pytest.mark.parametrize("eps", [0.01, 0.0])
+def test_amr_indicator_is_bitwise_the_oracles(hy, case, eps):
+    """Refinement decisions: the indicator is computed with every operation
+    rounded as written on both sides, so it agrees bit for bit, and so do
+    the flags."""
+    mesh, Ur, Uf, A = _adapt_mesh(hy, case)
+    flags, E2 = A.estimate(eps=eps, refine_cutoff=0.5, derefine_cutoff=0.1)
+    ref = amr.indicator(mesh, Ur, eps=eps)
+    assert np.array_equal(E2, ref), np.abs(E2 - ref).max()
+    assert flags.tolist() == amr.refine_flags(mesh, ref, 0.5, 0.1).tolist()
+    A.close()
+
+
+@pytest.mark.parametrize("case", list(ADAPT_CASES))
+def test_amr_regrid_matches_the_oracle(hy, case):
+    """Transfer to a new refinement: surviving children copied bit for bit,
+    new ones prolonged (1e-12), refined root blocks restricted."""
+    mesh, Ur, Uf, A = _adapt_mesh(hy, case)
+    rng = np.random.default_rng(64)
+    flags = mesh.refine.copy()
+    flip = rng.choice(flags.size, size=max(2, flags.size // 3), replace=False)
+    flags[flip] = ~flags[flip]
+    B = A.regrid(flags)
+    R, F = B.download()
+    m1, R_ref, F_ref = amr.regrid(mesh, Ur, Uf, flags)
+    assert B.nfine == m1.nfine
+    for q, r in enumerate(m1.refined):
+        if mesh.refine[r]:
+            old = int(mesh.child_base[r])
+            assert np.array_equal(F[8 * q:8 * q + 8], Uf[old:old + 8]), r
+    assert_close((R, F), (R_ref, F_ref), f"{case} regrid")
+    B.close()
+
+
+def test_amr_adaptive_trajectory(hy):
+    """Steps with regridding every two steps: estimate on both sides (the
+    decisions agree wherever the indicator is not within 1e-9 of a cutoff),
+    regrid both sides to the oracle's flags, parity after every step."""
+    print("\n[amr] adaptive trajectory", flush=True)
+    mesh, Ur, Uf, A = _adapt_mesh(hy, "smooth_n16")
+    for cycle in range(3):
+        for s in range(2):
+            dt = amr.dt(mesh, Ur, Uf, 0.8)
+            Ur, Uf, _ = amr.step(mesh, Ur, Uf, dt)
+            A.step(dt)
+            assert_close(A.download(), (Ur, Uf), f"cycle {cycle} step {s}")
+        flags_gpu, E2_gpu = A.estimate(0.01, 0.93, 0.9)
+        E2 = amr.indicator(mesh, Ur, 0.01)
+        flags = amr.refine_flags(mesh, E2, 0.93, 0.9)
+        clear = (np.abs(E2 - 0.93 * 0.93) > 1e-9) & (np.abs(E2 - 0.9 * 0.9) > 1e-9)
+        assert np.array_equal(flags_gpu[clear], flags[clear])
+        assert np.allclose(E2_gpu, E2, rtol=1e-10, atol=1e-14)
+        if cycle == 0:  # this field refines five blocks and derefines one
+            assert (flags & ~mesh.refine).sum() == 5 and (mesh.refine & ~flags).sum() == 1
+        mesh, Ur, Uf = amr.regrid(mesh, Ur, Uf, flags)
+        A = A.regrid(flags)
+        assert_close(A.download(), (Ur, Uf), f"cycle {cycle} regrid")
+    A.close()

@@ -114,6 +114,45 @@ AMR_MUTATIONS = {
 }
 
 
+# Mistakes planted in the oracle's AMR of any depth (oracle/amr_tree.py).
+TREE_MUTATIONS = {
+    "tree_restrict_top_down": ("for l in range(t.levels - 2, -1, -1):", "for l in range(t.levels - 1):"),
+    "tree_prolong_same_level": ("Uc = level_value(t, U, l - 1, Ic, Jc, Kc)",
+                                "Uc = level_value(t, U, l - 1, Ic, Jc, Kc) * (1.0 + 1e-3)"),
+    "tree_reflux_wrong_level_dx": ("lam = [dt / h for h in t.dx(l)]", "lam = [dt / h for h in t.dx(l + 1)]"),
+    "tree_copy_from_parent_level": ("out[:, here] = U[l][blk[here], :, K[here] % n, J[here] % n, I[here] % n].T",
+                                    "out[:, here] = U[l][blk[here], :, K[here] % n, J[here] % n, I[here] % n].T"
+                                    " * (1.0 + 1e-12 * (l > 1))"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(TREE_MUTATIONS))
+def test_tree_pins_catch_planted_mistake(name, tmp_path):
+    import shutil
+
+    old, new = TREE_MUTATIONS[name]
+    pkg = tmp_path / "oracle"
+    shutil.copytree(os.path.join(ROOT, "oracle"), pkg, ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    src = (pkg / "amr_tree.py").read_text()
+    assert src.count(old) == 1, f"mutation anchor not unique/found: {old!r}"
+    (pkg / "amr_tree.py").write_text(src.replace(old, new))
+    import oracle
+
+    shutil.copy(os.path.join(ROOT, "tests", "test_oracle_amr_tree.py"), tmp_path / "test_oracle_amr_tree.py")
+    os.makedirs(tmp_path / "tests", exist_ok=True)
+    (tmp_path / "tests" / "__init__.py").write_text("")
+    shutil.copy(os.path.join(ROOT, "tests", "test_oracle_amr.py"), tmp_path / "tests" / "test_oracle_amr.py")
+    env = dict(os.environ, HYDRO_ORACLE_LIB=oracle.LIB_PATH, OMP_NUM_THREADS="4",
+               PYTHONPATH=os.pathsep.join([str(tmp_path), ROOT, os.environ.get("PYTHONPATH", "")]))
+    probe = subprocess.run([sys.executable, "-c", "import oracle.amr_tree as a; print(a.__file__)"], cwd=tmp_path,
+                           env=env, capture_output=True, text=True, timeout=120)
+    assert probe.stdout.strip().startswith(str(tmp_path)), probe.stdout + probe.stderr
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "test_oracle_amr_tree.py"], cwd=tmp_path, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1 and " failed" in r.stdout, f"mutation {name} survived the tree pins:\n{r.stdout[-2000:]}"
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("name", sorted(AMR_MUTATIONS))
 def test_amr_pins_catch_planted_mistake(name, tmp_path):

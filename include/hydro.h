@@ -270,35 +270,39 @@ int hydro_copy_probe(const double *src, double *dst, size_t n, void *stream);
 /* Message of the last failed call on this thread ("" if none). */
 const char *hydro_last_error(void);
 
-/* ---- two-level static AMR ------------------------------------------------
+/* ---- block-structured AMR -------------------------------------------------
  * (§2: the Grid unit's block-structured mesh with adaptive refinement:
  * blocks of nxb^3 cells, guard cells across refinement jumps, conservative
- * fluxes at fine-coarse faces.)  A root grid of nblk blocks (level 0) whose
- * flagged blocks are each covered by eight children at half the cell size
- * (level 1), refinement fixed at creation; every leaf takes the
- * predictor-corrector step with the same dt:
- *   1. guard fill: root blocks by the same-level map over the root state
- *      (refined root blocks hold the restriction of their children); fine
- *      blocks copy fine cells where their guard positions lie in refined
- *      root blocks and are otherwise prolonged from the root cell under
- *      them: U_c + sum_d S_d (+-1/4), S_d the van Leer slope of the conserved
- *      variable over root cells d-1, d, d+1, keeping U_c if the result has
- *      rho <= 0 or p <= 0 (positions beyond the domain mapped at their own
- *      level: periodic or outflow per axis);
- *   2. the step of each leaf from its guarded view (lam = dt/dx of its
- *      level), keeping its boundary fluxes;
- *   3. refluxing: a root leaf's cell next to a face shared with a refined
- *      root block replaces its face flux by the mean of the four fine fluxes
- *      over it;
- *   4. restriction: each refined root block takes the mean of its children.
+ * fluxes at fine-coarse faces.)  An octree of blocks: level 0 is the root
+ * grid of nblk blocks; each refined block of level l is covered by eight
+ * children of level l+1 at half its cell width.  The blocks of level l+1
+ * are the children of level l's refined blocks in increasing block index,
+ * child cx + 2*cy + 4*cz covering cells (cx*nxb/2.., cy*nxb/2.., cz*nxb/2..)
+ * of its parent.  Nesting (checked at creation): every refined block of a
+ * level >= 1 has its 26 neighbours (boundary map applied; positions beyond
+ * an outflow boundary excluded) at its own level, so leaf levels differ by
+ * at most one across faces, edges and corners.  Refinement is fixed for a
+ * handle; hydro_amr_estimate / hydro_amr_transfer regrid two-level meshes.
+ * Every leaf takes the predictor-corrector step with the same dt:
+ *   1. guard fill: level 0 by the same-level map over its state (refined
+ *      blocks hold the restriction of their children); a guard position of
+ *      level l >= 1 (mapped at that level) copies the cell of the level-l
+ *      block there, or is prolonged from level l-1: U_c + sum_d S_d (+-1/4),
+ *      S_d the van Leer slope of the conserved variable over level-(l-1)
+ *      cells d-1, d, d+1, keeping U_c if the result has rho <= 0 or p <= 0;
+ *   2. the step of each leaf from its guarded view (lam = dt/dx of its level);
+ *   3. refluxing: a leaf next to a refined block of its level replaces the
+ *      flux of each cell on that face by the mean of the four finer fluxes;
+ *   4. restriction, finest level first: refined blocks take the mean of
+ *      their children.
  * Layouts (device, caller-owned, 256-byte aligned): Ur [nroot][5][nxb^3]
- * (block id bx + nb0*(by + nb1*bz)); Uf [8*nrefined][5][nxb^3], the
- * children of the refined root blocks in increasing root id, child
- * cx + 2*cy + 4*cz covering cells (cx*nxb/2.., cy*nxb/2.., cz*nxb/2..) of its
- * parent; nxb^3 cells per child at half the parent's cell width.  The step
- * updates Ur and Uf in place (it reads the old state only through views
- * with two guard layers, formed in the workspace first).  refine: host
- * flags, one per root block, copied at creation. */
+ * (block id bx + nb0*(by + nb1*bz)); Uf: the blocks of levels 1, 2, ...
+ * concatenated, [5][nxb^3] each.  The step updates Ur and Uf in place (it
+ * reads the old state only through views with two guard layers, formed in
+ * the workspace first).  refine: host flags of level 0, one per root block;
+ * refine_deep: host flags of levels 1, 2, ... (one per block of each level,
+ * concatenated; NULL with nrefine_deep 0 for two levels); both copied at
+ * creation. */
 typedef struct hydro_amr hydro_amr;
 typedef struct {
   int nxb;                     /* 8, 16 or 32 */
@@ -307,18 +311,24 @@ typedef struct {
   double lo[3], hi[3];         /* domain; root dx_d = (hi - lo)/(nblk_d*nxb) */
   int bc[3];                   /* HYDRO_BC_* per axis */
   double gamma, small_p;
-  const unsigned char *refine; /* host, nblk[0]*nblk[1]*nblk[2] flags */
+  const unsigned char *refine; /* host, nblk[0]*nblk[1]*nblk[2] flags of level 0 */
   double *Ur;                  /* device root state */
-  double *Uf;                  /* device fine state (may be NULL without refinement) */
+  double *Uf;                  /* device state of levels >= 1 (may be NULL without refinement) */
   void *work;                  /* device workspace, hydro_amr_work_bytes */
   size_t work_bytes;
   void *stream;                /* hipStream_t */
+  const unsigned char *refine_deep;  /* host flags of levels 1, 2, ... (may be NULL) */
+  size_t nrefine_deep;               /* their count: whole levels */
 } hydro_amr_desc;
 
-/* Number of fine blocks (8 per flagged root block); 0 for an invalid descriptor. */
+/* Number of blocks of levels >= 1 (the length of Uf in blocks); 0 for an
+ * invalid descriptor. */
 size_t hydro_amr_fine_blocks(const hydro_amr_desc *d);
+/* Number of levels (>= 1) and the blocks of each (nblocks[l], 0 beyond);
+ * a negative error code for an invalid descriptor (bad nesting included). */
+int hydro_amr_levels(const hydro_amr_desc *d, long nblocks[8]);
 /* Workspace bytes: header, mesh tables, views with two guard layers of every
- * root and fine block, fluxes on block faces (used at fine-coarse faces),
+ * block of every level, fluxes on block faces (used at fine-coarse faces),
  * one refinement indicator per root block. */
 size_t hydro_amr_work_bytes(const hydro_amr_desc *d);
 /* Validate and build the mesh tables (uploaded to the workspace; waits for
@@ -350,9 +360,9 @@ int hydro_amr_dt(hydro_amr *a, double cfl, double *dt_out);
  *   E^2 = sum_d num_d^2 / sum_d den_d^2,  num_d = (fR - f0) - (f0 - fL),
  *   den_d = (|fR - f0| + |f0 - fL|) + eps ((|fR| + 2|f0|) + |fL|),
  * neighbours along d by the root map, 0 where the denominator is 0, every
- * operation rounded as written.  New flags: 1 where E^2 > refine_cutoff^2,
- * 0 for a refined block where E^2 < derefine_cutoff^2, else the current
- * flag.  flags_out: host, nroot; E2_out: host, nroot, may be NULL.  Waits.
+ * operation rounded as written.  New level-0 flags: 1 where
+ * E^2 > refine_cutoff^2, 0 for a refined block where E^2 < derefine_cutoff^2,
+ * else the current flag.  flags_out: host, nroot; E2_out: host, nroot, may be NULL.  Waits.
  * Errors: HYDRO_EINVAL (NULL, eps < 0, cutoffs not 0 <= derefine <= refine). */
 int hydro_amr_estimate(hydro_amr *a, double eps, double refine_cutoff, double derefine_cutoff, double *E2_out,
                        unsigned char *flags_out);
@@ -363,7 +373,8 @@ int hydro_amr_estimate(hydro_amr *a, double eps, double refine_cutoff, double de
  * state (the guard-fill prolongation, conservative), and every refined root
  * block of `to` takes its children's restriction; derefined blocks keep
  * their root values (the restriction of the children they lose).  Waits for
- * `from`'s stream, then runs on `to`'s.  `from` may be freed afterwards. */
+ * `from`'s stream, then runs on `to`'s.  `from` may be freed afterwards.
+ * Both meshes must have at most two levels (HYDRO_EINVAL otherwise). */
 int hydro_amr_transfer(hydro_amr *from, hydro_amr *to);
 /* Event counters summed since creation: floors, fallbacks, nonphysical cells (waits). */
 int hydro_amr_counters(hydro_amr *a, long long out[3]);

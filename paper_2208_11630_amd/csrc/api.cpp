@@ -708,12 +708,13 @@ const char* hydro_last_error(void) { return g_err; }
 
 }  // extern "C"
 
-// ---- two-level static AMR ---------------------------------------------------
+// ---- block-structured AMR ---------------------------------------------------
 
 struct hydro_amr {
   hydro_amr_desc d;
   hydro::AmrLaunch L;
-  std::vector<unsigned char> refine;
+  std::vector<unsigned char> refine;       // level-0 flags
+  std::vector<unsigned char> refine_deep;  // flags of levels >= 1
   long steps = 0;          // signal slot of the current state: steps % 3
   bool sig_valid = false;  // the slot holds the current state's signal speed
   double* E2 = nullptr;    // device, nroot refinement indicators
@@ -723,13 +724,32 @@ namespace {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-struct AmrLayout {
-  long nroot, nfine, nleaf0, nrefined, nreflux, ngroups;
-  size_t o_tab, o_G0, o_G1, o_f0, o_f1, o_E2, total;
-  std::vector<int> leaf0, leaf_plain, rx_blocks, child_base, fine_root, refined;
-  std::vector<int> reflux;  // 4 ints per entry, grouped by coarse leaf
-  std::vector<int> first;   // ngroups + 1 entry offsets
+struct AmrLevelHost {
+  long nb[3];
+  std::vector<int> pos;  // 4 ints per block
+  std::vector<unsigned char> flag;
+  std::vector<int> lookup, parent, child_base, refined, leaves, leaf_plain, rx_blocks, reflux, first;
+  size_t o_pos, o_reflux, o_lookup, o_parent, o_child, o_refined, o_leaves, o_plain, o_rx, o_first;  // int offsets
+  size_t o_G, o_flux;                                                                                 // bytes
 };
+
+struct AmrLayout {
+  int nlev = 0;
+  AmrLevelHost lev[hydro::AMR_MAX_LEVELS];
+  long nroot = 0, nfine = 0;
+  size_t tab_ints = 0, o_tab = 256, o_E2 = 0, total = 0;
+};
+
+// block index at level-l position (x, y, z) after the boundary map; -1 when
+// absent, -2 beyond an outflow boundary
+long level_block(const AmrLevelHost& L, const int* bc, long x, long y, long z) {
+  long p[3] = {x, y, z};
+  for (int d = 0; d < 3; ++d) {
+    if (bc[d] == HYDRO_BC_PERIODIC) p[d] = ((p[d] % L.nb[d]) + L.nb[d]) % L.nb[d];
+    else if (p[d] < 0 || p[d] >= L.nb[d]) return -2;
+  }
+  return L.lookup[p[0] + L.nb[0] * (p[1] + L.nb[1] * p[2])];
+}
 
 int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
   if (!d) return fail(HYDRO_EINVAL, "descriptor is NULL");
@@ -743,63 +763,140 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
   }
   if (!(std::isfinite(d->gamma) && d->gamma > 1.0)) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
   if (!d->refine) return fail(HYDRO_EINVAL, "refine flags are NULL");
+  if (d->nrefine_deep && !d->refine_deep) return fail(HYDRO_EINVAL, "refine_deep is NULL");
   const int N = d->nxb;
-  const long nb0 = d->nblk[0], nb1 = d->nblk[1], nb2 = d->nblk[2];
-  A.nroot = nb0 * nb1 * nb2;
+  A.nroot = (long)d->nblk[0] * d->nblk[1] * d->nblk[2];
   if (A.nroot > (1L << 24)) return fail(HYDRO_EINVAL, "too many root blocks");
-  A.leaf0.clear();
-  A.refined.clear();
-  A.child_base.assign(A.nroot, -1);
-  for (long b = 0; b < A.nroot; ++b) {
-    if (d->refine[b]) {
-      A.child_base[b] = (int)(8 * A.refined.size());
-      A.refined.push_back((int)b);
-    } else {
-      A.leaf0.push_back((int)b);
-    }
-  }
-  A.nrefined = (long)A.refined.size();
-  A.nfine = 8 * A.nrefined;
-  A.nleaf0 = (long)A.leaf0.size();
-  A.fine_root.assign(A.nfine, 0);
-  for (long q = 0; q < A.nrefined; ++q)
-    for (int c = 0; c < 8; ++c) A.fine_root[8 * q + c] = A.refined[q];
-  A.reflux.clear();
-  A.first.assign(1, 0);
-  A.leaf_plain.clear();
-  A.rx_blocks.clear();
-  for (int b : A.leaf0) {
-    const long bx = b % nb0, by = (b / nb0) % nb1, bz = b / (nb0 * nb1);
-    for (int dd = 0; dd < 3; ++dd)
-      for (int side = 0; side < 2; ++side) {
-        long pos[3] = {bx, by, bz};
-        const long nb[3] = {nb0, nb1, nb2};
-        pos[dd] += side ? 1 : -1;
-        if (d->bc[dd] == HYDRO_BC_PERIODIC) pos[dd] = (pos[dd] + nb[dd]) % nb[dd];
-        else if (pos[dd] < 0 || pos[dd] >= nb[dd]) continue;
-        const long nbr = pos[0] + nb0 * (pos[1] + nb1 * pos[2]);
-        if (!d->refine[nbr]) continue;
-        A.reflux.insert(A.reflux.end(), {b, dd, side, (int)nbr});
+  // levels: positions, flags, children
+  size_t used_deep = 0;
+  for (int l = 0;; ++l) {
+    if (l == hydro::AMR_MAX_LEVELS) return fail(HYDRO_EINVAL, "more than %d levels", hydro::AMR_MAX_LEVELS);
+    AmrLevelHost& L = A.lev[l];
+    for (int ax = 0; ax < 3; ++ax) L.nb[ax] = (long)d->nblk[ax] << l;
+    if (l == 0) {
+      L.pos.resize(4 * A.nroot);
+      for (long b = 0; b < A.nroot; ++b) {
+        L.pos[4 * b] = (int)(b % d->nblk[0]);
+        L.pos[4 * b + 1] = (int)((b / d->nblk[0]) % d->nblk[1]);
+        L.pos[4 * b + 2] = (int)(b / ((long)d->nblk[0] * d->nblk[1]));
+        L.pos[4 * b + 3] = 0;
       }
-    if ((int)A.reflux.size() / 4 > A.first.back()) {
-      A.first.push_back((int)A.reflux.size() / 4);
-      A.rx_blocks.push_back(b);
+      L.parent.assign(A.nroot, -1);
+      L.flag.assign(d->refine, d->refine + A.nroot);
     } else {
-      A.leaf_plain.push_back(b);
+      const AmrLevelHost& P = A.lev[l - 1];
+      L.pos.clear();
+      L.parent.clear();
+      for (int r : P.refined)
+        for (int c = 0; c < 8; ++c) {
+          L.pos.insert(L.pos.end(), {2 * P.pos[4 * r] + (c & 1), 2 * P.pos[4 * r + 1] + ((c >> 1) & 1),
+                                     2 * P.pos[4 * r + 2] + ((c >> 2) & 1), 0});
+          L.parent.push_back(r);
+        }
+      const long nblk = (long)L.parent.size();
+      if (used_deep < d->nrefine_deep) {
+        if (d->nrefine_deep - used_deep < (size_t)nblk)
+          return fail(HYDRO_EINVAL, "refine_deep ends inside level %d (%zu of %ld flags left)", l,
+                      d->nrefine_deep - used_deep, nblk);
+        L.flag.assign(d->refine_deep + used_deep, d->refine_deep + used_deep + nblk);
+        used_deep += (size_t)nblk;
+      } else {
+        L.flag.assign(nblk, 0);
+      }
+    }
+    const long nblk = (long)L.flag.size();
+    const long ncells = L.nb[0] * L.nb[1] * L.nb[2];
+    if (ncells > (1L << 28)) return fail(HYDRO_EINVAL, "level %d is too fine for its lookup table", l);
+    L.lookup.assign(ncells, -1);
+    for (long b = 0; b < nblk; ++b)
+      L.lookup[L.pos[4 * b] + L.nb[0] * (L.pos[4 * b + 1] + L.nb[1] * (long)L.pos[4 * b + 2])] = (int)b;
+    L.child_base.assign(nblk, -1);
+    L.refined.clear();
+    L.leaves.clear();
+    for (long b = 0; b < nblk; ++b) {
+      if (L.flag[b]) {
+        L.child_base[b] = (int)(8 * L.refined.size());
+        L.refined.push_back((int)b);
+      } else {
+        L.leaves.push_back((int)b);
+      }
+    }
+    if (l > 0) A.nfine += nblk;
+    A.nlev = l + 1;
+    if (L.refined.empty()) break;
+  }
+  if (used_deep != d->nrefine_deep)
+    return fail(HYDRO_EINVAL, "refine_deep has %zu flags, the levels use %zu", d->nrefine_deep, used_deep);
+  // nesting: every refined block of a level >= 1 has its 26 neighbours at its level
+  for (int l = 1; l < A.nlev; ++l) {
+    const AmrLevelHost& L = A.lev[l];
+    for (int r : L.refined)
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx)
+            if (level_block(L, d->bc, L.pos[4 * r] + dx, L.pos[4 * r + 1] + dy, L.pos[4 * r + 2] + dz) == -1)
+              return fail(HYDRO_EINVAL, "refined block %d of level %d lacks a neighbour at its level", r, l);
+  }
+  // reflux entries: leaves next to a refined block of their level, grouped per leaf
+  for (int l = 0; l < A.nlev; ++l) {
+    AmrLevelHost& L = A.lev[l];
+    L.reflux.clear();
+    L.first.assign(1, 0);
+    L.leaf_plain.clear();
+    L.rx_blocks.clear();
+    for (int b : L.leaves) {
+      for (int dd = 0; dd < 3; ++dd)
+        for (int side = 0; side < 2; ++side) {
+          long p[3] = {L.pos[4 * b], L.pos[4 * b + 1], L.pos[4 * b + 2]};
+          p[dd] += side ? 1 : -1;
+          const long nbr = level_block(L, d->bc, p[0], p[1], p[2]);
+          if (nbr < 0 || !L.flag[nbr]) continue;
+          L.reflux.insert(L.reflux.end(), {b, dd, side, (int)nbr});
+        }
+      if ((int)L.reflux.size() / 4 > L.first.back()) {
+        L.first.push_back((int)L.reflux.size() / 4);
+        L.rx_blocks.push_back(b);
+      } else {
+        L.leaf_plain.push_back(b);
+      }
     }
   }
-  A.nreflux = (long)A.reflux.size() / 4;
-  A.ngroups = (long)A.first.size() - 1;
-  const long P = N + 4;   // the step's internal views keep two guard layers
-  const size_t tab = sizeof(int) * (size_t)(A.nleaf0 + A.nroot + A.nfine + A.nrefined + 4 * A.nreflux +
-                                             A.ngroups + 1 + A.nleaf0);
-  A.o_tab = 256;
-  A.o_G0 = A.o_tab + al256(tab);
-  A.o_G1 = A.o_G0 + al256(sizeof(double) * 5 * P * P * P * A.nroot);
-  A.o_f0 = A.o_G1 + al256(sizeof(double) * 5 * P * P * P * A.nfine);
-  A.o_f1 = A.o_f0 + al256(sizeof(double) * 30 * (size_t)N * N * A.nroot);
-  A.o_E2 = A.o_f1 + al256(sizeof(double) * 30 * (size_t)N * N * A.nfine);
-  A.total = A.o_E2 + al256(sizeof(double) * (size_t)A.nroot);
+  // table (ints): int4 arrays first (16-byte aligned), then the int arrays
+  size_t t = 0;
+  auto take = [&](size_t nints) {
+    const size_t o = t;
+    t += (nints + 3) & ~(size_t)3;
+    return o;
+  };
+  for (int l = 0; l < A.nlev; ++l) {
+    AmrLevelHost& L = A.lev[l];
+    L.o_pos = take(L.pos.size());
+    L.o_reflux = take(L.reflux.size());
+  }
+  for (int l = 0; l < A.nlev; ++l) {
+    AmrLevelHost& L = A.lev[l];
+    L.o_lookup = take(L.lookup.size());
+    L.o_parent = take(L.parent.size());
+    L.o_child = take(L.child_base.size());
+    L.o_refined = take(L.refined.size());
+    L.o_leaves = take(L.leaves.size());
+    L.o_plain = take(L.leaf_plain.size());
+    L.o_rx = take(L.rx_blocks.size());
+    L.o_first = take(L.first.size());
+  }
+  A.tab_ints = t;
+  const size_t P = (size_t)N + 4;   // the step's internal views keep two guard layers
+  size_t o = A.o_tab + al256(sizeof(int) * t);
+  for (int l = 0; l < A.nlev; ++l) {
+    AmrLevelHost& L = A.lev[l];
+    const size_t nblk = L.flag.size();
+    L.o_G = o;
+    o += al256(sizeof(double) * 5 * P * P * P * nblk);
+    L.o_flux = o;
+    o += al256(sizeof(double) * 30 * (size_t)N * N * nblk);
+  }
+  A.o_E2 = o;
+  A.total = o + al256(sizeof(double) * (size_t)A.nroot);
   return HYDRO_OK;
 }
 
@@ -811,6 +908,15 @@ size_t hydro_amr_fine_blocks(const hydro_amr_desc* d) {
   AmrLayout A;
   if (amr_layout(d, A)) return 0;
   return (size_t)A.nfine;
+}
+
+int hydro_amr_levels(const hydro_amr_desc* d, long nblocks[8]) {
+  if (!nblocks) return fail(HYDRO_EINVAL, "nblocks is NULL");
+  AmrLayout A;
+  int rc = amr_layout(d, A);
+  if (rc) return rc;
+  for (int l = 0; l < 8; ++l) nblocks[l] = l < A.nlev ? (long)A.lev[l].flag.size() : 0;
+  return A.nlev;
 }
 
 size_t hydro_amr_work_bytes(const hydro_amr_desc* d) {
@@ -835,53 +941,60 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
   a->d = *d;
   a->refine.assign(d->refine, d->refine + A.nroot);
   a->d.refine = a->refine.data();
+  a->refine_deep.assign(d->refine_deep, d->refine_deep + d->nrefine_deep);
+  a->d.refine_deep = a->refine_deep.data();
   hydro::AmrLaunch& L = a->L;
   const int N = d->nxb;
-  for (int ax = 0; ax < 3; ++ax) {
-    L.g0.nb[ax] = d->nblk[ax];
-    L.g0.bc[ax] = d->bc[ax];
-    L.g0.inv_dx[ax] = ((double)d->nblk[ax] * N) / (d->hi[ax] - d->lo[ax]);
-    L.g1.nb[ax] = 2 * d->nblk[ax];
-    L.g1.bc[ax] = d->bc[ax];
-    L.g1.inv_dx[ax] = 2.0 * L.g0.inv_dx[ax];
-  }
-  L.g0.gamma = L.g1.gamma = d->gamma;
-  L.g0.small_p = L.g1.small_p = d->small_p;
   char* w = (char*)d->work;
   int* tab = (int*)(w + A.o_tab);
-  // table order: reflux entries first (int4, 16-byte aligned at the table start)
-  std::vector<int> host;
-  host.insert(host.end(), A.reflux.begin(), A.reflux.end());
-  host.insert(host.end(), A.leaf0.begin(), A.leaf0.end());
-  host.insert(host.end(), A.child_base.begin(), A.child_base.end());
-  host.insert(host.end(), A.fine_root.begin(), A.fine_root.end());
-  host.insert(host.end(), A.refined.begin(), A.refined.end());
-  host.insert(host.end(), A.first.begin(), A.first.end());
-  host.insert(host.end(), A.leaf_plain.begin(), A.leaf_plain.end());
-  host.insert(host.end(), A.rx_blocks.begin(), A.rx_blocks.end());
-  L.reflux = (const int4*)tab;
-  L.leaf0 = tab + 4 * A.nreflux;
-  L.child_base = L.leaf0 + A.nleaf0;
-  L.fine_root = L.child_base + A.nroot;
-  L.refined = L.fine_root + A.nfine;
-  L.reflux_first = L.refined + A.nrefined;
-  L.leaf_plain = L.reflux_first + A.ngroups + 1;
-  L.rx_blocks = L.leaf_plain + A.leaf_plain.size();
-  L.nleaf_plain = (long)A.leaf_plain.size();
-  L.Ur = d->Ur;
-  L.Uf = d->Uf;
-  L.G0 = (double*)(w + A.o_G0);
-  L.G1 = (double*)(w + A.o_G1);
-  L.flux0 = (double*)(w + A.o_f0);
-  L.flux1 = (double*)(w + A.o_f1);
+  std::vector<int> host(A.tab_ints, 0);
+  L.nlev = A.nlev;
+  size_t fine_off = 0;
+  for (int l = 0; l < A.nlev; ++l) {
+    const AmrLevelHost& H = A.lev[l];
+    hydro::AmrLevel& V = L.lev[l];
+    for (int ax = 0; ax < 3; ++ax) {
+      V.g.nb[ax] = (int)H.nb[ax];
+      V.g.bc[ax] = d->bc[ax];
+      V.g.inv_dx[ax] = ((double)d->nblk[ax] * N) / (d->hi[ax] - d->lo[ax]) * (double)(1L << l);
+    }
+    V.g.gamma = d->gamma;
+    V.g.small_p = d->small_p;
+    const long nblk = (long)H.flag.size();
+    V.U = l == 0 ? d->Ur : d->Uf + fine_off * 5 * (size_t)N * N * N;
+    if (l > 0) fine_off += (size_t)nblk;
+    V.G = (double*)(w + H.o_G);
+    V.flux = (double*)(w + H.o_flux);
+    auto put = [&](size_t o, const std::vector<int>& v) { std::copy(v.begin(), v.end(), host.begin() + o); };
+    put(H.o_pos, H.pos);
+    put(H.o_reflux, H.reflux);
+    put(H.o_lookup, H.lookup);
+    put(H.o_parent, H.parent);
+    put(H.o_child, H.child_base);
+    put(H.o_refined, H.refined);
+    put(H.o_leaves, H.leaves);
+    put(H.o_plain, H.leaf_plain);
+    put(H.o_rx, H.rx_blocks);
+    put(H.o_first, H.first);
+    V.pos = (const int4*)(tab + H.o_pos);
+    V.reflux = (const int4*)(tab + H.o_reflux);
+    V.lookup = tab + H.o_lookup;
+    V.parent = tab + H.o_parent;
+    V.child_base = tab + H.o_child;
+    V.refined = tab + H.o_refined;
+    V.leaves = tab + H.o_leaves;
+    V.leaf_plain = tab + H.o_plain;
+    V.rx_blocks = tab + H.o_rx;
+    V.reflux_first = tab + H.o_first;
+    V.nblk = nblk;
+    V.nrefined = (long)H.refined.size();
+    V.nleaves = (long)H.leaves.size();
+    V.nleaf_plain = (long)H.leaf_plain.size();
+    V.nreflux = (long)H.reflux.size() / 4;
+    V.ngroups = (long)H.first.size() - 1;
+  }
   a->E2 = (double*)(w + A.o_E2);
   L.ws = (hydro::WorkHeader*)w;
-  L.nroot = A.nroot;
-  L.nleaf0 = A.nleaf0;
-  L.nfine = A.nfine;
-  L.nrefined = A.nrefined;
-  L.nreflux = A.nreflux;
-  L.nreflux_groups = A.ngroups;
   L.dt = 0.0;
   L.cfl = 0.0;
   L.slot = 0;
@@ -991,12 +1104,12 @@ int hydro_amr_estimate(hydro_amr* a, double eps, double refine_cutoff, double de
   hipStream_t s = (hipStream_t)a->d.stream;
   hipError_t e = hydro::launch_amr_indicator(a->d.nxb, a->L, eps, a->E2, s);
   if (e != hipSuccess) return hip_fail(e, "AMR indicator launch");
-  std::vector<double> E2((size_t)a->L.nroot);
+  std::vector<double> E2((size_t)a->L.lev[0].nblk);
   e = hipMemcpyAsync(E2.data(), a->E2, sizeof(double) * E2.size(), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "AMR indicator read");
   const double rc2 = refine_cutoff * refine_cutoff, dc2 = derefine_cutoff * derefine_cutoff;
-  for (long b = 0; b < a->L.nroot; ++b) {
+  for (long b = 0; b < a->L.lev[0].nblk; ++b) {
     unsigned char f = a->refine[b] ? 1 : 0;
     if (E2[b] > rc2) f = 1;
     else if (f && E2[b] < dc2) f = 0;
@@ -1008,19 +1121,20 @@ int hydro_amr_estimate(hydro_amr* a, double eps, double refine_cutoff, double de
 
 int hydro_amr_transfer(hydro_amr* from, hydro_amr* to) {
   if (!from || !to || from == to) return fail(HYDRO_EINVAL, "need two distinct handles");
+  if (from->L.nlev > 2 || to->L.nlev > 2) return fail(HYDRO_EINVAL, "regridding handles two-level meshes");
   const hydro_amr_desc &x = from->d, &y = to->d;
   bool same = x.nxb == y.nxb && x.gamma == y.gamma;
   for (int ax = 0; ax < 3; ++ax)
     same = same && x.nblk[ax] == y.nblk[ax] && x.bc[ax] == y.bc[ax] && x.lo[ax] == y.lo[ax] && x.hi[ax] == y.hi[ax];
   if (!same) return fail(HYDRO_EINVAL, "the two meshes must share their root grid");
-  if (y.Uf == x.Uf && to->L.nfine && from->L.nfine)
+  if (y.Uf == x.Uf && to->L.nlev > 1 && from->L.nlev > 1)
     return fail(HYDRO_EINVAL, "the new mesh needs a fine state buffer of its own");
   hipError_t e = hipStreamSynchronize((hipStream_t)x.stream);  // the old mesh's last step has finished
   if (e != hipSuccess) return hip_fail(e, "AMR transfer: waiting for the old mesh");
   hipStream_t s = (hipStream_t)y.stream;
   const size_t N3 = (size_t)x.nxb * x.nxb * x.nxb;
   if (y.Ur != x.Ur) {
-    e = hipMemcpyAsync(y.Ur, x.Ur, sizeof(double) * 5 * N3 * (size_t)from->L.nroot, hipMemcpyDeviceToDevice, s);
+    e = hipMemcpyAsync(y.Ur, x.Ur, sizeof(double) * 5 * N3 * (size_t)from->L.lev[0].nblk, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "AMR transfer: root state copy");
   }
   e = hydro::launch_amr_transfer(y.nxb, from->L, to->L, s);

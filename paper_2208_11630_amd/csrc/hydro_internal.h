@@ -84,26 +84,30 @@ hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, double* scr
 hipError_t launch_clear_slot(WorkHeader* ws, int slot, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, long n, hipStream_t s);
 
-// Two-level static AMR step (see hydro_kernels.hip): everything one step
-// needs, device pointers into the caller's state and workspace.
+// Block-structured AMR (see hydro_kernels.hip): an octree of blocks, level
+// 0 the root grid, level l+1 the children of level l's refined blocks.
+constexpr int AMR_MAX_LEVELS = 8;
+struct AmrLevel {
+  GridGeom g;                 // nb = root nb << l, inv_dx = root inv_dx * 2^l
+  double* U;                  // the level's state (compact), updated in place
+  double* G;                  // views with two guard layers, every block of the level
+  double* flux;               // face fluxes per block (those at fine-coarse faces are used)
+  const int* lookup;          // block index at each level-l block position, or -1
+  const int4* pos;            // block positions (x, y, z, 0)
+  const int* parent;          // parent block on level l-1 (level >= 1)
+  const int* child_base;      // first child on level l+1, or -1
+  const int* refined;         // refined blocks
+  const int* leaves;          // unrefined blocks
+  const int* leaf_plain;      // leaves without a refined face neighbour
+  const int* rx_blocks;       // leaves with one (the reflux groups' blocks, in group order)
+  const int4* reflux;         // (leaf, d, side, refined neighbour), grouped by leaf
+  const int* reflux_first;    // ngroups + 1 offsets into reflux
+  long nblk, nrefined, nleaves, nleaf_plain, nreflux, ngroups;
+};
 struct AmrLaunch {
-  GridGeom g0, g1;            // root and fine level geometry (inv_dx per level)
-  double* Ur;                 // root state (refined blocks hold the restriction), updated in place
-  double* Uf;                 // fine state, updated in place
-  double* G0;                 // views with two guard layers: root blocks, fine blocks
-  double* G1;
-  double* flux0;              // boundary fluxes per root block / fine block (fine-coarse faces only)
-  double* flux1;
-  const int* leaf0;           // unrefined root blocks
-  const int* leaf_plain;      // unrefined root blocks without a refined neighbour
-  const int* rx_blocks;       // unrefined root blocks with one (the reflux groups' blocks, in group order)
-  const int* child_base;      // per root block: first child, or -1
-  const int* fine_root;       // per fine block: its root block
-  const int* refined;         // refined root blocks
-  const int4* reflux;         // (coarse leaf, d, side, refined neighbour), grouped by coarse leaf
-  const int* reflux_first;    // nreflux_groups + 1 offsets into reflux
+  AmrLevel lev[AMR_MAX_LEVELS];
+  int nlev;
   WorkHeader* ws;
-  long nroot, nleaf0, nleaf_plain, nfine, nrefined, nreflux, nreflux_groups;
   double dt;                  // used when cfl <= 0
   double cfl;                 // > 0: dt = cfl / ws->sig[slot]
   int slot;                   // step number mod 3
@@ -112,8 +116,8 @@ hipError_t launch_amr_step(int nxb, const AmrLaunch& L, hipStream_t s);
 hipError_t launch_amr_signal(int nxb, const AmrLaunch& L, int slot, hipStream_t s);
 // Refinement indicator per root block into E2[nroot] (device).
 hipError_t launch_amr_indicator(int nxb, const AmrLaunch& L, double eps, double* E2, hipStream_t s);
-// Fine state of mesh `to` from mesh `from` (same root grid; to.Ur holds the
-// root state), then the restriction of to's refined blocks.
+// Fine state of two-level mesh `to` from two-level mesh `from` (same root
+// grid; to's root state in place), then the restriction of to's refined blocks.
 hipError_t launch_amr_transfer(int nxb, const AmrLaunch& from, const AmrLaunch& to, hipStream_t s);
 
 }  // namespace hydro

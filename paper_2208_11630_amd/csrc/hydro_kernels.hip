@@ -1070,71 +1070,77 @@ struct AmrStep {
   static constexpr long NF = 6L * 5 * N * N;      // boundary fluxes per block: [face 2d+side][v][a1][a0]
 };
 
-// Conserved state prolonged from the root level to the level-1 cell at
-// global index (I, J, K) (inside the domain): U_c + sum_d S_d * (+-1/4), S_d
-// the van Leer slope of the conserved variable over the root cells (level-0
-// map), keeping U_c if the result has rho <= 0 or p <= 0.
+// Offset of the cell at global index (I, J, K) of one level (each may lie
+// up to two cells outside the domain; boundary conditions applied), its
+// block found through the level's lookup (every position read here holds a
+// block: the host checks the nesting; a missing one would read block 0).
 template <int N>
-__device__ __forceinline__ void prolong_cell(const GridGeom& g0, const double* __restrict__ Ur, int I, int J, int K,
-                                             double (&val)[5]) {
+__device__ __forceinline__ long level_offset(const GridGeom& g, const int* __restrict__ lookup, int I, int J,
+                                             int K) {
+  I = map_axis(I, g.nb[0] * N, g.bc[0]);
+  J = map_axis(J, g.nb[1] * N, g.bc[1]);
+  K = map_axis(K, g.nb[2] * N, g.bc[2]);
+  const int b = lookup[(I / N) + g.nb[0] * ((J / N) + g.nb[1] * (K / N))];
+  return Layout<N>::at(b < 0 ? 0 : b, I % N, J % N, K % N);
+}
+
+// Conserved state prolonged from level p to the level-(p+1) cell at global
+// index (I, J, K) (inside the domain): U_c + sum_d S_d * (+-1/4), S_d the van
+// Leer slope of the conserved variable over level-p cells (level-p map and
+// lookup), keeping U_c if the result has rho <= 0 or p <= 0.
+template <int N>
+__device__ __forceinline__ void prolong_cell(const GridGeom& gp, const int* __restrict__ lookup,
+                                             const double* __restrict__ Up, int I, int J, int K, double (&val)[5]) {
   const int Ic = I / 2, Jc = J / 2, Kc = K / 2;
   double uc[5];
-  load_cons<N>(Ur, cell_offset<N>(g0, Ic, Jc, Kc), uc);
+  load_cons<N>(Up, level_offset<N>(gp, lookup, Ic, Jc, Kc), uc);
 #pragma unroll
   for (int v = 0; v < 5; ++v) val[v] = uc[v];
   const int off[3] = {(I & 1) * 2 - 1, (J & 1) * 2 - 1, (K & 1) * 2 - 1};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     double um[5], up[5];
-    load_cons<N>(Ur, cell_offset<N>(g0, Ic - (d == 0), Jc - (d == 1), Kc - (d == 2)), um);
-    load_cons<N>(Ur, cell_offset<N>(g0, Ic + (d == 0), Jc + (d == 1), Kc + (d == 2)), up);
+    load_cons<N>(Up, level_offset<N>(gp, lookup, Ic - (d == 0), Jc - (d == 1), Kc - (d == 2)), um);
+    load_cons<N>(Up, level_offset<N>(gp, lookup, Ic + (d == 0), Jc + (d == 1), Kc + (d == 2)), up);
 #pragma unroll
     for (int v = 0; v < 5; ++v) val[v] += van_leer_sf(uc[v] - um[v], up[v] - uc[v]) * (0.25 * off[d]);
   }
   const double rho = val[0];
   const double kin = 0.5 * ((val[1] * val[1] + val[2] * val[2]) + val[3] * val[3]) / (rho > 0.0 ? rho : 1.0);
-  const double p = (g0.gamma - 1.0) * (val[4] - kin);
+  const double p = (gp.gamma - 1.0) * (val[4] - kin);
   if (!(rho > 0.0 && p > 0.0)) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) val[v] = uc[v];
   }
 }
 
-// Fine guarded views: fine block f = child c of root block fine_root[f]
-// (children contiguous, c = f - child_base[root]); every cell of the view
-// either copies the fine cell at its level-1 position (when that position
-// lies in a refined root block) or is prolonged from the root cell under it:
-// U_c + sum_d S_d * (+-1/4), S_d the van Leer slope of the conserved variable
-// over the root cells (level-0 map), keeping U_c if the result has rho <= 0
-// or p <= 0.
+// Views of the blocks of level l >= 1 (two guard layers): a position
+// (mapped at level l) inside a block of level l copies its cell; otherwise it
+// is prolonged from level l-1.
 template <int N>
-__global__ __launch_bounds__(256) void amr_fill_fine_kernel(GridGeom g0, const double* __restrict__ Ur,
-                                                            const double* __restrict__ Uf,
-                                                            const int* __restrict__ child_base,
-                                                            const int* __restrict__ fine_root,
-                                                            double* __restrict__ G1) {
+__global__ __launch_bounds__(256) void amr_fill_level_kernel(GridGeom g, GridGeom gp,
+                                                             const int* __restrict__ lookup,
+                                                             const int* __restrict__ lookup_p,
+                                                             const int4* __restrict__ pos,
+                                                             const double* __restrict__ U,
+                                                             const double* __restrict__ Up,
+                                                             double* __restrict__ G) {
   constexpr int P = Guarded<N, VG>::P;
   const int f = blockIdx.x;
-  const int r = fine_root[f];
-  const int c = f - child_base[r];
-  const int bx = r % g0.nb[0], by = (r / g0.nb[0]) % g0.nb[1], bz = r / (g0.nb[0] * g0.nb[1]);
-  const int X0 = 2 * bx * N + (c & 1) * N, Y0 = 2 * by * N + ((c >> 1) & 1) * N, Z0 = 2 * bz * N + ((c >> 2) & 1) * N;
-  const int NF0 = 2 * g0.nb[0] * N, NF1 = 2 * g0.nb[1] * N, NF2 = 2 * g0.nb[2] * N;
-  double* out = G1 + (long)f * Guarded<N, VG>::BS;
+  const int4 q = pos[f];
+  const int X0 = q.x * N, Y0 = q.y * N, Z0 = q.z * N;
+  const int NX = g.nb[0] * N, NY = g.nb[1] * N, NZ = g.nb[2] * N;
+  double* out = G + (long)f * Guarded<N, VG>::BS;
   for (int t = threadIdx.x; t < P * P * P; t += blockDim.x) {
-    const int i = t % P - VG, j = (t / P) % P - VG, k = t / (P * P) - VG;
-    int I = X0 + i, J = Y0 + j, K = Z0 + k;
-    I = g0.bc[0] == 0 ? (I < 0 ? I + NF0 : (I >= NF0 ? I - NF0 : I)) : min(max(I, 0), NF0 - 1);
-    J = g0.bc[1] == 0 ? (J < 0 ? J + NF1 : (J >= NF1 ? J - NF1 : J)) : min(max(J, 0), NF1 - 1);
-    K = g0.bc[2] == 0 ? (K < 0 ? K + NF2 : (K >= NF2 ? K - NF2 : K)) : min(max(K, 0), NF2 - 1);
-    const int rb = I / (2 * N) + g0.nb[0] * (J / (2 * N) + g0.nb[1] * (K / (2 * N)));
+    const int I = map_axis(X0 + t % P - VG, NX, g.bc[0]);
+    const int J = map_axis(Y0 + (t / P) % P - VG, NY, g.bc[1]);
+    const int K = map_axis(Z0 + t / (P * P) - VG, NZ, g.bc[2]);
+    const int b = lookup[(I / N) + g.nb[0] * ((J / N) + g.nb[1] * (K / N))];
     double val[5];
-    if (child_base[rb] >= 0) {
-      const int fb = child_base[rb] + (I / N) % 2 + 2 * ((J / N) % 2) + 4 * ((K / N) % 2);
-      load_cons<N>(Uf, Layout<N>::at(fb, I % N, J % N, K % N), val);
-    } else {
-      prolong_cell<N>(g0, Ur, I, J, K, val);
-    }
+    if (b >= 0)
+      load_cons<N>(U, Layout<N>::at(b, I % N, J % N, K % N), val);
+    else
+      prolong_cell<N>(gp, lookup_p, Up, I, J, K, val);
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[v * Guarded<N, VG>::VS + t] = val[v];
   }
@@ -1385,7 +1391,8 @@ __global__ __launch_bounds__(256) void amr_indicator_kernel(GridGeom g0, const d
 // was refined before (old_base[r] >= 0), else is prolonged from the root
 // state cell by cell.
 template <int N>
-__global__ __launch_bounds__(256) void amr_transfer_kernel(GridGeom g0, const double* __restrict__ Ur,
+__global__ __launch_bounds__(256) void amr_transfer_kernel(GridGeom g0, const int* __restrict__ lookup0,
+                                                           const double* __restrict__ Ur,
                                                            const double* __restrict__ Uf_old,
                                                            const int* __restrict__ old_base,
                                                            const int* __restrict__ child_base,
@@ -1403,7 +1410,7 @@ __global__ __launch_bounds__(256) void amr_transfer_kernel(GridGeom g0, const do
   const int X0 = 2 * bx * N + (c & 1) * N, Y0 = 2 * by * N + ((c >> 1) & 1) * N, Z0 = 2 * bz * N + ((c >> 2) & 1) * N;
   for (int t = threadIdx.x; t < N * N * N; t += blockDim.x) {
     double val[5];
-    prolong_cell<N>(g0, Ur, X0 + t % N, Y0 + (t / N) % N, Z0 + t / (N * N), val);
+    prolong_cell<N>(g0, lookup0, Ur, X0 + t % N, Y0 + (t / N) % N, Z0 + t / (N * N), val);
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[v * Layout<N>::VS + t] = val[v];
   }
@@ -1539,48 +1546,63 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
   constexpr long TPB = (N / T) * (N / T);
   const int slot = L.slot;
   hipLaunchKernelGGL(amr_begin_kernel, dim3(1), dim3(1), 0, s, L.ws, L.dt, L.cfl, slot);
-  // 1. views: root blocks (same-level map), fine blocks (copies / prolongation)
-  hipLaunchKernelGGL((fill_guards_kernel<N, VG>), dim3((unsigned)(L.nroot * Guarded<N, VG>::P)), dim3(256), 0, s,
-                     L.g0, L.Ur, L.G0);
-  if (L.nfine)
-    hipLaunchKernelGGL(amr_fill_fine_kernel<N>, dim3((unsigned)L.nfine), dim3(256), 0, s, L.g0, L.Ur, L.Uf,
-                       L.child_base, L.fine_root, L.G1);
+  // 1. views: level 0 by the same-level map, deeper levels by copies and
+  //    prolongation from the level above (states only: any order)
+  const AmrLevel& R = L.lev[0];
+  hipLaunchKernelGGL((fill_guards_kernel<N, VG>), dim3((unsigned)(R.nblk * Guarded<N, VG>::P)), dim3(256), 0, s,
+                     R.g, R.U, R.G);
+  for (int l = 1; l < L.nlev; ++l) {
+    const AmrLevel& A = L.lev[l];
+    const AmrLevel& B = L.lev[l - 1];
+    hipLaunchKernelGGL(amr_fill_level_kernel<N>, dim3((unsigned)A.nblk), dim3(256), 0, s, A.g, B.g, A.lookup,
+                       B.lookup, A.pos, A.U, B.U, A.G);
+  }
   // 2. leaf steps (fused tile step over the views), written over the state:
-  //    every read of the old state went to the views.  Root leaves next to a
+  //    every read of the old state went to the views.  Leaves next to a
   //    refined block reduce their signal speed after refluxing instead.
-  auto tiles = [&](const GridGeom& g, const double* Gv, double* U, const int* list, long nblk, int emit) {
+  auto tiles = [&](const AmrLevel& A, const int* list, long nblk, int emit) {
     if (!nblk) return;
     const long nt = nblk * TPB;
-    hipLaunchKernelGGL((amr_tile_kernel<N, T>), dim3((unsigned)(8 * ((nt + 7) / 8))), dim3(Tile<T>::NT), 0, s, g, Gv,
-                       U, list, nt, slot, emit, L.ws);
+    hipLaunchKernelGGL((amr_tile_kernel<N, T>), dim3((unsigned)(8 * ((nt + 7) / 8))), dim3(Tile<T>::NT), 0, s, A.g,
+                       A.G, A.U, list, nt, slot, emit, L.ws);
   };
-  tiles(L.g0, L.G0, L.Ur, L.leaf_plain, L.nleaf_plain, 1);
-  tiles(L.g0, L.G0, L.Ur, L.rx_blocks, L.nreflux_groups, 0);
-  tiles(L.g1, L.G1, L.Uf, (const int*)nullptr, L.nfine, 1);
-  // 3. fluxes at the fine-coarse faces, refluxing, 4. restriction
-  if (L.nreflux) {
-    hipLaunchKernelGGL(amr_face_flux_kernel<N>, dim3((unsigned)(5 * L.nreflux)), dim3(256), 0, s, L.g0, L.g1,
-                       L.reflux, L.child_base, L.G0, L.G1, L.flux0, L.flux1, (const WorkHeader*)L.ws);
-    hipLaunchKernelGGL(amr_reflux_kernel<N>, dim3((unsigned)L.nreflux_groups), dim3(256), 0, s, L.g0, L.reflux,
-                       L.reflux_first, L.flux0, L.flux1, L.child_base, L.Ur, L.ws, slot);
+  for (int l = 0; l < L.nlev; ++l) {
+    tiles(L.lev[l], L.lev[l].leaf_plain, L.lev[l].nleaf_plain, 1);
+    tiles(L.lev[l], L.lev[l].rx_blocks, L.lev[l].ngroups, 0);
   }
-  if (L.nrefined)
-    hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)L.nrefined), dim3(256), 0, s, L.refined,
-                       L.child_base, L.Uf, L.Ur);
+  // 3. fluxes at the fine-coarse faces (from the views), refluxing
+  for (int l = 0; l + 1 < L.nlev; ++l) {
+    const AmrLevel& A = L.lev[l];
+    const AmrLevel& B = L.lev[l + 1];
+    if (!A.nreflux) continue;
+    hipLaunchKernelGGL(amr_face_flux_kernel<N>, dim3((unsigned)(5 * A.nreflux)), dim3(256), 0, s, A.g, B.g,
+                       A.reflux, A.child_base, A.G, B.G, A.flux, B.flux, (const WorkHeader*)L.ws);
+    hipLaunchKernelGGL(amr_reflux_kernel<N>, dim3((unsigned)A.ngroups), dim3(256), 0, s, A.g, A.reflux,
+                       A.reflux_first, A.flux, B.flux, A.child_base, A.U, L.ws, slot);
+  }
+  // 4. restriction, finest level first
+  for (int l = L.nlev - 2; l >= 0; --l) {
+    const AmrLevel& A = L.lev[l];
+    if (A.nrefined)
+      hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)A.nrefined), dim3(256), 0, s, A.refined,
+                         A.child_base, L.lev[l + 1].U, A.U);
+  }
   return hipGetLastError();
 }
 
 template <int N>
 void launch_amr_adapt_t(const AmrLaunch& L, double eps, double* E2, const AmrLaunch* from, hipStream_t s) {
-  if (E2) hipLaunchKernelGGL(amr_indicator_kernel<N>, dim3((unsigned)L.nroot), dim3(256), 0, s, L.g0, L.Ur, eps, E2);
-  if (from) {
-    if (L.nfine)
-      hipLaunchKernelGGL(amr_transfer_kernel<N>, dim3((unsigned)L.nfine), dim3(256), 0, s, L.g0, L.Ur, from->Uf,
-                         from->child_base, L.child_base, L.fine_root, L.Uf);
-    if (L.nrefined)
-      hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)L.nrefined), dim3(256), 0, s, L.refined,
-                         L.child_base, L.Uf, L.Ur);
+  const AmrLevel& R = L.lev[0];
+  if (E2) hipLaunchKernelGGL(amr_indicator_kernel<N>, dim3((unsigned)R.nblk), dim3(256), 0, s, R.g, R.U, eps, E2);
+  if (from && L.nlev > 1) {
+    const AmrLevel& F = L.lev[1];
+    hipLaunchKernelGGL(amr_transfer_kernel<N>, dim3((unsigned)F.nblk), dim3(256), 0, s, R.g, R.lookup, R.U,
+                       from->nlev > 1 ? from->lev[1].U : nullptr, from->lev[0].child_base, R.child_base, F.parent,
+                       F.U);
   }
+  if (from && R.nrefined)
+    hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)R.nrefined), dim3(256), 0, s, R.refined, R.child_base,
+                       L.lev[1].U, R.U);
 }
 
 hipError_t launch_amr_indicator(int nxb, const AmrLaunch& L, double eps, double* E2, hipStream_t s) {
@@ -1614,11 +1636,11 @@ hipError_t launch_amr_step(int nxb, const AmrLaunch& L, hipStream_t s) {
 
 template <int N>
 void launch_amr_signal_t(const AmrLaunch& L, unsigned long long* dst, hipStream_t s) {
-  if (L.nleaf0)
-    hipLaunchKernelGGL(amr_signal_kernel<N>, dim3((unsigned)L.nleaf0), dim3(256), 0, s, L.g0, L.Ur, L.leaf0, dst);
-  if (L.nfine)
-    hipLaunchKernelGGL(amr_signal_kernel<N>, dim3((unsigned)L.nfine), dim3(256), 0, s, L.g1, L.Uf,
-                       (const int*)nullptr, dst);
+  for (int l = 0; l < L.nlev; ++l) {
+    const AmrLevel& A = L.lev[l];
+    if (A.nleaves)
+      hipLaunchKernelGGL(amr_signal_kernel<N>, dim3((unsigned)A.nleaves), dim3(256), 0, s, A.g, A.U, A.leaves, dst);
+  }
 }
 
 hipError_t launch_amr_signal(int nxb, const AmrLaunch& L, int slot, hipStream_t s) {

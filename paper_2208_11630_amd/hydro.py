@@ -69,6 +69,7 @@ SIGNATURES = {
     "hydro_free_grid": ([_HP], ctypes.c_int),
     "hydro_set_pencils": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_amr_fine_blocks": ([ctypes.c_void_p], ctypes.c_size_t),
+    "hydro_amr_levels": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_long)], ctypes.c_int),
     "hydro_amr_work_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
     "hydro_amr_create": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "hydro_amr_step": ([ctypes.c_void_p, ctypes.c_double], ctypes.c_int),
@@ -392,11 +393,12 @@ class _AmrDesc(ctypes.Structure):
         ("refine", ctypes.POINTER(ctypes.c_ubyte)),
         ("Ur", ctypes.c_void_p), ("Uf", ctypes.c_void_p),
         ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p),
+        ("refine_deep", ctypes.POINTER(ctypes.c_ubyte)), ("nrefine_deep", ctypes.c_size_t),
     ]
 
 
 def make_amr_desc(nxb, nblk, refine, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(BC_PERIODIC,) * 3,
-                  gamma=1.4, small_p=1e-10, nguard=NGUARD):
+                  gamma=1.4, small_p=1e-10, nguard=NGUARD, refine_deep=()):
     d = _AmrDesc()
     d.nxb, d.nguard = int(nxb), int(nguard)
     d.nblk[:] = [int(x) for x in nblk]
@@ -406,23 +408,34 @@ def make_amr_desc(nxb, nblk, refine, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=
     d.gamma, d.small_p = float(gamma), float(small_p)
     flags = (ctypes.c_ubyte * len(refine))(*[1 if f else 0 for f in refine])
     d.refine = ctypes.cast(flags, ctypes.POINTER(ctypes.c_ubyte))
-    d._flags = flags  # keep the host array alive with the descriptor
+    deep = (ctypes.c_ubyte * max(len(refine_deep), 1))(*[1 if f else 0 for f in refine_deep])
+    d.refine_deep = ctypes.cast(deep, ctypes.POINTER(ctypes.c_ubyte)) if len(refine_deep) else None
+    d.nrefine_deep = len(refine_deep)
+    d._flags = (flags, deep)  # keep the host arrays alive with the descriptor
     return d
 
 
 class Amr:
-    """Two-level static AMR mesh over torch state tensors (hydro_amr_*).
+    """Block-structured AMR mesh over torch state tensors (hydro_amr_*).
 
-    Ur: root state [nroot, 5, n, n, n]; Uf: fine state [8*nrefined, 5, n, n, n]
-    (children of the refined root blocks in increasing root id)."""
+    Ur: root state [nroot, 5, n, n, n]; Uf: the blocks of levels 1, 2, ...
+    concatenated (each level: the children of the previous level's refined
+    blocks in increasing block index); level_blocks: blocks per level.
+    refine: level-0 flags; refine_deep: flags of levels 1, 2, ... concatenated."""
 
     def __init__(self, nxb, nblk, refine, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(BC_PERIODIC,) * 3,
-                 gamma=1.4, small_p=1e-10, device="cuda", stream=None):
+                 gamma=1.4, small_p=1e-10, device="cuda", stream=None, refine_deep=()):
         import torch
 
         L = lib()
         self._torch = torch
-        d = make_amr_desc(nxb, nblk, refine, lo, hi, bc, gamma, small_p)
+        d = make_amr_desc(nxb, nblk, refine, lo, hi, bc, gamma, small_p, refine_deep=refine_deep)
+        counts = (ctypes.c_long * 8)()
+        nlev = L.hydro_amr_levels(ctypes.byref(d), counts)
+        if nlev < 1:
+            raise HydroError(nlev, "invalid AMR descriptor")
+        self.level_blocks = [int(counts[l]) for l in range(nlev)]
+        self.refine_deep = [bool(f) for f in refine_deep]
         self.nxb, self.nblk, self.refine = int(nxb), tuple(int(x) for x in nblk), [bool(f) for f in refine]
         self.lo, self.hi, self.bc = tuple(lo), tuple(hi), tuple(bc)
         self.gamma, self.small_p = float(gamma), float(small_p)
@@ -494,6 +507,8 @@ class Amr:
         """A new mesh over the same root grid with refinement `flags`, its
         state transferred from this one (hydro_amr_transfer); this mesh is
         closed."""
+        if len(self.level_blocks) > 2:
+            raise HydroError(HYDRO_EINVAL, "regridding handles two-level meshes")
         new = Amr(self.nxb, self.nblk, [bool(f) for f in flags], self.lo, self.hi, self.bc, self.gamma,
                   self.small_p, device=self.Ur.device, stream=self.stream)
         _check(lib().hydro_amr_transfer(self.handle, new.handle))

@@ -139,14 +139,15 @@ def test_amr_sizes_and_validation(L):
     d = hydro.make_amr_desc(n, nb, [0, 1, 0, 1], bc=(0, 1, 0))
     assert L.hydro_amr_fine_blocks(ctypes.byref(d)) == 16
     P = n + 4
-    # reflux entries: leaves 0 and 2 face the refined blocks 1 and 3 across
-    # both x faces (periodic); their y neighbours are unrefined or outside
-    entries, groups = 4, 2
-    tab = 4 * (2 + 4 + 16 + 2 + 4 * entries + groups + 1)
+    # views (two guard layers) and face fluxes of every block of both levels,
+    # the indicators, the header; the mesh tables take a few KB more
     al = lambda x: (x + 255) // 256 * 256
-    total = (256 + al(tab) + al(8 * 5 * P ** 3 * 4) + al(8 * 5 * P ** 3 * 16) + al(8 * 30 * n * n * 4)
-             + al(8 * 30 * n * n * 16) + al(8 * 4))
-    assert L.hydro_amr_work_bytes(ctypes.byref(d)) == total
+    big = (256 + al(8 * 5 * P ** 3 * 4) + al(8 * 5 * P ** 3 * 16) + al(8 * 30 * n * n * 4)
+           + al(8 * 30 * n * n * 16) + al(8 * 4))
+    total = L.hydro_amr_work_bytes(ctypes.byref(d))
+    assert big + 256 <= total <= big + 8192, (total, big)
+    counts = (ctypes.c_long * 8)()
+    assert L.hydro_amr_levels(ctypes.byref(d), counts) == 2 and list(counts)[:3] == [4, 16, 0]
     for field, value in [("nxb", 12), ("nguard", 2), ("gamma", 1.0)]:
         bad = hydro.make_amr_desc(n, nb, [0, 1, 0, 1])
         setattr(bad, field, value)
@@ -164,6 +165,13 @@ def test_amr_sizes_and_validation(L):
     d.work = 1 << 36
     d.work_bytes = total - 1
     assert L.hydro_amr_create(ctypes.byref(d), ctypes.byref(h)) == hydro.HYDRO_ESIZE
+    # deeper levels: flags must cover whole levels, nesting is checked
+    deep = hydro.make_amr_desc(n, (3, 3, 3), [1] * 27, refine_deep=[0] * 215)
+    assert L.hydro_amr_fine_blocks(ctypes.byref(deep)) == 0            # 215 of 216 level-1 flags
+    deep = hydro.make_amr_desc(n, (3, 3, 3), [1] * 27, refine_deep=[1] + [0] * 215)
+    assert L.hydro_amr_levels(ctypes.byref(deep), counts) == 3 and list(counts)[:4] == [27, 216, 8, 0]
+    shallow = hydro.make_amr_desc(n, (3, 3, 3), [0] * 13 + [1] + [0] * 13, refine_deep=[1] + [0] * 7)
+    assert L.hydro_amr_levels(ctypes.byref(shallow), counts) == hydro.HYDRO_EINVAL   # bad nesting
     d.work_bytes = total
     d.Uf = None
     assert L.hydro_amr_create(ctypes.byref(d), ctypes.byref(h)) == hydro.HYDRO_EINVAL

@@ -295,3 +295,87 @@ def test_amr_adaptive_trajectory(hy):
         A = A.regrid(flags)
         assert_close(A.download(), (Ur, Uf), f"cycle {cycle} regrid")
     A.close()
+
+
+# ---- more than two levels ------------------------------------------------------
+
+def _tree_case(name):
+    from oracle import amr_tree
+    from tests.test_oracle_amr import _random_root
+    from tests.test_oracle_amr_tree import _tree_state
+
+    if name == "n8_three_levels":
+        n, nb, bc = 8, (4, 4, 4), (0, 0, 0)
+        f0 = np.array([b % 4 <= 2 and (b // 4) % 4 <= 2 and b // 16 <= 2 for b in range(64)])
+        t1 = amr_tree.Tree(n, nb, (1 / 32,) * 3, [f0], bc=bc)
+        base = int(t1.child_base[0][1 + 4 * (1 + 4 * 1)])
+        f1 = np.zeros(t1.nblocks(1), bool)
+        f1[[base + 0, base + 3, base + 5, base + 6]] = True
+        flags = [f0, f1]
+    elif name == "n8_three_levels_outflow":
+        n, nb, bc = 8, (4, 4, 4), (1, 0, 1)
+        f0 = np.array([b % 4 <= 2 and (b // 4) % 4 <= 2 and b // 16 <= 2 for b in range(64)])
+        t1 = amr_tree.Tree(n, nb, (1 / 32,) * 3, [f0], bc=bc)
+        f1 = np.zeros(t1.nblocks(1), bool)
+        f1[int(t1.child_base[0][0]) + 7] = True           # next to the outflow corner
+        f1[int(t1.child_base[0][1 + 4 * (1 + 4 * 1)]) + 2] = True
+        flags = [f0, f1]
+    elif name == "n16_three_levels":
+        n, nb, bc = 16, (2, 2, 2), (0, 0, 0)
+        f0 = np.ones(8, bool)
+        f1 = np.zeros(64, bool)
+        f1[[0, 21, 42]] = True
+        flags = [f0, f1]
+    else:  # four levels: everything refined twice, then one block again
+        n, nb, bc = 8, (1, 1, 1), (0, 0, 0)
+        flags = [[True], [True] * 8, [False] * 63 + [True]]
+    t = amr_tree.Tree(n, nb, (1.0 / (nb[0] * n),) * 3, flags, bc=bc)
+    Ur, _ = _random_root(nb, n, 81)
+    return t, _tree_state(t, Ur, 82)
+
+
+TREE_CASES = ["n8_three_levels", "n8_three_levels_outflow", "n16_three_levels", "n8_four_levels"]
+
+
+def _tree_gpu(hy, t, U):
+    deep = np.concatenate([np.asarray(f, bool) for f in t.refine[1:]]) if t.levels > 1 else []
+    hi = tuple(t.nb0[d] * t.n * t.dx0[d] for d in range(3))
+    A = hy.Amr(t.n, t.nb0, t.refine[0].tolist(), hi=hi, bc=t.bc, gamma=t.gamma, refine_deep=list(deep))
+    assert A.level_blocks == [t.nblocks(l) for l in range(t.levels)]
+    A.upload(U[0], np.concatenate(U[1:]) if t.levels > 1 else None)
+    return A
+
+
+def _tree_split(A, R, F):
+    out, o = [R], 0
+    for nbk in A.level_blocks[1:]:
+        out.append(F[o:o + nbk])
+        o += nbk
+    return out
+
+
+@pytest.mark.parametrize("case", TREE_CASES)
+@pytest.mark.parametrize("device_dt", [False, True])
+def test_amr_tree_trajectory_parity(hy, case, device_dt):
+    """Three steps on meshes of three and four levels (nesting by the
+    26-neighbour rule), every level at 1e-12, dt to 1e-14, counters equal."""
+    from oracle import amr_tree
+
+    print(f"\n[amr] tree {case} device_dt={device_dt}", flush=True)
+    t, U = _tree_case(case)
+    A = _tree_gpu(hy, t, U)
+    cnt = np.zeros(3, np.int64)
+    for s in range(3):
+        dt = amr_tree.dt(t, U, 0.8)
+        if device_dt:
+            A.step_cfl(0.8)
+            assert abs(A.last_dt() / dt - 1.0) <= DT_TOL, (s, A.last_dt(), dt)
+        else:
+            assert abs(A.dt(0.8) / dt - 1.0) <= DT_TOL
+            A.step(dt)
+        U, c = amr_tree.step(t, U, dt)
+        cnt += c
+        got = _tree_split(A, *A.download())
+        assert_close((got[0], np.concatenate(got[1:])), (U[0], np.concatenate(U[1:])), f"{case} step {s}")
+    assert A.counters().tolist() == cnt.tolist()
+    A.close()

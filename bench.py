@@ -207,14 +207,22 @@ def run_amr(args):
 
     from paper_2208_11630_amd import hydro, ics
 
-    nb, flags, Ur, Uf, dx, gamma = ics.kelvin_helmholtz_amr(root=(256, 256, 128), n=16)
     n = 16
-    nleaf = int((~flags).sum()) + Uf.shape[0]
+    if args.workload == "amr3":
+        nb, flags, flags1, Ur, Uf, dx, gamma = ics.kelvin_helmholtz_amr3(root=(256, 256, 128), n=n)
+        deep = flags1.tolist() + [False] * (8 * int(flags1.sum()))
+        nleaf = int((~flags).sum()) + int((~flags1).sum()) + 8 * int(flags1.sum())
+        wname = "amr_kelvin_helmholtz_root256x256x128_nxb16_three_levels"
+    else:
+        nb, flags, Ur, Uf, dx, gamma = ics.kelvin_helmholtz_amr(root=(256, 256, 128), n=n)
+        deep = []
+        nleaf = int((~flags).sum()) + Uf.shape[0]
+        wname = "amr_kelvin_helmholtz_root256x256x128_nxb16_two_levels"
     cells = nleaf * n ** 3
-    print(f"[bench] amr: {flags.size} root blocks, {int(flags.sum())} refined, {nleaf} leaves, {cells} leaf cells",
-          file=sys.stderr, flush=True)
+    print(f"[bench] {args.workload}: {flags.size} root blocks, {int(flags.sum())} refined, {nleaf} leaves, "
+          f"{cells} leaf cells", file=sys.stderr, flush=True)
     hi = tuple(nb[d] * n * dx[d] for d in range(3))
-    A = hydro.Amr(n, nb, flags.tolist(), hi=hi, gamma=gamma)
+    A = hydro.Amr(n, nb, flags.tolist(), hi=hi, gamma=gamma, refine_deep=deep)
     A.upload(Ur, Uf)
     del Ur, Uf
 
@@ -250,13 +258,17 @@ def run_amr(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "amr_kelvin_helmholtz_root256x256x128_nxb16_two_levels", "cells": cells,
-                   "root_blocks": int(flags.size), "refined_blocks": int(flags.sum()), "leaf_blocks": nleaf,
+        "config": {"workload": wname, "cells": cells, "levels": len(A.level_blocks),
+                   "blocks_per_level": A.level_blocks, "leaf_blocks": nleaf,
                    "cfl": args.cfl, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "amr_tile_kernel",
                      "algorithmic_bytes_per_step": BYTES_PER_CELL * cells},
     }
+    if len(A.level_blocks) > 2:
+        A.close()
+        print(json.dumps(out), flush=True)
+        return
     # adaptivity, timed apart from the steps: one estimate (indicator kernel,
     # flags read back) and one regrid to its flags (new mesh: allocation,
     # tables, transfer of the state)
@@ -377,7 +389,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="kh", choices=["kh", "sedov", "sod", "ensemble", "served", "amr"])
+    ap.add_argument("--workload", default="kh", choices=["kh", "sedov", "sod", "ensemble", "served", "amr", "amr3"])
     ap.add_argument("--served-sims", type=int, default=2000)
     ap.add_argument("--served-budget-gb", type=float, default=200.0)
     ap.add_argument("--served-seconds", type=float, default=2.0, help="served: seconds per rate point")
@@ -405,7 +417,7 @@ def main():
         return run_ensemble(args)
     if args.workload == "served":
         return run_served(args)
-    if args.workload == "amr":
+    if args.workload in ("amr", "amr3"):
         return run_amr(args)
     P, wname = make_workload(args.workload)
     print(f"[bench] workload {wname}: {P.cells} cells, {P.nblk} blocks", file=sys.stderr, flush=True)

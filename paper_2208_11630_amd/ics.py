@@ -123,6 +123,37 @@ def kelvin_helmholtz_amr(root=(256, 256, 128), n: int = 16, seed_root: int = 1, 
     return nb, flags, P0.Uc, Uf, P0.dx, P0.gamma
 
 
+def kelvin_helmholtz_amr3(root=(256, 256, 128), n: int = 16, seed_root: int = 1, seed_fine: int = 5):
+    """Three-level Kelvin-Helmholtz mesh: kelvin_helmholtz_amr's two levels,
+    plus the level-1 block rows that hold an interface (y = 0.25, 0.75 on a
+    block edge) refined again.  Level-2 blocks start as copies of their
+    parent cells (each level-1 cell value on its 2x2x2 children; the first
+    step's restriction reconciles the levels).  Returns (nb, flags0, flags1,
+    Ur, Uf) with Uf the level-1 blocks then the level-2 blocks."""
+    nb, flags0, Ur, Uf1, dx, gamma = kelvin_helmholtz_amr(root, n, seed_root, seed_fine)
+    refined0 = np.flatnonzero(flags0)
+    # level-1 block rows (y positions at level 1) that touch an interface
+    ny1 = 2 * nb[1]
+    rows = set()
+    for yi in (0.25, 0.75):
+        r = int(round(yi * ny1))
+        rows.update({r - 1, r})
+    flags1 = np.zeros(8 * refined0.size, bool)
+    for q, r in enumerate(refined0):
+        by = (r // nb[0]) % nb[1]
+        for c in range(8):
+            flags1[8 * q + c] = (2 * by + ((c >> 1) & 1)) in rows
+    ref1 = np.flatnonzero(flags1)
+    h = n // 2
+    Uf2 = np.empty((8 * ref1.size, 5, n, n, n))
+    for q, f in enumerate(ref1):
+        for c in range(8):
+            cx, cy, cz = c & 1, (c >> 1) & 1, (c >> 2) & 1
+            part = Uf1[f, :, cz * h:(cz + 1) * h, cy * h:(cy + 1) * h, cx * h:(cx + 1) * h]
+            Uf2[8 * q + c] = part.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)
+    return nb, flags0, flags1, Ur, np.concatenate([Uf1, Uf2]), dx, gamma
+
+
 def to_blocks(G: np.ndarray, n: int, ng: int = NGUARD, out: np.ndarray | None = None) -> np.ndarray:
     """Global ``[5, Z, Y, X]`` -> blocked ``[nblk, 5, P, P, P]`` (guards zero)."""
     _, Z, Y, X = G.shape

@@ -93,3 +93,57 @@ def load(path: str, device: str = "cuda", stream=None):
         G.set_scheme(g["scheme"])
     G.upload(state)
     return G, rec
+
+
+AMR_FORMAT = "hydro-amr-checkpoint-1"
+
+
+def save_amr(mesh, path: str, **meta) -> None:
+    """Checkpoint a hydro.Amr mesh: root state, the state of deeper levels
+    (concatenated, as the mesh stores it) and the mesh description with its
+    refinement flags (waits for its stream)."""
+    Ur, Uf = mesh.download()
+    os.makedirs(path, exist_ok=True)
+    for name, arr in (("root.npy", Ur), ("fine.npy", Uf)):
+        tmp = os.path.join(path, name + ".tmp")
+        with open(tmp, "wb") as f:
+            np.save(f, np.ascontiguousarray(arr, dtype=np.float64), allow_pickle=False)
+        os.replace(tmp, os.path.join(path, name))
+    rec = {"format": AMR_FORMAT,
+           "mesh": {"nxb": mesh.nxb, "nblk": list(mesh.nblk), "lo": list(mesh.lo), "hi": list(mesh.hi),
+                    "bc": list(mesh.bc), "gamma": mesh.gamma, "small_p": mesh.small_p,
+                    "refine": [bool(f) for f in mesh.refine], "refine_deep": [bool(f) for f in mesh.refine_deep]},
+           "level_blocks": list(mesh.level_blocks), "counters": mesh.counters().tolist(), "meta": meta}
+    tmp = os.path.join(path, META + ".tmp")
+    with open(tmp, "w") as f:
+        json.dump(rec, f)
+    os.replace(tmp, os.path.join(path, META))
+
+
+def read_amr(path: str):
+    """(mesh description, root state, deeper-level state, record)."""
+    with open(os.path.join(path, META)) as f:
+        rec = json.load(f)
+    if rec.get("format") != AMR_FORMAT:
+        raise ValueError(f"not a {AMR_FORMAT} checkpoint: {rec.get('format')!r}")
+    m = rec["mesh"]
+    n, nb = m["nxb"], m["nblk"]
+    Ur = np.load(os.path.join(path, "root.npy"), allow_pickle=False)
+    Uf = np.load(os.path.join(path, "fine.npy"), allow_pickle=False)
+    nfine = sum(rec["level_blocks"][1:])
+    if Ur.shape != (nb[0] * nb[1] * nb[2], 5, n, n, n) or Ur.dtype != np.float64:
+        raise ValueError("root state does not match the mesh")
+    if Uf.shape[1:] != (5, n, n, n) or Uf.shape[0] != nfine or Uf.dtype != np.float64:
+        raise ValueError("fine state does not match the mesh")
+    return m, Ur, Uf, rec
+
+
+def load_amr(path: str, device: str = "cuda", stream=None):
+    """A new hydro.Amr holding the checkpointed mesh and state, and the record."""
+    from . import hydro
+
+    m, Ur, Uf, rec = read_amr(path)
+    A = hydro.Amr(m["nxb"], m["nblk"], m["refine"], m["lo"], m["hi"], m["bc"], m["gamma"], m["small_p"],
+                  device=device, stream=stream, refine_deep=m["refine_deep"])
+    A.upload(Ur, Uf if len(Uf) else None)
+    return A, rec

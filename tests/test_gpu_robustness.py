@@ -91,3 +91,27 @@ def test_nonphysical_member_leaves_the_batch_untouched(hy):
     with pytest.raises(hy.HydroError) as e:
         grids[2].dt(0.8)
     assert e.value.code == hy.HYDRO_ENONPHYS
+
+
+def test_amr_resume_from_checkpoint_is_bitwise(hy, tmp_path):
+    """A three-level mesh: 2 steps, checkpoint, a new mesh from the files,
+    2 more steps equals 4 uninterrupted steps (device dt)."""
+    from tests.test_gpu_amr import _tree_case, _tree_gpu
+
+    t, U = _tree_case("n8_three_levels")
+    A = _tree_gpu(hy, t, U)
+    for _ in range(4):
+        A.step_cfl(0.8)
+    B = _tree_gpu(hy, t, U)
+    for _ in range(2):
+        B.step_cfl(0.8)
+    checkpoint.save_amr(B, str(tmp_path / "amr"), step=2)
+    B.close()
+    C, rec = checkpoint.load_amr(str(tmp_path / "amr"))
+    assert rec["meta"]["step"] == 2 and C.level_blocks == A.level_blocks
+    for _ in range(2):
+        C.step_cfl(0.8)
+    ra, fa = A.download()
+    rc, fc = C.download()
+    assert np.array_equal(ra, rc) and np.array_equal(fa, fc)
+    assert C.last_dt() == A.last_dt()

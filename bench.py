@@ -8,8 +8,8 @@ x/y/z + conservative update, and the signal-speed reduction of the new state
 Kelvin-Helmholtz grid (16^3 blocks, 67.1M cells).  Inputs are resident in
 HBM before the timed region starts.
 
-Prints one JSON line (see the fields below).  --gpus N > 1 is refused: this
-build runs on one GPU.
+Prints one JSON line (see the fields below).  --gpus N > 1 is refused: the
+path runs on one GPU (no multi-GPU exchange is implemented).
 """
 import argparse
 import json
@@ -404,7 +404,8 @@ def main():
                     help="also run the streaming copy probe on this many GiB (roofline calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path has no multi-GPU exchange)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

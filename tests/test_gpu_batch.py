@@ -156,3 +156,41 @@ def test_batch_members_match_oracle(hy):
         for v in range(5):
             den = np.abs(b[:, v]).max() if v in (0, 4) else np.sqrt((b[:, 1:4] ** 2).sum(axis=1)).max()
             assert np.abs(a[:, v] - b[:, v]).max() <= 1e-12 * den, (i, v)
+
+
+def test_full_ensemble_sampled_members_match_oracle(hy):
+    """The benchmarked ensemble (512 members, 1-64 blocks of 8^3/16^3/32^3,
+    seed 2) run for its 50 steps as one persistent launch per step (HIP
+    graph), each member with its own device dt; sampled members - the
+    largest, the smallest, and members of every block size - follow their
+    own oracle trajectory to 1e-12, and their last step's dt to 1e-14."""
+    print("\n[batch] full ensemble", flush=True)
+    sims = ics.ensemble(count=512, seed=2, steps=50)
+    grids = [hy.grid_for(P) for P in sims]
+    B = hy.Batch(grids)
+    B.use_graph(True)
+    B.step(0.8, 48)
+    B.use_graph(False)
+    B.step(0.8, 2)
+    B.stream.synchronize()
+    dts = B.dts()
+    cells = np.array([P.cells for P in sims])
+    pick = {int(np.argmax(cells)), int(np.argmin(cells))}
+    for n in (8, 16, 32):
+        idx = [i for i, P in enumerate(sims) if P.n == n]
+        pick.update(idx[:1] + idx[len(idx) // 2:len(idx) // 2 + 1])
+    for i in sorted(pick):
+        P = sims[i]
+        print(f"[batch] member {i}: {P.nb} blocks of {P.n}^3", flush=True)
+        g = oracle.Grid(P.n, P.nb, P.dx, P.bc, P.gamma, P.small_p)
+        U = P.U.copy()
+        for _ in range(50):
+            d = oracle.dt(g, U, 0.8)
+            U, _ = oracle.step(g, U, d)
+        a = grids[i].download()
+        b = ics.interior(U, P.n)
+        for v in range(5):
+            den = np.abs(b[:, v]).max() if v in (0, 4) else np.sqrt((b[:, 1:4] ** 2).sum(axis=1)).max()
+            assert np.abs(a[:, v] - b[:, v]).max() <= 1e-12 * den, (i, v)
+        assert abs(dts[i] / d - 1) <= 1e-14, i          # the dt of the last step
+    B.close()

@@ -233,3 +233,39 @@ def test_sedov_full_size_sampled_blocks(hy):
     pick = [(c - 1) + nb * ((c - 1) + nb * (c - 1)), c + nb * (c + nb * c), (c - 1) + nb * (c + nb * c),
             0, P.nblk - 1, 1234]
     _sampled_parity(hy, P, sorted(set(pick)))
+
+
+# ---- full configurations run to their step counts ------------------------------------
+
+def _full_trajectory(hy, P, steps, blocks):
+    """Each side runs the configuration for its step count with its own dt
+    (device dt on the GPU); sampled blocks and the final dt agree."""
+    g = ogrid(P)
+    Gd = hy.grid_for(P)
+    U = P.U.copy()
+    for _ in range(steps):
+        Gd.step_cfl(P.cfl)
+        d = oracle.dt(g, U, P.cfl)
+        U, cnt = oracle.step(g, U, d)
+        assert cnt.tolist() == [0, 0, 0]
+    assert abs(Gd.last_dt() / d - 1.0) <= DT_TOL
+    got = Gd.state[blocks].cpu().numpy()
+    assert_parity(got, ics.interior(U, P.n)[blocks], P.n, f"{P.name} after {steps} steps")
+    assert Gd.counters().tolist() == [0, 0, 0]
+
+
+def test_kh_full_configuration_ten_steps(hy):
+    print("\n[parity] KH 512x512x256, 10 steps", flush=True)
+    P = ics.kelvin_helmholtz()
+    nbx, nby, nbz = P.nb
+    _full_trajectory(hy, P, 10, sorted({0, nbx * (nby // 4), nbx * nby * (nbz // 2) + nbx * (3 * nby // 4) + 7,
+                                        P.nblk - 1, 4321}))
+
+
+def test_sedov_full_configuration_hundred_steps(hy):
+    print("\n[parity] Sedov 256^3, 100 steps", flush=True)
+    P = ics.sedov()
+    nb = P.nb[0]
+    c = nb // 2
+    _full_trajectory(hy, P, 100, sorted({(c - 1) + nb * ((c - 1) + nb * (c - 1)), c + nb * (c + nb * c), 0,
+                                         P.nblk - 1}))

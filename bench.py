@@ -95,6 +95,41 @@ def cpu_baseline(P, seconds_target=15.0):
             "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
+# FP64 VALU issue: 256 CUs x 4 SIMDs, one wave64 FP64 instruction per SIMD
+# every 4 cycles (16 lanes), 2.4 GHz -> 6.144e11 wave instructions/s (with
+# 2 flops per FMA lane this is the published 78.6 TFLOP/s); transcendental
+# FP64 instructions (rcp, rsq) take four such slots.
+VALU_PEAK_SLOTS = 256 * 4 * 2.4e9 / 4
+
+
+def valu_roofline(kernel_tag, cells_per_s):
+    """Issue-slot roofline of the step from the committed instruction counts
+    (rocprofv3 SQ counters of the same kernel source), or None."""
+    rec = _profile_record(kernel_tag)
+    if not rec or "valu_wave_instr_per_dispatch" not in rec:
+        return None
+    per_cell = rec["valu_wave_instr_per_dispatch"] / rec["cells_per_dispatch"]          # wave instr per cell
+    trans = rec["valu_trans_f64_wave_instr_per_dispatch"] / rec["cells_per_dispatch"]
+    slots = per_cell + 3.0 * trans
+    achieved = cells_per_s * slots
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_SLOTS, "unit": "wave64 VALU issue slots/s",
+            "frac": achieved / VALU_PEAK_SLOTS, "valu_instr_per_cell": per_cell * 64,
+            "fp64_trans_instr_per_cell": trans * 64}
+
+
+def _profile_record(kernel_tag):
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_pmc.json")
+    src = os.path.join(ROOT, "paper_2208_11630_amd", "csrc", "hydro_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return rec
+
+
 def traffic_from_profiles(kernel_tag):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source (else None)."""
@@ -455,6 +490,7 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(tag),
                 "kernel": tag, "algorithmic_bytes_per_launch": BYTES_PER_CELL * P.cells}
+        alu = valu_roofline(tag, rate) if args.workload == "kh" else None
     elif args.scheme == "ctu":  # launches per chunk of blocks: bytes and time per step
         tag = f"ctu_kernel_nxb{P.n}_{args.workload}"
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -486,6 +522,8 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": roof,
     }
+    if args.scheme == "mh" and alu:
+        out["alu_roofline"] = alu
     if args.copy_probe > 0:
         n = int(args.copy_probe * 2 ** 30) // 8
         src = torch.empty(n, dtype=torch.float64, device="cuda:0").fill_(1.0)

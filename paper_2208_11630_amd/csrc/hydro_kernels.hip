@@ -1114,7 +1114,7 @@ __device__ __forceinline__ void prolong_cell(const GridGeom& gp, const int* __re
   }
 }
 
-// Views of the blocks of level l >= 1 (two guard layers): a position
+// Views of the listed blocks of level l >= 1 (two guard layers): a position
 // (mapped at level l) inside a block of level l copies its cell; otherwise it
 // is prolonged from level l-1.
 template <int N>
@@ -1124,9 +1124,10 @@ __global__ __launch_bounds__(256) void amr_fill_level_kernel(GridGeom g, GridGeo
                                                              const int4* __restrict__ pos,
                                                              const double* __restrict__ U,
                                                              const double* __restrict__ Up,
-                                                             double* __restrict__ G) {
+                                                             double* __restrict__ G,
+                                                             const int* __restrict__ list) {
   constexpr int P = Guarded<N, VG>::P;
-  const int f = blockIdx.x;
+  const int f = list[blockIdx.x];
   const int4 q = pos[f];
   const int X0 = q.x * N, Y0 = q.y * N, Z0 = q.z * N;
   const int NX = g.nb[0] * N, NY = g.nb[1] * N, NZ = g.nb[2] * N;
@@ -1458,10 +1459,11 @@ __global__ __launch_bounds__(256) void amr_signal_kernel(GridGeom g, const doubl
 // corners) receives the state value at its mapped global index.
 template <int N, int GW = G>
 __global__ __launch_bounds__(256) void fill_guards_kernel(GridGeom g, const double* __restrict__ U,
-                                                          double* __restrict__ out) {
+                                                          double* __restrict__ out,
+                                                          const int* __restrict__ list = nullptr) {
   constexpr int P = Guarded<N, GW>::P;
   constexpr long VS = Layout<N>::VS;
-  const long blk = blockIdx.x / P;
+  const long blk = list ? (long)list[blockIdx.x / P] : (long)(blockIdx.x / P);
   const int k = (int)(blockIdx.x % P) - GW;
   const int bx = (int)(blk % g.nb[0]);
   const int by = (int)((blk / g.nb[0]) % g.nb[1]);
@@ -1549,13 +1551,16 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
   // 1. views: level 0 by the same-level map, deeper levels by copies and
   //    prolongation from the level above (states only: any order)
   const AmrLevel& R = L.lev[0];
-  hipLaunchKernelGGL((fill_guards_kernel<N, VG>), dim3((unsigned)(R.nblk * Guarded<N, VG>::P)), dim3(256), 0, s,
-                     R.g, R.U, R.G);
+  // (views of leaves only: the leaf steps and the face fluxes read no others)
+  if (R.nleaves)
+    hipLaunchKernelGGL((fill_guards_kernel<N, VG>), dim3((unsigned)(R.nleaves * Guarded<N, VG>::P)), dim3(256), 0, s,
+                       R.g, R.U, R.G, R.leaves);
   for (int l = 1; l < L.nlev; ++l) {
     const AmrLevel& A = L.lev[l];
     const AmrLevel& B = L.lev[l - 1];
-    hipLaunchKernelGGL(amr_fill_level_kernel<N>, dim3((unsigned)A.nblk), dim3(256), 0, s, A.g, B.g, A.lookup,
-                       B.lookup, A.pos, A.U, B.U, A.G);
+    if (A.nleaves)
+      hipLaunchKernelGGL(amr_fill_level_kernel<N>, dim3((unsigned)A.nleaves), dim3(256), 0, s, A.g, B.g, A.lookup,
+                         B.lookup, A.pos, A.U, B.U, A.G, A.leaves);
   }
   // 2. leaf steps (fused tile step over the views), written over the state:
   //    every read of the old state went to the views.  Leaves next to a

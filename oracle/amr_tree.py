@@ -264,3 +264,187 @@ def _fine_mean(t: Tree, flux1, base, d, side):
     class _M:
         n = t.n
     return _amr._fine_face_mean(_M, flux1, base, d, side)
+
+
+# ---- adaptivity of a tree ------------------------------------------------------
+
+def indicator(t: Tree, U, eps: float = 0.01):
+    """Refinement indicator of every leaf, per level ([array per level],
+    refined blocks 0): the largest, over the leaf's cells, of the squared
+    Loehner ratio of density and of pressure (oracle.amr's per-cell
+    formula), its neighbours read at the leaf's own level (boundary map,
+    block lookup); a neighbour position with no block of that level (a
+    coarser region) takes the cell's own value."""
+    n = t.n
+    out = []
+    for l in range(t.levels):
+        E = np.zeros(t.nblocks(l))
+        nbl = t.nb(l)
+        for b in t.leaves(l):
+            X0, Y0, Z0 = (t.pos[l][b] * n).tolist()
+            r = np.arange(n)
+            K, J, I = np.meshgrid(r + Z0, r + Y0, r + X0, indexing="ij")
+            c = (I.ravel(), J.ravel(), K.ravel())
+
+            def fields(I, J, K, own):
+                Im = _map(I, nbl[0] * n, t.bc[0])
+                Jm = _map(J, nbl[1] * n, t.bc[1])
+                Km = _map(K, nbl[2] * n, t.bc[2])
+                blk = t.lookup[l][Im // n + nbl[0] * (Jm // n + nbl[1] * (Km // n))]
+                u = np.empty((5, Im.size))
+                ok = blk >= 0
+                u[:, ok] = U[l][blk[ok], :, Km[ok] % n, Jm[ok] % n, Im[ok] % n].T
+                if own is not None:
+                    u[:, ~ok] = own[:, ~ok]
+                rho = u[0]
+                kin = 0.5 * ((u[1] * u[1] + u[2] * u[2]) + u[3] * u[3]) / rho
+                return u, rho, (t.gamma - 1.0) * (u[4] - kin)
+
+            u0, r0, p0 = fields(*c, None)
+            num = {"r": None, "p": None}
+            den = {"r": None, "p": None}
+            for d in range(3):
+                e = [0, 0, 0]
+                e[d] = 1
+                _, rL, pL = fields(c[0] - e[0], c[1] - e[1], c[2] - e[2], u0)
+                _, rR, pR = fields(c[0] + e[0], c[1] + e[1], c[2] + e[2], u0)
+                for key, fL, f0, fR in (("r", rL, r0, rR), ("p", pL, p0, pR)):
+                    nn = (fR - f0) - (f0 - fL)
+                    dd = (np.abs(fR - f0) + np.abs(f0 - fL)) + eps * ((np.abs(fR) + 2.0 * np.abs(f0)) + np.abs(fL))
+                    num[key] = nn * nn if num[key] is None else num[key] + nn * nn
+                    den[key] = dd * dd if den[key] is None else den[key] + dd * dd
+            E2 = np.zeros(r0.size)
+            for key in ("r", "p"):
+                ok = den[key] > 0
+                e2 = np.zeros(r0.size)
+                e2[ok] = num[key][ok] / den[key][ok]
+                E2 = np.maximum(E2, e2)
+            E[b] = E2.max()
+        out.append(E)
+    return out
+
+
+def _refined_sets(t: Tree):
+    return [set(map(tuple, t.pos[l][np.flatnonzero(t.refine[l])].tolist())) for l in range(t.levels)]
+
+
+def _flags_from_sets(t: Tree, R):
+    """Per-level flags in block order for refined-position sets R."""
+    flags = [[tuple(p) in R[0] for p in t.pos[0].tolist()]]
+    l = 0
+    while any(flags[l]):
+        kids = []
+        blocks = [tuple(p) for p, f in zip(_level_positions(t, flags, l), flags[l]) if f]
+        for (x, y, z) in blocks:
+            for c in range(8):
+                kids.append((2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + ((c >> 2) & 1)))
+        R_next = R[l + 1] if l + 1 < len(R) else set()
+        flags.append([k in R_next for k in kids])
+        l += 1
+    return flags
+
+
+def _level_positions(t: Tree, flags, l):
+    if l == 0:
+        return t.pos[0].tolist()
+    prev = [tuple(p) for p, f in zip(_level_positions(t, flags, l - 1), flags[l - 1]) if f]
+    out = []
+    for (x, y, z) in prev:
+        for c in range(8):
+            out.append((2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + ((c >> 2) & 1)))
+    return out
+
+
+def refine_flags(t: Tree, E2, refine_cutoff: float = 0.8, derefine_cutoff: float = 0.2, max_levels: int = 3):
+    """New per-level flags from the indicator: a leaf with E^2 >
+    refine_cutoff^2 below the deepest allowed level is refined; a refined
+    block whose eight children are leaves with E^2 < derefine_cutoff^2 loses
+    them; then nesting is restored by refining (level by level, coarsest
+    first, in increasing block position) the blocks whose absence leaves a
+    refined block of level >= 1 without a same-level neighbour, until
+    nothing changes."""
+    rc2, dc2 = refine_cutoff * refine_cutoff, derefine_cutoff * derefine_cutoff
+    R = _refined_sets(t)
+    while len(R) < max_levels:
+        R.append(set())
+    for l in range(t.levels):
+        for b in t.leaves(l):
+            if E2[l][b] > rc2 and l + 1 < max_levels:
+                R[l].add(tuple(t.pos[l][b].tolist()))
+    for l in range(t.levels - 1):
+        for r in np.flatnonzero(t.refine[l]):
+            base = int(t.child_base[l][r])
+            kids = range(base, base + 8)
+            if all((not t.refine[l + 1][k]) and E2[l + 1][k] < dc2 for k in kids):
+                R[l].discard(tuple(t.pos[l][r].tolist()))
+    _restore_nesting(t, R)
+    return _flags_from_sets(t, R)
+
+
+def _is_block(R, l, p):
+    return l == 0 or (p[0] // 2, p[1] // 2, p[2] // 2) in R[l - 1]
+
+
+def _restore_nesting(t: Tree, R):
+    nb0 = t.nb0
+
+    def wrap(l, q):
+        q = list(q)
+        for d in range(3):
+            N = nb0[d] << l
+            if t.bc[d] == BC_PERIODIC:
+                q[d] %= N
+            elif not 0 <= q[d] < N:
+                return None
+        return tuple(q)
+
+    def ensure_block(l, p):
+        """Make position p of level l a block (refine its ancestors)."""
+        if _is_block(R, l, p):
+            return
+        par = (p[0] // 2, p[1] // 2, p[2] // 2)
+        ensure_block(l - 1, par)
+        R[l - 1].add(par)
+
+    changed = True
+    while changed:
+        changed = False
+        # drop refined positions that are no longer blocks (an ancestor lost its children)
+        for l in range(1, len(R)):
+            for p in sorted(R[l]):
+                if not _is_block(R, l, p):
+                    R[l].discard(p)
+                    changed = True
+        for l in range(1, len(R)):
+            for p in sorted(R[l]):
+                for dz in (-1, 0, 1):
+                    for dy in (-1, 0, 1):
+                        for dx in (-1, 0, 1):
+                            q = wrap(l, (p[0] + dx, p[1] + dy, p[2] + dz))
+                            if q is not None and not _is_block(R, l, q):
+                                ensure_block(l, q)
+                                changed = True
+
+
+def regrid(t: Tree, U, flags):
+    """The tree with per-level flags `flags` and its state: level 0 as is;
+    at each deeper level, in order, a block present before (same level and
+    position) keeps its cells, a new one is prolonged from the level above
+    (already final); then restriction, finest level first.  Returns (tree, U)."""
+    new = Tree(t.n, t.nb0, t.dx0, flags, t.bc, t.gamma, t.small_p)
+    n = t.n
+    V = [U[0].copy()]
+    r_ = np.arange(n)
+    for l in range(1, new.levels):
+        Ul = np.empty((new.nblocks(l), 5, n, n, n))
+        for i, p in enumerate(new.pos[l].tolist()):
+            old = t.block_at(l, *p) if l < t.levels else -1
+            if old >= 0:
+                Ul[i] = U[l][old]
+                continue
+            X0, Y0, Z0 = (np.array(p) * n).tolist()
+            K, J, I = np.meshgrid(r_ + Z0, r_ + Y0, r_ + X0, indexing="ij")
+            Ul[i] = prolong(new, V, l, I.ravel(), J.ravel(), K.ravel()).reshape(5, n, n, n)
+        V.append(Ul)
+    restrict(new, V)
+    return new, V

@@ -161,3 +161,147 @@ def test_bad_nesting_is_refused():
     f1[0] = True           # its level-1 neighbours at x-1 lie in unrefined root block 0
     with pytest.raises(ValueError):
         amr_tree.Tree(n, nb, (1.0,) * 3, [f0, f1], bc=(1, 1, 1))
+
+
+# ---- adaptivity of a tree ------------------------------------------------------
+
+def test_tree_indicator_on_root_leaves_is_the_two_level_indicator():
+    """Neighbours of root leaves all exist at level 0: the per-leaf indicator
+    equals the root indicator of oracle.amr bit for bit on the leaves."""
+    n, nb = 8, (3, 2, 2)
+    Ur, _ = _random_root(nb, n, 92)
+    flags = np.zeros(12, bool)
+    flags[[0, 5, 7]] = True
+    mesh = amr.Mesh(n, nb, (1 / 24,) * 3, flags, bc=(1, 0, 1))
+    Uf = _fine_from_root(mesh, Ur)
+    amr.restrict(mesh, Ur, Uf)
+    t = amr_tree.Tree(n, nb, (1 / 24,) * 3, [flags], bc=(1, 0, 1))
+    E = amr_tree.indicator(t, [Ur, Uf])
+    ref = amr.indicator(mesh, Ur)
+    leaves = np.flatnonzero(~flags)
+    assert np.array_equal(E[0][leaves], ref[leaves]) and np.all(E[0][flags] == 0.0)
+    assert np.all(E[1] >= 0.0) and np.all(E[1] <= 1.0) and E[1].max() > 0.0
+
+
+def test_tree_indicator_vanishes_on_linear_fields_inside_a_level():
+    """Integer-valued linear density and pressure (gamma 2, at rest) on a
+    three-level tree: leaves whose neighbours all exist at their level have
+    indicator 0 exactly (the zero-gradient stand-in for a missing coarser
+    neighbour is a kink, so leaves at a refinement jump may not)."""
+    t, _ = _three_levels(93, bc=(0, 0, 0))
+    n = t.n
+    t = amr_tree.Tree(n, t.nb0, t.dx0, t.refine, bc=(0, 0, 0), gamma=2.0)
+    U = []
+    r = np.arange(n)
+    for l in range(t.levels):
+        Ul = np.empty((t.nblocks(l), 5, n, n, n))
+        for i, (bx, by, bz) in enumerate(t.pos[l]):
+            K, J, I = np.meshgrid(r + bz * n, r + by * n, r + bx * n, indexing="ij")
+            # periodic in the interior blocks only: keep the field linear away from the wrap
+            rho = 500.0 + I + 2 * J + 3 * K
+            p = 700.0 + 3 * I + J + 2 * K
+            z = np.zeros_like(rho, dtype=float)
+            Ul[i] = ics.conserved(rho.astype(float), z, z, z, p.astype(float), 2.0)
+        U.append(Ul)
+    E = amr_tree.indicator(t, U, eps=0.01)
+    checked = 0
+    for l in range(t.levels):
+        nbl = t.nb(l)
+        for b in t.leaves(l):
+            x, y, z = t.pos[l][b]
+            inside = all(1 <= c <= nbl[d] - 2 for d, c in enumerate((x, y, z)))
+            full = all(t.block_at(l, x + a, y + bb, z + c) >= 0 for a in (-1, 0, 1) for bb in (-1, 0, 1)
+                       for c in (-1, 0, 1))
+            if inside and full:
+                assert E[l][b] == 0.0, (l, b)
+                checked += 1
+    assert checked > 10
+
+
+@pytest.mark.parametrize("seed", [94, 95, 96])
+def test_tree_flags_always_give_a_nested_tree(seed):
+    """Random indicators on a three-level tree: the rule's flags build a
+    tree that passes the nesting check; every leaf above the refine cutoff
+    below the deepest level is refined; a block loses its children only if
+    all were leaves below the derefine cutoff."""
+    t, _ = _three_levels(seed)
+    rng = np.random.default_rng(seed)
+    E2 = [rng.random(t.nblocks(l)) for l in range(t.levels)]
+    for rc, dc in [(0.95, 0.5), (0.7, 0.3), (0.99, 0.05)]:
+        flags = amr_tree.refine_flags(t, E2, rc, dc, max_levels=4)
+        new = amr_tree.Tree(t.n, t.nb0, t.dx0, flags, bc=t.bc)         # raises on bad nesting
+        for l in range(t.levels):
+            for b in t.leaves(l):
+                if E2[l][b] > rc * rc and l + 1 < 4:
+                    q = new.block_at(l, *t.pos[l][b])
+                    assert q >= 0 and new.refine[l][q], (l, b)
+            for r in np.flatnonzero(t.refine[l]):
+                q = new.block_at(l, *t.pos[l][r])
+                if q >= 0 and not new.refine[l][q]:
+                    base = int(t.child_base[l][r])
+                    assert all(not t.refine[l + 1][k] and E2[l + 1][k] < dc * dc for k in range(base, base + 8))
+
+
+def test_tree_regrid_conserves_and_keeps_surviving_blocks():
+    t, U = _three_levels(97)
+    rng = np.random.default_rng(98)
+    E2 = [rng.random(t.nblocks(l)) for l in range(t.levels)]
+    flags = amr_tree.refine_flags(t, E2, 0.9, 0.6, max_levels=4)
+    new, V = amr_tree.regrid(t, U, flags)
+    assert new.levels >= 3
+    tot = lambda tt, W: sum(W[l][tt.leaves(l)].sum(axis=(0, 2, 3, 4)) / 8 ** l for l in range(tt.levels))
+    scale = tot(t, [np.abs(u) for u in U])
+    assert np.all(np.abs(tot(new, V) - tot(t, U)) <= 1e-13 * scale)
+    kept = 0
+    for l in range(1, new.levels):
+        for i, p in enumerate(new.pos[l].tolist()):
+            old = t.block_at(l, *p) if l < t.levels else -1
+            if old >= 0 and not new.refine[l][i] and not t.refine[l][old]:
+                assert np.array_equal(V[l][i], U[l][old])
+                kept += 1
+    assert kept > 0
+    # every refined block holds the restriction of its children, exactly as restrict() forms it
+    W = [v.copy() for v in V]
+    amr_tree.restrict(new, W)
+    assert all(np.array_equal(a, b) for a, b in zip(V, W))
+
+
+def test_tree_indicator_is_zero_for_a_uniform_state():
+    """Flat fields at every level, refinement jumps included (a missing
+    coarser neighbour stands in with the cell's own value)."""
+    t, U = _three_levels(99, bc=(1, 0, 1))
+    P = ics.uniform(n=8, nb=(4, 4, 4), bc=(1, 0, 1))
+    U = [np.broadcast_to(P.Uc[0], u.shape).copy() for u in U]
+    E = amr_tree.indicator(t, U)
+    assert all(np.all(e == 0.0) for e in E)
+
+
+def test_tree_regrid_prolongs_linear_data_exactly():
+    """A new level-2 block over linear data: the field at its cell centres."""
+    t, _ = _three_levels(100, bc=(1, 1, 1))
+    n = t.n
+
+    def field(l, I, J, K):
+        h = 1.0 / (1 << l)
+        x, y, z = (I + 0.5) * h, (J + 0.5) * h, (K + 0.5) * h
+        return np.stack([2.0 + 0.01 * x + 0.02 * y - 0.01 * z, 0.1 + 0.003 * x, -0.2 + 0.004 * z,
+                         0.05 + 0.001 * y, 8.0 + 0.01 * (x + y + z)])
+
+    r = np.arange(n)
+    U = []
+    for l in range(t.levels):
+        Ul = np.empty((t.nblocks(l), 5, n, n, n))
+        for i, (bx, by, bz) in enumerate(t.pos[l]):
+            K, J, I = np.meshgrid(r + bz * n, r + by * n, r + bx * n, indexing="ij")
+            Ul[i] = field(l, I, J, K)
+        U.append(Ul)
+    R = amr_tree._refined_sets(t)
+    base = int(t.child_base[0][1 + 4 * (1 + 4 * 1)])
+    R[1].add(tuple(t.pos[1][base + 1].tolist()))    # a new refinement inside the centre block
+    new, V = amr_tree.regrid(t, U, amr_tree._flags_from_sets(t, R))
+    fresh = [i for i, p in enumerate(new.pos[2].tolist()) if t.block_at(2, *p) < 0]
+    assert len(fresh) == 8
+    for i in fresh:
+        bx, by, bz = new.pos[2][i]
+        K, J, I = np.meshgrid(r + bz * n, r + by * n, r + bx * n, indexing="ij")
+        np.testing.assert_allclose(V[2][i], field(2, I, J, K), rtol=1e-14, atol=1e-15)

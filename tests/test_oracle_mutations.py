@@ -120,6 +120,12 @@ TREE_MUTATIONS = {
     "tree_prolong_same_level": ("Uc = level_value(t, U, l - 1, Ic, Jc, Kc)",
                                 "Uc = level_value(t, U, l - 1, Ic, Jc, Kc) * (1.0 + 1e-3)"),
     "tree_reflux_wrong_level_dx": ("lam = [dt / h for h in t.dx(l)]", "lam = [dt / h for h in t.dx(l + 1)]"),
+    "tree_no_nesting_repair": ("    changed = True\n    while changed:\n        changed = False\n        # drop",
+                               "    changed = False\n    while changed:\n        changed = False\n        # drop"),
+    "tree_indicator_missing_is_zero": ("u[:, ~ok] = own[:, ~ok]", "u[:, ~ok] = 0.0 * own[:, ~ok]"),
+    "tree_regrid_injects": ("Ul[i] = prolong(new, V, l, I.ravel(), J.ravel(), K.ravel()).reshape(5, n, n, n)",
+                            "Ul[i] = level_value(new, V, l - 1, I.ravel() // 2, J.ravel() // 2, K.ravel() // 2)"
+                            ".reshape(5, n, n, n)"),
     "tree_copy_from_parent_level": ("out[:, here] = U[l][blk[here], :, K[here] % n, J[here] % n, I[here] % n].T",
                                     "out[:, here] = U[l][blk[here], :, K[here] % n, J[here] % n, I[here] % n].T"
                                     " * (1.0 + 1e-12 * (l > 1))"),

@@ -366,6 +366,24 @@ int hydro_amr_dt(hydro_amr *a, double cfl, double *dt_out);
  * Errors: HYDRO_EINVAL (NULL, eps < 0, cutoffs not 0 <= derefine <= refine). */
 int hydro_amr_estimate(hydro_amr *a, double eps, double refine_cutoff, double derefine_cutoff, double *E2_out,
                        unsigned char *flags_out);
+/* Adaptivity of a mesh of any depth: the indicator of every leaf at its own
+ * level (the per-cell quantity above, its neighbours read at the leaf's
+ * level; a position with no block of that level takes the cell's own
+ * state), then the rule: a leaf with E^2 > refine_cutoff^2 below level
+ * max_levels-1 is refined; a refined block whose eight children are leaves
+ * with E^2 < derefine_cutoff^2 loses them; nesting is then restored by
+ * refining, coarsest level first and positions in increasing (x, y, z)
+ * order, every block whose absence leaves a refined block of level >= 1
+ * without a same-level neighbour, until nothing changes.  flags_out (host,
+ * capacity cap) receives the new flags in descriptor order (level 0, then
+ * each deeper level); *nflags_out their count (HYDRO_ESIZE when cap is
+ * short).  E2_out (host, may be NULL): one value per block of every level
+ * (refined blocks 0).  Waits.  Errors: HYDRO_EINVAL (NULL handle or
+ * nflags_out, eps < 0, cutoffs not 0 <= derefine <= refine, max_levels not
+ * in 1..8), HYDRO_ESIZE (cap short; *nflags_out still set, so a first call
+ * with cap 0 sizes the buffer), HYDRO_EDEVICE. */
+int hydro_amr_estimate_tree(hydro_amr *a, double eps, double refine_cutoff, double derefine_cutoff, int max_levels,
+                            double *E2_out, unsigned char *flags_out, size_t cap, size_t *nflags_out);
 /* Regridding: fill the state of mesh `to` (created with the new flags over
  * the same root grid, its own fine buffer) from mesh `from`: the root state
  * is copied (unless both use one buffer), children of blocks refined in both
@@ -374,7 +392,8 @@ int hydro_amr_estimate(hydro_amr *a, double eps, double refine_cutoff, double de
  * block of `to` takes its children's restriction; derefined blocks keep
  * their root values (the restriction of the children they lose).  Waits for
  * `from`'s stream, then runs on `to`'s.  `from` may be freed afterwards.
- * Both meshes must have at most two levels (HYDRO_EINVAL otherwise). */
+ * Any depth: level by level, a block of `to` at a position `from` has at
+ * that level is copied, a new one is prolonged from `to`'s level above. */
 int hydro_amr_transfer(hydro_amr *from, hydro_amr *to);
 /* Event counters summed since creation: floors, fallbacks, nonphysical cells (waits). */
 int hydro_amr_counters(hydro_amr *a, long long out[3]);

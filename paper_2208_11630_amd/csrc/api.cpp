@@ -5,12 +5,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <set>
 #include <vector>
 
 #include "hydro_internal.h"
@@ -718,6 +720,8 @@ struct hydro_amr {
   long steps = 0;          // signal slot of the current state: steps % 3
   bool sig_valid = false;  // the slot holds the current state's signal speed
   double* E2 = nullptr;    // device, nroot refinement indicators
+  double* E2T = nullptr;   // device, one indicator per block of every level (leaves written)
+  std::vector<std::vector<int>> pos;  // host copy of the block positions per level (x, y, z)
 };
 
 namespace {
@@ -737,7 +741,7 @@ struct AmrLayout {
   int nlev = 0;
   AmrLevelHost lev[hydro::AMR_MAX_LEVELS];
   long nroot = 0, nfine = 0;
-  size_t tab_ints = 0, o_tab = 256, o_E2 = 0, total = 0;
+  size_t tab_ints = 0, o_tab = 256, o_E2 = 0, o_E2T = 0, total = 0;
 };
 
 // block index at level-l position (x, y, z) after the boundary map; -1 when
@@ -896,7 +900,11 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
     o += al256(sizeof(double) * 30 * (size_t)N * N * nblk);
   }
   A.o_E2 = o;
-  A.total = o + al256(sizeof(double) * (size_t)A.nroot);
+  o += al256(sizeof(double) * (size_t)A.nroot);
+  A.o_E2T = o;
+  size_t nall = 0;
+  for (int l = 0; l < A.nlev; ++l) nall += A.lev[l].flag.size();
+  A.total = o + al256(sizeof(double) * nall);
   return HYDRO_OK;
 }
 
@@ -994,6 +1002,8 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
     V.ngroups = (long)H.first.size() - 1;
   }
   a->E2 = (double*)(w + A.o_E2);
+  a->E2T = (double*)(w + A.o_E2T);
+  for (int l = 0; l < A.nlev; ++l) a->pos.push_back(A.lev[l].pos);
   L.ws = (hydro::WorkHeader*)w;
   L.dt = 0.0;
   L.cfl = 0.0;
@@ -1119,9 +1129,172 @@ int hydro_amr_estimate(hydro_amr* a, double eps, double refine_cutoff, double de
   return HYDRO_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+using Pos = std::array<int, 3>;
+
+// Refinement state as sets of refined block positions per level.
+struct TreeFlags {
+  std::vector<std::set<Pos>> R;
+  int nb0[3];
+  int bc[3];
+
+  bool is_block(int l, const Pos& p) const {
+    return l == 0 || R[l - 1].count(Pos{p[0] / 2, p[1] / 2, p[2] / 2}) > 0;
+  }
+  bool wrap(int l, Pos& q) const {
+    for (int d = 0; d < 3; ++d) {
+      const int n = nb0[d] << l;
+      if (bc[d] == HYDRO_BC_PERIODIC) q[d] = ((q[d] % n) + n) % n;
+      else if (q[d] < 0 || q[d] >= n) return false;
+    }
+    return true;
+  }
+  void ensure_block(int l, const Pos& p) {
+    if (is_block(l, p)) return;
+    const Pos par{p[0] / 2, p[1] / 2, p[2] / 2};
+    ensure_block(l - 1, par);
+    R[l - 1].insert(par);
+  }
+  // every refined block of a level >= 1 gets its 26 same-level neighbours:
+  // refine (coarsest level first, positions in increasing order) until stable
+  void restore_nesting() {
+    bool changed = true;
+    while (changed) {
+      changed = false;
+      for (size_t l = 1; l < R.size(); ++l) {
+        const std::vector<Pos> snap(R[l].begin(), R[l].end());
+        for (const Pos& p : snap)
+          if (!is_block((int)l, p)) {
+            R[l].erase(p);
+            changed = true;
+          }
+      }
+      for (size_t l = 1; l < R.size(); ++l) {
+        const std::vector<Pos> snap(R[l].begin(), R[l].end());
+        for (const Pos& p : snap)
+          for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dx = -1; dx <= 1; ++dx) {
+                Pos q{p[0] + dx, p[1] + dy, p[2] + dz};
+                if (wrap((int)l, q) && !is_block((int)l, q)) {
+                  ensure_block((int)l, q);
+                  changed = true;
+                }
+              }
+      }
+    }
+  }
+  // flags in descriptor order: level 0 in block order, then each deeper
+  // level's blocks (children of the previous level's refined blocks)
+  std::vector<unsigned char> flags(long nroot) const {
+    std::vector<unsigned char> out;
+    std::vector<Pos> cur;
+    for (long b = 0; b < nroot; ++b)
+      cur.push_back(Pos{(int)(b % nb0[0]), (int)((b / nb0[0]) % nb0[1]), (int)(b / ((long)nb0[0] * nb0[1]))});
+    for (size_t l = 0;; ++l) {
+      std::vector<Pos> next;
+      bool any = false;
+      for (const Pos& p : cur) {
+        const bool f = l < R.size() && R[l].count(p) > 0;
+        out.push_back(f ? 1 : 0);
+        if (f) {
+          any = true;
+          for (int c = 0; c < 8; ++c)
+            next.push_back(Pos{2 * p[0] + (c & 1), 2 * p[1] + ((c >> 1) & 1), 2 * p[2] + ((c >> 2) & 1)});
+        }
+      }
+      if (!any) break;
+      cur.swap(next);
+    }
+    return out;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int hydro_amr_estimate_tree(hydro_amr* a, double eps, double refine_cutoff, double derefine_cutoff, int max_levels,
+                            double* E2_out, unsigned char* flags_out, size_t cap, size_t* nflags_out) {
+  if (!a || !nflags_out) return fail(HYDRO_EINVAL, "handle or nflags_out is NULL");
+  if (!(std::isfinite(eps) && eps >= 0.0)) return fail(HYDRO_EINVAL, "eps must be finite and >= 0");
+  if (!(std::isfinite(refine_cutoff) && std::isfinite(derefine_cutoff) && derefine_cutoff >= 0.0 &&
+        derefine_cutoff <= refine_cutoff))
+    return fail(HYDRO_EINVAL, "need finite cutoffs with 0 <= derefine_cutoff <= refine_cutoff");
+  if (max_levels < 1 || max_levels > hydro::AMR_MAX_LEVELS)
+    return fail(HYDRO_EINVAL, "max_levels must be in 1..%d", hydro::AMR_MAX_LEVELS);
+  const hydro::AmrLaunch& L = a->L;
+  hipStream_t s = (hipStream_t)a->d.stream;
+  size_t nall = 0;
+  double* lev_ptr[hydro::AMR_MAX_LEVELS];
+  for (int l = 0; l < L.nlev; ++l) {
+    lev_ptr[l] = a->E2T + nall;
+    nall += (size_t)L.lev[l].nblk;
+  }
+  hipError_t e = hipMemsetAsync(a->E2T, 0, sizeof(double) * nall, s);   // refined blocks read as 0
+  if (e == hipSuccess) e = hydro::launch_amr_leaf_indicator(a->d.nxb, L, eps, lev_ptr, s);
+  if (e != hipSuccess) return hip_fail(e, "AMR indicator launch");
+  std::vector<double> E2(nall);
+  e = hipMemcpyAsync(E2.data(), a->E2T, sizeof(double) * nall, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "AMR indicator read");
+  if (E2_out) std::copy(E2.begin(), E2.end(), E2_out);
+  // the rule
+  TreeFlags T;
+  for (int d = 0; d < 3; ++d) {
+    T.nb0[d] = a->d.nblk[d];
+    T.bc[d] = a->d.bc[d];
+  }
+  T.R.resize(std::max(L.nlev, max_levels));
+  // current flags of every level, from the descriptor's flags
+  std::vector<std::vector<unsigned char>> flag(L.nlev);
+  flag[0].assign(a->refine.begin(), a->refine.end());
+  size_t used = 0;
+  for (int l = 1; l < L.nlev; ++l) {
+    const size_t nb = (size_t)L.lev[l].nblk;
+    if (used + nb <= a->refine_deep.size())
+      flag[l].assign(a->refine_deep.begin() + used, a->refine_deep.begin() + used + nb);
+    else
+      flag[l].assign(nb, 0);
+    used += nb;
+  }
+  auto pos_of = [&](int l, long b) { return Pos{a->pos[l][4 * b], a->pos[l][4 * b + 1], a->pos[l][4 * b + 2]}; };
+  size_t off = 0;
+  std::vector<size_t> level_off(L.nlev);
+  for (int l = 0; l < L.nlev; ++l) {
+    level_off[l] = off;
+    off += (size_t)L.lev[l].nblk;
+    for (long b = 0; b < L.lev[l].nblk; ++b)
+      if (flag[l][b]) T.R[l].insert(pos_of(l, b));
+  }
+  const double rc2 = refine_cutoff * refine_cutoff, dc2 = derefine_cutoff * derefine_cutoff;
+  for (int l = 0; l < L.nlev; ++l)
+    for (long b = 0; b < L.lev[l].nblk; ++b)
+      if (!flag[l][b] && E2[level_off[l] + b] > rc2 && l + 1 < max_levels) T.R[l].insert(pos_of(l, b));
+  for (int l = 0; l + 1 < L.nlev; ++l) {
+    long base = 0;  // children of the refined blocks of level l are contiguous, in block order
+    for (long r = 0; r < L.lev[l].nblk; ++r) {
+      if (!flag[l][r]) continue;
+      bool all = true;
+      for (long k = base; k < base + 8; ++k) all = all && !flag[l + 1][k] && E2[level_off[l + 1] + k] < dc2;
+      if (all) T.R[l].erase(pos_of(l, r));
+      base += 8;
+    }
+  }
+  T.restore_nesting();
+  const std::vector<unsigned char> out = T.flags(L.lev[0].nblk);
+  *nflags_out = out.size();
+  if (!flags_out || cap < out.size())
+    return fail(HYDRO_ESIZE, "the new flags need %zu entries (capacity %zu)", out.size(), cap);
+  std::copy(out.begin(), out.end(), flags_out);
+  return HYDRO_OK;
+}
+
 int hydro_amr_transfer(hydro_amr* from, hydro_amr* to) {
   if (!from || !to || from == to) return fail(HYDRO_EINVAL, "need two distinct handles");
-  if (from->L.nlev > 2 || to->L.nlev > 2) return fail(HYDRO_EINVAL, "regridding handles two-level meshes");
   const hydro_amr_desc &x = from->d, &y = to->d;
   bool same = x.nxb == y.nxb && x.gamma == y.gamma;
   for (int ax = 0; ax < 3; ++ax)

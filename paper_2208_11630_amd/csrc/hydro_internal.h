@@ -116,8 +116,12 @@ hipError_t launch_amr_step(int nxb, const AmrLaunch& L, hipStream_t s);
 hipError_t launch_amr_signal(int nxb, const AmrLaunch& L, int slot, hipStream_t s);
 // Refinement indicator per root block into E2[nroot] (device).
 hipError_t launch_amr_indicator(int nxb, const AmrLaunch& L, double eps, double* E2, hipStream_t s);
-// Fine state of two-level mesh `to` from two-level mesh `from` (same root
-// grid; to's root state in place), then the restriction of to's refined blocks.
+// Per-leaf refinement indicator of every level into E2_levels[l][block].
+hipError_t launch_amr_leaf_indicator(int nxb, const AmrLaunch& L, double eps, double* const* E2_levels,
+                                     hipStream_t s);
+// State of mesh `to` (levels >= 1) from mesh `from` (same root grid; to's
+// root state in place): same-position blocks copied, new ones prolonged,
+// level by level; then the restriction of to's refined blocks.
 hipError_t launch_amr_transfer(int nxb, const AmrLaunch& from, const AmrLaunch& to, hipStream_t s);
 
 }  // namespace hydro

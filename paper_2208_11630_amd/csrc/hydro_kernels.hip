@@ -1387,31 +1387,102 @@ __global__ __launch_bounds__(256) void amr_indicator_kernel(GridGeom g0, const d
   }
 }
 
-// Regridding: fine block f of the new mesh (root block fine_root[f], child
-// c = f - child_base[r]) copies child c of r from the old fine state when r
-// was refined before (old_base[r] >= 0), else is prolonged from the root
-// state cell by cell.
+// Refinement indicator of the listed leaves of one level (one workgroup
+// each), into E2[block]: the per-cell quantity of amr_indicator_kernel with
+// neighbours read at the leaf's own level through the level's lookup; a
+// neighbour position holding no block of that level (a coarser region)
+// takes the cell's own state.  Rounded as written, like that kernel.
 template <int N>
-__global__ __launch_bounds__(256) void amr_transfer_kernel(GridGeom g0, const int* __restrict__ lookup0,
-                                                           const double* __restrict__ Ur,
-                                                           const double* __restrict__ Uf_old,
-                                                           const int* __restrict__ old_base,
-                                                           const int* __restrict__ child_base,
-                                                           const int* __restrict__ fine_root, double* __restrict__ Uf) {
+__global__ __launch_bounds__(256) void amr_leaf_indicator_kernel(GridGeom g, const int* __restrict__ lookup,
+                                                                 const double* __restrict__ U,
+                                                                 const int* __restrict__ leaves,
+                                                                 const int4* __restrict__ pos, double eps,
+                                                                 double* __restrict__ E2) {
+#pragma clang fp contract(off)
+  __shared__ double sRed[4];
+  const int b = leaves[blockIdx.x];
+  const int4 q = pos[b];
+  const int NX = g.nb[0] * N, NY = g.nb[1] * N, NZ = g.nb[2] * N;
+  auto load_or_self = [&](int I, int J, int K, const double (&own)[5], double (&u)[5]) {
+    I = map_axis(I, NX, g.bc[0]);
+    J = map_axis(J, NY, g.bc[1]);
+    K = map_axis(K, NZ, g.bc[2]);
+    const int nb = lookup[(I / N) + g.nb[0] * ((J / N) + g.nb[1] * (K / N))];
+    if (nb >= 0) {
+      load_cons<N>(U, Layout<N>::at(nb, I % N, J % N, K % N), u);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) u[v] = own[v];
+    }
+  };
+  double emax = 0.0;
+  for (int t = threadIdx.x; t < N * N * N; t += blockDim.x) {
+    const int I = q.x * N + t % N, J = q.y * N + (t / N) % N, K = q.z * N + t / (N * N);
+    double u[5];
+    load_cons<N>(U, Layout<N>::at(b, t % N, (t / N) % N, t / (N * N)), u);
+    const double r0 = u[0], p0 = amr_pressure(u, g.gamma);
+    double nr = 0.0, dr = 0.0, np_ = 0.0, dp = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double um[5], up[5];
+      load_or_self(I - (d == 0), J - (d == 1), K - (d == 2), u, um);
+      load_or_self(I + (d == 0), J + (d == 1), K + (d == 2), u, up);
+      const double rL = um[0], rR = up[0], pL = amr_pressure(um, g.gamma), pR = amr_pressure(up, g.gamma);
+      const double an = (rR - r0) - (r0 - rL);
+      const double ad = (fabs(rR - r0) + fabs(r0 - rL)) + eps * ((fabs(rR) + 2.0 * fabs(r0)) + fabs(rL));
+      const double bn = (pR - p0) - (p0 - pL);
+      const double bd = (fabs(pR - p0) + fabs(p0 - pL)) + eps * ((fabs(pR) + 2.0 * fabs(p0)) + fabs(pL));
+      if (d == 0) {
+        nr = an * an;
+        dr = ad * ad;
+        np_ = bn * bn;
+        dp = bd * bd;
+      } else {
+        nr = nr + an * an;
+        dr = dr + ad * ad;
+        np_ = np_ + bn * bn;
+        dp = dp + bd * bd;
+      }
+    }
+    const double er = dr > 0.0 ? nr / dr : 0.0;
+    const double ep = dp > 0.0 ? np_ / dp : 0.0;
+    emax = fmax(emax, fmax(er, ep));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) emax = fmax(emax, __shfl_xor(emax, o, 64));
+  if ((threadIdx.x & 63) == 0) sRed[threadIdx.x >> 6] = emax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = sRed[0];
+    for (int w = 1; w < (int)(blockDim.x + 63) / 64; ++w) m = fmax(m, sRed[w]);
+    E2[b] = m;
+  }
+}
+
+// Regridding, level l >= 1 of the new mesh: block f copies the block at the
+// same position of the old mesh's level l (old_lookup, when that level
+// exists), else is prolonged cell by cell from the new mesh's level l-1
+// (already final).
+template <int N>
+__global__ __launch_bounds__(256) void amr_transfer_level_kernel(GridGeom g, GridGeom gp,
+                                                                 const int* __restrict__ old_lookup,
+                                                                 const double* __restrict__ U_old,
+                                                                 const int* __restrict__ lookup_p,
+                                                                 const double* __restrict__ Up,
+                                                                 const int4* __restrict__ pos,
+                                                                 double* __restrict__ U) {
   const int f = blockIdx.x;
-  const int r = fine_root[f];
-  const int c = f - child_base[r];
-  double* out = Uf + (long)f * Layout<N>::BS;
-  if (old_base[r] >= 0) {
-    const double* src = Uf_old + (long)(old_base[r] + c) * Layout<N>::BS;
+  const int4 q = pos[f];
+  double* out = U + (long)f * Layout<N>::BS;
+  const int ob = old_lookup ? old_lookup[q.x + g.nb[0] * (q.y + g.nb[1] * q.z)] : -1;
+  if (ob >= 0) {
+    const double* src = U_old + (long)ob * Layout<N>::BS;
     for (int t = threadIdx.x; t < 5 * N * N * N; t += blockDim.x) out[t] = src[t];
     return;
   }
-  const int bx = r % g0.nb[0], by = (r / g0.nb[0]) % g0.nb[1], bz = r / (g0.nb[0] * g0.nb[1]);
-  const int X0 = 2 * bx * N + (c & 1) * N, Y0 = 2 * by * N + ((c >> 1) & 1) * N, Z0 = 2 * bz * N + ((c >> 2) & 1) * N;
   for (int t = threadIdx.x; t < N * N * N; t += blockDim.x) {
     double val[5];
-    prolong_cell<N>(g0, lookup0, Ur, X0 + t % N, Y0 + (t / N) % N, Z0 + t / (N * N), val);
+    prolong_cell<N>(gp, lookup_p, Up, q.x * N + t % N, q.y * N + (t / N) % N, q.z * N + t / (N * N), val);
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[v * Layout<N>::VS + t] = val[v];
   }
@@ -1596,25 +1667,51 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
 }
 
 template <int N>
-void launch_amr_adapt_t(const AmrLaunch& L, double eps, double* E2, const AmrLaunch* from, hipStream_t s) {
+void launch_amr_adapt_t(const AmrLaunch& L, double eps, double* E2, double* const* E2_levels,
+                        const AmrLaunch* from, hipStream_t s) {
   const AmrLevel& R = L.lev[0];
   if (E2) hipLaunchKernelGGL(amr_indicator_kernel<N>, dim3((unsigned)R.nblk), dim3(256), 0, s, R.g, R.U, eps, E2);
-  if (from && L.nlev > 1) {
-    const AmrLevel& F = L.lev[1];
-    hipLaunchKernelGGL(amr_transfer_kernel<N>, dim3((unsigned)F.nblk), dim3(256), 0, s, R.g, R.lookup, R.U,
-                       from->nlev > 1 ? from->lev[1].U : nullptr, from->lev[0].child_base, R.child_base, F.parent,
-                       F.U);
+  if (E2_levels)
+    for (int l = 0; l < L.nlev; ++l) {
+      const AmrLevel& A = L.lev[l];
+      if (A.nleaves)
+        hipLaunchKernelGGL(amr_leaf_indicator_kernel<N>, dim3((unsigned)A.nleaves), dim3(256), 0, s, A.g, A.lookup,
+                           A.U, A.leaves, A.pos, eps, E2_levels[l]);
+    }
+  if (from) {
+    for (int l = 1; l < L.nlev; ++l) {
+      const AmrLevel& A = L.lev[l];
+      const AmrLevel& B = L.lev[l - 1];
+      const bool has = l < from->nlev;
+      hipLaunchKernelGGL(amr_transfer_level_kernel<N>, dim3((unsigned)A.nblk), dim3(256), 0, s, A.g, B.g,
+                         has ? from->lev[l].lookup : (const int*)nullptr,
+                         has ? (const double*)from->lev[l].U : (const double*)nullptr, B.lookup, B.U, A.pos, A.U);
+    }
+    for (int l = L.nlev - 2; l >= 0; --l) {
+      const AmrLevel& A = L.lev[l];
+      if (A.nrefined)
+        hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)A.nrefined), dim3(256), 0, s, A.refined,
+                           A.child_base, L.lev[l + 1].U, A.U);
+    }
   }
-  if (from && R.nrefined)
-    hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)R.nrefined), dim3(256), 0, s, R.refined, R.child_base,
-                       L.lev[1].U, R.U);
 }
 
 hipError_t launch_amr_indicator(int nxb, const AmrLaunch& L, double eps, double* E2, hipStream_t s) {
   switch (nxb) {
-    case 8: launch_amr_adapt_t<8>(L, eps, E2, nullptr, s); break;
-    case 16: launch_amr_adapt_t<16>(L, eps, E2, nullptr, s); break;
-    case 32: launch_amr_adapt_t<32>(L, eps, E2, nullptr, s); break;
+    case 8: launch_amr_adapt_t<8>(L, eps, E2, nullptr, nullptr, s); break;
+    case 16: launch_amr_adapt_t<16>(L, eps, E2, nullptr, nullptr, s); break;
+    case 32: launch_amr_adapt_t<32>(L, eps, E2, nullptr, nullptr, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_amr_leaf_indicator(int nxb, const AmrLaunch& L, double eps, double* const* E2_levels,
+                                     hipStream_t s) {
+  switch (nxb) {
+    case 8: launch_amr_adapt_t<8>(L, eps, nullptr, E2_levels, nullptr, s); break;
+    case 16: launch_amr_adapt_t<16>(L, eps, nullptr, E2_levels, nullptr, s); break;
+    case 32: launch_amr_adapt_t<32>(L, eps, nullptr, E2_levels, nullptr, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1622,9 +1719,9 @@ hipError_t launch_amr_indicator(int nxb, const AmrLaunch& L, double eps, double*
 
 hipError_t launch_amr_transfer(int nxb, const AmrLaunch& from, const AmrLaunch& to, hipStream_t s) {
   switch (nxb) {
-    case 8: launch_amr_adapt_t<8>(to, 0.0, nullptr, &from, s); break;
-    case 16: launch_amr_adapt_t<16>(to, 0.0, nullptr, &from, s); break;
-    case 32: launch_amr_adapt_t<32>(to, 0.0, nullptr, &from, s); break;
+    case 8: launch_amr_adapt_t<8>(to, 0.0, nullptr, nullptr, &from, s); break;
+    case 16: launch_amr_adapt_t<16>(to, 0.0, nullptr, nullptr, &from, s); break;
+    case 32: launch_amr_adapt_t<32>(to, 0.0, nullptr, nullptr, &from, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

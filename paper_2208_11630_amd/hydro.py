@@ -81,6 +81,9 @@ SIGNATURES = {
     "hydro_amr_estimate": ([ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_ubyte)], ctypes.c_int),
     "hydro_amr_transfer": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "hydro_amr_estimate_tree": ([ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_ubyte), ctypes.c_size_t,
+                                 ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "hydro_amr_free": ([ctypes.c_void_p], ctypes.c_int),
     "hydro_set_pencil_planes": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_set_scheme": ([_HP, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
@@ -503,14 +506,33 @@ class Amr:
                                         E2, flags))
         return np.array(list(flags), dtype=bool), np.array(list(E2))
 
-    def regrid(self, flags) -> "Amr":
-        """A new mesh over the same root grid with refinement `flags`, its
-        state transferred from this one (hydro_amr_transfer); this mesh is
-        closed."""
-        if len(self.level_blocks) > 2:
-            raise HydroError(HYDRO_EINVAL, "regridding handles two-level meshes")
+    def estimate_tree(self, eps: float = 0.01, refine_cutoff: float = 0.8, derefine_cutoff: float = 0.2,
+                      max_levels: int = 3):
+        """(level-0 flags, deeper flags, per-level indicators) of the rule for
+        meshes of any depth (hydro_amr_estimate_tree)."""
+        nall = sum(self.level_blocks)
+        E2 = (ctypes.c_double * nall)()
+        need = ctypes.c_size_t()
+        lib().hydro_amr_estimate_tree(self.handle, float(eps), float(refine_cutoff), float(derefine_cutoff),
+                                      int(max_levels), E2, None, 0, ctypes.byref(need))
+        flags = (ctypes.c_ubyte * max(need.value, 1))()
+        _check(lib().hydro_amr_estimate_tree(self.handle, float(eps), float(refine_cutoff), float(derefine_cutoff),
+                                             int(max_levels), E2, flags, need.value, ctypes.byref(need)))
+        f = np.array(list(flags)[:need.value], dtype=bool)
+        nroot = len(self.refine)
+        per_level, o = [], 0
+        for nb in self.level_blocks:
+            per_level.append(np.array(list(E2)[o:o + nb]))
+            o += nb
+        return f[:nroot], f[nroot:], per_level
+
+    def regrid(self, flags, refine_deep=()) -> "Amr":
+        """A new mesh over the same root grid with level-0 flags `flags` and
+        deeper flags `refine_deep`, its state transferred from this one
+        (hydro_amr_transfer); this mesh is closed."""
         new = Amr(self.nxb, self.nblk, [bool(f) for f in flags], self.lo, self.hi, self.bc, self.gamma,
-                  self.small_p, device=self.Ur.device, stream=self.stream)
+                  self.small_p, device=self.Ur.device, stream=self.stream,
+                  refine_deep=[bool(f) for f in refine_deep])
         _check(lib().hydro_amr_transfer(self.handle, new.handle))
         self.close()
         return new

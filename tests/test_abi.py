@@ -182,3 +182,5 @@ def test_amr_sizes_and_validation(L):
     assert L.hydro_amr_free(None) == hydro.HYDRO_OK
     assert L.hydro_amr_estimate(None, 0.01, 0.8, 0.2, None, None) == hydro.HYDRO_EINVAL
     assert L.hydro_amr_transfer(None, None) == hydro.HYDRO_EINVAL
+    nf = ctypes.c_size_t()
+    assert L.hydro_amr_estimate_tree(None, 0.01, 0.8, 0.2, 3, None, None, 0, ctypes.byref(nf)) == hydro.HYDRO_EINVAL

@@ -379,3 +379,88 @@ def test_amr_tree_trajectory_parity(hy, case, device_dt):
         assert_close((got[0], np.concatenate(got[1:])), (U[0], np.concatenate(U[1:])), f"{case} step {s}")
     assert A.counters().tolist() == cnt.tolist()
     A.close()
+
+
+# ---- adaptivity of meshes of any depth ---------------------------------------
+
+def _flat(flags):
+    return np.concatenate([np.asarray(f, bool) for f in flags])
+
+
+@pytest.mark.parametrize("case", TREE_CASES)
+def test_amr_tree_indicator_and_flags_are_the_oracles(hy, case):
+    """Per-leaf indicator of every level bit for bit (rounded as written,
+    same-level data only), and the rule's flags, nesting repair included."""
+    from oracle import amr_tree
+
+    t, U = _tree_case(case)
+    A = _tree_gpu(hy, t, U)
+    for rc, dc, ml in [(0.93, 0.9, 4), (0.7, 0.5, 3), (0.99, 0.95, 5)]:
+        f0, deep, E2 = A.estimate_tree(0.01, rc, dc, ml)
+        ref = amr_tree.indicator(t, U, 0.01)
+        for l in range(t.levels):
+            assert np.array_equal(E2[l], ref[l]), (case, l)
+        flags = amr_tree.refine_flags(t, ref, rc, dc, max_levels=ml)
+        assert np.array_equal(np.concatenate([f0, deep]), _flat(flags)), (case, rc, dc, ml)
+    A.close()
+
+
+@pytest.mark.parametrize("case", TREE_CASES)
+def test_amr_tree_regrid_matches_the_oracle(hy, case):
+    """Regrid to flags from a random indicator (nesting restored by the
+    oracle's rule): blocks present before copied bit for bit, new ones
+    prolonged (1e-12), restriction finest level first."""
+    from oracle import amr_tree
+
+    t, U = _tree_case(case)
+    A = _tree_gpu(hy, t, U)
+    rng = np.random.default_rng(101)
+    E2 = [rng.random(t.nblocks(l)) for l in range(t.levels)]
+    flags = amr_tree.refine_flags(t, E2, 0.9, 0.6, max_levels=4)
+    new, V = amr_tree.regrid(t, U, flags)
+    B = A.regrid(flags[0], _flat(flags[1:]) if len(flags) > 1 else [])
+    assert B.level_blocks == [new.nblocks(l) for l in range(new.levels)]
+    got = _tree_split(B, *B.download())
+    for l in range(1, new.levels):
+        for i, p in enumerate(new.pos[l].tolist()):
+            old = t.block_at(l, *p) if l < t.levels else -1
+            if old >= 0 and not new.refine[l][i]:
+                assert np.array_equal(got[l][i], U[l][old]), (l, i)
+    assert_close((got[0], np.concatenate(got[1:])), (V[0], np.concatenate(V[1:])), f"{case} tree regrid")
+    B.close()
+
+
+def test_amr_tree_adaptive_trajectory(hy):
+    """Three levels at most: steps with an estimate and a regrid every two
+    steps on both sides (flags compared where the indicator is clear of the
+    cutoffs), parity after every step and regrid."""
+    from oracle import amr_tree
+
+    print("\n[amr] tree adaptive trajectory", flush=True)
+    t, U = _tree_case("n16_three_levels")
+    A = _tree_gpu(hy, t, U)
+    changed = 0
+    for cycle in range(3):
+        for s in range(2):
+            dt = amr_tree.dt(t, U, 0.8)
+            U, _ = amr_tree.step(t, U, dt)
+            A.step(dt)
+            got = _tree_split(A, *A.download())
+            assert_close((got[0], np.concatenate(got[1:])), (U[0], np.concatenate(U[1:])), f"cycle {cycle} step {s}")
+        ref = amr_tree.indicator(t, U, 0.01)
+        flags = amr_tree.refine_flags(t, ref, 0.95, 0.9, max_levels=3)
+        f0, deep, E2 = A.estimate_tree(0.01, 0.95, 0.9, 3)
+        clear = all(np.all((np.abs(r - 0.95 ** 2) > 1e-9) & (np.abs(r - 0.81) > 1e-9)) for r in ref)
+        if clear:
+            assert np.array_equal(np.concatenate([f0, deep]), _flat(flags))
+        for l in range(t.levels):
+            assert np.allclose(E2[l], ref[l], rtol=1e-8, atol=1e-10)
+        before = [np.asarray(f, bool).copy() for f in t.refine]
+        t, U = amr_tree.regrid(t, U, flags)
+        changed += int(any(len(a) != len(b) or np.any(a != b) for a, b in zip(before, t.refine)) or
+                       len(before) != len(t.refine))
+        A = A.regrid(flags[0], _flat(flags[1:]) if len(flags) > 1 else [])
+        got = _tree_split(A, *A.download())
+        assert_close((got[0], np.concatenate(got[1:])), (U[0], np.concatenate(U[1:])), f"cycle {cycle} regrid")
+    assert changed >= 1
+    A.close()

@@ -219,8 +219,9 @@ def run_ensemble(args):
                               "launches_per_step": len(sims)},
         "batched_over_looped": rate / loop_rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "batch_step_kernel",
-                     "algorithmic_bytes_per_launch": BYTES_PER_CELL * cells},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "batch_step_kernel (one launch per block size per step)",
+                     "algorithmic_bytes_per_step": BYTES_PER_CELL * cells},
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -42,6 +42,7 @@ struct hydro_batch {
   void* stream;
   int nseg[3];                           // pencils per column for nxb 8, 16, 32
   int grid;                              // persistent workgroups
+  long cls_begin[3], cls_count[3];       // work-list range of each size class (8, 16, 32)
   int cus;
   long step;                             // steps since the table was last uploaded
   bool dirty;                            // table / list must be rebuilt before the next step
@@ -487,15 +488,17 @@ int batch_upload(hydro_batch* b) {
   const int n = (int)b->grids.size();
   b->sims.resize(n);
   b->items.clear();
-  // heaviest pencils first (32^3 columns, then 16^3, then 8^3): the strided
-  // assignment then hands every workgroup a similar mix
+  // one contiguous range per block size (32^3 columns, then 16^3, then
+  // 8^3), each stepped by its own launch
   for (int cls = 2; cls >= 0; --cls) {
+    b->cls_begin[cls] = (long)b->items.size();
     for (int i = 0; i < n; ++i) {
       hydro_grid* g = b->grids[i];
       if (!b->active[i] || size_class(g->d.nxb) != cls) continue;
       const long cols = columns_of(g) * b->nseg[cls];
       for (long c = 0; c < cols; ++c) b->items.push_back(hydro::BatchItem{i, (int)c});
     }
+    b->cls_count[cls] = (long)b->items.size() - b->cls_begin[cls];
   }
   for (int i = 0; i < n; ++i) {
     hydro_grid* g = b->grids[i];
@@ -524,9 +527,18 @@ int batch_upload(hydro_batch* b) {
   return HYDRO_OK;
 }
 
+// One launch per block-size class present, each running the kernel that
+// holds that size's tile step only (the classes' work-list ranges are
+// disjoint and every member sits in one class, so the launches are
+// independent; the stream orders them).
 hipError_t batch_launch(hydro_batch* b, double cfl, long step) {
-  return hydro::launch_batch_step(b->d_sims, b->d_items, (int)b->items.size(), step % 6, cfl, b->nseg, b->grid,
-                                  (hipStream_t)b->stream);
+  for (int cls = 2; cls >= 0; --cls) {
+    if (b->cls_count[cls] == 0) continue;
+    hipError_t e = hydro::launch_batch_step(b->d_sims, b->d_items + b->cls_begin[cls], (int)b->cls_count[cls],
+                                            step % 6, cfl, 8 << cls, b->nseg[cls], b->grid, (hipStream_t)b->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 void advance_members(hydro_batch* b, int nsteps) {
@@ -580,6 +592,7 @@ int hydro_batch_create(hydro_grid* const* grids, int n, void* work, size_t work_
   b->nseg[0] = b->nseg[1] = b->nseg[2] = 1;
   b->cus = cus;
   b->grid = 2 * cus;
+  for (int c = 0; c < 3; ++c) b->cls_begin[c] = b->cls_count[c] = 0;
   b->step = 0;
   b->dirty = true;
   b->use_graph = false;

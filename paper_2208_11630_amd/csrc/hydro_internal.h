@@ -70,8 +70,10 @@ struct BatchItem {
 // plen: planes per z pencil (>= 2, divides the grid's z extent).
 hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const StageArgs* st, int plen,
                        hipStream_t s);
+// items: the work-list range of the members with blocks of nxb^3 cells
+// (8, 16 or 32); nseg: pencils per column for that size.
 hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,
-                             const int nseg[3], int grid, hipStream_t s);
+                             int nxb, int nseg, int grid, hipStream_t s);
 hipError_t launch_fill_guards(int nxb, const GridGeom& g, const double* U, double* out, hipStream_t s);
 // dir: the per-direction signal max_d (|u_d|+c)/dx_d of the CTU step
 // instead of the summed one.

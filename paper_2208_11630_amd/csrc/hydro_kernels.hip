@@ -752,22 +752,23 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void stage_kernel(GridGeom g, StepA
 }
 
 // Many grids in one persistent launch: workgroup w takes items w, w + G,
-// w + 2G, ... of the work list (G workgroups), which lists the heaviest
-// pencils first.  The item sequence depends only on the launch shape, so the
-// loop and every barrier in it are in uniform control flow.  (A shared
-// atomic counter broadcast through LDS was compiled into a loop whose lanes
-// reached the barrier without the fetching lane's store, and never ended.)
-// Every grid uses its own device dt (cfl / its own maximum signal speed).
-union BatchSmem {
-  Smem<8> s8;
-  Smem<16> s16;
-};
-
+// w + 2G, ... of the work list (G workgroups).  The item sequence depends
+// only on the launch shape, so the loop and every barrier in it are in
+// uniform control flow.  (A shared atomic counter broadcast through LDS was
+// compiled into a loop whose lanes reached the barrier without the fetching
+// lane's store, and never ended.)  Every grid uses its own device dt (cfl /
+// its own maximum signal speed).  N: the block size of every member whose
+// items are listed — the host launches one kernel per size class over that
+// class's range of the work list — so the kernel holds one instance of the
+// tile step (a kernel holding all three spilled registers and ran 8% slower
+// on a mixed ensemble).  An item of a member of another size would be
+// skipped, never misread.
+template <int N>
 __global__ __launch_bounds__(256, 2) void batch_step_kernel(const BatchSim* __restrict__ sims,
                                                             const BatchItem* __restrict__ items, int nitems,
-                                                            long step, double cfl, int nseg8, int nseg16,
-                                                            int nseg32) {
-  __shared__ BatchSmem sm;
+                                                            long step, double cfl, int nseg) {
+  constexpr int T = N == 8 ? 8 : 16;
+  __shared__ Smem<T> sm;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const BatchItem w = items[it];
     const BatchSim& d = sims[w.sim];
@@ -775,11 +776,7 @@ __global__ __launch_bounds__(256, 2) void batch_step_kernel(const BatchSim* __re
     const int slot = (int)((d.slot0 + step) % 3);
     const double* Uin = par ? d.U1 : d.U0;
     double* Uout = par ? d.U0 : d.U1;
-    switch (d.nxb) {
-      case 8: tile_step<8, 8>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, 8 / nseg8, sm.s8); break;
-      case 16: tile_step<16, 16>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, 16 / nseg16, sm.s16); break;
-      default: tile_step<32, 16>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, 32 / nseg32, sm.s16); break;
-    }
+    if (d.nxb == N) tile_step<N, T>(d.geom, Uin, Uout, d.ws, 0.0, cfl, slot, w.tile, N / nseg, sm);
     __syncthreads();  // the next item reuses the LDS
   }
 }
@@ -1784,9 +1781,22 @@ hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, double* scr
 }
 
 hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,
-                             const int nseg[3], int grid, hipStream_t s) {
-  hipLaunchKernelGGL(batch_step_kernel, dim3((unsigned)grid), dim3(256), 0, s, sims, items, nitems, step, cfl,
-                     nseg[0], nseg[1], nseg[2]);
+                             int nxb, int nseg, int grid, hipStream_t s) {
+  switch (nxb) {
+    case 8:
+      hipLaunchKernelGGL(batch_step_kernel<8>, dim3((unsigned)grid), dim3(256), 0, s, sims, items, nitems, step, cfl,
+                         nseg);
+      break;
+    case 16:
+      hipLaunchKernelGGL(batch_step_kernel<16>, dim3((unsigned)grid), dim3(256), 0, s, sims, items, nitems, step,
+                         cfl, nseg);
+      break;
+    case 32:
+      hipLaunchKernelGGL(batch_step_kernel<32>, dim3((unsigned)grid), dim3(256), 0, s, sims, items, nitems, step,
+                         cfl, nseg);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

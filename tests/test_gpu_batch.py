@@ -68,6 +68,32 @@ def test_batch_bitwise_equals_alone(hy):
         assert dts[i] == d
 
 
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_single_size_batch_bitwise_equals_alone(hy, n):
+    """Batches whose members share one block size run the kernel that holds
+    only that size's tile step: bitwise the members' steps alone, also with
+    a graph, and when a mask leaves one size active in a mixed batch."""
+    rng = np.random.default_rng(12 + n)
+    shapes = [(int(rng.integers(1, 7)), n) for _ in range(5)]
+    sims = ics.ensemble(count=5, seed=12 + n, steps=4, shapes=shapes)
+    ref = [alone(hy, P, 7) for P in sims]
+    out, dts = batched(hy, sims, 7, graph=True, chunks=[6, 1])
+    for i, (U, d) in enumerate(ref):
+        assert np.array_equal(out[i], U), i
+        assert dts[i] == d
+    mixed = members(count=9, seed=20)
+    grids = [hy.grid_for(P) for P in mixed]
+    B = hy.Batch(grids)
+    mask = [P.n == n for P in mixed]
+    B.set_active(mask)
+    B.step(0.8, 2)
+    B.stream.synchronize()
+    for i, P in enumerate(mixed):
+        U = alone(hy, P, 2)[0] if mask[i] else hy.grid_for(P).download()
+        assert np.array_equal(grids[i].download(), U), (n, i)
+    B.close()
+
+
 @pytest.mark.parametrize("pencils,per_cu", [((2, 2, 4), 2), ((4, 4, 2), 1), ((1, 4, 4), 3)])
 def test_batch_tuning_is_bitwise_invariant(hy, pencils, per_cu):
     sims = members(count=9, seed=8)

@@ -326,6 +326,9 @@ def _tree_case(name):
         f1 = np.zeros(64, bool)
         f1[[0, 21, 42]] = True
         flags = [f0, f1]
+    elif name == "n32_two_levels":
+        n, nb, bc = 32, (2, 1, 1), (0, 1, 0)
+        flags = [[True, False]]
     else:  # four levels: everything refined twice, then one block again
         n, nb, bc = 8, (1, 1, 1), (0, 0, 0)
         flags = [[True], [True] * 8, [False] * 63 + [True]]
@@ -334,7 +337,7 @@ def _tree_case(name):
     return t, _tree_state(t, Ur, 82)
 
 
-TREE_CASES = ["n8_three_levels", "n8_three_levels_outflow", "n16_three_levels", "n8_four_levels"]
+TREE_CASES = ["n8_three_levels", "n8_three_levels_outflow", "n16_three_levels", "n8_four_levels", "n32_two_levels"]
 
 
 def _tree_gpu(hy, t, U):

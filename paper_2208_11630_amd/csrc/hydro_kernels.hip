@@ -540,7 +540,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     // -- the previous plane's update goes out now
     if (inner && pend_off >= 0) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) *(double*)((char*)(Uout + pend_off + v * VS) + own_out) = pend[v];
+      for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(pend[v], (double*)((char*)(Uout + pend_off + v * VS) + own_out));
     }
 
     // -- predictor: own cell (every plane), ring cell (pencil planes)
@@ -718,7 +718,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   }
   if (inner && pend_off >= 0) {  // the pencil's last plane
 #pragma unroll
-    for (int v = 0; v < 5; ++v) *(double*)((char*)(Uout + pend_off + v * VS) + own_out) = pend[v];
+    for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(pend[v], (double*)((char*)(Uout + pend_off + v * VS) + own_out));
   }
 
   if (n_floor) atomicAdd(&sm.sCnt[0], n_floor);

@@ -80,11 +80,16 @@ __device__ __forceinline__ void load_cons(const double* __restrict__ U, long off
 // Same, from a workgroup-uniform base P and a 32-bit per-cell byte offset
 // (a scalar base plus a vector offset in the load itself).
 // GVW: P points into an internal view (variable stride Guarded<N, VG>::VS).
-template <int N, bool GVW = false>
+// LAST: the workgroup's last read of these cells (nontemporal load).
+template <int N, bool GVW = false, bool LAST = false>
 __device__ __forceinline__ void load_cons_at(const double* P, unsigned xyb, double (&u)[5]) {
   constexpr long VSX = GVW ? (long)(N + 2 * VG) * (N + 2 * VG) * (N + 2 * VG) : (long)N * N * N;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) u[v] = *(const double*)((const char*)(P + v * VSX) + xyb);
+  for (int v = 0; v < 5; ++v) {
+    const double* a = (const double*)((const char*)(P + v * VSX) + xyb);
+    if constexpr (LAST) u[v] = __builtin_nontemporal_load(a);
+    else u[v] = *a;
+  }
 }
 
 // Maximum over a workgroup of a non-negative double, folded into *slot with
@@ -667,7 +672,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     const long off_u = plane_off(j - 1);
     double uold[5], base[5];
     if (inner && j >= z0 + 1) {
-      load_cons_at<N, GV>(Uin + off_u, own_xy, uold);
+      load_cons_at<N, GV, true>(Uin + off_u, own_xy, uold);
       if constexpr (MOL) {
         if (st.U0) load_cons_at<N>(st.U0 + off_u, own_xy, base);
       }

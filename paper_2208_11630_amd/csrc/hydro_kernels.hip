@@ -424,12 +424,17 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   const double gamma = g.gamma, gm1inv = 1.0 / (g.gamma - 1.0);
 
   // roles; the second items (ring, halo) and the boundary faces sit on the
-  // wavefronts starting at (tile mod 4) so the busier wavefront moves
-  // between SIMDs from one workgroup to the next
+  // wavefronts starting at rotation r so the busier wavefront moves between
+  // SIMDs from one workgroup to the next: r steps by one between the
+  // consecutive workgroups of an XCD (workgroups are dealt to the 8 XCDs in
+  // turn) and by two between workgroups b and b + 256, the two a CU
+  // receives first (measured: 1.2% faster than without the second term,
+  // 3% slower with a step of one there)
   // (a workgroup may be wider than NT, e.g. 8^3 tiles in a 256-thread batch
   // launch: the threads beyond NT only take part in the barriers)
   const bool member = tid < NT;
-  const int role = member ? (tid + 64 * (int)(tile_in_sim & 3)) % NT : NT;
+  const int rot = (int)(((blockIdx.x >> 3) + (blockIdx.x >> 8) * 2) & 3);
+  const int role = member ? (tid + 64 * rot) % NT : NT;
   const bool inner = tid < NI;
   const int cx = tid % T, cy = tid / T;                // valid when inner
   const int cidx = (cy + 2) * WS + (cx + 2);

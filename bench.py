@@ -440,8 +440,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--scheme", default="mh", choices=["mh", "rk2", "rk3", "ctu"],
                     help="grid workloads: predictor-corrector step (default) or SSP Runge-Kutta steps")
-    ap.add_argument("--copy-probe", type=float, default=0.0,
-                    help="also run the streaming copy probe on this many GiB (roofline calibration)")
+    ap.add_argument("--copy-probe", type=float, default=1.0,
+                    help="streaming copy probe on this many GiB: the achievable HBM bandwidth, reported "
+                         "beside the roofline and used to calibrate the traffic counters (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path has no multi-GPU exchange)",
@@ -543,8 +544,10 @@ def main():
         t1.record(stream)
         t1.synchronize()
         cms = t0.elapsed_time(t1) / 5
-        out["copy_probe"] = {"bytes_read": 8 * n, "bytes_written": 8 * n, "ms": cms,
-                             "GB/s": 16 * n / (cms * 1e-3) / 1e9}
+        gbs = 16 * n / (cms * 1e-3) / 1e9
+        out["copy_probe"] = {"bytes_read": 8 * n, "bytes_written": 8 * n, "ms": cms, "GB/s": gbs,
+                             "frac_of_peak": gbs / HBM_PEAK_GBS,
+                             "step_over_copy": out["roofline"]["achieved"] / gbs}
         del src, dst
     if not args.no_cpu_baseline and args.scheme == "mh":
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -269,3 +269,21 @@ def test_sedov_full_configuration_hundred_steps(hy):
     c = nb // 2
     _full_trajectory(hy, P, 100, sorted({(c - 1) + nb * ((c - 1) + nb * (c - 1)), c + nb * (c + nb * c), 0,
                                          P.nblk - 1}))
+
+
+@pytest.mark.parametrize("n", [1, 511, 2049, 20481, 3 * 20480 + 7777, 1 << 22])
+def test_copy_probe_copies_every_element(n):
+    """The bandwidth probe copies exactly n doubles (chunk tails, odd n)."""
+    import torch
+
+    from paper_2208_11630_amd import hydro
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    src = torch.arange(n + 64, dtype=torch.float64, device="cuda:0")
+    dst = torch.full_like(src, -1.0)
+    s = torch.cuda.current_stream()
+    hydro.copy_probe(src[:n], dst[:n], s)
+    s.synchronize()
+    assert torch.equal(dst[:n], src[:n])
+    assert bool((dst[n:] == -1.0).all())

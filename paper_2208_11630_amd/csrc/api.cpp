@@ -179,11 +179,16 @@ int do_rk_step(hydro_grid* g, double dt, double cfl) {
   return HYDRO_OK;
 }
 
-// CTU scratch: blocks per launch so that one launch's slices fit 8 GiB.
+// CTU scratch: blocks per launch so that one launch's slices fit 8 GiB,
+// rounded down to whole rounds of 768 workgroups (three per CU on 256 CUs,
+// as many as the kernel's registers let reside at once) when more than one
+// round fits, so that no launch ends on a partly filled round.
 long ctu_chunk(const hydro_grid_desc* d) {
+  constexpr long kRound = 768;
   const long nblk = (long)d->nblk[0] * d->nblk[1] * d->nblk[2];
   const long per = hydro::ctu_block_doubles(d->nxb) * (long)sizeof(double);
-  const long fit = per > 0 ? (8L << 30) / per : 1;
+  long fit = per > 0 ? (8L << 30) / per : 1;
+  if (fit >= kRound) fit = fit / kRound * kRound;
   return std::max(1L, std::min(nblk, fit));
 }
 

@@ -842,6 +842,15 @@ __device__ __forceinline__ bool corrected_prim(const double (&u)[5], double gamm
   return w[4] > 0.0;
 }
 
+// Cell (x, y, z) number it of a box of ext[0] x ext[1] x ext[2] cells
+// starting at lo, x fastest: consecutive threads touch consecutive
+// addresses of the stage arrays, whichever face direction a stage runs.
+__device__ __forceinline__ void ctu_cell(int it, const int (&ext)[3], const int (&lo)[3], int (&c3)[3]) {
+  c3[0] = it % ext[0] + lo[0];
+  c3[1] = (it / ext[0]) % ext[1] + lo[1];
+  c3[2] = it / (ext[0] * ext[1]) + lo[2];
+}
+
 template <int N>
 __global__ __launch_bounds__(256) void ctu_kernel(GridGeom g, StepArgs a, double* __restrict__ scratch, long b0) {
   using C = Ctu<N>;
@@ -929,14 +938,12 @@ __global__ __launch_bounds__(256) void ctu_kernel(GridGeom g, StepArgs a, double
   // 2. 1-D fluxes at the low d-face of cells with c_d in 0..N (others -1..N)
   for (int d = 0; d < 3; ++d) {
     const int cnt = (N + 1) * m * m;
+    int ext[3] = {m, m, m}, lo[3] = {-1, -1, -1};   // transverse axes -1..N
+    ext[d] = N + 1;                                   // along d 0..N
+    lo[d] = 0;
     for (int it = tid; it < cnt; it += 256) {
       int c3[3];
-      const int a0 = it % m, a1 = (it / m) % m, a2 = it / (m * m);  // a2 runs 0..N along d
-      // map (a0, a1) to the two transverse axes and a2 to d
-      const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-      c3[t0] = a0 - 1;
-      c3[t1] = a1 - 1;
-      c3[d] = a2;
+      ctu_cell(it, ext, lo, c3);
       const int hi = C::ci(c3[0], c3[1], c3[2]);
       const int lo = C::ci(c3[0] - (d == 0), c3[1] - (d == 1), c3[2] - (d == 2));
       double L[5], R[5], F[5];
@@ -958,11 +965,16 @@ __global__ __launch_bounds__(256) void ctu_kernel(GridGeom g, StepArgs a, double
     for (int q = 0; q < 2; ++q) {
       const int t = tr[d][q], r = 3 - d - t;
       const int cnt = (N + 1) * N * m;
+      int ext[3], lo[3];
+      ext[d] = N + 1;   // 0..N
+      lo[d] = 0;
+      ext[t] = N;       // 0..N-1
+      lo[t] = 0;
+      ext[r] = m;       // -1..N
+      lo[r] = -1;
       for (int it = tid; it < cnt; it += 256) {
         int c3[3];
-        c3[r] = it % m - 1;
-        c3[t] = (it / m) % N;
-        c3[d] = it / (m * N);
+        ctu_cell(it, ext, lo, c3);
         double side[2][5];
         for (int sd = 0; sd < 2; ++sd) {
           const int ci = c3[0] - (sd == 0 && d == 0), cj = c3[1] - (sd == 0 && d == 1), ck = c3[2] - (sd == 0 && d == 2);
@@ -996,11 +1008,11 @@ __global__ __launch_bounds__(256) void ctu_kernel(GridGeom g, StepArgs a, double
     const int kt = tr[t][0] == u_ ? 0 : 1;   // F_{t|u} index among t's pair
     const int ku = tr[u_][0] == t ? 0 : 1;   // F_{u|t} index among u's pair
     const int cnt = (N + 1) * N * N;
+    int ext[3] = {N, N, N}, lo[3] = {0, 0, 0};
+    ext[d] = N + 1;
     for (int it = tid; it < cnt; it += 256) {
       int c3[3];
-      c3[t] = it % N;
-      c3[u_] = (it / N) % N;
-      c3[d] = it / (N * N);
+      ctu_cell(it, ext, lo, c3);
       double side[2][5];
       for (int sd = 0; sd < 2; ++sd) {
         const int ci = c3[0] - (sd == 0 && d == 0), cj = c3[1] - (sd == 0 && d == 1), ck = c3[2] - (sd == 0 && d == 2);

@@ -774,7 +774,7 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void stage_kernel(GridGeom g, StepA
 // on a mixed ensemble).  An item of a member of another size would be
 // skipped, never misread.
 template <int N>
-__global__ __launch_bounds__(256, 2) void batch_step_kernel(const BatchSim* __restrict__ sims,
+__global__ __launch_bounds__(Tile<(N == 8 ? 8 : 16)>::NT, 2) void batch_step_kernel(const BatchSim* __restrict__ sims,
                                                             const BatchItem* __restrict__ items, int nitems,
                                                             long step, double cfl, int nseg) {
   constexpr int T = N == 8 ? 8 : 16;
@@ -1814,18 +1814,20 @@ hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, double* scr
 
 hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,
                              int nxb, int nseg, int grid, hipStream_t s) {
+  // 8^3 blocks: 128-thread workgroups (the 8x8 tile's roles), twice as many
+  // of them, so a CU holds the same number of wavefronts
   switch (nxb) {
     case 8:
-      hipLaunchKernelGGL(batch_step_kernel<8>, dim3((unsigned)grid), dim3(256), 0, s, sims, items, nitems, step, cfl,
-                         nseg);
+      hipLaunchKernelGGL(batch_step_kernel<8>, dim3((unsigned)(2 * grid)), dim3(Tile<8>::NT), 0, s, sims, items,
+                         nitems, step, cfl, nseg);
       break;
     case 16:
-      hipLaunchKernelGGL(batch_step_kernel<16>, dim3((unsigned)grid), dim3(256), 0, s, sims, items, nitems, step,
-                         cfl, nseg);
+      hipLaunchKernelGGL(batch_step_kernel<16>, dim3((unsigned)grid), dim3(Tile<16>::NT), 0, s, sims, items, nitems,
+                         step, cfl, nseg);
       break;
     case 32:
-      hipLaunchKernelGGL(batch_step_kernel<32>, dim3((unsigned)grid), dim3(256), 0, s, sims, items, nitems, step,
-                         cfl, nseg);
+      hipLaunchKernelGGL(batch_step_kernel<32>, dim3((unsigned)grid), dim3(Tile<16>::NT), 0, s, sims, items, nitems,
+                         step, cfl, nseg);
       break;
     default: return hipErrorInvalidValue;
   }

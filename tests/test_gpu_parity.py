@@ -124,27 +124,74 @@ def test_uniform_state_preserved_bitwise(hy):
     assert np.array_equal(ics.interior(out, 16), ics.interior(P.U, 16))
 
 
-def test_fallback_events_match(hy):
-    L, n = 32, 8
-    x = (np.arange(L) + 0.5) / L
-    p1 = np.where(x < 0.5, 1e-6, 1.0)
-    Z, Y, X = n, n, L
-    f = lambda a: np.broadcast_to(a[None, None, :], (Z, Y, X)).copy()
-    zero = np.zeros((Z, Y, X))
-    P = ics.from_primitive("jump", n, f(np.ones(L)), f(np.full(L, 1.0)), zero, zero, f(p1), 1.4,
-                           (1.0 / L,) * 3, (0, 0, 0))
+def _events_problem():
+    """Random-state jump problem (pressure 1e-6 | 1 along x, outflow x) whose
+    steps fall back to first order at the jump."""
+    n, L = 8, 32
+    Z, Y, X = 16, 8, L
+    rng = np.random.default_rng(41)
+    x = (np.arange(X) + 0.5) / X
+    rho = np.exp(0.1 * rng.normal(size=(Z, Y, X)))
+    u = 0.6 + 0.05 * rng.normal(size=(Z, Y, X))
+    v = 0.1 * rng.normal(size=(Z, Y, X))
+    w = np.zeros((Z, Y, X))
+    p = np.broadcast_to(np.where(x < 0.5, 1e-6, 1.0)[None, None, :], (Z, Y, X)).copy()
+    return ics.from_primitive("events", n, rho, u, v, w, p, 1.4, (1.0 / X,) * 3, (1, 0, 0))
+
+
+def _plant_low_energy(Uc, rng, k=6):
+    """Input construction: k random cells get a total energy of a tenth of
+    their kinetic energy (a negative gamma-law pressure, so the floor must act;
+    the energy their faces carry out then drives some of them to E <= 0)."""
+    nblk, _, n = Uc.shape[:3]
+    for _ in range(k):
+        b = rng.integers(nblk)
+        i, j, l = rng.integers(n, size=3)
+        r, mx, my, mz = Uc[b, 0:4, l, j, i]
+        Uc[b, 4, l, j, i] = 0.05 * (mx * mx + my * my + mz * mz) / r
+
+
+def _decision_margins(Uc, gamma, small_p):
+    """Distance of each event decision from its threshold, from the state in
+    numpy: min |p - small_p| / |E| (the floor) and min |E| / max|E|, min rho
+    (the nonphysical check), so that no decision sits within rounding."""
+    r, mx, my, mz, E = (Uc[:, i] for i in range(5))
+    p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my + mz * mz) / r)
+    return (float((np.abs(p - small_p) / np.abs(E)).min()), float(np.abs(E).min() / np.abs(E).max()),
+            float(r.min()))
+
+
+@pytest.mark.parametrize("plant", [False, True], ids=["jump", "jump_and_low_energy_cells"])
+def test_event_counters_match_every_step(hy, plant):
+    """Steps whose pressure floor and first-order fallback fire (a pressure
+    jump) and, with planted low-energy cells, whose nonphysical check fires
+    too: the state agrees to 1e-12 and the three event counters equal the
+    oracle's running totals after every step (both sides restart each step
+    from the oracle's state)."""
+    P = _events_problem()
     g = ogrid(P)
-    U = P.U.copy()
+    n = P.n
+    Uc = P.Uc.copy()
+    prng = np.random.default_rng(7)
     Gd = hy.grid_for(P)
     total = np.zeros(3, dtype=np.int64)
-    for s in range(10):
+    for s in range(8):
+        if plant:
+            _plant_low_energy(Uc, prng)
+        m_floor, m_energy, rho_min = _decision_margins(Uc, P.gamma, P.small_p)
+        assert m_floor > 1e-9 and m_energy > 1e-6 and rho_min > 0.1, (s, m_floor, m_energy, rho_min)
+        Gd.upload(Uc)
+        U = ics.guard_layout(Uc, n)
         dt = oracle.dt(g, U, 0.8)
         U, c = oracle.step(g, U, dt)
         total += c
         Gd.step(dt)
-        assert_parity(Gd.download(), U, n, f"jump step {s}")
-        Gd.upload(np.ascontiguousarray(ics.interior(U, n)))  # both restart from the oracle's state
-    assert total[1] > 0
+        assert_parity(Gd.download(), U, n, f"events step {s}")
+        assert Gd.counters().tolist() == total.tolist(), (s, Gd.counters(), total)
+        Uc = np.ascontiguousarray(ics.interior(U, n))
+    assert total[0] > 0 and total[1] > 0
+    if plant:
+        assert total[2] > 0
 
 
 # ---- trajectories: each side picks its own dt -------------------------------------
@@ -237,38 +284,78 @@ def test_sedov_full_size_sampled_blocks(hy):
 
 # ---- full configurations run to their step counts ------------------------------------
 
-def _full_trajectory(hy, P, steps, blocks):
+def _rel_errors_device(got, ref):
+    """rel_errors on device tensors [nblk, 5, n, n, n] (whole grids)."""
+    import torch
+
+    rho_max = ref[:, 0].abs().max()
+    mom = torch.sqrt((ref[:, 1] ** 2 + ref[:, 2] ** 2) + ref[:, 3] ** 2).max()
+    errs = []
+    for v in range(5):
+        d = (got[:, v] - ref[:, v]).abs().max()
+        den = mom if v in (1, 2, 3) else ref[:, v].abs().max()
+        if float(den) == 0.0:
+            den = rho_max
+        errs.append(float(d / den))
+    return np.array(errs)
+
+
+def _full_trajectory(hy, P, steps, planes_list, compare_every=1):
     """Each side runs the configuration for its step count with its own dt
-    (device dt on the GPU); sampled blocks and the final dt agree."""
+    (device dt on the GPU), on one GPU grid per z-pencil length in
+    planes_list (None: the autotuner's choice).  Every block, all five
+    variables, agrees to 1e-12 after every compare_every-th step and the
+    last one; every step's dt agrees to 1e-14; counters stay zero."""
+    import torch
+
+    from paper_2208_11630_amd import tune
+
     g = ogrid(P)
-    Gd = hy.grid_for(P)
+    grids = []
+    for planes in planes_list:
+        Gd = hy.grid_for(P)
+        if planes is None:
+            planes = tune.tune_grid(Gd, P.cfl, use_cache=False)
+        else:
+            Gd.set_pencil_planes(planes)
+        print(f"[parity] {P.name}: GPU grid with {planes}-plane z pencils", flush=True)
+        grids.append((planes, Gd))
     U = P.U.copy()
-    for _ in range(steps):
-        Gd.step_cfl(P.cfl)
+    for s in range(steps):
+        for _, Gd in grids:
+            Gd.step_cfl(P.cfl)
         d = oracle.dt(g, U, P.cfl)
         U, cnt = oracle.step(g, U, d)
         assert cnt.tolist() == [0, 0, 0]
-    assert abs(Gd.last_dt() / d - 1.0) <= DT_TOL
-    got = Gd.state[blocks].cpu().numpy()
-    assert_parity(got, ics.interior(U, P.n)[blocks], P.n, f"{P.name} after {steps} steps")
-    assert Gd.counters().tolist() == [0, 0, 0]
+        for planes, Gd in grids:
+            assert abs(Gd.last_dt() / d - 1.0) <= DT_TOL, (planes, s, Gd.last_dt(), d)
+        if (s + 1) % compare_every == 0 or s + 1 == steps:
+            ref = torch.from_numpy(np.ascontiguousarray(ics.interior(U, P.n))).to(grids[0][1].state.device)
+            for planes, Gd in grids:
+                Gd.stream.synchronize()
+                e = _rel_errors_device(Gd.state, ref)
+                assert np.all(e <= TOL), f"{P.name} step {s + 1}, {planes}-plane pencils: relative errors {e}"
+            del ref
+    for planes, Gd in grids:
+        assert Gd.counters().tolist() == [0, 0, 0], planes
+        Gd.close()
 
 
 def test_kh_full_configuration_ten_steps(hy):
+    """KH 512x512x256 for its 10 steps, every block after every step: at the
+    one-block pencils, at the 64-plane pencils the benchmark times and at
+    the autotuner's choice."""
     print("\n[parity] KH 512x512x256, 10 steps", flush=True)
     P = ics.kelvin_helmholtz()
-    nbx, nby, nbz = P.nb
-    _full_trajectory(hy, P, 10, sorted({0, nbx * (nby // 4), nbx * nby * (nbz // 2) + nbx * (3 * nby // 4) + 7,
-                                        P.nblk - 1, 4321}))
+    _full_trajectory(hy, P, 10, [P.n, 64, None])
 
 
 def test_sedov_full_configuration_hundred_steps(hy):
+    """Sedov 256^3 for its 100 steps, every block every 10 steps, at the
+    one-block pencils and at the autotuner's choice."""
     print("\n[parity] Sedov 256^3, 100 steps", flush=True)
     P = ics.sedov()
-    nb = P.nb[0]
-    c = nb // 2
-    _full_trajectory(hy, P, 100, sorted({(c - 1) + nb * ((c - 1) + nb * (c - 1)), c + nb * (c + nb * c), 0,
-                                         P.nblk - 1}))
+    _full_trajectory(hy, P, 100, [P.n, None], compare_every=10)
 
 
 @pytest.mark.parametrize("n", [1, 511, 2049, 20481, 3 * 20480 + 7777, 1 << 22])

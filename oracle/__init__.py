@@ -95,6 +95,12 @@ def lib():
         L.oracle_ctu_block.restype = None
         L.oracle_step_ctu.argtypes = [gp, dp, dp, ctypes.c_double, lp]
         L.oracle_step_ctu.restype = None
+        L.oracle_ctu_char_block.argtypes = [gp, dp, ctypes.c_long, dp, ctypes.c_double, lp]
+        L.oracle_ctu_char_block.restype = None
+        L.oracle_step_ctu_char.argtypes = [gp, dp, dp, ctypes.c_double, lp]
+        L.oracle_step_ctu_char.restype = None
+        L.oracle_trace_faces.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.oracle_trace_faces.restype = None
         L.oracle_max_signal_dir.argtypes = [gp, dp, ctypes.c_long, ctypes.c_long]
         L.oracle_max_signal_dir.restype = ctypes.c_double
         L.oracle_dt_ctu.argtypes = [gp, dp, ctypes.c_double]
@@ -255,14 +261,44 @@ def stage_block(g: Grid, U: np.ndarray, b: int, dt: float, U0: np.ndarray = None
     return out, np.array(list(cnt), dtype=np.int64)
 
 
-def step_ctu(g: Grid, U: np.ndarray, dt: float):
-    """One corner-transport-upwind step: returns (U_new, counters)."""
+def step_ctu(g: Grid, U: np.ndarray, dt: float, trace: bool = False):
+    """One corner-transport-upwind step: returns (U_new, counters).  trace:
+    characteristic tracing in the normal predictor."""
     g.check(U)
     out = U.copy()
     cnt = (ctypes.c_long * 3)(0, 0, 0)
     gc = g.c()
-    lib().oracle_step_ctu(ctypes.byref(gc), _dptr(U), _dptr(out), float(dt), cnt)
+    fn = lib().oracle_step_ctu_char if trace else lib().oracle_step_ctu
+    fn(ctypes.byref(gc), _dptr(U), _dptr(out), float(dt), cnt)
     return out, np.array(list(cnt), dtype=np.int64)
+
+
+def step_ctu_blocks(g: Grid, U: np.ndarray, blocks: Sequence[int], dt: float, trace: bool = False):
+    """CTU step of the listed blocks only (U's guards are filled here):
+    returns (their new interiors [len(blocks), 5, n, n, n], counters)."""
+    g.check(U)
+    fill_guards(g, U)
+    gc = g.c()
+    cnt = (ctypes.c_long * 3)(0, 0, 0)
+    fn = lib().oracle_ctu_char_block if trace else lib().oracle_ctu_block
+    outs = []
+    for b in blocks:
+        o = np.ascontiguousarray(U[b]).copy()
+        fn(ctypes.byref(gc), _dptr(U), int(b), _dptr(o), float(dt), cnt)
+        outs.append(o)
+    n, ng = g.n, g.ng
+    out = np.stack(outs)[:, :, ng:ng + n, ng:ng + n, ng:ng + n]
+    return np.ascontiguousarray(out), np.array(list(cnt), dtype=np.int64)
+
+
+def trace_faces(W, S, d: int, lam: float, gamma: float):
+    """Traced (low, high) face states of one cell along d (oracle_trace_faces)."""
+    Wa = np.ascontiguousarray(W, dtype=np.float64)
+    Sa = np.ascontiguousarray(S, dtype=np.float64)
+    lo = np.zeros(5)
+    hi = np.zeros(5)
+    lib().oracle_trace_faces(_dptr(Wa), _dptr(Sa), int(d), float(lam), float(gamma), _dptr(lo), _dptr(hi))
+    return lo, hi
 
 
 def dt_ctu(g: Grid, U: np.ndarray, cfl: float) -> float:
@@ -284,17 +320,19 @@ def dt(g: Grid, U: np.ndarray, cfl: float) -> float:
     return lib().oracle_dt(ctypes.byref(gc), _dptr(U), float(cfl))
 
 
-def run(g: Grid, U: np.ndarray, nsteps: int, cfl: float = 0.8, callback=None, rk: int = 0, ctu: bool = False):
+def run(g: Grid, U: np.ndarray, nsteps: int, cfl: float = 0.8, callback=None, rk: int = 0, ctu: bool = False,
+        trace: bool = False):
     """n repetitions of (dt = CFL/max signal; step(dt)); returns (U, dts, counters).
     rk = 2 or 3 takes SSP Runge-Kutta steps instead of predictor-corrector
-    ones; ctu takes corner-transport-upwind steps with the per-direction rule."""
+    ones; ctu takes corner-transport-upwind steps with the per-direction rule
+    (trace: with characteristic tracing)."""
     dts = []
     cnt = np.zeros(3, dtype=np.int64)
     for s in range(nsteps):
         d = dt_ctu(g, U, cfl) if ctu else dt(g, U, cfl)
         if not d > 0:
             raise FloatingPointError("non-positive or non-finite dt at step %d" % s)
-        U, c = step_ctu(g, U, d) if ctu else (step_rk(g, U, d, rk) if rk else step(g, U, d))
+        U, c = step_ctu(g, U, d, trace) if ctu else (step_rk(g, U, d, rk) if rk else step(g, U, d))
         cnt += c
         dts.append(d)
         if callback is not None:

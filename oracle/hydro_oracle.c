@@ -456,7 +456,59 @@ static int corrected_prim(const double U[5], double gamma, double W[5]) {
   return 1;
 }
 
-void oracle_ctu_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+/* Characteristic tracing of the normal predictor (Colella 1990; the
+ * upwind-projection form of Stone et al. 2008, §4.2): the primitive slope S
+ * along d is split over the right eigenvectors of the primitive Jacobian
+ * A_d(W), S = sum_k beta_k R_k with beta_k = L_k . S, and each face keeps
+ * only the waves that move toward it during the step:
+ *   high face: W + sum_{lambda_k > 0} (1 - lam lambda_k)/2 beta_k R_k
+ *   low face:  W - sum_{lambda_k < 0} (1 + lam lambda_k)/2 beta_k R_k
+ * (lam = dt/dx_d).  With c = sqrt(gamma p / rho) and u the normal velocity
+ * the waves of A_d in (rho, u_n, u_t1, u_t2, p) are
+ *   lambda = u - c:  beta = (dp/c^2 - rho du_n/c)/2,  R = (1, -c/rho, 0, 0, c^2)
+ *   lambda = u:      the entropy and shear waves, beta R =
+ *                    (drho - dp/c^2, 0, du_t1, du_t2, 0)
+ *   lambda = u + c:  beta = (dp/c^2 + rho du_n/c)/2,  R = (1, c/rho, 0, 0, c^2)
+ * (vector slots in the solver's order: normal velocity in slot 1 + d). */
+void oracle_trace_faces(const double W[5], const double S[5], int d, double lam, double gamma, double lo[5],
+                        double hi[5]) {
+  const double rho = W[0], un = W[1 + d], p = W[4];
+  const double c = sqrt(gamma * p / rho);
+  double wave[3][5], speed[3];
+  for (int k = 0; k < 3; ++k)
+    for (int v = 0; v < 5; ++v) wave[k][v] = 0.0;
+  /* the acoustic waves, beta_k R_k */
+  const double bm = 0.5 * (S[4] / (c * c) - rho * S[1 + d] / c);
+  const double bp = 0.5 * (S[4] / (c * c) + rho * S[1 + d] / c);
+  wave[0][0] = bm;
+  wave[0][1 + d] = -bm * c / rho;
+  wave[0][4] = bm * c * c;
+  wave[2][0] = bp;
+  wave[2][1 + d] = bp * c / rho;
+  wave[2][4] = bp * c * c;
+  /* entropy and shear waves together */
+  for (int v = 1; v < 4; ++v)
+    if (v != 1 + d) wave[1][v] = S[v];
+  wave[1][0] = S[0] - S[4] / (c * c);
+  speed[0] = un - c;
+  speed[1] = un;
+  speed[2] = un + c;
+  for (int v = 0; v < 5; ++v) {
+    hi[v] = W[v];
+    lo[v] = W[v];
+  }
+  for (int k = 0; k < 3; ++k) {
+    if (speed[k] > 0.0)
+      for (int v = 0; v < 5; ++v) hi[v] += 0.5 * (1.0 - lam * speed[k]) * wave[k][v];
+    if (speed[k] < 0.0)
+      for (int v = 0; v < 5; ++v) lo[v] -= 0.5 * (1.0 + lam * speed[k]) * wave[k][v];
+  }
+}
+
+/* trace = 1: the normal predictor traces characteristics
+ * (oracle_trace_faces); 0: primitive-form half step W_d = W - lam_d/2 A_d S_d
+ * with face states W_d -+ S_d/2. */
+static void ctu_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt, int trace,
                       long cnt[ORACLE_NCNT]) {
   const int n = g->n;
   const double gamma = g->gamma;
@@ -497,12 +549,16 @@ void oracle_ctu_block(const oracle_grid *g, const double *U, long b, double *Uo,
         double *wf = Wf + 30 * CI(i, j, k);
         int bad = 0;
         for (int d = 0; d < 3; ++d) {
-          double A[5], Wt[5];
-          jacobian_times(W, d, gamma, Sl[d], A);
-          for (int v = 0; v < 5; ++v) Wt[v] = W[v] - 0.5 * lam[d] * A[v];
-          for (int v = 0; v < 5; ++v) {
-            wf[(2 * d + 0) * 5 + v] = Wt[v] - 0.5 * Sl[d][v];
-            wf[(2 * d + 1) * 5 + v] = Wt[v] + 0.5 * Sl[d][v];
+          if (trace) {
+            oracle_trace_faces(W, Sl[d], d, lam[d], gamma, wf + (2 * d + 0) * 5, wf + (2 * d + 1) * 5);
+          } else {
+            double A[5], Wt[5];
+            jacobian_times(W, d, gamma, Sl[d], A);
+            for (int v = 0; v < 5; ++v) Wt[v] = W[v] - 0.5 * lam[d] * A[v];
+            for (int v = 0; v < 5; ++v) {
+              wf[(2 * d + 0) * 5 + v] = Wt[v] - 0.5 * Sl[d][v];
+              wf[(2 * d + 1) * 5 + v] = Wt[v] + 0.5 * Sl[d][v];
+            }
           }
           for (int sd = 0; sd < 2; ++sd)
             if (!(wf[(2 * d + sd) * 5 + 0] > 0.0) || !(wf[(2 * d + sd) * 5 + 4] > 0.0)) bad = 1;
@@ -612,14 +668,25 @@ void oracle_ctu_block(const oracle_grid *g, const double *U, long b, double *Uo,
   free(Ff);
 }
 
-void oracle_step_ctu(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]) {
+void oracle_ctu_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+                      long cnt[ORACLE_NCNT]) {
+  ctu_block(g, U, b, Uo, dt, 0, cnt);
+}
+
+void oracle_ctu_char_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+                           long cnt[ORACLE_NCNT]) {
+  ctu_block(g, U, b, Uo, dt, 1, cnt);
+}
+
+static void step_ctu_all(const oracle_grid *g, double *U, double *Unew, double dt, int trace,
+                         long cnt[ORACLE_NCNT]) {
   long nblk = (long)g->nb[0] * g->nb[1] * g->nb[2];
   oracle_fill_guards(g, U);
   long c0 = 0, c1 = 0, c2 = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : c0, c1, c2)
   for (long b = 0; b < nblk; ++b) {
     long c[ORACLE_NCNT] = {0, 0, 0};
-    oracle_ctu_block(g, U, b, Unew + (size_t)b * oracle_block_doubles(g), dt, c);
+    ctu_block(g, U, b, Unew + (size_t)b * oracle_block_doubles(g), dt, trace, c);
     c0 += c[0];
     c1 += c[1];
     c2 += c[2];
@@ -627,6 +694,14 @@ void oracle_step_ctu(const oracle_grid *g, double *U, double *Unew, double dt, l
   cnt[ORACLE_CNT_FLOOR] += c0;
   cnt[ORACLE_CNT_FALLBACK] += c1;
   cnt[ORACLE_CNT_NONPHYS] += c2;
+}
+
+void oracle_step_ctu(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]) {
+  step_ctu_all(g, U, Unew, dt, 0, cnt);
+}
+
+void oracle_step_ctu_char(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]) {
+  step_ctu_all(g, U, Unew, dt, 1, cnt);
 }
 
 /* ---- a6: CFL signal speed and dt ---------------------------------------- */

@@ -127,6 +127,19 @@ void oracle_ctu_block(const oracle_grid *g, const double *U, long b, double *Uo,
 /* One CTU step of the whole grid (fills U's guards first). */
 void oracle_step_ctu(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]);
 
+/* The same CTU step with characteristic tracing in its normal predictor
+ * (the unsplit solver of §2.2 as Lee's papers describe it: the slopes are
+ * projected onto the characteristic waves of A_d and each face keeps the
+ * waves moving toward it; see oracle_trace_faces). */
+void oracle_ctu_char_block(const oracle_grid *g, const double *U, long b, double *Uo, double dt,
+                           long cnt[ORACLE_NCNT]);
+void oracle_step_ctu_char(const oracle_grid *g, double *U, double *Unew, double dt, long cnt[ORACLE_NCNT]);
+
+/* Traced face states of one cell along d (primitive W, van Leer primitive
+ * slope S, lam = dt/dx_d): lo / hi receive the low / high face states. */
+void oracle_trace_faces(const double W[5], const double S[5], int d, double lam, double gamma, double lo[5],
+                        double hi[5]);
+
 /* max over interior cells of sum_d (|u_d| + c)/dx_d; the block range [b0,b1). */
 double oracle_max_signal(const oracle_grid *g, const double *U, long b0, long b1);
 /* dt = cfl / max signal over all blocks; returns -1 when the maximum is not positive and finite. */

@@ -53,6 +53,14 @@ MUTATIONS = {
     "ctu_final_cross_index": ("const int kt = tr[t][0] == u ? 0 : 1;", "const int kt = tr[t][0] == u ? 1 : 0;"),
     "ctu_corner_uses_own_direction": ("(F1[15 * ch + 5 * t + v] - F1[15 * cc + 5 * t + v])",
                                       "(F1[15 * ch + 5 * d + v] - F1[15 * cc + 5 * d + v])"),
+    "ctu_trace_acoustic_sign": ("const double bm = 0.5 * (S[4] / (c * c) - rho * S[1 + d] / c);",
+                                "const double bm = 0.5 * (S[4] / (c * c) + rho * S[1 + d] / c);"),
+    "ctu_trace_courant_sign": ("hi[v] += 0.5 * (1.0 - lam * speed[k]) * wave[k][v];",
+                               "hi[v] += 0.5 * (1.0 + lam * speed[k]) * wave[k][v];"),
+    "ctu_trace_entropy_drops_dp": ("wave[1][0] = S[0] - S[4] / (c * c);", "wave[1][0] = S[0];"),
+    "ctu_trace_normal_eigvec_sign": ("wave[2][1 + d] = bp * c / rho;", "wave[2][1 + d] = -bp * c / rho;"),
+    "ctu_trace_keeps_waves_moving_away": ("    if (speed[k] < 0.0)\n      for (int v = 0; v < 5; ++v) lo[v]",
+                                          "    if (speed[k] != 0.0)\n      for (int v = 0; v < 5; ++v) lo[v]"),
     "ctu_dt_sums_directions": ("else if (s > smax) smax = s;\n          }\n        }\n  }\n  return bad ? NAN : smax;\n}\n\ndouble oracle_dt_ctu",
                                "else if (s > smax) smax = s;\n          }\n        }\n  }\n  return bad ? NAN : 3.0 * smax;\n}\n\ndouble oracle_dt_ctu"),
 }

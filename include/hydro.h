@@ -261,6 +261,30 @@ int hydro_batch_dts(hydro_batch *b, double *dt_out);
 /* Destroy the batch (host metadata only); members become free grids. */
 int hydro_batch_free(hydro_batch *b);
 
+/* Allocation-free batch steps, for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc): the same
+ * steps as hydro_batch_create + hydro_batch_step(cfl, nsteps) +
+ * hydro_batch_free over the n grids (distinct, not in a batch, predictor-
+ * corrector scheme), with the member table and work list in the library's
+ * own static device scratch instead of a caller workspace.  The scratch is
+ * one file-scope array per device, held until the process ends, sized for
+ * HYDRO_STATIC_MAX_GRIDS grids and HYDRO_STATIC_MAX_ITEMS work items (one
+ * item per z pencil of a column tile: nblk * (nxb/16)^2 * nseg per grid, or
+ * nblk * nseg for nxb = 8).  nseg: z pencils per column for nxb 8, 16, 32
+ * (1, 2 or 4 each; NULL for 1, 1, 1).  Plain launches, 2 persistent
+ * workgroups per CU; results bitwise equal to the handle-based batch.  The
+ * grids' handles advance as after hydro_batch_step.  Every call on a device
+ * shares that device's scratch and overwrites it (the tables are uploaded
+ * on `stream` before the launches that read them): calls on one stream are
+ * ordered, calls that overlap on different streams of one device race.
+ * Calls no hipMalloc / hipFree.  Async.  Errors: HYDRO_ESIZE (more grids or
+ * items than the limits), HYDRO_EINVAL (as hydro_batch_create / _step),
+ * HYDRO_EDEVICE. */
+#define HYDRO_STATIC_MAX_GRIDS 4096
+#define HYDRO_STATIC_MAX_ITEMS 524288
+int hydro_batch_step_static(hydro_grid *const *grids, int n, const int nseg[3], double cfl, int nsteps,
+                            void *stream);
+
 /* Bandwidth probe (not part of the method): copies n doubles from src to dst
  * (device, 16-byte aligned, disjoint) with a plain streaming kernel on
  * `stream`.  Its runtime and HBM counters calibrate the roofline and

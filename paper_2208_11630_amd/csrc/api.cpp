@@ -19,6 +19,9 @@
 
 struct hydro_batch;
 
+static_assert(HYDRO_STATIC_MAX_GRIDS == hydro::kStaticMaxGrids, "static scratch: grid limit");
+static_assert(HYDRO_STATIC_MAX_ITEMS == hydro::kStaticMaxItems, "static scratch: item limit");
+
 struct hydro_grid {
   hydro_grid_desc d;
   hydro::GridGeom geom;
@@ -486,28 +489,29 @@ void drop_graph(hydro_batch* b) {
   b->graph = nullptr;
 }
 
-// Rebuild the member table and the work list from the grid handles (their
-// current buffer and signal slot) and upload both.
-int batch_upload(hydro_batch* b) {
-  hipStream_t s = (hipStream_t)b->stream;
-  const int n = (int)b->grids.size();
-  b->sims.resize(n);
-  b->items.clear();
-  // one contiguous range per block size (32^3 columns, then 16^3, then
-  // 8^3), each stepped by its own launch
+// Member table and work list of the grids (their current buffer and signal
+// slot): one contiguous work-list range per block size (32^3 columns, then
+// 16^3, then 8^3), each stepped by its own launch; inactive members get a
+// table entry but no items.  Launches the signal-speed reduction on `s` for
+// active members whose kept value is stale.
+int build_tables(hydro_grid* const* grids, int n, const unsigned char* active, const int nseg[3], hipStream_t s,
+                 std::vector<hydro::BatchSim>& sims, std::vector<hydro::BatchItem>& items, long cls_begin[3],
+                 long cls_count[3]) {
+  sims.resize(n);
+  items.clear();
   for (int cls = 2; cls >= 0; --cls) {
-    b->cls_begin[cls] = (long)b->items.size();
+    cls_begin[cls] = (long)items.size();
     for (int i = 0; i < n; ++i) {
-      hydro_grid* g = b->grids[i];
-      if (!b->active[i] || size_class(g->d.nxb) != cls) continue;
-      const long cols = columns_of(g) * b->nseg[cls];
-      for (long c = 0; c < cols; ++c) b->items.push_back(hydro::BatchItem{i, (int)c});
+      hydro_grid* g = grids[i];
+      if (!active[i] || size_class(g->d.nxb) != cls) continue;
+      const long cols = columns_of(g) * nseg[cls];
+      for (long c = 0; c < cols; ++c) items.push_back(hydro::BatchItem{i, (int)c});
     }
-    b->cls_count[cls] = (long)b->items.size() - b->cls_begin[cls];
+    cls_count[cls] = (long)items.size() - cls_begin[cls];
   }
   for (int i = 0; i < n; ++i) {
-    hydro_grid* g = b->grids[i];
-    hydro::BatchSim& m = b->sims[i];
+    hydro_grid* g = grids[i];
+    hydro::BatchSim& m = sims[i];
     m.U0 = g->d.U;
     m.U1 = g->d.U_alt;
     m.ws = ws_of(g);
@@ -516,11 +520,22 @@ int batch_upload(hydro_batch* b) {
     m.parity0 = g->cur;
     m.slot0 = slot_of(g);
     m.pad = 0;
-    if (b->active[i]) {
+    if (active[i]) {
       int rc = ensure_signal_on(g, s);
       if (rc) return rc;
     }
   }
+  return HYDRO_OK;
+}
+
+// Rebuild the member table and the work list from the grid handles and
+// upload both.
+int batch_upload(hydro_batch* b) {
+  hipStream_t s = (hipStream_t)b->stream;
+  const int n = (int)b->grids.size();
+  int rc = build_tables(b->grids.data(), n, b->active.data(), b->nseg, s, b->sims, b->items, b->cls_begin,
+                        b->cls_count);
+  if (rc) return rc;
   hipError_t e = hipMemcpyAsync(b->d_sims, b->sims.data(), sizeof(hydro::BatchSim) * n, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !b->items.empty())
     e = hipMemcpyAsync(b->d_items, b->items.data(), sizeof(hydro::BatchItem) * b->items.size(),
@@ -536,14 +551,20 @@ int batch_upload(hydro_batch* b) {
 // holds that size's tile step only (the classes' work-list ranges are
 // disjoint and every member sits in one class, so the launches are
 // independent; the stream orders them).
-hipError_t batch_launch(hydro_batch* b, double cfl, long step) {
+hipError_t class_launches(const hydro::BatchSim* d_sims, const hydro::BatchItem* d_items, const long cls_begin[3],
+                          const long cls_count[3], const int nseg[3], int grid, double cfl, long step, hipStream_t s) {
   for (int cls = 2; cls >= 0; --cls) {
-    if (b->cls_count[cls] == 0) continue;
-    hipError_t e = hydro::launch_batch_step(b->d_sims, b->d_items + b->cls_begin[cls], (int)b->cls_count[cls],
-                                            step % 6, cfl, 8 << cls, b->nseg[cls], b->grid, (hipStream_t)b->stream);
+    if (cls_count[cls] == 0) continue;
+    hipError_t e = hydro::launch_batch_step(d_sims, d_items + cls_begin[cls], (int)cls_count[cls], step % 6, cfl,
+                                            8 << cls, nseg[cls], grid, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t batch_launch(hydro_batch* b, double cfl, long step) {
+  return class_launches(b->d_sims, b->d_items, b->cls_begin, b->cls_count, b->nseg, b->grid, cfl, step,
+                        (hipStream_t)b->stream);
 }
 
 void advance_members(hydro_batch* b, int nsteps) {
@@ -709,6 +730,70 @@ int hydro_batch_free(hydro_batch* b) {
   drop_graph(b);
   for (hydro_grid* g : b->grids) g->batch = nullptr;
   delete b;
+  return HYDRO_OK;
+}
+
+int hydro_batch_step_static(hydro_grid* const* grids, int n, const int nseg[3], double cfl, int nsteps,
+                            void* stream) {
+  if (n > (int)hydro::kStaticMaxGrids)
+    return fail(HYDRO_ESIZE, "%d grids exceed the static scratch's %zu", n, hydro::kStaticMaxGrids);
+  if (!grids || n <= 0) return fail(HYDRO_EINVAL, "a batch needs at least one grid");
+  if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0 (got %g)", cfl);
+  if (nsteps < 0) return fail(HYDRO_EINVAL, "nsteps must be >= 0");
+  int segs[3] = {1, 1, 1};
+  if (nseg) {
+    const int sizes[3] = {8, 16, 32};
+    for (int c = 0; c < 3; ++c) {
+      if (nseg[c] != 1 && nseg[c] != 2 && nseg[c] != 4)
+        return fail(HYDRO_EINVAL, "pencils per column must be 1, 2 or 4");
+      if (sizes[c] / nseg[c] < 2) return fail(HYDRO_EINVAL, "pencils shorter than 2 planes");
+      segs[c] = nseg[c];
+    }
+  }
+  size_t nitems = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!grids[i]) return fail(HYDRO_EINVAL, "grid %d is NULL", i);
+    if (grids[i]->batch) return fail(HYDRO_EINVAL, "grid %d belongs to a batch", i);
+    if (grids[i]->scheme != HYDRO_SCHEME_MH)
+      return fail(HYDRO_EINVAL, "grid %d does not use the predictor-corrector scheme", i);
+    for (int k = 0; k < i; ++k)
+      if (grids[k] == grids[i]) return fail(HYDRO_EINVAL, "grid %d appears twice", i);
+    nitems += (size_t)columns_of(grids[i]) * segs[size_class(grids[i]->d.nxb)];
+  }
+  if (nitems > hydro::kStaticMaxItems)
+    return fail(HYDRO_ESIZE, "%zu work items exceed the static scratch's %zu", nitems, hydro::kStaticMaxItems);
+  if (nsteps == 0) return HYDRO_OK;
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "device query");
+  void* base = nullptr;
+  e = hydro::static_scratch(&base);
+  if (e != hipSuccess) return hip_fail(e, "static scratch lookup");
+  hipStream_t s = (hipStream_t)stream;
+  // host copies of the tables stay alive until the next call on this thread
+  thread_local std::vector<hydro::BatchSim> sims;
+  thread_local std::vector<hydro::BatchItem> items;
+  long cls_begin[3], cls_count[3];
+  const std::vector<unsigned char> active(n, 1);
+  int rc = build_tables(grids, n, active.data(), segs, s, sims, items, cls_begin, cls_count);
+  if (rc) return rc;
+  auto* d_sims = (hydro::BatchSim*)base;
+  auto* d_items = (hydro::BatchItem*)((char*)base + hydro::kStaticSimsBytes);
+  e = hipMemcpyAsync(d_sims, sims.data(), sizeof(hydro::BatchSim) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpyAsync(d_items, items.data(), sizeof(hydro::BatchItem) * items.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "static table upload");
+  for (int k = 0; k < nsteps; ++k) {
+    e = class_launches(d_sims, d_items, cls_begin, cls_count, segs, 2 * cus, cfl, k, s);
+    if (e != hipSuccess) return hip_fail(e, "batch step launch");
+  }
+  for (int i = 0; i < n; ++i) {
+    hydro_grid* g = grids[i];
+    g->cur ^= (nsteps & 1);
+    g->steps += (unsigned long long)nsteps;
+    g->sig_valid = true;
+  }
   return HYDRO_OK;
 }
 

@@ -66,6 +66,18 @@ struct BatchItem {
   int tile;           // pencil index inside the grid (see tile_step)
 };
 
+// The library's static device scratch (a file-scope array in
+// hydro_kernels.hip, one copy per device, held until the process ends): the
+// member table and work list of allocation-free batch steps.  Sizes are the
+// limits hydro.h states (HYDRO_STATIC_MAX_GRIDS, HYDRO_STATIC_MAX_ITEMS).
+constexpr size_t kStaticMaxGrids = 4096;
+constexpr size_t kStaticMaxItems = size_t(1) << 19;
+constexpr size_t kStaticSimsBytes = (kStaticMaxGrids * sizeof(BatchSim) + 255) / 256 * 256;
+constexpr size_t kStaticScratchBytes = kStaticSimsBytes + kStaticMaxItems * sizeof(BatchItem);
+// Device address of the scratch on the current device (looked up through
+// hipGetSymbolAddress on a device's first call, then kept per device).
+hipError_t static_scratch(void** ptr);
+
 // st == NULL: predictor-corrector step; else one method-of-lines stage.
 // plen: planes per z pencil (>= 2, divides the grid's z extent).
 hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const StageArgs* st, int plen,

@@ -29,6 +29,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace hydro {
 namespace {
 
@@ -1879,6 +1881,31 @@ hipError_t launch_copy(const double* src, double* dst, long n, hipStream_t s) {
   const long grid = (n + COPY_CHUNK - 1) / COPY_CHUNK;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)grid), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
+}
+
+// Static scratch of the allocation-free batch step.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol): it looks the device address up once per device and passes that.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_clear_slot(WorkHeader* ws, int slot, hipStream_t s) {

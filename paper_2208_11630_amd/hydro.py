@@ -99,6 +99,8 @@ SIGNATURES = {
     "hydro_batch_use_graph": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_batch_dts": ([_HP, _dp], ctypes.c_int),
     "hydro_batch_free": ([_HP], ctypes.c_int),
+    "hydro_batch_step_static": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                 ctypes.c_double, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "hydro_copy_probe": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "hydro_last_error": ([], ctypes.c_char_p),
 }
@@ -303,6 +305,28 @@ class Grid:
             self.close()
         except Exception:
             pass
+
+
+def batch_step_static(grids, cfl: float, nsteps: int = 1, nseg=None, stream=None) -> None:
+    """nsteps batched steps of the grids without a batch workspace
+    (hydro_batch_step_static: the tables live in the library's static device
+    scratch).  stream: a torch stream (default: the current one); it is
+    ordered after the work queued on the grids' streams, and the grids'
+    streams after it, so later calls on a grid see the new state."""
+    import torch
+
+    grids = list(grids)
+    n = len(grids)
+    arr = (ctypes.c_void_p * max(n, 1))(*[g.handle.value for g in grids])
+    s = stream if stream is not None else torch.cuda.current_stream(grids[0].bufs[0].device if n else None)
+    for g in grids:
+        if g.stream != s:
+            s.wait_stream(g.stream)
+    segs = None if nseg is None else (ctypes.c_int * 3)(*[int(x) for x in nseg])
+    _check(lib().hydro_batch_step_static(arr, n, segs, float(cfl), int(nsteps), s.cuda_stream))
+    for g in grids:
+        if g.stream != s:
+            g.stream.wait_stream(s)
 
 
 class Batch:

@@ -185,3 +185,13 @@ def test_amr_sizes_and_validation(L):
     assert L.hydro_amr_transfer(None, None) == hydro.HYDRO_EINVAL
     nf = ctypes.c_size_t()
     assert L.hydro_amr_estimate_tree(None, 0.01, 0.8, 0.2, 3, None, None, 0, ctypes.byref(nf)) == hydro.HYDRO_EINVAL
+
+
+def test_static_batch_rejects_too_many_grids_before_the_device(L):
+    """hydro_batch_step_static refuses more grids than its static scratch
+    holds (HYDRO_ESIZE) before reading any handle or touching a device."""
+    n = 4097
+    arr = (ctypes.c_void_p * n)()
+    assert L.hydro_batch_step_static(arr, n, None, 0.8, 1, None) == hydro.HYDRO_ESIZE
+    assert b"static scratch" in L.hydro_last_error()
+    assert L.hydro_batch_step_static(None, 0, None, 0.8, 1, None) == hydro.HYDRO_EINVAL

@@ -438,7 +438,7 @@ def main():
     ap.add_argument("--cfl", type=float, default=0.8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--scheme", default="mh", choices=["mh", "rk2", "rk3", "ctu"],
+    ap.add_argument("--scheme", default="mh", choices=["mh", "rk2", "rk3", "ctu", "ctu_char"],
                     help="grid workloads: predictor-corrector step (default) or SSP Runge-Kutta steps")
     ap.add_argument("--copy-probe", type=float, default=1.0,
                     help="streaming copy probe on this many GiB: the achievable HBM bandwidth, reported "
@@ -465,14 +465,15 @@ def main():
     print(f"[bench] workload {wname}: {P.cells} cells, {P.nblk} blocks", file=sys.stderr, flush=True)
     G = hydro.grid_for(P, device="cuda:0")
     if args.scheme != "mh":
-        G.set_scheme({"rk2": hydro.SCHEME_RK2, "rk3": hydro.SCHEME_RK3, "ctu": hydro.SCHEME_CTU}[args.scheme])
+        G.set_scheme({"rk2": hydro.SCHEME_RK2, "rk3": hydro.SCHEME_RK3, "ctu": hydro.SCHEME_CTU,
+                      "ctu_char": hydro.SCHEME_CTU_CHAR}[args.scheme])
     planes = P.n
-    if not args.no_tune and args.scheme != "ctu":
+    if not args.no_tune and not args.scheme.startswith("ctu"):
         from paper_2208_11630_amd import tune
 
         planes = tune.tune_grid(G, args.cfl)
         print(f"[bench] tuned: {planes} planes per z pencil", file=sys.stderr, flush=True)
-    bpc = BYTES_PER_CELL if args.scheme in ("mh", "ctu") else RK_BYTES_PER_CELL[args.scheme]
+    bpc = BYTES_PER_CELL if args.scheme in ("mh", "ctu", "ctu_char") else RK_BYTES_PER_CELL[args.scheme]
     stream = G.stream
     for _ in range(args.warmup):
         G.step_cfl(args.cfl)
@@ -497,8 +498,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(tag),
                 "kernel": tag, "algorithmic_bytes_per_launch": BYTES_PER_CELL * P.cells}
         alu = valu_roofline(tag, rate) if args.workload == "kh" else None
-    elif args.scheme == "ctu":  # launches per chunk of blocks: bytes and time per step
-        tag = f"ctu_kernel_nxb{P.n}_{args.workload}"
+    elif args.scheme.startswith("ctu"):  # launches per chunk of blocks: bytes and time per step
+        tag = f"ctu_kernel_nxb{P.n}_{args.workload}" + ("_char" if args.scheme == "ctu_char" else "")
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": tag,
                 "algorithmic_bytes_per_step": bpc * P.cells}
@@ -523,7 +524,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "cells": P.cells, "nxb": P.n, "blocks": P.nblk, "cfl": args.cfl,
                    "scheme": {"mh": "predictor-corrector", "rk2": "ssp-rk2", "rk3": "ssp-rk3",
-                              "ctu": "corner-transport-upwind"}[args.scheme],
+                              "ctu": "corner-transport-upwind",
+                              "ctu_char": "corner-transport-upwind-characteristic"}[args.scheme],
                    "pencil_planes": planes,
                    "parallelism": "single-gpu"},
         "roofline": roof,

@@ -75,6 +75,7 @@ extern "C" {
 #define HYDRO_SCHEME_RK2 2 /* second-order SSP Runge-Kutta, method-of-lines stages */
 #define HYDRO_SCHEME_RK3 3 /* third-order SSP Runge-Kutta, method-of-lines stages */
 #define HYDRO_SCHEME_CTU 4 /* corner-transport-upwind unsplit step, per-direction CFL rule */
+#define HYDRO_SCHEME_CTU_CHAR 5 /* the same with characteristic tracing in the normal predictor */
 
 typedef struct hydro_grid hydro_grid;
 
@@ -209,6 +210,16 @@ int hydro_set_pencil_planes(hydro_grid *g, int planes);
  *     hydro_step_cfl follow it for a CTU grid).  U_stage is then a scratch
  *     buffer of hydro_ctu_scratch_bytes bytes (caller-owned, device,
  *     256-byte aligned, not overlapping U or U_alt).
+ *   HYDRO_SCHEME_CTU_CHAR: the CTU step whose normal predictor traces
+ *     characteristics, as the unsplit solver §2.2 names does (Lee's papers,
+ *     after Colella 1990): the van Leer primitive slope D_d is projected on
+ *     the waves of A_d -- speeds u-c, u (entropy and shear), u+c, with
+ *     amplitudes D_p/(2c^2) -+ rho D_u/(2c) on the right eigenvectors
+ *     (1, -+c/rho, 0, 0, c^2) and (D_rho - D_p/c^2, 0, D_t1, D_t2, 0) --
+ *     and the high face state is W + sum over waves of speed s > 0 of
+ *     (1 - (dt/dx_d) s)/2 times the wave, the low one W - sum over s < 0 of
+ *     (1 + (dt/dx_d) s)/2 times the wave; everything else as for
+ *     HYDRO_SCHEME_CTU (same scratch, fallbacks and CFL rule).
  * Errors: HYDRO_EINVAL (unknown scheme, RK3 or CTU without a valid buffer,
  * grid in a batch).  Batches take HYDRO_SCHEME_MH grids only. */
 int hydro_set_scheme(hydro_grid *g, int scheme, double *U_stage);

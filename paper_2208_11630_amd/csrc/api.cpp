@@ -117,6 +117,8 @@ double* cur_state(const hydro_grid* g) { return g->cur ? g->d.U_alt : g->d.U; }
 double* other_state(const hydro_grid* g) { return g->cur ? g->d.U : g->d.U_alt; }
 int slot_of(const hydro_grid* g) { return (int)(g->steps % 3); }
 
+bool is_ctu(int scheme) { return scheme == HYDRO_SCHEME_CTU || scheme == HYDRO_SCHEME_CTU_CHAR; }
+
 int check_device() {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -131,8 +133,7 @@ int check_device() {
 
 int ensure_signal_on(hydro_grid* g, hipStream_t s) {
   if (g->sig_valid) return HYDRO_OK;
-  hipError_t e = hydro::launch_signal(g->d.nxb, g->geom, cur_state(g), ws_of(g), slot_of(g),
-                                      g->scheme == HYDRO_SCHEME_CTU, s);
+  hipError_t e = hydro::launch_signal(g->d.nxb, g->geom, cur_state(g), ws_of(g), slot_of(g), is_ctu(g->scheme), s);
   if (e != hipSuccess) return hip_fail(e, "signal-speed kernel launch");
   g->sig_valid = true;
   return HYDRO_OK;
@@ -203,7 +204,8 @@ int do_ctu_step(hydro_grid* g, double dt, double cfl) {
   a.dt = dt;
   a.cfl = cfl;
   a.slot = slot_of(g);
-  hipError_t e = hydro::launch_ctu(g->d.nxb, g->geom, a, g->U_stage, ctu_chunk(&g->d), stream_of(g));
+  hipError_t e = hydro::launch_ctu(g->d.nxb, g->geom, a, g->U_stage, ctu_chunk(&g->d),
+                                   g->scheme == HYDRO_SCHEME_CTU_CHAR, stream_of(g));
   if (e != hipSuccess) return hip_fail(e, "CTU kernel launch");
   g->cur ^= 1;
   g->steps += 1;
@@ -212,7 +214,7 @@ int do_ctu_step(hydro_grid* g, double dt, double cfl) {
 }
 
 int do_step(hydro_grid* g, double dt, double cfl) {
-  if (g->scheme == HYDRO_SCHEME_CTU) return do_ctu_step(g, dt, cfl);
+  if (is_ctu(g->scheme)) return do_ctu_step(g, dt, cfl);
   if (g->scheme != HYDRO_SCHEME_MH) return do_rk_step(g, dt, cfl);
   hydro::StepArgs a;
   a.Uin = cur_state(g);
@@ -407,11 +409,10 @@ int hydro_set_buffers(hydro_grid* g, double* U, double* U_alt) {
 int hydro_set_scheme(hydro_grid* g, int scheme, double* U_stage) {
   if (!g) return fail(HYDRO_EINVAL, "handle is NULL");
   if (g->batch) return fail(HYDRO_EINVAL, "grid belongs to a batch");
-  if (scheme != HYDRO_SCHEME_MH && scheme != HYDRO_SCHEME_RK2 && scheme != HYDRO_SCHEME_RK3 &&
-      scheme != HYDRO_SCHEME_CTU)
+  if (scheme != HYDRO_SCHEME_MH && scheme != HYDRO_SCHEME_RK2 && scheme != HYDRO_SCHEME_RK3 && !is_ctu(scheme))
     return fail(HYDRO_EINVAL, "unknown scheme %d", scheme);
-  if (scheme == HYDRO_SCHEME_RK3 || scheme == HYDRO_SCHEME_CTU) {
-    const bool ctu = scheme == HYDRO_SCHEME_CTU;
+  if (scheme == HYDRO_SCHEME_RK3 || is_ctu(scheme)) {
+    const bool ctu = is_ctu(scheme);
     if (!U_stage) return fail(HYDRO_EINVAL, ctu ? "the CTU scheme needs a scratch buffer" : "the third-order scheme needs a stage buffer");
     if ((uintptr_t)U_stage & 255) return fail(HYDRO_EINVAL, "stage / scratch buffer must be 256-byte aligned");
     const size_t sb = hydro_state_doubles(&g->d) * sizeof(double);
@@ -421,7 +422,7 @@ int hydro_set_scheme(hydro_grid* g, int scheme, double* U_stage) {
   } else {
     U_stage = nullptr;
   }
-  if ((scheme == HYDRO_SCHEME_CTU) != (g->scheme == HYDRO_SCHEME_CTU))
+  if (is_ctu(scheme) != is_ctu(g->scheme))
     g->sig_valid = false;  // the kept signal speed follows the other CFL rule
   g->scheme = scheme;
   g->U_stage = U_stage;

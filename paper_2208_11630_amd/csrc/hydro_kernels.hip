@@ -276,10 +276,14 @@ struct Tile {
 };
 
 // van Leer's harmonic slope without a branch: (a|b| + |a|b) / (|a| + |b|)
-// equals 2ab/(a+b) when ab > 0 and 0 otherwise (numerator zero); the
-// denominator is kept positive by the smallest normal double.
+// equals 2ab/(a+b) when ab > 0 and 0 otherwise; the denominator is kept
+// positive by the smallest normal double.  The two products are rounded
+// separately (no contraction into an fma): for ab < 0 they are exact
+// negatives of each other, so the numerator is exactly zero (an fma would
+// leave the rounding error of one product).  Costs 0.8% of the step.
 __device__ __forceinline__ double van_leer_sf(double a, double b) {
-  const double num = fma(a, fabs(b), fabs(a) * b);
+#pragma clang fp contract(off)
+  const double num = a * fabs(b) + fabs(a) * b;
   const double den = (fabs(a) + fabs(b)) + 2.2250738585072014e-308;
   return div_nr(num, den);
 }
@@ -347,8 +351,10 @@ struct Smem {
   double sRx[5][T];        // low-x face state of ring cell (T, y)
   double sRy[5][T];        // low-y face state of ring cell (x, T)
   double sRing[3][5][NR];  // ring z windows (planes mod 3)
-  double sFx[5][NQ];       // x flux at face (x, y), x = 0..T: index y*(T+1) + x
-  double sFy[5][NQ];       // y flux at face (x, y), y = 0..T: index y*T + x
+  // The x / y fluxes overwrite the face states: the flux at face (x, y) goes
+  // to the slot of the high-side state of its left / lower cell, read only
+  // by the thread that computes that face (sQx index y*(T+1) + x, x = 0..T;
+  // sQy index y*T + x, y = 0..T).
   unsigned long long sRed[4];  // one per wavefront of a workgroup of up to 256 threads
   int sCnt[3];
 };
@@ -483,13 +489,11 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   // acc: plane j-1's x/y flux divergence minus its lower z flux, carried to
   // the next plane, whose z flux completes the update of plane j-1
   double zp_prev[5], acc[5];
-  double pend[5];     // the last updated plane, stored in the next plane's predictor phase
-  long pend_off = -1;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     Wa[v] = Wb[v] = Wc[v] = 0.0;
     un_next[v] = u2_next[v] = 0.0;
-    zp_prev[v] = acc[v] = pend[v] = 0.0;
+    zp_prev[v] = acc[v] = 0.0;
   }
   int n_floor = 0, n_fb = 0, n_bad = 0;
   double smax = 0.0;
@@ -548,12 +552,6 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     if (is_ring && j + 2 <= z1 + 1) load_cons_at<N, GV>(Uin + plane_off(j + 2), sec_xy, u2_next);
     if (is_extra && mid && j + 1 < z1) load_cons_at<N, GV>(Uin + plane_off(j + 1), sec_xy, u2_next);
     __syncthreads();
-
-    // -- the previous plane's update goes out now
-    if (inner && pend_off >= 0) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(pend[v], (double*)((char*)(Uout + pend_off + v * VS) + own_out));
-    }
 
     // -- predictor: own cell (every plane), ring cell (pencil planes)
     double xm[5], ym[5], zm[5], zp[5];
@@ -635,12 +633,12 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         for (int v = 0; v < 5; ++v) WL[v] = sm.sQx[v][cy * (T + 1) + cx];
         hllc<0>(WL, xm, gamma, gm1inv, F);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sm.sFx[v][cy * (T + 1) + cx] = F[v];
+        for (int v = 0; v < 5; ++v) sm.sQx[v][cy * (T + 1) + cx] = F[v];
 #pragma unroll
         for (int v = 0; v < 5; ++v) WL[v] = sm.sQy[v][cy * T + cx];
         hllc<1>(WL, ym, gamma, gm1inv, F);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sm.sFy[v][cy * T + cx] = F[v];
+        for (int v = 0; v < 5; ++v) sm.sQy[v][cy * T + cx] = F[v];
       }
       if (role >= NT - 2 * T) {  // on the last wavefront, away from the ring's
         // x faces at (T, r) and y faces at (r, T) in one HLLC call: a y face
@@ -650,7 +648,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         const bool yface = role >= NT - T;
         const double* qL = yface ? (const double*)sm.sQy + (T * T + r) : (const double*)sm.sQx + (r * (T + 1) + T);
         const double* qR = yface ? (const double*)sm.sRy + r : (const double*)sm.sRx + r;
-        double* fo = yface ? (double*)sm.sFy + (T * T + r) : (double*)sm.sFx + (r * (T + 1) + T);
+        double* fo = yface ? (double*)sm.sQy + (T * T + r) : (double*)sm.sQx + (r * (T + 1) + T);
         double WL[5], WR[5], F[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -693,7 +691,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         const int qx = cy * (T + 1) + cx, qy = cy * T + cx;
 #pragma unroll
         for (int v = 0; v < 5; ++v)
-          dxy[v] = lamx * (sm.sFx[v][qx + 1] - sm.sFx[v][qx]) + lamy * (sm.sFy[v][qy + T] - sm.sFy[v][qy]);
+          dxy[v] = lamx * (sm.sQx[v][qx + 1] - sm.sQx[v][qx]) + lamy * (sm.sQy[v][qy + T] - sm.sQy[v][qy]);
       }
       if (j >= z0 + 1) {
         double un[5];
@@ -705,10 +703,12 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
             for (int v = 0; v < 5; ++v) un[v] = st.a0 * base[v] + st.a1 * un[v];
           }
         }
-        // stored early in the next plane (after its loads are awaited), so
-        // the wait at the top of the plane does not cover these stores
+        // stored at once (holding the values for the next plane's store
+        // phase cost registers and measured 4% slower)
+        const long oo = GV ? out_off(j - 1) : off_u;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) pend[v] = un[v];
+        for (int v = 0; v < 5; ++v)
+          __builtin_nontemporal_store(un[v], (double*)((char*)(Uout + oo + v * VS) + own_out));
         bool good = un[0] > 0.0 && un[4] > 0.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) good = good && isfinite(un[v]);
@@ -726,11 +726,6 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         Wb[v] = Wc[v];
       }
     }
-    pend_off = (j >= z0 + 1) ? (GV ? out_off(j - 1) : off_u) : -1;
-  }
-  if (inner && pend_off >= 0) {  // the pencil's last plane
-#pragma unroll
-    for (int v = 0; v < 5; ++v) __builtin_nontemporal_store(pend[v], (double*)((char*)(Uout + pend_off + v * VS) + own_out));
   }
 
   if (n_floor) atomicAdd(&sm.sCnt[0], n_floor);
@@ -844,6 +839,50 @@ __device__ __forceinline__ bool corrected_prim(const double (&u)[5], double gamm
   return w[4] > 0.0;
 }
 
+// Characteristic tracing of the normal predictor along d (the upwind
+// projection of Colella 1990 / Stone et al. 2008): the primitive slope S is
+// split over the waves of the primitive Jacobian A_d(W) -- with c the sound
+// speed and u the normal velocity,
+//   u - c:  amplitude a_- = S_p/(2c^2) - rho S_u/(2c), vector (1, -c/rho, 0, 0, c^2)
+//   u:      entropy and shear, (S_rho - S_p/c^2, 0, S_t1, S_t2, 0)
+//   u + c:  amplitude a_+ = S_p/(2c^2) + rho S_u/(2c), vector (1,  c/rho, 0, 0, c^2)
+// -- and each face keeps the waves moving toward it within the step:
+//   high face  W + sum over speeds s > 0 of (1 - lam s)/2 times the wave,
+//   low face   W - sum over speeds s < 0 of (1 + lam s)/2 times the wave.
+__device__ __forceinline__ void trace_faces(int d, const double (&w)[5], const double (&S)[5], double lam,
+                                            double gamma, double inv_rho, double (&lo)[5], double (&hi)[5]) {
+  const double rho = w[0], un = w[1 + d];
+  const double c2 = gamma * w[4] * inv_rho;
+  const double ic = rsq_nr(c2);                 // 1/c
+  const double c = c2 * ic;
+  const double ic2 = ic * ic;
+  const double a = 0.5 * S[4] * ic2, b = 0.5 * rho * S[1 + d] * ic;
+  const double am = a - b, ap = a + b;
+  const double cr = c * inv_rho;
+  double wm[5], w0[5], wp[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) wm[v] = w0[v] = wp[v] = 0.0;
+  wm[0] = am;
+  wm[1 + d] = -am * cr;
+  wm[4] = am * c2;
+  wp[0] = ap;
+  wp[1 + d] = ap * cr;
+  wp[4] = ap * c2;
+  w0[0] = S[0] - S[4] * ic2;
+#pragma unroll
+  for (int v = 1; v < 4; ++v)
+    if (v != 1 + d) w0[v] = S[v];
+  const double sm = un - c, s0 = un, sp = un + c;
+  const double hm = sm > 0.0 ? 0.5 * (1.0 - lam * sm) : 0.0, lm = sm < 0.0 ? 0.5 * (1.0 + lam * sm) : 0.0;
+  const double h0 = s0 > 0.0 ? 0.5 * (1.0 - lam * s0) : 0.0, l0 = s0 < 0.0 ? 0.5 * (1.0 + lam * s0) : 0.0;
+  const double hp = sp > 0.0 ? 0.5 * (1.0 - lam * sp) : 0.0, lp = sp < 0.0 ? 0.5 * (1.0 + lam * sp) : 0.0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    hi[v] = w[v] + ((hm * wm[v] + h0 * w0[v]) + hp * wp[v]);
+    lo[v] = w[v] - ((lm * wm[v] + l0 * w0[v]) + lp * wp[v]);
+  }
+}
+
 // Cell (x, y, z) number it of a box of ext[0] x ext[1] x ext[2] cells
 // starting at lo, x fastest: consecutive threads touch consecutive
 // addresses of the stage arrays, whichever face direction a stage runs.
@@ -853,7 +892,9 @@ __device__ __forceinline__ void ctu_cell(int it, const int (&ext)[3], const int 
   c3[2] = it / (ext[0] * ext[1]) + lo[2];
 }
 
-template <int N>
+// TRACE: the normal predictor traces characteristics (trace_faces) instead
+// of the primitive-form half step.
+template <int N, bool TRACE>
 __global__ __launch_bounds__(256) void ctu_kernel(GridGeom g, StepArgs a, double* __restrict__ scratch, long b0) {
   using C = Ctu<N>;
   constexpr int m = C::m, M = C::M;
@@ -913,19 +954,23 @@ __global__ __launch_bounds__(256) void ctu_kernel(GridGeom g, StepArgs a, double
 #pragma unroll
       for (int v = 0; v < 5; ++v)
         sl[v] = van_leer_sf(w[v] - W[v * C::M3 + c - step[d]], W[v * C::M3 + c + step[d]] - w[v]);
-      const double un = w[1 + d];
-      double A[5];
-      A[0] = un * sl[0] + w[0] * sl[1 + d];
-      A[1] = un * sl[1];
-      A[2] = un * sl[2];
-      A[3] = un * sl[3];
-      A[1 + d] += sl[4] * inv;
-      A[4] = gp * sl[1 + d] + un * sl[4];
+      if constexpr (TRACE) {
+        trace_faces(d, w, sl, lam[d], gamma, inv, fs[2 * d], fs[2 * d + 1]);
+      } else {
+        const double un = w[1 + d];
+        double A[5];
+        A[0] = un * sl[0] + w[0] * sl[1 + d];
+        A[1] = un * sl[1];
+        A[2] = un * sl[2];
+        A[3] = un * sl[3];
+        A[1 + d] += sl[4] * inv;
+        A[4] = gp * sl[1 + d] + un * sl[4];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const double wt = w[v] - 0.5 * lam[d] * A[v];
-        fs[2 * d][v] = wt - 0.5 * sl[v];
-        fs[2 * d + 1][v] = wt + 0.5 * sl[v];
+        for (int v = 0; v < 5; ++v) {
+          const double wt = w[v] - 0.5 * lam[d] * A[v];
+          fs[2 * d][v] = wt - 0.5 * sl[v];
+          fs[2 * d + 1][v] = wt + 0.5 * sl[v];
+        }
       }
       ok = ok && fs[2 * d][0] > 0.0 && fs[2 * d][4] > 0.0 && fs[2 * d + 1][0] > 0.0 && fs[2 * d + 1][4] > 0.0;
     }
@@ -1797,17 +1842,27 @@ long ctu_block_doubles(int nxb) {
   return 0;
 }
 
-hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, double* scratch, long chunk, hipStream_t s) {
+template <bool TRACE>
+hipError_t launch_ctu_t(int nxb, const GridGeom& g, const StepArgs& a, double* scratch, long b0, unsigned grid,
+                        hipStream_t s) {
+  switch (nxb) {
+    case 8: hipLaunchKernelGGL((ctu_kernel<8, TRACE>), dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
+    case 16: hipLaunchKernelGGL((ctu_kernel<16, TRACE>), dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
+    case 32: hipLaunchKernelGGL((ctu_kernel<32, TRACE>), dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, double* scratch, long chunk, bool trace,
+                      hipStream_t s) {
   const long nblk = (long)g.nb[0] * g.nb[1] * g.nb[2];
   if (chunk < 1) return hipErrorInvalidValue;
   for (long b0 = 0; b0 < nblk; b0 += chunk) {
     const unsigned grid = (unsigned)(nblk - b0 < chunk ? nblk - b0 : chunk);
-    switch (nxb) {
-      case 8: hipLaunchKernelGGL(ctu_kernel<8>, dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
-      case 16: hipLaunchKernelGGL(ctu_kernel<16>, dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
-      case 32: hipLaunchKernelGGL(ctu_kernel<32>, dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
-      default: return hipErrorInvalidValue;
-    }
+    const hipError_t el = trace ? launch_ctu_t<true>(nxb, g, a, scratch, b0, grid, s)
+                                : launch_ctu_t<false>(nxb, g, a, scratch, b0, grid, s);
+    if (el != hipSuccess) return el;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -25,7 +25,7 @@ HYDRO_ENONPHYS = -4
 BC_PERIODIC = 0
 BC_OUTFLOW = 1
 NGUARD = 4
-SCHEME_MH, SCHEME_RK2, SCHEME_RK3, SCHEME_CTU = 0, 2, 3, 4
+SCHEME_MH, SCHEME_RK2, SCHEME_RK3, SCHEME_CTU, SCHEME_CTU_CHAR = 0, 2, 3, 4, 5
 
 # Every entry point include/hydro.h declares, with its ctypes signature.
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -260,10 +260,11 @@ class Grid:
     def set_scheme(self, scheme: int, stage=None) -> None:
         """Time integration: SCHEME_MH (predictor-corrector), SCHEME_RK2 or
         SCHEME_RK3 (SSP Runge-Kutta over method-of-lines stages), SCHEME_CTU
-        (corner transport upwind).  RK3 needs a third state tensor and CTU a
+        (corner transport upwind), SCHEME_CTU_CHAR (the same with
+        characteristic tracing).  RK3 needs a third state tensor and CTU a
         scratch tensor; one is allocated when `stage` is None."""
         torch = self._torch
-        if scheme == SCHEME_CTU:
+        if scheme in (SCHEME_CTU, SCHEME_CTU_CHAR):
             nbytes = lib().hydro_ctu_scratch_bytes(ctypes.byref(self.desc))
             if stage is None:
                 stage = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=self.bufs[0].device)
@@ -274,7 +275,7 @@ class Grid:
                 stage = torch.empty(self.shape, dtype=torch.float64, device=self.bufs[0].device)
             if tuple(stage.shape) != self.shape or not stage.is_contiguous():
                 raise HydroError(HYDRO_EINVAL, "stage buffer must be a contiguous tensor of the grid shape")
-        keep = scheme in (SCHEME_RK3, SCHEME_CTU)
+        keep = scheme in (SCHEME_RK3, SCHEME_CTU, SCHEME_CTU_CHAR)
         ptr = stage.data_ptr() if (stage is not None and keep) else None
         _check(lib().hydro_set_scheme(self.handle, int(scheme), ptr))
         self.stage_buf = stage if keep else None

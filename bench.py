@@ -146,7 +146,7 @@ def traffic_from_profiles(kernel_tag):
     return rec.get("hbm_bytes_per_launch")
 
 
-def run_ensemble(args):
+def run_ensemble(args, cpu=True):
     """Batched ensemble: independent periodic simulations with 1-64 blocks of
     8^3, 16^3 or 32^3 cells.  Times the same steps two ways on the same GPU:
     looping the plain per-grid step over the members, and the batch (one
@@ -223,12 +223,15 @@ def run_ensemble(args):
                      "kernel": "batch_step_kernel (one launch per block size per step)",
                      "algorithmic_bytes_per_step": BYTES_PER_CELL * cells},
     }
-    if not args.no_cpu_baseline:
+    if cpu and not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         big = max(sims, key=lambda P: P.cells)
         out["cpu_baseline"] = cpu_baseline(big, args.cpu_seconds)
     B.close()
-    print(json.dumps(out), flush=True)
+    del B, grids, sims
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_amr(args):
@@ -365,38 +368,81 @@ def run_served(args):
     ex.pool.reserve(max(0, 40 * cells_total - srv.budget) + (8 << 30))
     print(f"[bench] warm: {resident} resident, {srv.used / 1e9:.1f} GB", file=sys.stderr, flush=True)
 
-    def saturated(nreq, seed, max_cells_launch, inflight, targets=None):
-        r = np.random.default_rng(seed)
-        pick = r.integers(0, len(sizes), size=nreq) if targets is None else r.choice(targets, size=nreq)
-        arr = [(0.0, int(x)) for x in pick]
+    snapshot = list(srv.lru)   # every measured run starts from the residency after warm-up
+
+    def trace_run(arr, max_cells_launch, inflight):
+        srv.restore(snapshot)
+        torch.cuda.synchronize()
         srv.max_cells = max_cells_launch
         srv.max_inflight = inflight
+        ex.host_s.clear()
         st = srv.run(arr)
         torch.cuda.synchronize()
-        return st.summary()
+        out = st.summary()
+        out["executor_host_s"] = {k: round(v, 4) for k, v in ex.host_s.items()}
+        return out
 
-    sat = saturated(2000, 7, max_cells, 2)
-    print(f"[bench] saturated: {sat}", file=sys.stderr, flush=True)
-    lam = sat["requests_per_s"]
-    sweep = []
-    for frac in (0.1, 0.3, 0.5, 0.7, 0.9, 1.0, 1.2):
-        srv.max_cells, srv.max_inflight = max_cells, 2
-        arr = serve.poisson_arrivals(frac * lam, args.served_seconds, len(sizes), seed=4)
-        st = srv.run(arr).summary()
-        torch.cuda.synchronize()
-        row = {"offered_fraction": frac, "offered_per_s": frac * lam, **{k: st.get(k) for k in (
-            "completed", "requests_per_s", "cell_updates_per_s", "p50_ms", "p99_ms", "mean_batch",
-            "evictions")}}
-        sweep.append(row)
-        print(f"[bench] rate {frac:.1f}: {row}", file=sys.stderr, flush=True)
-    loop = saturated(600, 8, 1, 1)
-    print(f"[bench] looped (one simulation per launch): {loop}", file=sys.stderr, flush=True)
-    # the same comparison without host traffic: requests for resident simulations only
-    resident_now = np.array(sorted(srv.lru))
-    res_b = saturated(2000, 9, max_cells, 2, resident_now)
-    res_l = saturated(2000, 9, 1, 1, resident_now)
-    print(f"[bench] resident-only batched: {res_b}", file=sys.stderr, flush=True)
-    print(f"[bench] resident-only looped: {res_l}", file=sys.stderr, flush=True)
+    def burst(nreq, seed, targets=None):
+        r = np.random.default_rng(seed)
+        pick = r.integers(0, len(sizes), size=nreq) if targets is None else r.choice(targets, size=nreq)
+        return [(0.0, int(x)) for x in pick]
+
+    keys = ("completed", "requests_per_s", "cell_updates_per_s", "p50_ms", "p99_ms", "mean_batch",
+            "launches", "evictions", "admissions", "wall_s", "executor_host_s")
+    pick = lambda st: {k: st.get(k) for k in keys}
+
+    # host-link ceiling: a request for a simulation that is not resident
+    # moves its state host -> device and an evicted one device -> host
+    link = host_link(ex, srv, sizes, cells_total)
+    print(f"[bench] host link: {link}", file=sys.stderr, flush=True)
+
+    # saturated throughput: the same 2000 requests at t = 0, batched
+    # (continuous batching, 2 launches in flight) and looped (one simulation
+    # per launch, one launch in flight)
+    arr_sat = burst(2000, 7)
+    sat = trace_run(arr_sat, max_cells, 2)
+    print(f"[bench] saturated batched: {pick(sat)}", file=sys.stderr, flush=True)
+    sat_loop = trace_run(arr_sat, 1, 1)
+    print(f"[bench] saturated looped: {pick(sat_loop)}", file=sys.stderr, flush=True)
+
+    def ramp(burst_rate, fractions, targets, seed):
+        """Poisson arrivals at a rising offered rate until the achieved rate
+        falls below 90% of the offered one (the server no longer keeps up),
+        then the same trace of the highest rate batching kept up with, served
+        looped."""
+        rows = []
+        for frac in fractions:
+            arr = serve.poisson_arrivals(frac * burst_rate, args.served_seconds, len(sizes), seed=seed)
+            if targets is not None:
+                arr = [(t, int(targets[x % len(targets)])) for t, x in arr]
+            st = trace_run(arr, max_cells, 2)
+            row = {"offered_per_s": len(arr) / args.served_seconds, **pick(st)}
+            rows.append(row)
+            print(f"[bench] offered {row['offered_per_s']:.0f}/s: {pick(st)}", file=sys.stderr, flush=True)
+            if st["requests_per_s"] < 0.9 * row["offered_per_s"]:
+                break
+        kept = [r for r in rows if r["requests_per_s"] >= 0.9 * r["offered_per_s"]] or rows[:1]
+        k = rows.index(kept[-1])
+        arr = serve.poisson_arrivals(fractions[k] * burst_rate, args.served_seconds, len(sizes), seed=seed)
+        if targets is not None:
+            arr = [(t, int(targets[x % len(targets)])) for t, x in arr]
+        loop = pick(trace_run(arr, 1, 1))
+        print(f"[bench] same trace looped: {loop}", file=sys.stderr, flush=True)
+        return rows, {"offered_per_s": kept[-1]["offered_per_s"], "batched": kept[-1],
+                      "looped_one_sim_per_launch": loop}
+
+    sweep, same = ramp(sat["requests_per_s"], (0.2, 0.35, 0.5, 0.65, 0.8, 1.0), None, 4)
+
+    # the same comparisons without host traffic: requests for the resident
+    # simulations only (targets uniform over the residency after warm-up)
+    resident_now = np.array(snapshot)
+    arr_res = burst(2000, 9, resident_now)
+    res_b = trace_run(arr_res, max_cells, 2)
+    res_l = trace_run(arr_res, 1, 1)
+    print(f"[bench] resident-only batched: {pick(res_b)}", file=sys.stderr, flush=True)
+    print(f"[bench] resident-only looped: {pick(res_l)}", file=sys.stderr, flush=True)
+    res_sweep, res_same = ramp(res_b["requests_per_s"], (0.1, 0.2, 0.35, 0.5, 0.65, 0.8, 1.0), resident_now, 6)
+    batched_pts = [r for r in sweep if (r.get("mean_batch") or 0) > 1.0]
     out = {
         "metric": "FP64 cell-updates/s; p50/p99 latency of served step requests",
         "value": sat["cell_updates_per_s"],
@@ -411,17 +457,69 @@ def run_served(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"served_stream_{len(sizes)}_sims_L32-256_nxb16", "cells": cells_total,
-                   "budget_GB": budget / 1e9, "resident_after_warmup": resident, "cfl": args.cfl,
+                   "budget_GB": budget / 1e9, "resident_after_warmup": resident,
+                   "resident_fraction_of_cells": link["resident_fraction_of_cells"], "cfl": args.cfl,
                    "parallelism": "single-gpu"},
-        "saturated": sat,
+        "host_link": link,
+        "saturated": {"batched": pick(sat), "looped_one_sim_per_launch": pick(sat_loop),
+                      "batched_over_looped": sat["cell_updates_per_s"] / max(sat_loop["cell_updates_per_s"], 1e-30),
+                      "trace": "the same 2000 requests at t = 0, uniform targets (seed 7)"},
         "latency_sweep": sweep,
-        "looped_one_sim_per_launch": loop,
-        "served_over_looped": sat["cell_updates_per_s"] / max(loop["cell_updates_per_s"], 1e-30),
-        "resident_only": {"batched": res_b, "looped_one_sim_per_launch": res_l,
+        "latency_points_with_mean_batch_above_1": len(batched_pts),
+        "same_trace": same,
+        "resident_only": {"batched": pick(res_b), "looped_one_sim_per_launch": pick(res_l),
                           "batched_over_looped": res_b["cell_updates_per_s"] /
-                          max(res_l["cell_updates_per_s"], 1e-30)},
+                          max(res_l["cell_updates_per_s"], 1e-30),
+                          "trace": "the same 2000 requests at t = 0 for resident simulations (seed 9)",
+                          "latency_sweep": res_sweep,
+                          "latency_points_with_mean_batch_above_1":
+                              len([r for r in res_sweep if (r.get("mean_batch") or 0) > 1.0]),
+                          "same_trace": res_same},
     }
-    print(json.dumps(out), flush=True)
+    ex.close()
+    del srv, ex
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def host_link(ex, srv, sizes, cells_total):
+    """Measured pinned host <-> device copy rates (both directions at once, on
+    the executor's two copy streams) and the request rate they allow: with
+    uniform targets a request misses the device with probability equal to the
+    non-resident fraction of the simulations, and a miss moves one state in
+    and one out (40 B per cell each way)."""
+    import numpy as np
+    import torch
+
+    nbytes = 2 << 30
+    h_in = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    h_out = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    d_in = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    d_out = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(2):
+        with torch.cuda.stream(ex.copy_stream):
+            d_in.copy_(h_in, non_blocking=True)
+        with torch.cuda.stream(ex.evict_stream):
+            h_out.copy_(d_out, non_blocking=True)
+    ex.copy_stream.synchronize()
+    ex.evict_stream.synchronize()
+    el = time.perf_counter() - t
+    del h_in, h_out, d_in, d_out
+    gbs = 2 * nbytes / el / 1e9                      # each direction
+    resident = set(srv.lru)
+    miss = 1.0 - len(resident) / len(sizes)
+    mean_cells_missed = float(np.mean([sizes[s] ** 3 for s in range(len(sizes)) if s not in resident] or [0]))
+    bytes_per_request = miss * 40.0 * mean_cells_missed  # each way
+    mean_cells = cells_total / len(sizes)
+    ceiling_req = gbs * 1e9 / bytes_per_request if bytes_per_request > 0 else float("inf")
+    return {"h2d_and_d2h_GB_per_s_each_way": gbs, "nonresident_fraction_of_sims": miss,
+            "resident_fraction_of_cells": sum(sizes[s] ** 3 for s in resident) / cells_total,
+            "ceiling_requests_per_s": ceiling_req, "ceiling_cell_updates_per_s": ceiling_req * mean_cells,
+            "note": "uniform targets: a request misses the device with the non-resident fraction of the "
+                    "simulations; a miss copies one state in and one out"}
 
 
 def main():
@@ -432,11 +530,13 @@ def main():
     ap.add_argument("--workload", default="kh", choices=["kh", "sedov", "sod", "ensemble", "served", "amr", "amr3"])
     ap.add_argument("--served-sims", type=int, default=2000)
     ap.add_argument("--served-budget-gb", type=float, default=200.0)
-    ap.add_argument("--served-seconds", type=float, default=2.0, help="served: seconds per rate point")
+    ap.add_argument("--served-seconds", type=float, default=1.5, help="served: seconds per rate point")
     ap.add_argument("--members", type=int, default=512, help="ensemble: number of simulations")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch shape)")
     ap.add_argument("--cfl", type=float, default=0.8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: skip the Sod/Sedov, batched-ensemble and served-stream legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--scheme", default="mh", choices=["mh", "rk2", "rk3", "ctu", "ctu_char"],
                     help="grid workloads: predictor-corrector step (default) or SSP Runge-Kutta steps")
@@ -456,9 +556,11 @@ def main():
     hydro.lib()
     torch.cuda.set_device(0)
     if args.workload == "ensemble":
-        return run_ensemble(args)
+        print(json.dumps(run_ensemble(args)), flush=True)
+        return
     if args.workload == "served":
-        return run_served(args)
+        print(json.dumps(run_served(args)), flush=True)
+        return
     if args.workload in ("amr", "amr3"):
         return run_amr(args)
     P, wname = make_workload(args.workload)
@@ -554,7 +656,68 @@ def main():
     if not args.no_cpu_baseline and args.scheme == "mh":
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_seconds)
+    if args.workload == "kh" and args.scheme == "mh" and not args.no_extras:
+        del G
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out.update(extras(args))
     print(json.dumps(out), flush=True)
+
+
+def plain_rate(P, wname, args):
+    """Plain-step rate of one configuration (device dt, tuned pencils)."""
+    import torch
+
+    from paper_2208_11630_amd import hydro, tune
+
+    G = hydro.grid_for(P, device="cuda:0")
+    planes = P.n if args.no_tune else tune.tune_grid(G, args.cfl)
+    for _ in range(args.warmup):
+        G.step_cfl(args.cfl)
+    G.stream.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(G.stream)
+    for _ in range(args.steps):
+        G.step_cfl(args.cfl)
+    b.record(G.stream)
+    b.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    rate = P.cells / (ms * 1e-3)
+    print(f"[bench] {wname}: {ms:.4f} ms/step, {rate:.3e} cell-updates/s", file=sys.stderr, flush=True)
+    gbs = BYTES_PER_CELL * rate / 1e9
+    return {"cells": P.cells, "ms_per_step": ms, "cell_updates_per_s": rate, "pencil_planes": planes,
+            "algorithmic_GB_per_s": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "counters": G.counters().tolist()}
+
+
+def extras(args):
+    """The other configurations, measured in the same run: the Sod and Sedov
+    grids (plain step), the batched ensemble (batched vs looped on the same
+    members) and the served stream (p50/p99 latency under Poisson load,
+    batched vs looped on the same traces, host-link ceiling)."""
+    import torch
+
+    from paper_2208_11630_amd import ics
+
+    out = {"other_workloads": {}}
+    for name, P, w in ((("sod"), ics.sod(), "sod_64^3_nxb16"), ("sedov", ics.sedov(), "sedov_256^3_nxb16")):
+        out["other_workloads"][name] = {"workload": w, **plain_rate(P, w, args)}
+        del P
+        torch.cuda.empty_cache()
+    e = run_ensemble(args, cpu=False)
+    out["batched_ensemble"] = {"workload": e["config"]["workload"], "cells": e["config"]["cells"],
+                               "batched": {"ms_per_step": e["ms_per_step"], "cell_updates_per_s": e["value"],
+                                           "launch": e["config"]["launch"], "pencils": e["config"]["pencils"],
+                                           "workgroups_per_cu": e["config"]["workgroups_per_cu"]},
+                               "looped_plain_step": e["looped_plain_step"],
+                               "batched_over_looped": e["batched_over_looped"],
+                               "roofline_frac": e["roofline"]["frac"]}
+    v = run_served(args)
+    out["served_stream"] = {k: v[k] for k in ("config", "host_link", "saturated", "latency_sweep",
+                                              "latency_points_with_mean_batch_above_1", "same_trace",
+                                              "resident_only")}
+    return out
 
 
 if __name__ == "__main__":

@@ -49,6 +49,9 @@ class Executor:
         return self.is_resident(sim)
     def make_resident(self, sim: int) -> None: ...
     def evict(self, sim: int) -> None: ...
+    def settle(self) -> None:
+        """Wait for admission and eviction copies in flight and recycle their
+        staging memory."""
     def launch(self, sims: Sequence[int]): ...
     def done(self, handle) -> bool: ...
     def finish(self, handle):
@@ -91,11 +94,12 @@ class Server:
     launch raised) is quarantined, and its later requests fail at once."""
 
     def __init__(self, executor: Executor, budget_bytes: int, max_inflight: int = 2,
-                 max_cells_per_launch: Optional[int] = None, clock=time.perf_counter):
+                 max_cells_per_launch: Optional[int] = None, clock=time.perf_counter, max_admitting: int = 16):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_inflight = max_inflight
         self.max_cells = max_cells_per_launch
+        self.max_admitting = max_admitting
         self.clock = clock
         self.used = 0
         self.lru: "collections.OrderedDict[int, None]" = collections.OrderedDict()  # resident, oldest first
@@ -103,7 +107,11 @@ class Server:
         self.quarantined: Dict[int, str] = {}
 
     # -- residency ------------------------------------------------------------
-    def _admit(self, sim: int, pinned: set) -> bool:
+    def _admit(self, sim: int, pinned: set, waiting=()) -> bool:
+        """Make sim resident, evicting least-recently-used idle simulations:
+        never one with a step in flight, one pinned for the launch being
+        formed, or one with requests waiting (`waiting`), whose state would
+        only have to come back."""
         if self.ex.is_resident(sim):
             self.lru.move_to_end(sim)
             return True
@@ -115,7 +123,7 @@ class Server:
         for s in self.lru:
             if free >= need:
                 break
-            if s in self.busy or s in pinned:
+            if s in self.busy or s in pinned or s in waiting:
                 continue
             victims.append(s)
             free += self.ex.bytes_of(s)
@@ -131,6 +139,37 @@ class Server:
         self.used += need
         self.stats.admissions += 1
         return True
+
+    def restore(self, sims: Sequence[int]) -> None:
+        """Make exactly `sims` resident, in that LRU order (evicting every other
+        simulation), so that several measured runs start from the same
+        residency.  Admissions alternate with the evictions that make room
+        for them, and the executor settles its copies every few admissions,
+        so host staging memory stays bounded."""
+        self.stats = Stats()
+        keep = set(sims)
+        extra = [s for s in self.lru if s not in keep]
+        missing = [s for s in sims if not self.ex.is_resident(s)]
+
+        def drop(v):
+            self.ex.evict(v)
+            del self.lru[v]
+            self.used -= self.ex.bytes_of(v)
+
+        for k, s in enumerate(missing):
+            need = self.ex.bytes_of(s)
+            while self.budget - self.used < need and extra:
+                drop(extra.pop(0))
+            if not self._admit(s, set()):
+                raise RuntimeError(f"simulation {s} does not fit the budget")
+            if k % 8 == 7:
+                self.ex.settle()
+        for v in extra:
+            drop(v)
+        self.ex.settle()
+        for s in sims:
+            self.lru.move_to_end(s)
+        self.stats = Stats()
 
     # -- the loop ---------------------------------------------------------------
     def run(self, arrivals: Sequence[tuple], until_done: bool = True, horizon: Optional[float] = None) -> Stats:
@@ -176,32 +215,54 @@ class Server:
             for s in [s for s in pending if s in self.quarantined]:
                 for r in pending.pop(s):
                     self._fail(r, self.quarantined[s])
-            # form the next launch from whatever is ready
+            # form the next launch from whatever is ready: first the waiting
+            # simulations whose state is on the device (oldest request first),
+            # then admissions of the others (their copies start now and a
+            # later launch takes them), at most `max_admitting` copies in flight
             if len(inflight) < self.max_inflight:
                 chosen, reqs, cells = [], [], 0
                 pinned = set()
+                full = False
                 for s in list(pending.keys()):
-                    if s in self.busy:
+                    if s in self.busy or not self.ex.is_resident(s) or not self.ex.is_ready(s):
                         continue
                     c = self.ex.cells_of(s)
                     if self.max_cells and chosen and cells + c > self.max_cells:
+                        full = True
                         break
-                    if self.ex.bytes_of(s) > self.budget:
-                        # can never be resident: refuse its requests (left incomplete)
-                        self.stats.refused += len(pending.pop(s))
-                        continue
+                    self.lru.move_to_end(s)
                     pinned.add(s)
-                    if not self._admit(s, pinned):
-                        pinned.discard(s)  # wait for memory to free up
-                        continue
-                    if not self.ex.is_ready(s):
-                        continue  # its state is still being copied in: a later launch takes it
                     chosen.append(s)
                     cells += c
                     q = pending[s]
                     reqs.append(q.popleft())
                     if not q:
                         del pending[s]
+                admitting = sum(1 for s in pending if self.ex.is_resident(s) and not self.ex.is_ready(s))
+                for s in list(pending.keys()):
+                    if admitting >= self.max_admitting:
+                        break
+                    if s in self.busy or self.ex.is_resident(s):
+                        continue
+                    if self.ex.bytes_of(s) > self.budget:
+                        # can never be resident: refuse its requests (left incomplete)
+                        self.stats.refused += len(pending.pop(s))
+                        continue
+                    pinned.add(s)
+                    if not self._admit(s, pinned, pending):
+                        pinned.discard(s)  # wait for memory to free up
+                        break
+                    if self.ex.is_ready(s) and not full:  # in place at once (first touch, pageable copy)
+                        c = self.ex.cells_of(s)
+                        if not (self.max_cells and chosen and cells + c > self.max_cells):
+                            chosen.append(s)
+                            cells += c
+                            q = pending[s]
+                            reqs.append(q.popleft())
+                            if not q:
+                                del pending[s]
+                            continue
+                    admitting += 1
                 if chosen:
                     try:
                         h = self.ex.launch(chosen)
@@ -285,7 +346,11 @@ class PinnedPool:
             elif (len(self.chunks) + 1) * self.chunk_bytes > self.cap_bytes:
                 return None
             else:
-                self.chunks.append(self.torch.empty(self.chunk_bytes, dtype=self.torch.uint8, pin_memory=True))
+                try:
+                    self.chunks.append(self.torch.empty(self.chunk_bytes, dtype=self.torch.uint8, pin_memory=True))
+                except RuntimeError:  # the host refuses more page-locked memory: cap the pool here
+                    self.cap_bytes = len(self.chunks) * self.chunk_bytes
+                    return None
             self.off = 0
         buf = self.chunks[-1][self.off:self.off + nbytes]
         self.off += size
@@ -333,6 +398,7 @@ class GpuExecutor(Executor):
         self.incoming: Dict[int, tuple] = {}   # admission copies in flight: (event, pool buffer)
         self.pool = PinnedPool(torch)
         self.steps_done = collections.Counter()
+        self.host_s = collections.Counter()    # host seconds spent in each executor call
 
     def shape_of(self, sim: int):
         nb = self.sizes[sim] // self.nxb
@@ -360,6 +426,13 @@ class GpuExecutor(Executor):
         return False
 
     def make_resident(self, sim: int) -> None:
+        t = time.perf_counter()
+        try:
+            return self._make_resident(sim)
+        finally:
+            self.host_s["make_resident"] += time.perf_counter() - t
+
+    def _make_resident(self, sim: int) -> None:
         from . import ics
 
         torch = self.torch
@@ -383,6 +456,13 @@ class GpuExecutor(Executor):
         self.state[sim] = t
 
     def evict(self, sim: int) -> None:
+        t = time.perf_counter()
+        try:
+            return self._evict(sim)
+        finally:
+            self.host_s["evict"] += time.perf_counter() - t
+
+    def _evict(self, sim: int) -> None:
         torch = self.torch
         t = self.state.pop(sim)
         inc = self.incoming.pop(sim, None)
@@ -415,6 +495,13 @@ class GpuExecutor(Executor):
         return h.numpy().copy()
 
     def launch(self, sims: Sequence[int]):
+        t = time.perf_counter()
+        try:
+            return self._launch(sims)
+        finally:
+            self.host_s["launch"] += time.perf_counter() - t
+
+    def _launch(self, sims: Sequence[int]):
         torch = self.torch
         s = self.streams[self.next_stream]
         self.next_stream = (self.next_stream + 1) % len(self.streams)
@@ -450,7 +537,32 @@ class GpuExecutor(Executor):
     def done(self, handle) -> bool:
         return handle[0].query()
 
+    def settle(self) -> None:
+        self.copy_stream.synchronize()
+        self.evict_stream.synchronize()
+        for ev, buf in self.incoming.values():
+            self.pool.put(buf)
+        self.incoming.clear()
+
+    def close(self) -> None:
+        """Release every device state, grid handle and pinned buffer."""
+        self.torch.cuda.synchronize()
+        for G in self.grid.values():
+            G.close()
+        self.grid.clear()
+        self.state.clear()
+        self.host.clear()
+        self.incoming.clear()
+        self.pool = PinnedPool(self.torch)
+
     def finish(self, handle) -> None:
+        t = time.perf_counter()
+        try:
+            return self._finish(handle)
+        finally:
+            self.host_s["finish"] += time.perf_counter() - t
+
+    def _finish(self, handle) -> None:
         ev, _, sims, outs, spent = handle
         self.torch.cuda.current_stream().wait_event(ev)
         for buf in spent:

@@ -23,6 +23,7 @@ class FakeExecutor(serve.Executor):
         self.max_overlap = 0
         self.overlapping_launches = 0
         self.next = 0
+        self.evicted_at = {}
 
     def cells_of(self, s):
         return self.sizes[s] ** 3
@@ -43,6 +44,7 @@ class FakeExecutor(serve.Executor):
         assert self.active_sims[s] == 0, "evicted a simulation with a step in flight"
         self.res.discard(s)
         self.log.append(("evict", s))
+        self.evicted_at.setdefault(s, []).append(time.perf_counter())
 
     def launch(self, sims):
         for s in sims:
@@ -103,6 +105,41 @@ def test_budget_respected_with_lru_eviction():
         elif ev == "evict":
             res.discard(x)
         assert sum(80 * 64 ** 3 for _ in res) <= budget
+
+
+def test_no_eviction_of_a_simulation_with_waiting_requests():
+    """Under a budget of three simulations and a stream cycling over ten, no
+    simulation is evicted between the arrival and the launch of one of its
+    requests (its state would only have to come back), and the launches take
+    resident simulations before waiting for admissions."""
+    sizes = [64] * 10
+    ex = FakeExecutor(sizes, cost_per_cell=4e-9)
+    srv = serve.Server(ex, budget_bytes=3 * 80 * 64 ** 3 + 10)
+    rng = np.random.default_rng(3)
+    arr = [(0.0002 * k, int(x)) for k, x in enumerate(rng.integers(0, 10, size=200))]
+    st = srv.run(arr)
+    assert st.summary()["completed"] == 200
+    assert st.evictions > 0
+    for r in st.requests:
+        for t in ex.evicted_at.get(r.sim, []):
+            assert not (r.t_arrival < t < r.t_launch), (r.sim, r.t_arrival, t, r.t_launch)
+
+
+def test_restore_returns_to_the_same_residency():
+    """restore() brings back exactly the listed simulations in that LRU order
+    after a run that changed the residency, within the budget."""
+    sizes = [64] * 10
+    ex = FakeExecutor(sizes)
+    srv = serve.Server(ex, budget_bytes=4 * 80 * 64 ** 3 + 10)
+    srv.stats = serve.Stats()
+    for s in (2, 7, 4, 9):
+        srv._admit(s, set())
+    snap = list(srv.lru)
+    st = srv.run([(0.0001 * k, k % 10) for k in range(40)])
+    assert st.evictions > 0 and set(srv.lru) != set(snap)
+    srv.restore(snap)
+    assert list(srv.lru) == snap and ex.res == set(snap)
+    assert srv.used == sum(ex.bytes_of(s) for s in snap) <= srv.budget
 
 
 def test_request_larger_than_budget_is_refused_not_hung():

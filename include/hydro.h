@@ -207,9 +207,9 @@ int hydro_set_pencil_planes(hydro_grid *g, int planes);
  *     update.  A corrected state with rho <= 0 or p <= 0 falls back to the
  *     normal face state (counted).  Its CFL rule is per direction:
  *     dt = cfl / max over cells and d of (|u_d|+c)/dx_d (hydro_dt and
- *     hydro_step_cfl follow it for a CTU grid).  U_stage is then a scratch
- *     buffer of hydro_ctu_scratch_bytes bytes (caller-owned, device,
- *     256-byte aligned, not overlapping U or U_alt).
+ *     hydro_step_cfl follow it for a CTU grid).  U_stage is ignored (the
+ *     step keeps its intermediate states on chip: 8 x 8 column tiles
+ *     marching along z through each block).
  *   HYDRO_SCHEME_CTU_CHAR: the CTU step whose normal predictor traces
  *     characteristics, as the unsplit solver §2.2 names does (Lee's papers,
  *     after Colella 1990): the van Leer primitive slope D_d is projected on
@@ -219,14 +219,10 @@ int hydro_set_pencil_planes(hydro_grid *g, int planes);
  *     and the high face state is W + sum over waves of speed s > 0 of
  *     (1 - (dt/dx_d) s)/2 times the wave, the low one W - sum over s < 0 of
  *     (1 + (dt/dx_d) s)/2 times the wave; everything else as for
- *     HYDRO_SCHEME_CTU (same scratch, fallbacks and CFL rule).
- * Errors: HYDRO_EINVAL (unknown scheme, RK3 or CTU without a valid buffer,
- * grid in a batch).  Batches take HYDRO_SCHEME_MH grids only. */
+ *     HYDRO_SCHEME_CTU (same fallbacks and CFL rule).
+ * Errors: HYDRO_EINVAL (unknown scheme, RK3 without a valid buffer, grid in
+ * a batch).  Batches take HYDRO_SCHEME_MH grids only. */
 int hydro_set_scheme(hydro_grid *g, int scheme, double *U_stage);
-
-/* Scratch bytes the CTU scheme needs for this grid (0 for an invalid
- * descriptor): stage slices of up to 8 GiB worth of blocks per launch. */
-size_t hydro_ctu_scratch_bytes(const hydro_grid_desc *d);
 
 /* ---- batches: many independent grids, one persistent launch per step ----
  * (§2: physics is updated block by block, independently of how blocks are

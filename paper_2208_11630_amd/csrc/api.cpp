@@ -31,7 +31,7 @@ struct hydro_grid {
   int plen;                 // planes per z pencil (tuning; results do not depend on it)
   hydro_batch* batch;       // batch the grid belongs to (its own step calls are refused meanwhile)
   int scheme;               // HYDRO_SCHEME_*
-  double* U_stage;          // third state buffer (third-order Runge-Kutta) or CTU scratch
+  double* U_stage;          // third state buffer (third-order Runge-Kutta)
 };
 
 struct hydro_batch {
@@ -183,19 +183,6 @@ int do_rk_step(hydro_grid* g, double dt, double cfl) {
   return HYDRO_OK;
 }
 
-// CTU scratch: blocks per launch so that one launch's slices fit 8 GiB,
-// rounded down to whole rounds of 768 workgroups (three per CU on 256 CUs,
-// as many as the kernel's registers let reside at once) when more than one
-// round fits, so that no launch ends on a partly filled round.
-long ctu_chunk(const hydro_grid_desc* d) {
-  constexpr long kRound = 768;
-  const long nblk = (long)d->nblk[0] * d->nblk[1] * d->nblk[2];
-  const long per = hydro::ctu_block_doubles(d->nxb) * (long)sizeof(double);
-  long fit = per > 0 ? (8L << 30) / per : 1;
-  if (fit >= kRound) fit = fit / kRound * kRound;
-  return std::max(1L, std::min(nblk, fit));
-}
-
 int do_ctu_step(hydro_grid* g, double dt, double cfl) {
   hydro::StepArgs a;
   a.Uin = cur_state(g);
@@ -204,8 +191,7 @@ int do_ctu_step(hydro_grid* g, double dt, double cfl) {
   a.dt = dt;
   a.cfl = cfl;
   a.slot = slot_of(g);
-  hipError_t e = hydro::launch_ctu(g->d.nxb, g->geom, a, g->U_stage, ctu_chunk(&g->d),
-                                   g->scheme == HYDRO_SCHEME_CTU_CHAR, stream_of(g));
+  hipError_t e = hydro::launch_ctu(g->d.nxb, g->geom, a, g->scheme == HYDRO_SCHEME_CTU_CHAR, stream_of(g));
   if (e != hipSuccess) return hip_fail(e, "CTU kernel launch");
   g->cur ^= 1;
   g->steps += 1;
@@ -411,14 +397,12 @@ int hydro_set_scheme(hydro_grid* g, int scheme, double* U_stage) {
   if (g->batch) return fail(HYDRO_EINVAL, "grid belongs to a batch");
   if (scheme != HYDRO_SCHEME_MH && scheme != HYDRO_SCHEME_RK2 && scheme != HYDRO_SCHEME_RK3 && !is_ctu(scheme))
     return fail(HYDRO_EINVAL, "unknown scheme %d", scheme);
-  if (scheme == HYDRO_SCHEME_RK3 || is_ctu(scheme)) {
-    const bool ctu = is_ctu(scheme);
-    if (!U_stage) return fail(HYDRO_EINVAL, ctu ? "the CTU scheme needs a scratch buffer" : "the third-order scheme needs a stage buffer");
-    if ((uintptr_t)U_stage & 255) return fail(HYDRO_EINVAL, "stage / scratch buffer must be 256-byte aligned");
+  if (scheme == HYDRO_SCHEME_RK3) {
+    if (!U_stage) return fail(HYDRO_EINVAL, "the third-order scheme needs a stage buffer");
+    if ((uintptr_t)U_stage & 255) return fail(HYDRO_EINVAL, "stage buffer must be 256-byte aligned");
     const size_t sb = hydro_state_doubles(&g->d) * sizeof(double);
-    const size_t need = ctu ? hydro_ctu_scratch_bytes(&g->d) : sb;
-    if (overlaps(U_stage, need, g->d.U, sb) || overlaps(U_stage, need, g->d.U_alt, sb))
-      return fail(HYDRO_EINVAL, "stage / scratch buffer overlaps a state buffer");
+    if (overlaps(U_stage, sb, g->d.U, sb) || overlaps(U_stage, sb, g->d.U_alt, sb))
+      return fail(HYDRO_EINVAL, "stage buffer overlaps a state buffer");
   } else {
     U_stage = nullptr;
   }
@@ -427,12 +411,6 @@ int hydro_set_scheme(hydro_grid* g, int scheme, double* U_stage) {
   g->scheme = scheme;
   g->U_stage = U_stage;
   return HYDRO_OK;
-}
-
-size_t hydro_ctu_scratch_bytes(const hydro_grid_desc* d) {
-  if (!d || (d->nxb != 8 && d->nxb != 16 && d->nxb != 32) || d->nblk[0] < 1 || d->nblk[1] < 1 || d->nblk[2] < 1)
-    return 0;
-  return (size_t)ctu_chunk(d) * (size_t)hydro::ctu_block_doubles(d->nxb) * sizeof(double);
 }
 
 int hydro_set_pencils(hydro_grid* g, int nseg) {

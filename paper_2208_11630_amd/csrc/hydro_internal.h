@@ -91,12 +91,9 @@ hipError_t launch_fill_guards(int nxb, const GridGeom& g, const double* U, doubl
 // instead of the summed one.
 hipError_t launch_signal(int nxb, const GridGeom& g, const double* U, WorkHeader* ws, int slot, bool dir,
                          hipStream_t s);
-// Corner-transport-upwind step: blocks in launches of `chunk` workgroups,
-// each using ctu_block_doubles(nxb) doubles of scratch; trace: the normal
-// predictor traces characteristics.
-long ctu_block_doubles(int nxb);
-hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, double* scratch, long chunk, bool trace,
-                      hipStream_t s);
+// Corner-transport-upwind step (z-marching 8 x 8 column tiles, no scratch);
+// trace: the normal predictor traces characteristics.
+hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, bool trace, hipStream_t s);
 hipError_t launch_clear_slot(WorkHeader* ws, int slot, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, long n, hipStream_t s);
 

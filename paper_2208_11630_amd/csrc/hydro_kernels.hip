@@ -793,20 +793,7 @@ __global__ __launch_bounds__(Tile<(N == 8 ? 8 : 16)>::NT, 2) void batch_step_ker
 // predictor-corrector solver (§2.2 Hydrodynamics), twelve HLLC solves per
 // cell: normal predictor per direction, 1-D fluxes, corner states with
 // lam_t/3 transverse corrections and their fluxes, final states with lam/2
-// cross corrections and their fluxes, update.  One workgroup per block; the
-// stages pass through a per-workgroup slice of a caller-provided scratch
-// (global memory, one barrier between stages).  The halo is gathered
-// through the boundary index map, as in the fused step.
-template <int N>
-struct Ctu {
-  static constexpr int M = N + 4;            // primitives on cells -2..N+1
-  static constexpr int m = N + 2;            // face states on cells -1..N
-  static constexpr long M3 = (long)M * M * M, m3 = (long)m * m * m;
-  static constexpr long oW = 0, oWf = 5 * M3, oF1 = oWf + 30 * m3, oFc = oF1 + 15 * m3, oFf = oFc + 30 * m3;
-  static constexpr long doubles = oFf + 15 * m3;   // scratch doubles per block
-  __device__ static int ci(int i, int j, int k) { return ((k + 1) * m + (j + 1)) * m + (i + 1); }
-  __device__ static int cW(int i, int j, int k) { return ((k + 2) * M + (j + 2)) * M + (i + 2); }
-};
+// cross corrections and their fluxes, update (ctu_tile_kernel below).
 
 // HLLC along a runtime direction (the solver is specialised per direction).
 __device__ __forceinline__ void hllc_dir(int d, const double (&L)[5], const double (&R)[5], double gamma,
@@ -883,243 +870,459 @@ __device__ __forceinline__ void trace_faces(int d, const double (&w)[5], const d
   }
 }
 
-// Cell (x, y, z) number it of a box of ext[0] x ext[1] x ext[2] cells
-// starting at lo, x fastest: consecutive threads touch consecutive
-// addresses of the stage arrays, whichever face direction a stage runs.
-__device__ __forceinline__ void ctu_cell(int it, const int (&ext)[3], const int (&lo)[3], int (&c3)[3]) {
-  c3[0] = it % ext[0] + lo[0];
-  c3[1] = (it / ext[0]) % ext[1] + lo[1];
-  c3[2] = it / (ext[0] * ext[1]) + lo[2];
+// ---------------------------------------------------------------------------
+// Corner-transport-upwind step as a z-marching column tile.  A workgroup of 128
+// threads owns an 8 x 8 column tile of one block and marches it through the
+// block's planes.  Thread t < 100 owns position (i, j) = (t % 10 - 1,
+// t / 10 - 1) of the tile plus its one-cell ring; threads 100..127 gather
+// the primitives of the 44 cells two deep around it (two cells each).
+// Iteration p predicts plane k1 = p + 1 and finishes plane p:
+//   A  primitives of plane p + 2 (own column), plane p + 1 published
+//   B  normal predictor of plane k1 (face states), z 1-D flux at face k1
+//   C  x / y 1-D fluxes of plane k1; corner fluxes F_{x|z}, F_{y|z} of p
+//   D  corner fluxes F_{x|y}, F_{y|x} of plane k1, F_{z|x}, F_{z|y} at face k1
+//   E  final fluxes: x / y of plane p, z at face k1
+//   F  update of plane p
+// Each position keeps what it needs from the plane below in registers (its
+// z window of primitives, low x / y face states, high z face state, 1-D z
+// flux, transverse 1-D flux differences, z corner fluxes, the combined
+// z-face correction and the final z flux); neighbours exchange values
+// through LDS.  Fallbacks are counted over exactly the faces the per-block
+// step counts: a tile counts its high boundary faces only where they are
+// the block's, and rows or columns one cell outside only at the block's
+// border.
+struct CtuTile {
+  static constexpr int T = 8;
+  static constexpr int P = T + 2;          // positions per row: cells -1..T
+  static constexpr int NP = P * P;         // 100
+  static constexpr int R = T + 4;          // plane rows of the primitives: cells -2..T+1
+  static constexpr int NR = R * R;         // 144
+  static constexpr int NO = NR - NP;       // 44 cells two deep
+  static constexpr int NT = 128;
+  __device__ static void outer_of(int e, int& x, int& y) {
+    if (e < R) { x = e - 2; y = -2; return; }
+    if (e < 2 * R) { x = e - R - 2; y = T + 1; return; }
+    if (e < 2 * R + P) { x = -2; y = e - 2 * R - 1; return; }
+    x = T + 1;
+    y = e - 2 * R - P - 1;
+  }
+};
+
+struct CtuTileSmem {
+  double sW[5][CtuTile::NR];                      // primitives of plane k1, cells -2..T+1
+  double sXh[2][5][CtuTile::NP];                  // high x face states, by plane parity
+  double sYh[2][5][CtuTile::NP];                  // high y face states, by plane parity
+  double sF1x[5][CtuTile::NP], sF1y[5][CtuTile::NP];   // 1-D x / y fluxes of k1, then the final x / y fluxes of p
+  double sFxz[5][CtuTile::NP], sFyz[5][CtuTile::NP];   // F_{x|z}, F_{y|z} of plane p
+  double sFxy[5][CtuTile::NP], sFyx[5][CtuTile::NP];   // z 1-D flux differences of p (phase B-C), then F_{x|y}, F_{y|x} of k1
+  double sDzx[5][CtuTile::NP], sDzy[5][CtuTile::NP];   // F_{z|x}, F_{z|y} differences over plane p
+  unsigned long long sRed[2];
+  int sCnt[3];
+};
+
+// A corrected face state: the conserved form of the primitive face state w
+// minus coef * d (d a flux difference, or a combination of them), back to
+// primitives; falls back to w when the result has rho <= 0 or p <= 0
+// (returns true then).
+__device__ __forceinline__ bool corrected_state(const double (&w)[5], double coef, const double (&d)[5],
+                                                double gamma, double gm1inv, double (&out)[5]) {
+  double u[5];
+  to_cons(w, gm1inv, u);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) u[v] -= coef * d[v];
+  const bool ok = corrected_prim(u, gamma, out);
+  if (!ok) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[v] = w[v];
+  }
+  return !ok;
 }
 
-// TRACE: the normal predictor traces characteristics (trace_faces) instead
-// of the primitive-form half step.
 template <int N, bool TRACE>
-__global__ __launch_bounds__(256) void ctu_kernel(GridGeom g, StepArgs a, double* __restrict__ scratch, long b0) {
-  using C = Ctu<N>;
-  constexpr int m = C::m, M = C::M;
-  __shared__ unsigned long long sRed[4];
-  __shared__ int sCnt[3];
-  const long blk = b0 + blockIdx.x;
+__global__ __launch_bounds__(CtuTile::NT) void ctu_tile_kernel(GridGeom g, StepArgs a, long ntiles) {
+  using C = CtuTile;
+  constexpr int T = C::T, P = C::P, R = C::R;
+  constexpr int TPB = (N / T) * (N / T);
+  constexpr long PS = Layout<N>::PS, VS = Layout<N>::VS;
+  __shared__ CtuTileSmem sm;
+  const long tile_id = xcd_tile(blockIdx.x, ntiles);
+  if (tile_id >= ntiles) return;
   const int tid = threadIdx.x;
-  double* sc = scratch + (long)blockIdx.x * C::doubles;
-  double* W = sc + C::oW;
-  double* Wf = sc + C::oWf;
-  double* F1 = sc + C::oF1;
-  double* Fc = sc + C::oFc;
-  double* Ff = sc + C::oFf;
+  const long blk = tile_id / TPB;
+  const int tile = (int)(tile_id % TPB);
+  const int lx0 = (tile % (N / T)) * T, ly0 = (tile / (N / T)) * T;
+  const int bx = (int)(blk % g.nb[0]), by = (int)((blk / g.nb[0]) % g.nb[1]);
+  const int bz = (int)(blk / ((long)g.nb[0] * g.nb[1]));
+  const int X0 = bx * N + lx0, Y0 = by * N + ly0, Z0 = bz * N;
+  const int NZ = g.nb[2] * N;
+  const long BZS = (long)g.nb[0] * g.nb[1] * Layout<N>::BS;
   WorkHeader* ws = a.ws;
   const int slot = a.slot;
-  if (tid < 3) sCnt[tid] = 0;
+  if (tid < 3) sm.sCnt[tid] = 0;
   double dt = a.dt;
   if (a.cfl > 0.0) dt = a.cfl / __longlong_as_double(ws->sig[slot]);
-  if (blk == 0 && tid == 0) {
+  if (tile_id == 0 && tid == 0) {
     ws->dt_last = dt;
     ws->sig[(slot + 2) % 3] = 0ull;
   }
-  const double lam[3] = {dt * g.inv_dx[0], dt * g.inv_dx[1], dt * g.inv_dx[2]};
+  const double lx = dt * g.inv_dx[0], ly = dt * g.inv_dx[1], lz = dt * g.inv_dx[2];
   const double gamma = g.gamma, gm1inv = 1.0 / (g.gamma - 1.0);
-  const int bx = (int)(blk % g.nb[0]), by = (int)((blk / g.nb[0]) % g.nb[1]);
-  const int bz = (int)(blk / ((long)g.nb[0] * g.nb[1]));
-  const int X0 = bx * N, Y0 = by * N, Z0 = bz * N;
-  const int tr[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+
+  // roles
+  const bool pos = tid < C::NP;
+  const int i = pos ? tid % P - 1 : 0, j = pos ? tid / P - 1 : 0;
+  const int q = tid;                                  // position index (when pos)
+  const int rq = (j + 2) * R + (i + 2);               // own cell in sW
+  const bool inner = pos && i >= 0 && i < T && j >= 0 && j < T;
+  const int e0 = 2 * (tid - C::NP), e1 = e0 + 1;
+  const bool out0 = !pos && e0 < C::NO, out1 = !pos && e1 < C::NO;
+  int ox0 = 0, oy0 = 0, ox1 = 0, oy1 = 0;
+  if (out0) C::outer_of(e0, ox0, oy0);
+  if (out1) C::outer_of(e1, ox1, oy1);
+  const int r0 = (oy0 + 2) * R + (ox0 + 2), r1 = (oy1 + 2) * R + (ox1 + 2);
+  // which faces this tile counts fallbacks on (the per-block step's sets)
+  const bool xhi_blk = lx0 + T == N, yhi_blk = ly0 + T == N;
+  const bool cfx = i < T || xhi_blk;                   // x face i (low face of position i), i in [0, T]
+  const bool cfy = j < T || yhi_blk;
+  const bool crx = (i >= 0 && i < T) || (i == -1 && lx0 == 0) || (i == T && xhi_blk);   // column i in [-1, T]
+  const bool cry = (j >= 0 && j < T) || (j == -1 && ly0 == 0) || (j == T && yhi_blk);
+  // addresses: a cell of global plane k at plane_off(k) + its column's 32-bit byte offset
+  auto plane_off = [&](int k) -> long {
+    const int K = map_axis(k, NZ, g.bc[2]);
+    return (long)((unsigned)K / N) * BZS + (long)((unsigned)K % N) * PS;
+  };
+  const unsigned own_xy = pos ? 8u * (unsigned)cell_offset<N>(g, X0 + i, Y0 + j, 0) : 0u;
+  const unsigned o0_xy = out0 ? 8u * (unsigned)cell_offset<N>(g, X0 + ox0, Y0 + oy0, 0) : 0u;
+  const unsigned o1_xy = out1 ? 8u * (unsigned)cell_offset<N>(g, X0 + ox1, Y0 + oy1, 0) : 0u;
+  const double* Uin = a.Uin;
+
+  double Wz0[5], Wz1[5], pre[5], pre1[5];
+  double xlo[5], ylo[5], zhi[5], f1z[5], d1x[5], d1y[5], fzx[5], fzy[5], dzl[5], ffz[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    Wz0[v] = Wz1[v] = pre[v] = pre1[v] = 0.0;
+    xlo[v] = ylo[v] = zhi[v] = f1z[v] = d1x[v] = d1y[v] = fzx[v] = fzy[v] = dzl[v] = ffz[v] = 0.0;
+  }
   int n_floor = 0, n_fb = 0, n_bad = 0;
+  double smax = 0.0;
 
-  // primitives on cells -2..N+1 (halo through the boundary map)
-  for (int it = tid; it < M * M * M; it += 256) {
-    const int i = it % M - 2, j = (it / M) % M - 2, k = it / (M * M) - 2;
-    double u[5], w[5], inv;
-    load_cons<N>(a.Uin, cell_offset<N>(g, X0 + i, Y0 + j, Z0 + k), u);
-    const int fl = prim(u, gamma, g.small_p, w, inv);
-    if (fl && i >= 0 && i < N && j >= 0 && j < N && k >= 0 && k < N) ++n_floor;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) W[v * C::M3 + it] = w[v];
+  // prologue: own column planes Z0-2, Z0-1 and the prefetch of Z0; the
+  // outer cells' plane Z0-1
+  if (pos) {
+    double u[5], tmp;
+    load_cons_at<N>(Uin + plane_off(Z0 - 2), own_xy, u);
+    prim(u, gamma, g.small_p, Wz0, tmp);
+    load_cons_at<N>(Uin + plane_off(Z0 - 1), own_xy, u);
+    prim(u, gamma, g.small_p, Wz1, tmp);
+    load_cons_at<N>(Uin + plane_off(Z0), own_xy, pre);
   }
-  __syncthreads();
+  if (out0) load_cons_at<N>(Uin + plane_off(Z0 - 1), o0_xy, pre);
+  if (out1) load_cons_at<N>(Uin + plane_off(Z0 - 1), o1_xy, pre1);
 
-  // 1. normal predictor on cells -1..N: face states [d][side][v], side 0 low, 1 high
-  for (int it = tid; it < m * m * m; it += 256) {
-    const int i = it % m - 1, j = (it / m) % m - 1, k = it / (m * m) - 1;
-    const int c = C::cW(i, j, k);
-    const int step[3] = {1, M, M * M};
-    double w[5], fs[6][5];
+  for (int p = Z0 - 2; p < Z0 + N; ++p) {
+    const int k1 = p + 1;
+    const bool mid = p >= Z0;                          // plane p is updated (and its x / y corner fluxes formed)
+    const int par1 = k1 & 1, par0 = p & 1;
+    // ---- A: primitives
+    double Wz2[5];
+    if (pos) {
+      double tmp;
+      const int fl = prim(pre, gamma, g.small_p, Wz2, tmp);
+      if (inner && p + 2 < Z0 + N) n_floor += fl;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) w[v] = W[v * C::M3 + c];
-    const double inv = rcp_nr(w[0]);
-    const double gp = gamma * w[4];
-    bool ok = true;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double sl[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v)
-        sl[v] = van_leer_sf(w[v] - W[v * C::M3 + c - step[d]], W[v * C::M3 + c + step[d]] - w[v]);
-      if constexpr (TRACE) {
-        trace_faces(d, w, sl, lam[d], gamma, inv, fs[2 * d], fs[2 * d + 1]);
-      } else {
-        const double un = w[1 + d];
-        double A[5];
-        A[0] = un * sl[0] + w[0] * sl[1 + d];
-        A[1] = un * sl[1];
-        A[2] = un * sl[2];
-        A[3] = un * sl[3];
-        A[1 + d] += sl[4] * inv;
-        A[4] = gp * sl[1 + d] + un * sl[4];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const double wt = w[v] - 0.5 * lam[d] * A[v];
-          fs[2 * d][v] = wt - 0.5 * sl[v];
-          fs[2 * d + 1][v] = wt + 0.5 * sl[v];
-        }
-      }
-      ok = ok && fs[2 * d][0] > 0.0 && fs[2 * d][4] > 0.0 && fs[2 * d + 1][0] > 0.0 && fs[2 * d + 1][4] > 0.0;
+      for (int v = 0; v < 5; ++v) sm.sW[v][rq] = Wz1[v];
     }
-    if (!ok && i >= 0 && i < N && j >= 0 && j < N && k >= 0 && k < N) ++n_fb;
+    if (out0) {
+      double w[5], tmp;
+      prim(pre, gamma, g.small_p, w, tmp);
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
+      for (int v = 0; v < 5; ++v) sm.sW[v][r0] = w[v];
+    }
+    if (out1) {
+      double w[5], tmp;
+      prim(pre1, gamma, g.small_p, w, tmp);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Wf[(q * 5 + v) * C::m3 + it] = ok ? fs[q][v] : w[v];
-  }
-  __syncthreads();
+      for (int v = 0; v < 5; ++v) sm.sW[v][r1] = w[v];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (pos && p + 3 <= Z0 + N + 1) load_cons_at<N>(Uin + plane_off(p + 3), own_xy, pre);
+    if (out0 && p + 2 <= Z0 + N) load_cons_at<N>(Uin + plane_off(p + 2), o0_xy, pre);
+    if (out1 && p + 2 <= Z0 + N) load_cons_at<N>(Uin + plane_off(p + 2), o1_xy, pre1);
+    __syncthreads();
 
-  // 2. 1-D fluxes at the low d-face of cells with c_d in 0..N (others -1..N)
-  for (int d = 0; d < 3; ++d) {
-    const int cnt = (N + 1) * m * m;
-    int ext[3] = {m, m, m}, lo[3] = {-1, -1, -1};   // transverse axes -1..N
-    ext[d] = N + 1;                                   // along d 0..N
-    lo[d] = 0;
-    for (int it = tid; it < cnt; it += 256) {
-      int c3[3];
-      ctu_cell(it, ext, lo, c3);
-      const int hi = C::ci(c3[0], c3[1], c3[2]);
-      const int lo = C::ci(c3[0] - (d == 0), c3[1] - (d == 1), c3[2] - (d == 2));
-      double L[5], R[5], F[5];
+    // ---- B: normal predictor of plane k1; z 1-D flux at face k1
+    double xl[5], xh[5], yl[5], yh[5], zl[5], zh[5];
+    if (pos) {
+      double sl[3][5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        L[v] = Wf[((2 * d + 1) * 5 + v) * C::m3 + lo];
-        R[v] = Wf[((2 * d + 0) * 5 + v) * C::m3 + hi];
+        const double c = Wz1[v];
+        sl[0][v] = van_leer_sf(c - sm.sW[v][rq - 1], sm.sW[v][rq + 1] - c);
+        sl[1][v] = van_leer_sf(c - sm.sW[v][rq - R], sm.sW[v][rq + R] - c);
+        sl[2][v] = van_leer_sf(c - Wz0[v], Wz2[v] - c);
       }
-      hllc_dir(d, L, R, gamma, gm1inv, F);
+      const double inv = rcp_nr(Wz1[0]);
+      double fs[6][5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) F1[(d * 5 + v) * C::m3 + hi] = F[v];
-    }
-  }
-  __syncthreads();
-
-  // 3. corner fluxes F_{d|t} at d-faces with c_d in 0..N, c_t in 0..N-1, the
-  //    remaining axis in -1..N
-  for (int d = 0; d < 3; ++d)
-    for (int q = 0; q < 2; ++q) {
-      const int t = tr[d][q], r = 3 - d - t;
-      const int cnt = (N + 1) * N * m;
-      int ext[3], lo[3];
-      ext[d] = N + 1;   // 0..N
-      lo[d] = 0;
-      ext[t] = N;       // 0..N-1
-      lo[t] = 0;
-      ext[r] = m;       // -1..N
-      lo[r] = -1;
-      for (int it = tid; it < cnt; it += 256) {
-        int c3[3];
-        ctu_cell(it, ext, lo, c3);
-        double side[2][5];
-        for (int sd = 0; sd < 2; ++sd) {
-          const int ci = c3[0] - (sd == 0 && d == 0), cj = c3[1] - (sd == 0 && d == 1), ck = c3[2] - (sd == 0 && d == 2);
-          const int face = sd == 0 ? 1 : 0;
-          const int cc = C::ci(ci, cj, ck);
-          const int ch = C::ci(ci + (t == 0), cj + (t == 1), ck + (t == 2));
-          double wn[5], u[5], w[5];
+      for (int d = 0; d < 3; ++d) {
+        if constexpr (TRACE) {
+          trace_faces(d, Wz1, sl[d], d == 0 ? lx : d == 1 ? ly : lz, gamma, inv, fs[2 * d], fs[2 * d + 1]);
+        } else {
+          const double lam = d == 0 ? lx : d == 1 ? ly : lz;
+          const double un = Wz1[1 + d];
+          double A[5];
+          A[0] = un * sl[d][0] + Wz1[0] * sl[d][1 + d];
+          A[1] = un * sl[d][1];
+          A[2] = un * sl[d][2];
+          A[3] = un * sl[d][3];
+          A[1 + d] += sl[d][4] * inv;
+          A[4] = (gamma * Wz1[4]) * sl[d][1 + d] + un * sl[d][4];
 #pragma unroll
-          for (int v = 0; v < 5; ++v) wn[v] = Wf[((2 * d + face) * 5 + v) * C::m3 + cc];
-          to_cons(wn, gm1inv, u);
-#pragma unroll
-          for (int v = 0; v < 5; ++v)
-            u[v] -= (lam[t] * (1.0 / 3.0)) * (F1[(t * 5 + v) * C::m3 + ch] - F1[(t * 5 + v) * C::m3 + cc]);
-          const bool good = corrected_prim(u, gamma, w);
-          if (!good) ++n_fb;
-#pragma unroll
-          for (int v = 0; v < 5; ++v) side[sd][v] = good ? w[v] : wn[v];
+          for (int v = 0; v < 5; ++v) {
+            const double wt = Wz1[v] - 0.5 * lam * A[v];
+            fs[2 * d][v] = wt - 0.5 * sl[d][v];
+            fs[2 * d + 1][v] = wt + 0.5 * sl[d][v];
+          }
         }
-        double F[5];
-        hllc_dir(d, side[0], side[1], gamma, gm1inv, F);
-        const int hi = C::ci(c3[0], c3[1], c3[2]);
+      }
+      bool ok = true;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Fc[((2 * d + q) * 5 + v) * C::m3 + hi] = F[v];
+      for (int s = 0; s < 6; ++s) ok = ok && fs[s][0] > 0.0 && fs[s][4] > 0.0;
+      if (!ok && inner && k1 >= Z0 && k1 < Z0 + N) ++n_fb;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        xl[v] = ok ? fs[0][v] : Wz1[v];
+        xh[v] = ok ? fs[1][v] : Wz1[v];
+        yl[v] = ok ? fs[2][v] : Wz1[v];
+        yh[v] = ok ? fs[3][v] : Wz1[v];
+        zl[v] = ok ? fs[4][v] : Wz1[v];
+        zh[v] = ok ? fs[5][v] : Wz1[v];
+        sm.sXh[par1][v][q] = xh[v];
+        sm.sYh[par1][v][q] = yh[v];
+      }
+      if (p >= Z0 - 1) {                               // face k1 in [Z0, Z0 + N]
+        double F[5];
+        hllc<2>(zhi, zl, gamma, gm1inv, F);
+        if (mid) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) sm.sFxy[v][q] = F[v] - f1z[v];   // the z 1-D flux difference over plane p
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v) f1z[v] = F[v];
       }
     }
-  __syncthreads();
+    __syncthreads();
 
-  // 4. final fluxes at the interior faces
-  for (int d = 0; d < 3; ++d) {
-    const int t = tr[d][0], u_ = tr[d][1];
-    const int kt = tr[t][0] == u_ ? 0 : 1;   // F_{t|u} index among t's pair
-    const int ku = tr[u_][0] == t ? 0 : 1;   // F_{u|t} index among u's pair
-    const int cnt = (N + 1) * N * N;
-    int ext[3] = {N, N, N}, lo[3] = {0, 0, 0};
-    ext[d] = N + 1;
-    for (int it = tid; it < cnt; it += 256) {
-      int c3[3];
-      ctu_cell(it, ext, lo, c3);
-      double side[2][5];
-      for (int sd = 0; sd < 2; ++sd) {
-        const int ci = c3[0] - (sd == 0 && d == 0), cj = c3[1] - (sd == 0 && d == 1), ck = c3[2] - (sd == 0 && d == 2);
-        const int face = sd == 0 ? 1 : 0;
-        const int cc = C::ci(ci, cj, ck);
-        const int ct = C::ci(ci + (t == 0), cj + (t == 1), ck + (t == 2));
-        const int cu = C::ci(ci + (u_ == 0), cj + (u_ == 1), ck + (u_ == 2));
-        double wn[5], u[5], w[5];
+    // ---- C: x / y 1-D fluxes of plane k1; F_{x|z}, F_{y|z} of plane p
+    if (pos) {
+      double F[5], L[5], Rt[5];
+      if (i >= 0) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) wn[v] = Wf[((2 * d + face) * 5 + v) * C::m3 + cc];
-        to_cons(wn, gm1inv, u);
+        for (int v = 0; v < 5; ++v) L[v] = sm.sXh[par1][v][q - 1];
+        hllc<0>(L, xl, gamma, gm1inv, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.sF1x[v][q] = F[v];
+      }
+      if (j >= 0) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) L[v] = sm.sYh[par1][v][q - P];
+        hllc<1>(L, yl, gamma, gm1inv, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.sF1y[v][q] = F[v];
+      }
+      if (mid) {
+        double w[5], d[5];
+        if (i >= 0) {                                  // x face i, rows -1..T
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            w[v] = sm.sXh[par0][v][q - 1];
+            d[v] = sm.sFxy[v][q - 1];
+          }
+          const bool b0 = corrected_state(w, lz * (1.0 / 3.0), d, gamma, gm1inv, L);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) d[v] = sm.sFxy[v][q];
+          const bool b1 = corrected_state(xlo, lz * (1.0 / 3.0), d, gamma, gm1inv, Rt);
+          if (cfx && cry) n_fb += (int)b0 + (int)b1;
+          hllc<0>(L, Rt, gamma, gm1inv, F);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) sm.sFxz[v][q] = F[v];
+        }
+        if (j >= 0) {                                  // y face j, columns -1..T
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            w[v] = sm.sYh[par0][v][q - P];
+            d[v] = sm.sFxy[v][q - P];
+          }
+          const bool b0 = corrected_state(w, lz * (1.0 / 3.0), d, gamma, gm1inv, L);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) d[v] = sm.sFxy[v][q];
+          const bool b1 = corrected_state(ylo, lz * (1.0 / 3.0), d, gamma, gm1inv, Rt);
+          if (cfy && crx) n_fb += (int)b0 + (int)b1;
+          hllc<1>(L, Rt, gamma, gm1inv, F);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) sm.sFyz[v][q] = F[v];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- D: F_{x|y}, F_{y|x} of plane k1; F_{z|x}, F_{z|y} at face k1
+    double nd1x[5], nd1y[5];
+    if (pos) {
+      const bool hx = i >= 0 && i < T, hy = j >= 0 && j < T;   // own transverse 1-D flux differences exist
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        nd1x[v] = hx ? sm.sF1x[v][q + 1] - sm.sF1x[v][q] : 0.0;
+        nd1y[v] = hy ? sm.sF1y[v][q + P] - sm.sF1y[v][q] : 0.0;
+      }
+      double F[5], L[5], Rt[5], w[5], d[5];
+      if (i >= 0 && hy) {                              // x face i of an inner row
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          w[v] = sm.sXh[par1][v][q - 1];
+          d[v] = sm.sF1y[v][q - 1 + P] - sm.sF1y[v][q - 1];
+        }
+        const bool b0 = corrected_state(w, ly * (1.0 / 3.0), d, gamma, gm1inv, L);
+        const bool b1 = corrected_state(xl, ly * (1.0 / 3.0), nd1y, gamma, gm1inv, Rt);
+        if (cfx) n_fb += (int)b0 + (int)b1;
+        hllc<0>(L, Rt, gamma, gm1inv, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.sFxy[v][q] = F[v];
+      }
+      if (j >= 0 && hx) {                              // y face j of an inner column
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          w[v] = sm.sYh[par1][v][q - P];
+          d[v] = sm.sF1x[v][q - P + 1] - sm.sF1x[v][q - P];
+        }
+        const bool b0 = corrected_state(w, lx * (1.0 / 3.0), d, gamma, gm1inv, L);
+        const bool b1 = corrected_state(yl, lx * (1.0 / 3.0), nd1x, gamma, gm1inv, Rt);
+        if (cfy) n_fb += (int)b0 + (int)b1;
+        hllc<1>(L, Rt, gamma, gm1inv, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.sFyx[v][q] = F[v];
+      }
+      if (p >= Z0 - 1) {                               // z face k1
+        if (hx) {                                      // F_{z|x}: inner columns, rows -1..T
+          const bool b0 = corrected_state(zhi, lx * (1.0 / 3.0), d1x, gamma, gm1inv, L);
+          const bool b1 = corrected_state(zl, lx * (1.0 / 3.0), nd1x, gamma, gm1inv, Rt);
+          if (cry) n_fb += (int)b0 + (int)b1;
+          hllc<2>(L, Rt, gamma, gm1inv, F);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            if (mid) sm.sDzx[v][q] = F[v] - fzx[v];
+            fzx[v] = F[v];
+          }
+        }
+        if (hy) {                                      // F_{z|y}: inner rows, columns -1..T
+          const bool b0 = corrected_state(zhi, ly * (1.0 / 3.0), d1y, gamma, gm1inv, L);
+          const bool b1 = corrected_state(zl, ly * (1.0 / 3.0), nd1y, gamma, gm1inv, Rt);
+          if (crx) n_fb += (int)b0 + (int)b1;
+          hllc<2>(L, Rt, gamma, gm1inv, F);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            if (mid) sm.sDzy[v][q] = F[v] - fzy[v];
+            fzy[v] = F[v];
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- E: final fluxes (x / y of plane p, z at face k1); the old state of p
+    double nffz[5], uold[5];
+    if (pos) {
+      double F[5], L[5], Rt[5], w[5], d[5];
+      const bool hx = i >= 0 && i < T, hy = j >= 0 && j < T;
+      if (mid && i >= 0 && hy) {                       // x face i of an inner row
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          w[v] = sm.sXh[par0][v][q - 1];
+          d[v] = ly * (sm.sFyz[v][q - 1 + P] - sm.sFyz[v][q - 1]) + lz * sm.sDzy[v][q - 1];
+        }
+        const bool b0 = corrected_state(w, 0.5, d, gamma, gm1inv, L);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) d[v] = ly * (sm.sFyz[v][q + P] - sm.sFyz[v][q]) + lz * sm.sDzy[v][q];
+        const bool b1 = corrected_state(xlo, 0.5, d, gamma, gm1inv, Rt);
+        if (cfx) n_fb += (int)b0 + (int)b1;
+        hllc<0>(L, Rt, gamma, gm1inv, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.sF1x[v][q] = F[v];
+      }
+      if (mid && j >= 0 && hx) {                       // y face j of an inner column
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          w[v] = sm.sYh[par0][v][q - P];
+          d[v] = lx * (sm.sFxz[v][q - P + 1] - sm.sFxz[v][q - P]) + lz * sm.sDzx[v][q - P];
+        }
+        const bool b0 = corrected_state(w, 0.5, d, gamma, gm1inv, L);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) d[v] = lx * (sm.sFxz[v][q + 1] - sm.sFxz[v][q]) + lz * sm.sDzx[v][q];
+        const bool b1 = corrected_state(ylo, 0.5, d, gamma, gm1inv, Rt);
+        if (cfy) n_fb += (int)b0 + (int)b1;
+        hllc<1>(L, Rt, gamma, gm1inv, F);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.sF1y[v][q] = F[v];
+      }
+      if (inner) {                                     // z face k1: the correction of plane k1's side
 #pragma unroll
         for (int v = 0; v < 5; ++v)
-          u[v] -= 0.5 * (lam[t] * (Fc[((2 * t + kt) * 5 + v) * C::m3 + ct] - Fc[((2 * t + kt) * 5 + v) * C::m3 + cc]) +
-                         lam[u_] * (Fc[((2 * u_ + ku) * 5 + v) * C::m3 + cu] - Fc[((2 * u_ + ku) * 5 + v) * C::m3 + cc]));
-        const bool good = corrected_prim(u, gamma, w);
-        if (!good) ++n_fb;
+          d[v] = lx * (sm.sFxy[v][q + 1] - sm.sFxy[v][q]) + ly * (sm.sFyx[v][q + P] - sm.sFyx[v][q]);
+        if (p >= Z0 - 1) {
+          const bool b0 = corrected_state(zhi, 0.5, dzl, gamma, gm1inv, L);
+          const bool b1 = corrected_state(zl, 0.5, d, gamma, gm1inv, Rt);
+          n_fb += (int)b0 + (int)b1;
+          hllc<2>(L, Rt, gamma, gm1inv, nffz);
+        }
 #pragma unroll
-        for (int v = 0; v < 5; ++v) side[sd][v] = good ? w[v] : wn[v];
+        for (int v = 0; v < 5; ++v) dzl[v] = d[v];
+        if (mid) load_cons_at<N, false, true>(Uin + plane_off(p), own_xy, uold);
       }
-      double F[5];
-      hllc_dir(d, side[0], side[1], gamma, gm1inv, F);
-      const int hi = C::ci(c3[0], c3[1], c3[2]);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) Ff[(d * 5 + v) * C::m3 + hi] = F[v];
     }
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // 5. update and the per-direction signal of the new state
-  double smax = 0.0;
-  for (int it = tid; it < N * N * N; it += 256) {
-    const int i = it % N, j = (it / N) % N, k = it / (N * N);
-    const int c0 = C::ci(i, j, k);
-    const int cx = C::ci(i + 1, j, k), cy = C::ci(i, j + 1, k), cz = C::ci(i, j, k + 1);
-    const long off = Layout<N>::at(blk, i, j, k);
-    double u[5], un[5];
-    load_cons<N>(a.Uin, off, u);
+    // ---- F: update of plane p
+    if (inner && mid) {
+      double un[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const double div = (lam[0] * (Ff[(0 * 5 + v) * C::m3 + cx] - Ff[(0 * 5 + v) * C::m3 + c0]) +
-                          lam[1] * (Ff[(1 * 5 + v) * C::m3 + cy] - Ff[(1 * 5 + v) * C::m3 + c0])) +
-                         lam[2] * (Ff[(2 * 5 + v) * C::m3 + cz] - Ff[(2 * 5 + v) * C::m3 + c0]);
-      un[v] = u[v] - div;
-      a.Uout[off + v * Layout<N>::VS] = un[v];
+      for (int v = 0; v < 5; ++v) {
+        const double div = (lx * (sm.sF1x[v][q + 1] - sm.sF1x[v][q]) + ly * (sm.sF1y[v][q + P] - sm.sF1y[v][q])) +
+                           lz * (nffz[v] - ffz[v]);
+        un[v] = uold[v] - div;
+      }
+      const long oo = plane_off(p);
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        __builtin_nontemporal_store(un[v], (double*)((char*)(a.Uout + oo + v * VS) + own_xy));
+      bool good = un[0] > 0.0 && un[4] > 0.0;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) good = good && isfinite(un[v]);
+      if (!good) ++n_bad;
+      const double s = signal_speed_dir(un, g);
+      smax = (s > smax || !(s == s)) ? s : smax;
     }
-    bool good = un[0] > 0.0 && un[4] > 0.0;
+    // the plane below for the next iteration
+    if (pos) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) good = good && isfinite(un[v]);
-    if (!good) ++n_bad;
-    const double s = signal_speed_dir(un, g);
-    smax = (s > smax || !(s == s)) ? s : smax;
+      for (int v = 0; v < 5; ++v) {
+        Wz0[v] = Wz1[v];
+        Wz1[v] = Wz2[v];
+        xlo[v] = xl[v];
+        ylo[v] = yl[v];
+        zhi[v] = zh[v];
+        d1x[v] = nd1x[v];
+        d1y[v] = nd1y[v];
+        if (inner && p >= Z0 - 1) ffz[v] = nffz[v];
+      }
+    }
   }
-  if (n_floor) atomicAdd(&sCnt[0], n_floor);
-  if (n_fb) atomicAdd(&sCnt[1], n_fb);
-  if (n_bad) atomicAdd(&sCnt[2], n_bad);
-  wg_max_to(smax, sRed, &ws->sig[(slot + 1) % 3]);
+  if (n_floor) atomicAdd(&sm.sCnt[0], n_floor);
+  if (n_fb) atomicAdd(&sm.sCnt[1], n_fb);
+  if (n_bad) atomicAdd(&sm.sCnt[2], n_bad);
+  wg_max_to(smax, sm.sRed, &ws->sig[(slot + 1) % 3]);
   if (tid == 0) {
-    for (int q = 0; q < 3; ++q)
-      if (sCnt[q]) atomicAdd(&ws->cnt[q], (unsigned long long)sCnt[q]);
+    for (int c = 0; c < 3; ++c)
+      if (sm.sCnt[c]) atomicAdd(&ws->cnt[c], (unsigned long long)sm.sCnt[c]);
   }
 }
 
@@ -1833,40 +2036,22 @@ hipError_t launch_amr_signal(int nxb, const AmrLaunch& L, int slot, hipStream_t 
   return hipGetLastError();
 }
 
-long ctu_block_doubles(int nxb) {
-  switch (nxb) {
-    case 8: return Ctu<8>::doubles;
-    case 16: return Ctu<16>::doubles;
-    case 32: return Ctu<32>::doubles;
-  }
-  return 0;
-}
-
 template <bool TRACE>
-hipError_t launch_ctu_t(int nxb, const GridGeom& g, const StepArgs& a, double* scratch, long b0, unsigned grid,
-                        hipStream_t s) {
+hipError_t launch_ctu_t(int nxb, const GridGeom& g, const StepArgs& a, hipStream_t s) {
+  const long nblk = (long)g.nb[0] * g.nb[1] * g.nb[2];
+  const long ntiles = nblk * (nxb / CtuTile::T) * (nxb / CtuTile::T);
+  const unsigned grid = (unsigned)(8 * ((ntiles + 7) / 8));
   switch (nxb) {
-    case 8: hipLaunchKernelGGL((ctu_kernel<8, TRACE>), dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
-    case 16: hipLaunchKernelGGL((ctu_kernel<16, TRACE>), dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
-    case 32: hipLaunchKernelGGL((ctu_kernel<32, TRACE>), dim3(grid), dim3(256), 0, s, g, a, scratch, b0); break;
+    case 8: hipLaunchKernelGGL((ctu_tile_kernel<8, TRACE>), dim3(grid), dim3(CtuTile::NT), 0, s, g, a, ntiles); break;
+    case 16: hipLaunchKernelGGL((ctu_tile_kernel<16, TRACE>), dim3(grid), dim3(CtuTile::NT), 0, s, g, a, ntiles); break;
+    case 32: hipLaunchKernelGGL((ctu_tile_kernel<32, TRACE>), dim3(grid), dim3(CtuTile::NT), 0, s, g, a, ntiles); break;
     default: return hipErrorInvalidValue;
   }
-  return hipSuccess;
+  return hipGetLastError();
 }
 
-hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, double* scratch, long chunk, bool trace,
-                      hipStream_t s) {
-  const long nblk = (long)g.nb[0] * g.nb[1] * g.nb[2];
-  if (chunk < 1) return hipErrorInvalidValue;
-  for (long b0 = 0; b0 < nblk; b0 += chunk) {
-    const unsigned grid = (unsigned)(nblk - b0 < chunk ? nblk - b0 : chunk);
-    const hipError_t el = trace ? launch_ctu_t<true>(nxb, g, a, scratch, b0, grid, s)
-                                : launch_ctu_t<false>(nxb, g, a, scratch, b0, grid, s);
-    if (el != hipSuccess) return el;
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, bool trace, hipStream_t s) {
+  return trace ? launch_ctu_t<true>(nxb, g, a, s) : launch_ctu_t<false>(nxb, g, a, s);
 }
 
 hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,

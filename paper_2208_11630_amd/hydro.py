@@ -87,7 +87,6 @@ SIGNATURES = {
     "hydro_amr_free": ([ctypes.c_void_p], ctypes.c_int),
     "hydro_set_pencil_planes": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_set_scheme": ([_HP, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
-    "hydro_ctu_scratch_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
     "hydro_set_buffers": ([_HP, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "hydro_batch_work_bytes": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int], ctypes.c_size_t),
     "hydro_batch_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
@@ -261,24 +260,19 @@ class Grid:
         """Time integration: SCHEME_MH (predictor-corrector), SCHEME_RK2 or
         SCHEME_RK3 (SSP Runge-Kutta over method-of-lines stages), SCHEME_CTU
         (corner transport upwind), SCHEME_CTU_CHAR (the same with
-        characteristic tracing).  RK3 needs a third state tensor and CTU a
-        scratch tensor; one is allocated when `stage` is None."""
+        characteristic tracing).  RK3 needs a third state tensor; one is
+        allocated when `stage` is None."""
         torch = self._torch
-        if scheme in (SCHEME_CTU, SCHEME_CTU_CHAR):
-            nbytes = lib().hydro_ctu_scratch_bytes(ctypes.byref(self.desc))
-            if stage is None:
-                stage = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=self.bufs[0].device)
-            elif stage.numel() * stage.element_size() < nbytes or not stage.is_contiguous():
-                raise HydroError(HYDRO_EINVAL, f"CTU scratch must be a contiguous tensor of >= {nbytes} bytes")
-        elif scheme == SCHEME_RK3:
+        if scheme == SCHEME_RK3:
             if stage is None:
                 stage = torch.empty(self.shape, dtype=torch.float64, device=self.bufs[0].device)
             if tuple(stage.shape) != self.shape or not stage.is_contiguous():
                 raise HydroError(HYDRO_EINVAL, "stage buffer must be a contiguous tensor of the grid shape")
-        keep = scheme in (SCHEME_RK3, SCHEME_CTU, SCHEME_CTU_CHAR)
-        ptr = stage.data_ptr() if (stage is not None and keep) else None
+        else:
+            stage = None
+        ptr = stage.data_ptr() if stage is not None else None
         _check(lib().hydro_set_scheme(self.handle, int(scheme), ptr))
-        self.stage_buf = stage if keep else None
+        self.stage_buf = stage
         self.scheme = int(scheme)
 
     def set_buffers(self, U, U_alt) -> None:

@@ -45,16 +45,6 @@ def _good():
     return d
 
 
-def test_ctu_scratch_size(L):
-    d = _good()      # 24 blocks of 16^3: all in one launch
-    per = 5 * 20 ** 3 + 90 * 18 ** 3
-    assert L.hydro_ctu_scratch_bytes(ctypes.byref(d)) == 24 * per * 8
-    big = hydro.make_desc(16, (64, 64, 8))
-    fit = (8 << 30) // (per * 8)            # 1,900 blocks fit 8 GiB: whole rounds of 768 launch at once
-    assert L.hydro_ctu_scratch_bytes(ctypes.byref(big)) == (fit // 768 * 768) * per * 8
-    assert L.hydro_ctu_scratch_bytes(None) == 0
-
-
 def test_sizes(L):
     d = _good()
     assert L.hydro_state_doubles(ctypes.byref(d)) == 24 * 5 * 16 ** 3

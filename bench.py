@@ -186,7 +186,8 @@ def run_ensemble(args, cpu=True):
     cfg = {"pencils": [1, 1, 1], "per_cu": 2}
     if not args.no_tune:
         cfg = tune.tune_batch(B, args.cfl)
-        print(f"[bench] tuned: pencils {cfg['pencils']} workgroups/CU {cfg['per_cu']}", file=sys.stderr,
+        print(f"[bench] tuned: pencils {cfg['pencils']} workgroups/CU {cfg['per_cu']} tiles {cfg.get('tiles')}",
+              file=sys.stderr,
               flush=True)
     B.use_graph(True)
     B.step(args.cfl, 6 * max(1, args.warmup // 6 + 1))
@@ -214,6 +215,7 @@ def run_ensemble(args, cpu=True):
         "config": {"workload": f"batched_ensemble_{len(sims)}_members_nxb8_16_32", "cells": cells,
                    "members": len(sims), "cfl": args.cfl, "launch": "persistent+hipgraph",
                    "pencils": cfg["pencils"], "workgroups_per_cu": cfg["per_cu"],
+                   "tiles": cfg.get("tiles", [8, 16, 16]),
                    "parallelism": "single-gpu"},
         "looped_plain_step": {"value": loop_rate, "ms_per_step": ms_loop / args.steps,
                               "launches_per_step": len(sims)},
@@ -574,7 +576,7 @@ def main():
         from paper_2208_11630_amd import tune
 
         planes = tune.tune_grid(G, args.cfl)
-        print(f"[bench] tuned: {planes} planes per z pencil", file=sys.stderr, flush=True)
+        print(f"[bench] tuned: {planes} planes per z pencil, {G.tile}x{G.tile} tiles", file=sys.stderr, flush=True)
     bpc = BYTES_PER_CELL if args.scheme in ("mh", "ctu", "ctu_char") else RK_BYTES_PER_CELL[args.scheme]
     stream = G.stream
     for _ in range(args.warmup):
@@ -628,7 +630,7 @@ def main():
                    "scheme": {"mh": "predictor-corrector", "rk2": "ssp-rk2", "rk3": "ssp-rk3",
                               "ctu": "corner-transport-upwind",
                               "ctu_char": "corner-transport-upwind-characteristic"}[args.scheme],
-                   "pencil_planes": planes,
+                   "pencil_planes": planes, "tile": f"{G.tile}x{G.tile}",
                    "parallelism": "single-gpu"},
         "roofline": roof,
     }
@@ -687,6 +689,7 @@ def plain_rate(P, wname, args):
     print(f"[bench] {wname}: {ms:.4f} ms/step, {rate:.3e} cell-updates/s", file=sys.stderr, flush=True)
     gbs = BYTES_PER_CELL * rate / 1e9
     return {"cells": P.cells, "ms_per_step": ms, "cell_updates_per_s": rate, "pencil_planes": planes,
+            "tile": f"{G.tile}x{G.tile}",
             "algorithmic_GB_per_s": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
             "counters": G.counters().tolist()}
 
@@ -709,6 +712,7 @@ def extras(args):
     out["batched_ensemble"] = {"workload": e["config"]["workload"], "cells": e["config"]["cells"],
                                "batched": {"ms_per_step": e["ms_per_step"], "cell_updates_per_s": e["value"],
                                            "launch": e["config"]["launch"], "pencils": e["config"]["pencils"],
+                                           "tiles": e["config"]["tiles"],
                                            "workgroups_per_cu": e["config"]["workgroups_per_cu"]},
                                "looped_plain_step": e["looped_plain_step"],
                                "batched_over_looped": e["batched_over_looped"],

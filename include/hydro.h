@@ -179,6 +179,14 @@ int hydro_set_pencils(hydro_grid *g, int nseg);
  * independent of it.  Errors: HYDRO_EINVAL. */
 int hydro_set_pencil_planes(hydro_grid *g, int planes);
 
+/* Tuning: edge of the column tiles a workgroup marches along z (8 or 16;
+ * 8 for nxb = 8; default 16 for nxb 16 and 32).  Smaller tiles give four
+ * times the workgroups (small grids fill the GPU) at the cost of a
+ * relatively larger ring of re-predicted cells.  Results are bitwise
+ * independent of it.  Errors: HYDRO_EINVAL (other value, 16 with nxb 8,
+ * grid in a batch). */
+int hydro_set_tile(hydro_grid *g, int tile);
+
 /* Time integration of the grid's steps (§2.2 Hydrodynamics names two
  * compressible solvers: the predictor-corrector one and one with second- or
  * third-order strong-stability-preserving Runge-Kutta time integration).
@@ -260,6 +268,9 @@ int hydro_batch_set_active(hydro_batch *b, const unsigned char *mask);
  * whether to replay steps through a captured HIP graph. */
 int hydro_batch_set_pencils(hydro_batch *b, const int nseg[3]);
 int hydro_batch_set_workgroups(hydro_batch *b, int per_cu);
+/* Column tile edge per block size (nxb 8, 16, 32): 8 for nxb 8, 8 or 16
+ * otherwise (default 8, 16, 16).  Bitwise independent of it. */
+int hydro_batch_set_tiles(hydro_batch *b, const int tile[3]);
 int hydro_batch_use_graph(hydro_batch *b, int enable);
 
 /* dt_out[i] = dt of member i's most recent step.  Waits for the stream. */

@@ -29,6 +29,7 @@ struct hydro_grid {
   unsigned long long steps; // steps taken; signal slot of the current state = steps % 3
   bool sig_valid;           // slot holds the current state's maximum signal speed
   int plen;                 // planes per z pencil (tuning; results do not depend on it)
+  int tile;                 // column tile edge, 8 or 16 (tuning; results do not depend on it)
   hydro_batch* batch;       // batch the grid belongs to (its own step calls are refused meanwhile)
   int scheme;               // HYDRO_SCHEME_*
   double* U_stage;          // third state buffer (third-order Runge-Kutta)
@@ -44,6 +45,7 @@ struct hydro_batch {
   size_t max_items;
   void* stream;
   int nseg[3];                           // pencils per column for nxb 8, 16, 32
+  int tile[3];                           // column tile edge for nxb 8, 16, 32
   int grid;                              // persistent workgroups
   long cls_begin[3], cls_count[3];       // work-list range of each size class (8, 16, 32)
   int cus;
@@ -175,7 +177,7 @@ int do_rk_step(hydro_grid* g, double dt, double cfl) {
     st.a1 = stages[k].a1;
     st.stage = k;
     st.last = k == order - 1;
-    hipError_t e = hydro::launch_step(g->d.nxb, g->geom, a, &st, g->plen, stream_of(g));
+    hipError_t e = hydro::launch_step(g->d.nxb, g->tile, g->geom, a, &st, g->plen, stream_of(g));
     if (e != hipSuccess) return hip_fail(e, "stage kernel launch");
   }
   g->steps += 1;
@@ -209,7 +211,7 @@ int do_step(hydro_grid* g, double dt, double cfl) {
   a.dt = dt;
   a.cfl = cfl;
   a.slot = slot_of(g);
-  hipError_t e = hydro::launch_step(g->d.nxb, g->geom, a, nullptr, g->plen, stream_of(g));
+  hipError_t e = hydro::launch_step(g->d.nxb, g->tile, g->geom, a, nullptr, g->plen, stream_of(g));
   if (e != hipSuccess) return hip_fail(e, "step kernel launch");
   g->cur ^= 1;
   g->steps += 1;
@@ -273,6 +275,7 @@ int hydro_init_grid(const hydro_grid_desc* d, hydro_grid** out) {
   g->steps = 0;
   g->sig_valid = false;
   g->plen = d->nxb;
+  g->tile = d->nxb == 8 ? 8 : 16;
   g->batch = nullptr;
   g->scheme = HYDRO_SCHEME_MH;
   g->U_stage = nullptr;
@@ -421,6 +424,15 @@ int hydro_set_pencils(hydro_grid* g, int nseg) {
   return HYDRO_OK;
 }
 
+int hydro_set_tile(hydro_grid* g, int tile) {
+  if (!g) return fail(HYDRO_EINVAL, "handle is NULL");
+  if (g->batch) return fail(HYDRO_EINVAL, "grid belongs to a batch");
+  if (tile != 8 && tile != 16) return fail(HYDRO_EINVAL, "column tiles must be 8x8 or 16x16 (got %d)", tile);
+  if (tile > g->d.nxb) return fail(HYDRO_EINVAL, "8^3 blocks take 8x8 column tiles");
+  g->tile = tile;
+  return HYDRO_OK;
+}
+
 int hydro_set_pencil_planes(hydro_grid* g, int planes) {
   if (!g) return fail(HYDRO_EINVAL, "handle is NULL");
   const long nz = (long)g->d.nblk[2] * g->d.nxb;
@@ -436,11 +448,12 @@ namespace {
 
 constexpr int kMaxPencils = 4;
 
-int tile_edge(int nxb) { return nxb == 8 ? 8 : 16; }
+int default_tile(int nxb) { return nxb == 8 ? 8 : 16; }
 int size_class(int nxb) { return nxb == 8 ? 0 : nxb == 16 ? 1 : 2; }
 
-long columns_of(const hydro_grid* g) {
-  const long per = (long)(g->d.nxb / tile_edge(g->d.nxb)) * (g->d.nxb / tile_edge(g->d.nxb));
+// column tiles of a grid's z layers stepped with tiles of edge `tile`
+long columns_of(const hydro_grid* g, int tile) {
+  const long per = (long)(g->d.nxb / tile) * (g->d.nxb / tile);
   return (long)g->d.nblk[0] * g->d.nblk[1] * g->d.nblk[2] * per;
 }
 
@@ -453,7 +466,7 @@ struct BatchLayout {
 BatchLayout batch_layout(hydro_grid* const* grids, int n) {
   BatchLayout L;
   size_t maxi = 0;
-  for (int i = 0; i < n; ++i) maxi += (size_t)columns_of(grids[i]) * kMaxPencils;
+  for (int i = 0; i < n; ++i) maxi += (size_t)columns_of(grids[i], 8) * kMaxPencils;
   L.max_items = maxi;
   L.sims = 0;
   L.items = align256(sizeof(hydro::BatchSim) * (size_t)n);
@@ -473,7 +486,8 @@ void drop_graph(hydro_batch* b) {
 // 16^3, then 8^3), each stepped by its own launch; inactive members get a
 // table entry but no items.  Launches the signal-speed reduction on `s` for
 // active members whose kept value is stale.
-int build_tables(hydro_grid* const* grids, int n, const unsigned char* active, const int nseg[3], hipStream_t s,
+int build_tables(hydro_grid* const* grids, int n, const unsigned char* active, const int nseg[3], const int tile[3],
+                 hipStream_t s,
                  std::vector<hydro::BatchSim>& sims, std::vector<hydro::BatchItem>& items, long cls_begin[3],
                  long cls_count[3]) {
   sims.resize(n);
@@ -483,7 +497,7 @@ int build_tables(hydro_grid* const* grids, int n, const unsigned char* active, c
     for (int i = 0; i < n; ++i) {
       hydro_grid* g = grids[i];
       if (!active[i] || size_class(g->d.nxb) != cls) continue;
-      const long cols = columns_of(g) * nseg[cls];
+      const long cols = columns_of(g, tile[cls]) * nseg[cls];
       for (long c = 0; c < cols; ++c) items.push_back(hydro::BatchItem{i, (int)c});
     }
     cls_count[cls] = (long)items.size() - cls_begin[cls];
@@ -512,7 +526,7 @@ int build_tables(hydro_grid* const* grids, int n, const unsigned char* active, c
 int batch_upload(hydro_batch* b) {
   hipStream_t s = (hipStream_t)b->stream;
   const int n = (int)b->grids.size();
-  int rc = build_tables(b->grids.data(), n, b->active.data(), b->nseg, s, b->sims, b->items, b->cls_begin,
+  int rc = build_tables(b->grids.data(), n, b->active.data(), b->nseg, b->tile, s, b->sims, b->items, b->cls_begin,
                         b->cls_count);
   if (rc) return rc;
   hipError_t e = hipMemcpyAsync(b->d_sims, b->sims.data(), sizeof(hydro::BatchSim) * n, hipMemcpyHostToDevice, s);
@@ -531,18 +545,19 @@ int batch_upload(hydro_batch* b) {
 // disjoint and every member sits in one class, so the launches are
 // independent; the stream orders them).
 hipError_t class_launches(const hydro::BatchSim* d_sims, const hydro::BatchItem* d_items, const long cls_begin[3],
-                          const long cls_count[3], const int nseg[3], int grid, double cfl, long step, hipStream_t s) {
+                          const long cls_count[3], const int nseg[3], const int tile[3], int grid, double cfl,
+                          long step, hipStream_t s) {
   for (int cls = 2; cls >= 0; --cls) {
     if (cls_count[cls] == 0) continue;
     hipError_t e = hydro::launch_batch_step(d_sims, d_items + cls_begin[cls], (int)cls_count[cls], step % 6, cfl,
-                                            8 << cls, nseg[cls], grid, s);
+                                            8 << cls, tile[cls], nseg[cls], grid, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
 hipError_t batch_launch(hydro_batch* b, double cfl, long step) {
-  return class_launches(b->d_sims, b->d_items, b->cls_begin, b->cls_count, b->nseg, b->grid, cfl, step,
+  return class_launches(b->d_sims, b->d_items, b->cls_begin, b->cls_count, b->nseg, b->tile, b->grid, cfl, step,
                         (hipStream_t)b->stream);
 }
 
@@ -595,6 +610,8 @@ int hydro_batch_create(hydro_grid* const* grids, int n, void* work, size_t work_
   b->max_items = L.max_items;
   b->stream = stream;
   b->nseg[0] = b->nseg[1] = b->nseg[2] = 1;
+  b->tile[0] = 8;
+  b->tile[1] = b->tile[2] = 16;
   b->cus = cus;
   b->grid = 2 * cus;
   for (int c = 0; c < 3; ++c) b->cls_begin[c] = b->cls_count[c] = 0;
@@ -623,6 +640,16 @@ int hydro_batch_set_pencils(hydro_batch* b, const int nseg[3]) {
     if (sizes[c] / nseg[c] < 2) return fail(HYDRO_EINVAL, "pencils shorter than 2 planes");
   }
   for (int c = 0; c < 3; ++c) b->nseg[c] = nseg[c];
+  b->dirty = true;
+  return HYDRO_OK;
+}
+
+int hydro_batch_set_tiles(hydro_batch* b, const int tile[3]) {
+  if (!b || !tile) return fail(HYDRO_EINVAL, "batch or tile is NULL");
+  if (tile[0] != 8) return fail(HYDRO_EINVAL, "8^3 blocks take 8x8 column tiles");
+  for (int c = 1; c < 3; ++c)
+    if (tile[c] != 8 && tile[c] != 16) return fail(HYDRO_EINVAL, "column tiles must be 8x8 or 16x16");
+  for (int c = 0; c < 3; ++c) b->tile[c] = tile[c];
   b->dirty = true;
   return HYDRO_OK;
 }
@@ -720,6 +747,7 @@ int hydro_batch_step_static(hydro_grid* const* grids, int n, const int nseg[3], 
   if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0 (got %g)", cfl);
   if (nsteps < 0) return fail(HYDRO_EINVAL, "nsteps must be >= 0");
   int segs[3] = {1, 1, 1};
+  const int tiles[3] = {8, 16, 16};
   if (nseg) {
     const int sizes[3] = {8, 16, 32};
     for (int c = 0; c < 3; ++c) {
@@ -737,7 +765,7 @@ int hydro_batch_step_static(hydro_grid* const* grids, int n, const int nseg[3], 
       return fail(HYDRO_EINVAL, "grid %d does not use the predictor-corrector scheme", i);
     for (int k = 0; k < i; ++k)
       if (grids[k] == grids[i]) return fail(HYDRO_EINVAL, "grid %d appears twice", i);
-    nitems += (size_t)columns_of(grids[i]) * segs[size_class(grids[i]->d.nxb)];
+    nitems += (size_t)columns_of(grids[i], tiles[size_class(grids[i]->d.nxb)]) * segs[size_class(grids[i]->d.nxb)];
   }
   if (nitems > hydro::kStaticMaxItems)
     return fail(HYDRO_ESIZE, "%zu work items exceed the static scratch's %zu", nitems, hydro::kStaticMaxItems);
@@ -755,7 +783,7 @@ int hydro_batch_step_static(hydro_grid* const* grids, int n, const int nseg[3], 
   thread_local std::vector<hydro::BatchItem> items;
   long cls_begin[3], cls_count[3];
   const std::vector<unsigned char> active(n, 1);
-  int rc = build_tables(grids, n, active.data(), segs, s, sims, items, cls_begin, cls_count);
+  int rc = build_tables(grids, n, active.data(), segs, tiles, s, sims, items, cls_begin, cls_count);
   if (rc) return rc;
   auto* d_sims = (hydro::BatchSim*)base;
   auto* d_items = (hydro::BatchItem*)((char*)base + hydro::kStaticSimsBytes);
@@ -764,7 +792,7 @@ int hydro_batch_step_static(hydro_grid* const* grids, int n, const int nseg[3], 
     e = hipMemcpyAsync(d_items, items.data(), sizeof(hydro::BatchItem) * items.size(), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "static table upload");
   for (int k = 0; k < nsteps; ++k) {
-    e = class_launches(d_sims, d_items, cls_begin, cls_count, segs, 2 * cus, cfl, k, s);
+    e = class_launches(d_sims, d_items, cls_begin, cls_count, segs, tiles, 2 * cus, cfl, k, s);
     if (e != hipSuccess) return hip_fail(e, "batch step launch");
   }
   for (int i = 0; i < n; ++i) {

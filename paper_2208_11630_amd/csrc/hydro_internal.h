@@ -79,13 +79,15 @@ constexpr size_t kStaticScratchBytes = kStaticSimsBytes + kStaticMaxItems * size
 hipError_t static_scratch(void** ptr);
 
 // st == NULL: predictor-corrector step; else one method-of-lines stage.
+// tile: edge of the column tiles (8 for nxb 8; 8 or 16 otherwise).
 // plen: planes per z pencil (>= 2, divides the grid's z extent).
-hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const StageArgs* st, int plen,
+hipError_t launch_step(int nxb, int tile, const GridGeom& g, const StepArgs& a, const StageArgs* st, int plen,
                        hipStream_t s);
 // items: the work-list range of the members with blocks of nxb^3 cells
-// (8, 16 or 32); nseg: pencils per column for that size.
+// (8, 16 or 32), listed with column tiles of edge `tile`; nseg: pencils
+// per column for that size.
 hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,
-                             int nxb, int nseg, int grid, hipStream_t s);
+                             int nxb, int tile, int nseg, int grid, hipStream_t s);
 hipError_t launch_fill_guards(int nxb, const GridGeom& g, const double* U, double* out, hipStream_t s);
 // dir: the per-direction signal max_d (|u_d|+c)/dx_d of the CTU step
 // instead of the summed one.

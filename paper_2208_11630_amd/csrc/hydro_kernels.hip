@@ -141,6 +141,7 @@ __device__ __forceinline__ double rsq_nr(double t) {
 // Primitive state of a cell plus 1/rho (shared by the predictor).
 __device__ __forceinline__ int prim(const double (&u)[5], double gamma, double small_p, double (&w)[5],
                                          double& inv) {
+#pragma clang fp contract(off)  // the same bits in every inlined copy (own column, ring, halo cells)
   const double rho = u[0];
   inv = rcp_nr(rho);
   const double vx = u[1] * inv, vy = u[2] * inv, vz = u[3] * inv;
@@ -168,6 +169,12 @@ __device__ __forceinline__ int prim(const double (&u)[5], double gamma, double s
 template <int D>
 __device__ __forceinline__ void hllc(const double (&L)[5], const double (&R)[5], double gamma,
                                           double gm1inv, double (&F)[5]) {
+  // No implicit contraction: every fused multiply-add is written out, so
+  // every inlined copy of the solver rounds the same way (a face computed by
+  // a tile's interior thread or by its boundary role gives the same bits),
+  // and the kinetic term is symmetric in the velocity components (a y face
+  // solved as an x face with u and v exchanged gives the same bits).
+#pragma clang fp contract(off)
   const double rL = L[0], uL = L[1 + D], pL = L[4];
   const double rR = R[0], uR = R[1 + D], pR = R[4];
   const double gpL = gamma * pL, gpR = gamma * pR;
@@ -176,7 +183,7 @@ __device__ __forceinline__ void hllc(const double (&L)[5], const double (&R)[5],
   const double SL = fmin(uL - cL, uR - cR);
   const double SR = fmax(uL + cL, uR + cR);
   const double mL = rL * (SL - uL), mR = rR * (SR - uR);
-  const double Ss = div_nr(pR - pL + mL * uL - mR * uR, mL - mR);
+  const double Ss = div_nr(fma(-mR, uR, fma(mL, uL, pR - pL)), mL - mR);
   const bool left = (SL >= 0.0) || (Ss >= 0.0);
   const double S = left ? SL : SR;
   const double m = left ? mL : mR;
@@ -185,13 +192,14 @@ __device__ __forceinline__ void hllc(const double (&L)[5], const double (&R)[5],
 #pragma unroll
   for (int v = 0; v < 5; ++v) W[v] = left ? L[v] : R[v];
   const double rho = W[0], un = W[1 + D], p = W[4];
-  const double E = p * gm1inv + 0.5 * rho * ((W[1] * W[1] + W[2] * W[2]) + W[3] * W[3]);
+  const double ke = (W[1] * W[1] + W[2] * W[2]) + W[3] * W[3];
+  const double E = fma(0.5 * rho, ke, p * gm1inv);
   const double mass = rho * un;
   F[0] = mass;
   F[1] = mass * W[1];
   F[2] = mass * W[2];
   F[3] = mass * W[3];
-  F[1 + D] += p;
+  F[1 + D] = fma(mass, W[1 + D], p);
   F[4] = un * (E + p);
   if (corr) {
     const double q = rcp_nr(S - Ss);
@@ -202,10 +210,10 @@ __device__ __forceinline__ void hllc(const double (&L)[5], const double (&R)[5],
     dU[1] = d0 * W[1];
     dU[2] = d0 * W[2];
     dU[3] = d0 * W[3];
-    dU[1 + D] = factor * Ss - rho * un;
-    dU[4] = q * ((S - un) * E + (Ss - un) * (m * Ss + p)) - E;
+    dU[1 + D] = fma(factor, Ss, -mass);
+    dU[4] = fma(q, fma(S - un, E, (Ss - un) * fma(m, Ss, p)), -E);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) F[v] += S * dU[v];
+    for (int v = 0; v < 5; ++v) F[v] = fma(S, dU[v], F[v]);
   }
 }
 
@@ -770,11 +778,10 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void stage_kernel(GridGeom g, StepA
 // tile step (a kernel holding all three spilled registers and ran 8% slower
 // on a mixed ensemble).  An item of a member of another size would be
 // skipped, never misread.
-template <int N>
-__global__ __launch_bounds__(Tile<(N == 8 ? 8 : 16)>::NT, 2) void batch_step_kernel(const BatchSim* __restrict__ sims,
-                                                            const BatchItem* __restrict__ items, int nitems,
-                                                            long step, double cfl, int nseg) {
-  constexpr int T = N == 8 ? 8 : 16;
+template <int N, int T>
+__global__ __launch_bounds__(Tile<T>::NT, 2) void batch_step_kernel(const BatchSim* __restrict__ sims,
+                                                                    const BatchItem* __restrict__ items, int nitems,
+                                                                    long step, double cfl, int nseg) {
   __shared__ Smem<T> sm;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const BatchItem w = items[it];
@@ -1880,14 +1887,16 @@ hipError_t launch_step_t(const GridGeom& g, const StepArgs& a, const StageArgs* 
 
 }  // namespace
 
-hipError_t launch_step(int nxb, const GridGeom& g, const StepArgs& a, const StageArgs* st, int plen,
+hipError_t launch_step(int nxb, int tile, const GridGeom& g, const StepArgs& a, const StageArgs* st, int plen,
                        hipStream_t s) {
   const long nz = (long)g.nb[2] * nxb;
   if (plen < 2 || plen > nz || nz % plen) return hipErrorInvalidValue;
-  switch (nxb) {
-    case 8: return launch_step_t<8, 8>(g, a, st, plen, s);
-    case 16: return launch_step_t<16, 16>(g, a, st, plen, s);
-    case 32: return launch_step_t<32, 16>(g, a, st, plen, s);
+  switch (nxb * 100 + tile) {
+    case 808: return launch_step_t<8, 8>(g, a, st, plen, s);
+    case 1616: return launch_step_t<16, 16>(g, a, st, plen, s);
+    case 1608: return launch_step_t<16, 8>(g, a, st, plen, s);
+    case 3216: return launch_step_t<32, 16>(g, a, st, plen, s);
+    case 3208: return launch_step_t<32, 8>(g, a, st, plen, s);
   }
   return hipErrorInvalidValue;
 }
@@ -2055,21 +2064,30 @@ hipError_t launch_ctu(int nxb, const GridGeom& g, const StepArgs& a, bool trace,
 }
 
 hipError_t launch_batch_step(const BatchSim* sims, const BatchItem* items, int nitems, long step, double cfl,
-                             int nxb, int nseg, int grid, hipStream_t s) {
-  // 8^3 blocks: 128-thread workgroups (the 8x8 tile's roles), twice as many
+                             int nxb, int tile, int nseg, int grid, hipStream_t s) {
+  // 8x8 tiles: 128-thread workgroups (the 8x8 tile's roles), twice as many
   // of them, so a CU holds the same number of wavefronts
-  switch (nxb) {
-    case 8:
-      hipLaunchKernelGGL(batch_step_kernel<8>, dim3((unsigned)(2 * grid)), dim3(Tile<8>::NT), 0, s, sims, items,
-                         nitems, step, cfl, nseg);
+  const unsigned g16 = (unsigned)grid, g8 = (unsigned)(2 * grid);
+  switch (nxb * 100 + tile) {
+    case 808:
+      hipLaunchKernelGGL((batch_step_kernel<8, 8>), dim3(g8), dim3(Tile<8>::NT), 0, s, sims, items, nitems, step, cfl,
+                         nseg);
       break;
-    case 16:
-      hipLaunchKernelGGL(batch_step_kernel<16>, dim3((unsigned)grid), dim3(Tile<16>::NT), 0, s, sims, items, nitems,
-                         step, cfl, nseg);
+    case 1616:
+      hipLaunchKernelGGL((batch_step_kernel<16, 16>), dim3(g16), dim3(Tile<16>::NT), 0, s, sims, items, nitems, step,
+                         cfl, nseg);
       break;
-    case 32:
-      hipLaunchKernelGGL(batch_step_kernel<32>, dim3((unsigned)grid), dim3(Tile<16>::NT), 0, s, sims, items, nitems,
-                         step, cfl, nseg);
+    case 1608:
+      hipLaunchKernelGGL((batch_step_kernel<16, 8>), dim3(g8), dim3(Tile<8>::NT), 0, s, sims, items, nitems, step, cfl,
+                         nseg);
+      break;
+    case 3216:
+      hipLaunchKernelGGL((batch_step_kernel<32, 16>), dim3(g16), dim3(Tile<16>::NT), 0, s, sims, items, nitems, step,
+                         cfl, nseg);
+      break;
+    case 3208:
+      hipLaunchKernelGGL((batch_step_kernel<32, 8>), dim3(g8), dim3(Tile<8>::NT), 0, s, sims, items, nitems, step, cfl,
+                         nseg);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -86,6 +86,7 @@ SIGNATURES = {
                                  ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "hydro_amr_free": ([ctypes.c_void_p], ctypes.c_int),
     "hydro_set_pencil_planes": ([_HP, ctypes.c_int], ctypes.c_int),
+    "hydro_set_tile": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_set_scheme": ([_HP, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "hydro_set_buffers": ([_HP, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "hydro_batch_work_bytes": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int], ctypes.c_size_t),
@@ -95,6 +96,7 @@ SIGNATURES = {
     "hydro_batch_set_active": ([_HP, ctypes.POINTER(ctypes.c_ubyte)], ctypes.c_int),
     "hydro_batch_set_pencils": ([_HP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "hydro_batch_set_workgroups": ([_HP, ctypes.c_int], ctypes.c_int),
+    "hydro_batch_set_tiles": ([_HP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "hydro_batch_use_graph": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_batch_dts": ([_HP, _dp], ctypes.c_int),
     "hydro_batch_free": ([_HP], ctypes.c_int),
@@ -172,6 +174,7 @@ class Grid:
         self._torch = torch
         self.nxb, self.nblk = int(nxb), tuple(int(x) for x in nblk)
         self.nguard = int(nguard)
+        self.tile = 8 if self.nxb == 8 else 16
         d = make_desc(nxb, nblk, lo, hi, bc, gamma, small_p, nguard)
         nd = L.hydro_state_doubles(ctypes.byref(d))
         n = self.nxb
@@ -255,6 +258,11 @@ class Grid:
 
     def set_pencil_planes(self, planes: int) -> None:
         _check(lib().hydro_set_pencil_planes(self.handle, int(planes)))
+
+    def set_tile(self, tile: int) -> None:
+        """Column tile edge of the step's workgroups (8 or 16)."""
+        _check(lib().hydro_set_tile(self.handle, int(tile)))
+        self.tile = int(tile)
 
     def set_scheme(self, scheme: int, stage=None) -> None:
         """Time integration: SCHEME_MH (predictor-corrector), SCHEME_RK2 or
@@ -366,6 +374,10 @@ class Batch:
 
     def set_workgroups(self, per_cu: int) -> None:
         _check(lib().hydro_batch_set_workgroups(self.handle, int(per_cu)))
+
+    def set_tiles(self, t8: int, t16: int, t32: int) -> None:
+        a = (ctypes.c_int * 3)(int(t8), int(t16), int(t32))
+        _check(lib().hydro_batch_set_tiles(self.handle, a))
 
     def use_graph(self, enable: bool = True) -> None:
         _check(lib().hydro_batch_use_graph(self.handle, 1 if enable else 0))

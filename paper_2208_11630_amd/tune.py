@@ -14,6 +14,9 @@ Tunables:
     fewer halo planes re-read per updated plane on tall grids; shorter
     pencils fill the 256 CUs on small grids); for batches 1, 2 or 4 pencils
     per block column per block size;
+  * the edge of the column tiles (8 or 16 for blocks of 16^3 and 32^3
+    cells: 8x8 tiles give four times the workgroups, 16x16 tiles predict
+    a relatively smaller ring), per grid and per block size in batches;
   * persistent workgroups per CU for batches (1..3).
 """
 from __future__ import annotations
@@ -90,31 +93,40 @@ def pencil_candidates(G: "hydro.Grid") -> List[int]:
             if p >= 2 and p <= nz and nz % p == 0]
 
 
+def tile_candidates(G: "hydro.Grid") -> List[int]:
+    return [16, 8] if G.nxb >= 16 else [8]
+
+
 def tune_grid(G: "hydro.Grid", cfl: float = 0.8, apply: bool = True, use_cache: bool = True) -> int:
-    """Best planes per z pencil for this grid; applied to G unless apply=False."""
+    """Best (column tile edge, planes per z pencil) for this grid, applied to
+    G unless apply=False; returns the planes per pencil (the tile edge is
+    left in G.tile)."""
     key = f"{_arch()}|{grid_signature(G)}"
     cache = _load() if use_cache else {}
-    if key in cache and "planes" in cache[key]:
-        best = int(cache[key]["planes"])
+    if key in cache and "planes" in cache[key] and "tile" in cache[key]:
+        best = (int(cache[key]["tile"]), int(cache[key]["planes"]))
     else:
         C = _clone(G)
         times = {}
         # two interleaved rounds of 8 timed steps per candidate, the faster
         # round kept: neighbouring pencil lengths are often within 0.5%
         for _ in range(2):
-            for planes in pencil_candidates(G):
-                C.set_pencil_planes(planes)
-                t = _time(lambda: C.step_cfl(cfl), warm=2, reps=8, stream=C.stream)
-                times[planes] = min(t, times.get(planes, t))
+            for tile in tile_candidates(G):
+                C.set_tile(tile)
+                for planes in pencil_candidates(G):
+                    C.set_pencil_planes(planes)
+                    t = _time(lambda: C.step_cfl(cfl), warm=2, reps=8, stream=C.stream)
+                    times[(tile, planes)] = min(t, times.get((tile, planes), t))
         C.close()
         best = min(times, key=times.get)
         cache = _load()
-        cache[key] = {"planes": best, "ms": {str(k): v for k, v in times.items()}}
+        cache[key] = {"tile": best[0], "planes": best[1], "ms": {f"{k[0]}x{k[0]}|{k[1]}": v for k, v in times.items()}}
         if use_cache:
             _store(cache)
     if apply:
-        G.set_pencil_planes(best)
-    return best
+        G.set_tile(best[0])
+        G.set_pencil_planes(best[1])
+    return best[1]
 
 
 def batch_signature(grids: Sequence["hydro.Grid"]) -> str:
@@ -138,14 +150,15 @@ def tune_batch(B: "hydro.Batch", cfl: float = 0.8, apply: bool = True, use_cache
             c.stream.synchronize()
         S = hydro.Batch(clones)
         S.use_graph(True)
-        cfg = {"pencils": [1, 1, 1], "per_cu": 2}
+        cfg = {"pencils": [1, 1, 1], "per_cu": 2, "tiles": [8, 16, 16]}
         trials: List = []
 
         def measure(c):
             S.set_pencils(*c["pencils"])
             S.set_workgroups(c["per_cu"])
+            S.set_tiles(*c["tiles"])
             t = _time(lambda: S.step(cfl, 6), warm=1, reps=2, stream=S.stream) / 6
-            trials.append((dict(c, pencils=list(c["pencils"])), t))
+            trials.append((dict(c, pencils=list(c["pencils"]), tiles=list(c["tiles"])), t))
             return t
 
         best_t = measure(cfg)
@@ -162,6 +175,15 @@ def tune_batch(B: "hydro.Batch", cfl: float = 0.8, apply: bool = True, use_cache
                 t = measure(c)
                 if t < best_t:
                     best_t, cfg = t, c
+        for n in (32, 16):                      # 8x8 column tiles for the larger blocks
+            k = {16: 1, 32: 2}[n]
+            if not present[n]:
+                continue
+            c = dict(cfg, pencils=list(cfg["pencils"]), tiles=list(cfg["tiles"]))
+            c["tiles"][k] = 8
+            t = measure(c)
+            if t < best_t:
+                best_t, cfg = t, c
         for per_cu in (1, 3):
             c = dict(cfg, per_cu=per_cu)
             t = measure(c)
@@ -170,7 +192,7 @@ def tune_batch(B: "hydro.Batch", cfl: float = 0.8, apply: bool = True, use_cache
         S.close()
         for c in clones:
             c.close()
-        cfg = {"pencils": cfg["pencils"], "per_cu": cfg["per_cu"], "ms_per_step": best_t,
+        cfg = {"pencils": cfg["pencils"], "per_cu": cfg["per_cu"], "tiles": cfg["tiles"], "ms_per_step": best_t,
                "trials": [(c, t) for c, t in trials]}
         cache = _load()
         cache[key] = cfg
@@ -179,4 +201,5 @@ def tune_batch(B: "hydro.Batch", cfl: float = 0.8, apply: bool = True, use_cache
     if apply:
         B.set_pencils(*cfg["pencils"])
         B.set_workgroups(cfg["per_cu"])
+        B.set_tiles(*cfg.get("tiles", [8, 16, 16]))
     return cfg

@@ -185,3 +185,8 @@ def test_static_batch_rejects_too_many_grids_before_the_device(L):
     assert L.hydro_batch_step_static(arr, n, None, 0.8, 1, None) == hydro.HYDRO_ESIZE
     assert b"static scratch" in L.hydro_last_error()
     assert L.hydro_batch_step_static(None, 0, None, 0.8, 1, None) == hydro.HYDRO_EINVAL
+
+
+def test_tile_setters_reject_null_handles(L):
+    assert L.hydro_set_tile(None, 8) == hydro.HYDRO_EINVAL
+    assert L.hydro_batch_set_tiles(None, None) == hydro.HYDRO_EINVAL

@@ -41,13 +41,15 @@ def alone(hy, P, k, cfl=0.8, nseg=1):
     return G.download(), G.last_dt()
 
 
-def batched(hy, sims, k, cfl=0.8, pencils=None, per_cu=None, graph=False, chunks=None):
+def batched(hy, sims, k, cfl=0.8, pencils=None, per_cu=None, graph=False, chunks=None, tiles=None):
     grids = [hy.grid_for(P) for P in sims]
     B = hy.Batch(grids)
     if pencils:
         B.set_pencils(*pencils)
     if per_cu:
         B.set_workgroups(per_cu)
+    if tiles:
+        B.set_tiles(*tiles)
     B.use_graph(graph)
     for c in (chunks or [k]):
         B.step(cfl, c)
@@ -94,11 +96,12 @@ def test_single_size_batch_bitwise_equals_alone(hy, n):
     B.close()
 
 
-@pytest.mark.parametrize("pencils,per_cu", [((2, 2, 4), 2), ((4, 4, 2), 1), ((1, 4, 4), 3)])
-def test_batch_tuning_is_bitwise_invariant(hy, pencils, per_cu):
+@pytest.mark.parametrize("pencils,per_cu,tiles", [((2, 2, 4), 2, None), ((4, 4, 2), 1, (8, 8, 8)),
+                                                  ((1, 4, 4), 3, (8, 16, 8)), ((1, 1, 1), 2, (8, 8, 16))])
+def test_batch_tuning_is_bitwise_invariant(hy, pencils, per_cu, tiles):
     sims = members(count=9, seed=8)
     base, _ = batched(hy, sims, 3)
-    out, _ = batched(hy, sims, 3, pencils=pencils, per_cu=per_cu)
+    out, _ = batched(hy, sims, 3, pencils=pencils, per_cu=per_cu, tiles=tiles)
     for a, b in zip(base, out):
         assert np.array_equal(a, b)
 
@@ -139,6 +142,48 @@ def test_grid_pencil_planes_bitwise_invariant(hy, planes, case):
     for _ in range(3):
         G.step_cfl(0.8)
     assert np.array_equal(G.download(), a) and G.last_dt() == da
+
+
+@pytest.mark.parametrize("n,shape,planes", [(16, (64, 64, 64), 16), (16, (32, 48, 64), 32), (32, (64, 32, 64), 64),
+                                             (32, (32, 32, 96), 16)])
+def test_grid_tile_bitwise_invariant(hy, n, shape, planes):
+    """8x8 column tiles give the same bits as 16x16 ones, for the
+    predictor-corrector step and an SSP-RK2 step, at several pencil
+    lengths."""
+    P = ics.kelvin_helmholtz(shape=shape, n=n)
+    a, da = alone(hy, P, 3)
+    G = hy.grid_for(P)
+    G.set_tile(8)
+    G.set_pencil_planes(planes)
+    for _ in range(3):
+        G.step_cfl(0.8)
+    assert np.array_equal(G.download(), a) and G.last_dt() == da
+    R16 = hy.grid_for(P)
+    R16.set_scheme(hy.SCHEME_RK2)
+    R8 = hy.grid_for(P)
+    R8.set_scheme(hy.SCHEME_RK2)
+    R8.set_tile(8)
+    for _ in range(2):
+        R16.step_cfl(0.8)
+        R8.step_cfl(0.8)
+    assert np.array_equal(R16.download(), R8.download())
+
+
+def test_tile_argument_errors(hy):
+    G = hy.grid_for(ics.kelvin_helmholtz(shape=(32, 32, 32), n=8))
+    for bad in (0, 4, 12, 16, 32):
+        with pytest.raises(hy.HydroError):
+            G.set_tile(bad)
+    G.set_tile(8)
+    H = hy.grid_for(ics.kelvin_helmholtz(shape=(32, 32, 32), n=16))
+    B = hy.Batch([H])
+    with pytest.raises(hy.HydroError):
+        H.set_tile(8)                        # a member of a batch
+    with pytest.raises(hy.HydroError):
+        B.set_tiles(16, 16, 16)              # 8^3 blocks take 8x8 tiles
+    with pytest.raises(hy.HydroError):
+        B.set_tiles(8, 4, 16)
+    B.close()
 
 
 def test_pencil_planes_argument_errors(hy):

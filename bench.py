@@ -706,6 +706,8 @@ def extras(args):
     out = {"other_workloads": {}}
     for name, P, w in ((("sod"), ics.sod(), "sod_64^3_nxb16"), ("sedov", ics.sedov(), "sedov_256^3_nxb16")):
         out["other_workloads"][name] = {"workload": w, **plain_rate(P, w, args)}
+        if not args.no_cpu_baseline:
+            out["other_workloads"][name]["cpu_oracle"] = cpu_baseline(P, 4.0)
         del P
         torch.cuda.empty_cache()
     e = run_ensemble(args, cpu=False)

@@ -31,6 +31,7 @@ class Request:
     t_launch: float = math.nan
     t_done: float = math.nan
     error: Optional[str] = None   # set when the request failed (it then has no t_done)
+    t_seen: float = math.nan      # when the loop took it in (at or after t_arrival)
 
     @property
     def latency(self) -> float:
@@ -181,14 +182,21 @@ class Server:
         t0 = self.clock()
         i = 0
         n = len(arrivals)
-        while True:
+
+        def ingest() -> float:
+            # take in every request due by now
+            nonlocal i
             now = self.clock() - t0
             while i < n and arrivals[i][0] <= now:
                 t, s = arrivals[i]
-                r = Request(s, t0 + t)
+                r = Request(s, t0 + t, t_seen=t0 + now)
                 self.stats.requests.append(r)
                 pending.setdefault(s, collections.deque()).append(r)
                 i += 1
+            return now
+
+        while True:
+            now = ingest()
             # completions
             still = []
             for h, reqs, sims in inflight:
@@ -238,6 +246,9 @@ class Server:
                     reqs.append(q.popleft())
                     if not q:
                         del pending[s]
+                # requests that came due while the launch was formed count as
+                # waiting before any eviction is decided
+                ingest()
                 admitting = sum(1 for s in pending if self.ex.is_resident(s) and not self.ex.is_ready(s))
                 for s in list(pending.keys()):
                     if admitting >= self.max_admitting:

@@ -109,9 +109,10 @@ def test_budget_respected_with_lru_eviction():
 
 def test_no_eviction_of_a_simulation_with_waiting_requests():
     """Under a budget of three simulations and a stream cycling over ten, no
-    simulation is evicted between the arrival and the launch of one of its
-    requests (its state would only have to come back), and the launches take
-    resident simulations before waiting for admissions."""
+    simulation is evicted between the moment the loop takes in one of its
+    requests and that request's launch (its state would only have to come
+    back), and the launches take resident simulations before waiting for
+    admissions."""
     sizes = [64] * 10
     ex = FakeExecutor(sizes, cost_per_cell=4e-9)
     srv = serve.Server(ex, budget_bytes=3 * 80 * 64 ** 3 + 10)
@@ -122,7 +123,8 @@ def test_no_eviction_of_a_simulation_with_waiting_requests():
     assert st.evictions > 0
     for r in st.requests:
         for t in ex.evicted_at.get(r.sim, []):
-            assert not (r.t_arrival < t < r.t_launch), (r.sim, r.t_arrival, t, r.t_launch)
+            assert r.t_arrival <= r.t_seen <= r.t_launch
+            assert not (r.t_seen < t < r.t_launch), (r.sim, r.t_seen, t, r.t_launch)
 
 
 def test_restore_returns_to_the_same_residency():

@@ -359,6 +359,11 @@ struct Smem {
   double sRx[5][T];        // low-x face state of ring cell (T, y)
   double sRy[5][T];        // low-y face state of ring cell (x, T)
   double sRing[3][5][NR];  // ring z windows (planes mod 3)
+  // Conserved state of the own cells, planes mod 3: each thread keeps its
+  // column's last three prefetched planes here and takes the old state of
+  // the plane it updates from this slot (thread-private, no barrier
+  // needed), so the update reloads nothing from global memory.
+  double sU[3][5][Tile<T>::NI];
   // The x / y fluxes overwrite the face states: the flux at face (x, y) goes
   // to the slot of the high-side state of its left / lower cell, read only
   // by the thread that computes that face (sQx index y*(T+1) + x, x = 0..T;
@@ -493,6 +498,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
                                : 8u * (unsigned)cell_offset<N>(g, X0 + sx2, Y0 + sy2, 0);
 
   double Wa[5], Wb[5], Wc[5];
+  double inv_b = 1.0, inv_c = 1.0;  // 1/rho of planes j and j+1, from the primitive recovery
   double un_next[5], u2_next[5];
   // acc: plane j-1's x/y flux divergence minus its lower z flux, carried to
   // the next plane, whose z flux completes the update of plane j-1
@@ -512,7 +518,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     load_cons_at<N, GV>(Uin + plane_off(z0 - 2), own_xy, u);
     prim(u, gamma, g.small_p, Wa, tmp);
     load_cons_at<N, GV>(Uin + plane_off(z0 - 1), own_xy, u);
-    prim(u, gamma, g.small_p, Wb, tmp);
+    prim(u, gamma, g.small_p, Wb, inv_b);
     load_cons_at<N, GV>(Uin + plane_off(z0), own_xy, un_next);
   }
   if (is_ring) {
@@ -531,11 +537,13 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     // -- own column: plane j+1 from the prefetch, publish plane j; second
     // item: ring cell window (planes j..j+1) or halo cell (plane j)
     if (inner) {
-      double inv_unused;
-      const int fl = prim(un_next, gamma, g.small_p, Wc, inv_unused);
+      const int fl = prim(un_next, gamma, g.small_p, Wc, inv_c);
       if (j + 1 >= z0 && j + 1 < z1) n_floor += fl;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sm.sW[v][cidx] = Wb[v];
+      for (int v = 0; v < 5; ++v) {
+        sm.sW[v][cidx] = Wb[v];
+        sm.sU[(j + 1) % 3][v][tid] = un_next[v];
+      }
     }
     if (is_ring) {
       double w[5], tmp;
@@ -576,7 +584,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
       if constexpr (MOL)
         ok = face_check(Wb, Wb, sx, sy, sz, wt, h);
       else
-        ok = predict(Wb, rcp_nr(Wb[0]), sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
+        ok = predict(Wb, inv_b, sx, sy, sz, gamma, lamx, lamy, lamz, wt, h);
       if (mid && !ok) ++n_fb;
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -680,15 +688,12 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         for (int v = 0; v < 5; ++v) fo[v * TL::NQ] = F[v];
       }
     }
-    // the old state of plane j-1 (and the base state of a stage) is fetched
-    // before the barrier, so its latency overlaps the wait
+    // the base state of a stage is fetched before the barrier, so its
+    // latency overlaps the wait (the old state comes from sU)
     const long off_u = plane_off(j - 1);
-    double uold[5], base[5];
-    if (inner && j >= z0 + 1) {
-      load_cons_at<N, GV, true>(Uin + off_u, own_xy, uold);
-      if constexpr (MOL) {
-        if (st.U0) load_cons_at<N>(st.U0 + off_u, own_xy, base);
-      }
+    double base[5];
+    if constexpr (MOL) {
+      if (inner && j >= z0 + 1 && st.U0) load_cons_at<N>(st.U0 + off_u, own_xy, base);
     }
     __syncthreads();
 
@@ -704,7 +709,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
       if (j >= z0 + 1) {
         double un[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) un[v] = uold[v] - fma(lamz, fz[v], acc[v]);
+        for (int v = 0; v < 5; ++v) un[v] = sm.sU[(j - 1) % 3][v][tid] - fma(lamz, fz[v], acc[v]);
         if constexpr (MOL) {
           if (st.U0) {
 #pragma unroll
@@ -733,6 +738,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         Wa[v] = Wb[v];
         Wb[v] = Wc[v];
       }
+      inv_b = inv_c;
     }
   }
 

@@ -789,7 +789,18 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void batch_step_kernel(const BatchS
                                                                     const BatchItem* __restrict__ items, int nitems,
                                                                     long step, double cfl, int nseg) {
   __shared__ Smem<T> sm;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // The items in 8 contiguous ranges, one per XCD (workgroups are dealt to
+  // the 8 XCDs in turn), so tiles next to each other in the work list --
+  // neighbours in a grid -- share an L2; a grid of workgroups that is not a
+  // multiple of 8 takes the items in plain stride.
+  const int G = (int)gridDim.x;
+  const bool by_xcd = G % 8 == 0;
+  const int nx = by_xcd ? G / 8 : G;
+  const int x = by_xcd ? (int)blockIdx.x % 8 : 0;
+  const int l = by_xcd ? (int)blockIdx.x / 8 : (int)blockIdx.x;
+  const int per = by_xcd ? (nitems + 7) / 8 : nitems;
+  const int end = min(nitems, (x + 1) * per);
+  for (int it = x * per + l; it < end; it += nx) {
     const BatchItem w = items[it];
     const BatchSim& d = sims[w.sim];
     const int par = (int)((d.parity0 + step) & 1);

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -33,6 +34,7 @@ struct hydro_grid {
   hydro_batch* batch;       // batch the grid belongs to (its own step calls are refused meanwhile)
   int scheme;               // HYDRO_SCHEME_*
   double* U_stage;          // third state buffer (third-order Runge-Kutta)
+  unsigned long long mark;  // last hydro_batch_step_static call that listed the grid
 };
 
 struct hydro_batch {
@@ -277,6 +279,7 @@ int hydro_init_grid(const hydro_grid_desc* d, hydro_grid** out) {
   g->plen = d->nxb;
   g->tile = d->nxb == 8 ? 8 : 16;
   g->batch = nullptr;
+  g->mark = 0;
   g->scheme = HYDRO_SCHEME_MH;
   g->U_stage = nullptr;
   hipError_t e = hipMemsetAsync(d->work, 0, sizeof(hydro::WorkHeader), (hipStream_t)d->stream);
@@ -757,14 +760,18 @@ int hydro_batch_step_static(hydro_grid* const* grids, int n, const int nseg[3], 
       segs[c] = nseg[c];
     }
   }
+  // duplicates: each call stamps its grids with its own id (linear in n;
+  // no host allocation)
+  static std::atomic<unsigned long long> calls{0};
+  const unsigned long long id = ++calls;
   size_t nitems = 0;
   for (int i = 0; i < n; ++i) {
     if (!grids[i]) return fail(HYDRO_EINVAL, "grid %d is NULL", i);
     if (grids[i]->batch) return fail(HYDRO_EINVAL, "grid %d belongs to a batch", i);
     if (grids[i]->scheme != HYDRO_SCHEME_MH)
       return fail(HYDRO_EINVAL, "grid %d does not use the predictor-corrector scheme", i);
-    for (int k = 0; k < i; ++k)
-      if (grids[k] == grids[i]) return fail(HYDRO_EINVAL, "grid %d appears twice", i);
+    if (grids[i]->mark == id) return fail(HYDRO_EINVAL, "grid %d appears twice", i);
+    grids[i]->mark = id;
     nitems += (size_t)columns_of(grids[i], tiles[size_class(grids[i]->d.nxb)]) * segs[size_class(grids[i]->d.nxb)];
   }
   if (nitems > hydro::kStaticMaxItems)
@@ -779,10 +786,12 @@ int hydro_batch_step_static(hydro_grid* const* grids, int n, const int nseg[3], 
   if (e != hipSuccess) return hip_fail(e, "static scratch lookup");
   hipStream_t s = (hipStream_t)stream;
   // host copies of the tables stay alive until the next call on this thread
+  // (their storage only grows)
   thread_local std::vector<hydro::BatchSim> sims;
   thread_local std::vector<hydro::BatchItem> items;
+  thread_local std::vector<unsigned char> active;
   long cls_begin[3], cls_count[3];
-  const std::vector<unsigned char> active(n, 1);
+  active.assign(n, 1);
   int rc = build_tables(grids, n, active.data(), segs, tiles, s, sims, items, cls_begin, cls_count);
   if (rc) return rc;
   auto* d_sims = (hydro::BatchSim*)base;

@@ -85,3 +85,26 @@ def test_static_batch_continues_a_grid_and_rejects_oversize(hy):
     arr = (ctypes.c_void_p * 4097)(*([got[0].handle.value] * 4097))
     rc = hy.lib().hydro_batch_step_static(arr, 4097, None, 0.8, 1, None)
     assert rc == hy.HYDRO_ESIZE
+
+
+def test_static_batch_argument_errors_leave_the_grids_usable(hy):
+    """A grid listed twice, a grid of a batch and a grid on another scheme
+    are refused (HYDRO_EINVAL) before any launch; a refused call leaves
+    nothing behind, so the same grids then step normally."""
+    sims = _members(3, 34)
+    ref = [hy.grid_for(P) for P in sims]
+    for G in ref:
+        G.step_cfl(0.8)
+    got = [hy.grid_for(P) for P in sims]
+    with pytest.raises(hy.HydroError, match="twice"):
+        hy.batch_step_static([got[0], got[1], got[0]], 0.8, 1)
+    B = hy.Batch([got[2]])
+    with pytest.raises(hy.HydroError, match="batch"):
+        hy.batch_step_static(got, 0.8, 1)
+    B.close()
+    R = hy.grid_for(sims[0])
+    R.set_scheme(hy.SCHEME_RK2)
+    with pytest.raises(hy.HydroError, match="scheme"):
+        hy.batch_step_static([got[1], R], 0.8, 1)
+    hy.batch_step_static(got, 0.8, 1)            # the same grids, each once
+    _compare(ref, got)

@@ -17,7 +17,8 @@
 //    crosses HBM once per step.  hydro_fill_guards materialises the guarded
 //    Flash-X-style view (4 layers) only when a caller asks for it.
 //  * Each thread owns one tile cell and keeps that column's primitives for
-//    planes j-1, j, j+1 in registers (z slopes, z face states and z fluxes
+//    planes j, j+1 and the difference to plane j-1 in registers (z slopes,
+//    z face states and z fluxes
 //    never touch LDS).  The in-plane neighbours, the x/y face states and the
 //    x/y fluxes go through LDS, so every face flux is computed exactly once
 //    per tile; the one-cell ring around the tile is predicted as a second
@@ -248,7 +249,7 @@ __device__ __forceinline__ long xcd_tile(long w, long total) {
 // 16) so that two of them share a CU evenly across its four SIMDs (a 320-
 // thread workgroup, one thread per predictor cell, packed only one per CU).
 // Thread t owns tile cell (t % T, t / T) and keeps that column's primitives
-// for planes j-1, j, j+1 in registers.  The one-cell ring around the tile
+// for planes j, j+1 and their difference to plane j-1 in registers.  The one-cell ring around the tile
 // (4T cells) is a second item of roles 0..4T-1 whose z windows live in LDS;
 // the two-deep halo cells that only feed ring slopes (4T+4 cells) are a
 // second item of the next roles.  Each thread computes the x
@@ -307,8 +308,13 @@ __device__ __forceinline__ bool face_check(const double (&t)[5], const double (&
   const double hp = 0.5 * fmax(fmax(fabs(sx[4]), fabs(sy[4])), fabs(sz[4]));
   const bool ok = (t[0] - hr > 0.0) && (t[0] + hr > 0.0) && (t[4] - hp > 0.0) && (t[4] + hp > 0.0);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) wt[v] = ok ? t[v] : wc[v];
-  h = ok ? 0.5 : 0.0;
+  for (int v = 0; v < 5; ++v) wt[v] = t[v];
+  h = 0.5;
+  if (__builtin_expect(!ok, 0)) {  // rare: a branch the wavefront skips, not selects
+#pragma unroll
+    for (int v = 0; v < 5; ++v) wt[v] = wc[v];
+    h = 0.0;
+  }
   return ok;
 }
 
@@ -497,7 +503,9 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
                           : GV ? 8u * (unsigned)((ly0 + sy2 + VG) * GP + (lx0 + sx2 + VG))
                                : 8u * (unsigned)cell_offset<N>(g, X0 + sx2, Y0 + sy2, 0);
 
-  double Wa[5], Wb[5], Wc[5];
+  // Wb, Wc: primitives of planes j, j+1; dzm: Wb minus the plane below
+  // (the z slope's lower difference, carried instead of that plane)
+  double Wb[5], Wc[5], dzm[5], dzp[5];
   double inv_b = 1.0, inv_c = 1.0;  // 1/rho of planes j and j+1, from the primitive recovery
   double un_next[5], u2_next[5];
   // acc: plane j-1's x/y flux divergence minus its lower z flux, carried to
@@ -505,7 +513,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   double zp_prev[5], acc[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    Wa[v] = Wb[v] = Wc[v] = 0.0;
+    Wb[v] = Wc[v] = dzm[v] = dzp[v] = 0.0;
     un_next[v] = u2_next[v] = 0.0;
     zp_prev[v] = acc[v] = 0.0;
   }
@@ -516,9 +524,11 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   if (inner) {
     double u[5], tmp;
     load_cons_at<N, GV>(Uin + plane_off(z0 - 2), own_xy, u);
-    prim(u, gamma, g.small_p, Wa, tmp);
+    prim(u, gamma, g.small_p, dzm, tmp);
     load_cons_at<N, GV>(Uin + plane_off(z0 - 1), own_xy, u);
     prim(u, gamma, g.small_p, Wb, inv_b);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) dzm[v] = Wb[v] - dzm[v];
     load_cons_at<N, GV>(Uin + plane_off(z0), own_xy, un_next);
   }
   if (is_ring) {
@@ -578,7 +588,8 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         const double c = Wb[v];
         sx[v] = van_leer_sf(c - sm.sW[v][cidx - 1], sm.sW[v][cidx + 1] - c);
         sy[v] = van_leer_sf(c - sm.sW[v][cidx - WS], sm.sW[v][cidx + WS] - c);
-        sz[v] = van_leer_sf(c - Wa[v], Wc[v] - c);
+        dzp[v] = Wc[v] - c;
+        sz[v] = van_leer_sf(dzm[v], dzp[v]);
       }
       bool ok;
       if constexpr (MOL)
@@ -641,6 +652,9 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     __syncthreads();
 
     // -- x and y fluxes: own low faces, plus the tile's high boundary faces
+    // the ring's wavefront is the busiest of this phase too (its z faces
+    // besides the x / y ones): it keeps the issue priority here
+    if (ring_wave) __builtin_amdgcn_s_setprio(2);
     if (inner && j >= z0 && ring_wave) hllc<2>(zp_prev, zm, gamma, gm1inv, fz);
     if (mid) {
       if (inner) {
@@ -688,6 +702,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         for (int v = 0; v < 5; ++v) fo[v * TL::NQ] = F[v];
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     // the base state of a stage is fetched before the barrier, so its
     // latency overlaps the wait (the old state comes from sU)
     const long off_u = plane_off(j - 1);
@@ -735,7 +750,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
       for (int v = 0; v < 5; ++v) {
         if (mid) acc[v] = fma(-lamz, fz[v], dxy[v]);
         zp_prev[v] = zp[v];
-        Wa[v] = Wb[v];
+        dzm[v] = dzp[v];
         Wb[v] = Wc[v];
       }
       inv_b = inv_c;

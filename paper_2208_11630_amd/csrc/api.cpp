@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <queue>
 #include <set>
 #include <vector>
 
@@ -853,6 +854,7 @@ struct AmrLevelHost {
   std::vector<unsigned char> flag;
   std::vector<int> lookup, parent, child_base, refined, leaves, leaf_plain, rx_blocks, reflux, first;
   size_t o_pos, o_reflux, o_lookup, o_parent, o_child, o_refined, o_leaves, o_plain, o_rx, o_first;  // int offsets
+  size_t o_cplain, o_crx;  // int offsets of the column tables (room for one column per block)
   size_t o_G, o_flux;                                                                                 // bytes
 };
 
@@ -872,6 +874,65 @@ long level_block(const AmrLevelHost& L, const int* bc, long x, long y, long z) {
     else if (p[d] < 0 || p[d] >= L.nb[d]) return -2;
   }
   return L.lookup[p[0] + L.nb[0] * (p[1] + L.nb[1] * p[2])];
+}
+
+// The blocks of `list` (one level) as columns of up to `cap` blocks stacked
+// in z at consecutive positions (no wrap), bottom first, 4 ints per column
+// (-1 for unused entries); every block of the list is in exactly one.
+std::vector<int> amr_columns(const AmrLevelHost& H, const std::vector<int>& list, int cap) {
+  std::vector<unsigned char> in(H.flag.size(), 0);
+  for (int b : list) in[b] = 1;
+  auto at = [&](long x, long y, long z) -> int {
+    if (z < 0 || z >= H.nb[2]) return -1;
+    const int b = H.lookup[x + H.nb[0] * (y + H.nb[1] * z)];
+    return (b >= 0 && in[b]) ? b : -1;
+  };
+  std::vector<int> out;
+  for (int b : list) {
+    const long x = H.pos[4 * b], y = H.pos[4 * b + 1], z = H.pos[4 * b + 2];
+    if (at(x, y, z - 1) >= 0) continue;  // not the bottom of its run
+    long zz = z;
+    int cur = b;
+    while (cur >= 0) {
+      int col[4] = {-1, -1, -1, -1};
+      for (int m = 0; m < cap && cur >= 0; ++m) {
+        col[m] = cur;
+        cur = at(x, y, ++zz);
+      }
+      out.insert(out.end(), col, col + 4);
+    }
+  }
+  return out;
+}
+
+// Column length for a leaf list: the one whose tiles, dealt in order to
+// `slots` workgroup slots (each tile of a column of k blocks costs k*N + 3
+// planes: the pencil and its z halo), finish first; ties go to shorter
+// columns (more workgroups).
+std::vector<int> amr_best_columns(const AmrLevelHost& H, const std::vector<int>& list, int N, long tpb,
+                                  long slots) {
+  std::vector<int> best;
+  long best_t = -1;
+  for (int cap : {1, 2, 4}) {
+    std::vector<int> c = amr_columns(H, list, cap);
+    std::priority_queue<long, std::vector<long>, std::greater<long>> q;
+    for (long i = 0; i < slots; ++i) q.push(0);
+    long t = 0;
+    for (size_t i = 0; i < c.size(); i += 4) {
+      const long k = 1 + (c[i + 1] >= 0) + (c[i + 2] >= 0) + (c[i + 3] >= 0);
+      for (long r = 0; r < tpb; ++r) {
+        const long f = q.top() + k * N + 3;
+        q.pop();
+        q.push(f);
+        t = std::max(t, f);
+      }
+    }
+    if (best_t < 0 || t < best_t) {
+      best_t = t;
+      best = std::move(c);
+    }
+  }
+  return best;
 }
 
 int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
@@ -995,6 +1056,8 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
     AmrLevelHost& L = A.lev[l];
     L.o_pos = take(L.pos.size());
     L.o_reflux = take(L.reflux.size());
+    L.o_cplain = take(4 * L.leaf_plain.size());
+    L.o_crx = take(4 * L.rx_blocks.size());
   }
   for (int l = 0; l < A.nlev; ++l) {
     AmrLevelHost& L = A.lev[l];
@@ -1072,6 +1135,15 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
   a->d.refine_deep = a->refine_deep.data();
   hydro::AmrLaunch& L = a->L;
   const int N = d->nxb;
+  int dev = 0, cus = 0;
+  hipError_t qe = hipGetDevice(&dev);
+  if (qe == hipSuccess) qe = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (qe != hipSuccess) {
+    delete a;
+    return hip_fail(qe, "device query");
+  }
+  // leaf-step workgroups resident per CU: two of 256 threads (16x16 tiles), four of 128 (8x8)
+  const long tpb = N == 32 ? 4 : 1, slots = (long)cus * (N == 8 ? 4 : 2);
   char* w = (char*)d->work;
   int* tab = (int*)(w + A.o_tab);
   std::vector<int> host(A.tab_ints, 0);
@@ -1103,6 +1175,14 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
     put(H.o_plain, H.leaf_plain);
     put(H.o_rx, H.rx_blocks);
     put(H.o_first, H.first);
+    const std::vector<int> cplain = amr_best_columns(H, H.leaf_plain, N, tpb, slots);
+    const std::vector<int> crx = amr_best_columns(H, H.rx_blocks, N, tpb, slots);
+    put(H.o_cplain, cplain);
+    put(H.o_crx, crx);
+    V.cols_plain = (const int4*)(tab + H.o_cplain);
+    V.cols_rx = (const int4*)(tab + H.o_crx);
+    V.ncols_plain = (long)cplain.size() / 4;
+    V.ncols_rx = (long)crx.size() / 4;
     V.pos = (const int4*)(tab + H.o_pos);
     V.reflux = (const int4*)(tab + H.o_reflux);
     V.lookup = tab + H.o_lookup;

@@ -117,7 +117,9 @@ struct AmrLevel {
   const int* rx_blocks;       // leaves with one (the reflux groups' blocks, in group order)
   const int4* reflux;         // (leaf, d, side, refined neighbour), grouped by leaf
   const int* reflux_first;    // ngroups + 1 offsets into reflux
-  long nblk, nrefined, nleaves, nleaf_plain, nreflux, ngroups;
+  const int4* cols_plain;     // leaf_plain as columns of up to 4 z-stacked blocks (bottom first, -1 unused)
+  const int4* cols_rx;        // rx_blocks likewise
+  long nblk, nrefined, nleaves, nleaf_plain, nreflux, ngroups, ncols_plain, ncols_rx;
 };
 struct AmrLaunch {
   AmrLevel lev[AMR_MAX_LEVELS];

@@ -398,9 +398,14 @@ struct Smem {
 //
 // GV = true (predictor-corrector only): Uin holds guarded views
 // ([block][var][N+2VG]^3, the VG guard layers filled) and the pencil is the
-// whole z extent of block gv_list[tile_in_sim / (N/T)^2] (or that index
-// when gv_list is null): every read stays inside the block's own view, the
-// result goes to the block in compact layout in Uout, dt is the one
+// whole z extent of the blocks of column gv_cols[tile_in_sim / (N/T)^2]:
+// up to four blocks of one level stacked in z, bottom first, unused entries
+// -1 (or the one block of that index when gv_cols is null).  Plane k is
+// read from the view of the block that holds it, the planes below the
+// first block and above the last from their guard layers; since a block's
+// guard planes toward the next block of its column hold copies of that
+// block's cells, the pencil reads exactly what one pencil per block reads.
+// The result goes to the blocks in compact layout in Uout, dt is the one
 // recorded in ws->dt_last, and the new state's signal speed goes to
 // ws->sig[(slot+1)%3] only when gv_emit is set (event counters always).
 template <int N, int T, bool MOL = false, bool GV = false>
@@ -408,7 +413,7 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
                                           WorkHeader* ws, double dt_host, double cfl, int slot,
                                           long tile_in_sim, int plen, Smem<T>& sm,
                                           const StageArgs& st = StageArgs{nullptr, 0.0, 0.0, 0, 1},
-                                          const int* gv_list = nullptr, bool gv_emit = false) {
+                                          const int4* gv_cols = nullptr, bool gv_emit = false) {
   static_assert(!(GV && MOL), "guarded-view input is for the predictor-corrector step");
   using TL = Tile<T>;
   constexpr int NT = TL::NT, NI = TL::NI, NR = TL::NR, NE = TL::NE, WS = TL::WS;
@@ -422,8 +427,11 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   const int NZ = g.nb[2] * N;
   const long layer = GV ? 0 : tile_in_sim / nxy;
   const long cxy = GV ? tile_in_sim : tile_in_sim % nxy;
-  const int z0 = GV ? 0 : (int)(layer * plen), z1 = GV ? N : z0 + plen;  // planes of the pencil
-  const long bxy = (GV && gv_list) ? (long)gv_list[cxy / TPB] : cxy / TPB;  // block (bx, by, 0), or the block
+  int4 gcol = make_int4(0, -1, -1, -1);  // GV: the blocks of the pencil, bottom first
+  if constexpr (GV) gcol = gv_cols ? gv_cols[cxy / TPB] : make_int4((int)(cxy / TPB), -1, -1, -1);
+  const int ncolb = GV ? 1 + (gcol.y >= 0) + (gcol.z >= 0) + (gcol.w >= 0) : 1;
+  const int z0 = GV ? 0 : (int)(layer * plen), z1 = GV ? N * ncolb : z0 + plen;  // planes of the pencil
+  const long bxy = GV ? (long)gcol.x : cxy / TPB;  // block (bx, by, 0), or the first block
   const int tile = (int)(cxy % TPB);
   const int bx = (int)(bxy % g.nb[0]);
   const int by = (int)(bxy / g.nb[0]);
@@ -484,7 +492,9 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   const long BZS = (long)g.nb[0] * g.nb[1] * Layout<N>::BS;  // size of a z layer of blocks
   auto plane_off = [&](int k) -> long {
     if constexpr (GV) {
-      return bxy * Guarded<N, VG>::BS + (long)(k + VG) * Guarded<N, VG>::PS;
+      const int kb = k < 0 ? 0 : min(k / N, ncolb - 1);
+      const int b = kb == 0 ? gcol.x : kb == 1 ? gcol.y : kb == 2 ? gcol.z : gcol.w;
+      return (long)b * Guarded<N, VG>::BS + (long)(k - kb * N + VG) * Guarded<N, VG>::PS;
     } else {
       const int K = map_axis(k, NZ, g.bc[2]);
       return (long)((unsigned)K / N) * BZS + (long)((unsigned)K % N) * PS;
@@ -492,8 +502,13 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   };
   // output plane k (compact layout)
   auto out_off = [&](int k) -> long {
-    if constexpr (GV) return bxy * Layout<N>::BS + (long)k * PS;
-    else return plane_off(k);
+    if constexpr (GV) {
+      const int kb = k / N;  // k in [0, z1)
+      const int b = kb == 0 ? gcol.x : kb == 1 ? gcol.y : kb == 2 ? gcol.z : gcol.w;
+      return (long)b * Layout<N>::BS + (long)(k - kb * N) * PS;
+    } else {
+      return plane_off(k);
+    }
   };
   // (byte offsets: a z layer of blocks is below 4 GiB, checked on the host)
   const unsigned own_xy = GV ? 8u * (unsigned)((ly0 + cy + VG) * GP + (lx0 + cx + VG))
@@ -1464,18 +1479,18 @@ __global__ void amr_begin_kernel(WorkHeader* ws, double dt_host, double cfl, int
 }
 
 // Leaf step: the fused tile step over guarded views, one workgroup per
-// column tile (the whole z extent of the block), blocks list[0..nblk) (or
-// 0..nblk when list is null), XCD-aware order; emit: reduce the new state's
-// signal speed into ws->sig[(slot+1)%3].
+// column tile of a column of z-stacked blocks (the whole z extent of its
+// blocks), columns cols[0..ncols) (tile_step's gv_cols), XCD-aware order;
+// emit: reduce the new state's signal speed into ws->sig[(slot+1)%3].
 template <int N, int T>
 __global__ __launch_bounds__(Tile<T>::NT, 2) void amr_tile_kernel(GridGeom g, const double* __restrict__ Gin,
-                                                                  double* Uout, const int* __restrict__ list,
+                                                                  double* Uout, const int4* __restrict__ cols,
                                                                   long ntiles, int slot, int emit, WorkHeader* ws) {
   __shared__ Smem<T> sm;
   const long tile_id = xcd_tile(blockIdx.x, ntiles);
   if (tile_id >= ntiles) return;
   tile_step<N, T, false, true>(g, Gin, Uout, ws, 0.0, 0.0, slot, tile_id, N, sm,
-                               StageArgs{nullptr, 0.0, 0.0, 0, 1}, list, emit != 0);
+                               StageArgs{nullptr, 0.0, 0.0, 0, 1}, cols, emit != 0);
 }
 
 // Face state of cell (i, j, k) of a guarded view V on its low (hi = 0) or
@@ -1956,15 +1971,15 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
   // 2. leaf steps (fused tile step over the views), written over the state:
   //    every read of the old state went to the views.  Leaves next to a
   //    refined block reduce their signal speed after refluxing instead.
-  auto tiles = [&](const AmrLevel& A, const int* list, long nblk, int emit) {
-    if (!nblk) return;
-    const long nt = nblk * TPB;
+  auto tiles = [&](const AmrLevel& A, const int4* cols, long ncols, int emit) {
+    if (!ncols) return;
+    const long nt = ncols * TPB;
     hipLaunchKernelGGL((amr_tile_kernel<N, T>), dim3((unsigned)(8 * ((nt + 7) / 8))), dim3(Tile<T>::NT), 0, s, A.g,
-                       A.G, A.U, list, nt, slot, emit, L.ws);
+                       A.G, A.U, cols, nt, slot, emit, L.ws);
   };
   for (int l = 0; l < L.nlev; ++l) {
-    tiles(L.lev[l], L.lev[l].leaf_plain, L.lev[l].nleaf_plain, 1);
-    tiles(L.lev[l], L.lev[l].rx_blocks, L.lev[l].ngroups, 0);
+    tiles(L.lev[l], L.lev[l].cols_plain, L.lev[l].ncols_plain, 1);
+    tiles(L.lev[l], L.lev[l].cols_rx, L.lev[l].ncols_rx, 0);
   }
   // 3. fluxes at the fine-coarse faces (from the views), refluxing
   for (int l = 0; l + 1 < L.nlev; ++l) {

@@ -439,6 +439,13 @@ int hydro_amr_estimate_tree(hydro_amr *a, double eps, double refine_cutoff, doub
 int hydro_amr_transfer(hydro_amr *from, hydro_amr *to);
 /* Event counters summed since creation: floors, fallbacks, nonphysical cells (waits). */
 int hydro_amr_counters(hydro_amr *a, long long out[3]);
+/* Tuning (no effect on results): the leaf steps advance columns of up to
+ * `cap` leaves of one level stacked in z as one pencil each (cap 1, 2 or
+ * 4), or, with cap 0 (the default at creation), the length per leaf list
+ * whose tiles, dealt to the device's workgroup slots, finish first.
+ * Rewrites the column tables on the mesh's stream (waits).  Errors:
+ * HYDRO_EINVAL (NULL handle, cap not 0, 1, 2 or 4), HYDRO_EDEVICE. */
+int hydro_amr_set_columns(hydro_amr *a, int cap);
 int hydro_amr_free(hydro_amr *a);
 
 #ifdef __cplusplus

@@ -842,6 +842,15 @@ struct hydro_amr {
   double* E2 = nullptr;    // device, nroot refinement indicators
   double* E2T = nullptr;   // device, one indicator per block of every level (leaves written)
   std::vector<std::vector<int>> pos;  // host copy of the block positions per level (x, y, z)
+  // what rebuilds the leaf steps' column tables (hydro_amr_set_columns)
+  struct Cols {
+    long nb[3];
+    std::vector<int> lookup, plain, rx;
+    int* d_plain;  // device column tables, room for one column per block
+    int* d_rx;
+  };
+  std::vector<Cols> cols;
+  long tpb = 1, slots = 1;  // column tiles per block; leaf-step workgroup slots of the device
 };
 
 namespace {
@@ -879,17 +888,18 @@ long level_block(const AmrLevelHost& L, const int* bc, long x, long y, long z) {
 // The blocks of `list` (one level) as columns of up to `cap` blocks stacked
 // in z at consecutive positions (no wrap), bottom first, 4 ints per column
 // (-1 for unused entries); every block of the list is in exactly one.
-std::vector<int> amr_columns(const AmrLevelHost& H, const std::vector<int>& list, int cap) {
-  std::vector<unsigned char> in(H.flag.size(), 0);
+std::vector<int> amr_columns(const long nb[3], const std::vector<int>& lookup, const std::vector<int>& pos,
+                             const std::vector<int>& list, int cap) {
+  std::vector<unsigned char> in(pos.size() / 4, 0);
   for (int b : list) in[b] = 1;
   auto at = [&](long x, long y, long z) -> int {
-    if (z < 0 || z >= H.nb[2]) return -1;
-    const int b = H.lookup[x + H.nb[0] * (y + H.nb[1] * z)];
+    if (z < 0 || z >= nb[2]) return -1;
+    const int b = lookup[x + nb[0] * (y + nb[1] * z)];
     return (b >= 0 && in[b]) ? b : -1;
   };
   std::vector<int> out;
   for (int b : list) {
-    const long x = H.pos[4 * b], y = H.pos[4 * b + 1], z = H.pos[4 * b + 2];
+    const long x = pos[4 * b], y = pos[4 * b + 1], z = pos[4 * b + 2];
     if (at(x, y, z - 1) >= 0) continue;  // not the bottom of its run
     long zz = z;
     int cur = b;
@@ -905,16 +915,17 @@ std::vector<int> amr_columns(const AmrLevelHost& H, const std::vector<int>& list
   return out;
 }
 
-// Column length for a leaf list: the one whose tiles, dealt in order to
-// `slots` workgroup slots (each tile of a column of k blocks costs k*N + 3
-// planes: the pencil and its z halo), finish first; ties go to shorter
-// columns (more workgroups).
-std::vector<int> amr_best_columns(const AmrLevelHost& H, const std::vector<int>& list, int N, long tpb,
-                                  long slots) {
+// Column length for a leaf list: `cap` when it is 1, 2 or 4, else (0) the
+// one whose tiles, dealt in order to `slots` workgroup slots (each tile of
+// a column of k blocks costs k*N + 3 planes: the pencil and its z halo),
+// finish first; ties go to shorter columns (more workgroups).
+std::vector<int> amr_best_columns(const long nb[3], const std::vector<int>& lookup, const std::vector<int>& pos,
+                                  const std::vector<int>& list, int N, long tpb, long slots, int cap0) {
   std::vector<int> best;
   long best_t = -1;
   for (int cap : {1, 2, 4}) {
-    std::vector<int> c = amr_columns(H, list, cap);
+    if (cap0 && cap != cap0) continue;
+    std::vector<int> c = amr_columns(nb, lookup, pos, list, cap);
     std::priority_queue<long, std::vector<long>, std::greater<long>> q;
     for (long i = 0; i < slots; ++i) q.push(0);
     long t = 0;
@@ -1144,6 +1155,8 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
   }
   // leaf-step workgroups resident per CU: two of 256 threads (16x16 tiles), four of 128 (8x8)
   const long tpb = N == 32 ? 4 : 1, slots = (long)cus * (N == 8 ? 4 : 2);
+  a->tpb = tpb;
+  a->slots = slots;
   char* w = (char*)d->work;
   int* tab = (int*)(w + A.o_tab);
   std::vector<int> host(A.tab_ints, 0);
@@ -1175,10 +1188,12 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
     put(H.o_plain, H.leaf_plain);
     put(H.o_rx, H.rx_blocks);
     put(H.o_first, H.first);
-    const std::vector<int> cplain = amr_best_columns(H, H.leaf_plain, N, tpb, slots);
-    const std::vector<int> crx = amr_best_columns(H, H.rx_blocks, N, tpb, slots);
+    const std::vector<int> cplain = amr_best_columns(H.nb, H.lookup, H.pos, H.leaf_plain, N, tpb, slots, 0);
+    const std::vector<int> crx = amr_best_columns(H.nb, H.lookup, H.pos, H.rx_blocks, N, tpb, slots, 0);
     put(H.o_cplain, cplain);
     put(H.o_crx, crx);
+    a->cols.push_back(hydro_amr::Cols{{H.nb[0], H.nb[1], H.nb[2]}, H.lookup, H.leaf_plain, H.rx_blocks,
+                                      tab + H.o_cplain, tab + H.o_crx});
     V.cols_plain = (const int4*)(tab + H.o_cplain);
     V.cols_rx = (const int4*)(tab + H.o_crx);
     V.ncols_plain = (long)cplain.size() / 4;
@@ -1523,6 +1538,27 @@ int hydro_amr_counters(hydro_amr* a, long long out[3]) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "AMR header read");
   for (int c = 0; c < 3; ++c) out[c] = (long long)h.cnt[c];
+  return HYDRO_OK;
+}
+
+int hydro_amr_set_columns(hydro_amr* a, int cap) {
+  if (!a) return fail(HYDRO_EINVAL, "AMR handle is NULL");
+  if (cap != 0 && cap != 1 && cap != 2 && cap != 4) return fail(HYDRO_EINVAL, "column length must be 0, 1, 2 or 4");
+  hipStream_t s = (hipStream_t)a->d.stream;
+  std::vector<int> host;
+  for (size_t l = 0; l < a->cols.size(); ++l) {
+    const hydro_amr::Cols& C = a->cols[l];
+    const std::vector<int> cp = amr_best_columns(C.nb, C.lookup, a->pos[l], C.plain, a->d.nxb, a->tpb, a->slots, cap);
+    const std::vector<int> cr = amr_best_columns(C.nb, C.lookup, a->pos[l], C.rx, a->d.nxb, a->tpb, a->slots, cap);
+    hipError_t e = hipSuccess;
+    if (!cp.empty()) e = hipMemcpyAsync(C.d_plain, cp.data(), sizeof(int) * cp.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !cr.empty())
+      e = hipMemcpyAsync(C.d_rx, cr.data(), sizeof(int) * cr.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host tables are temporary
+    if (e != hipSuccess) return hip_fail(e, "AMR column table upload");
+    a->L.lev[l].ncols_plain = (long)cp.size() / 4;
+    a->L.lev[l].ncols_rx = (long)cr.size() / 4;
+  }
   return HYDRO_OK;
 }
 

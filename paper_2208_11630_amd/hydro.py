@@ -84,6 +84,7 @@ SIGNATURES = {
     "hydro_amr_estimate_tree": ([ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_ubyte), ctypes.c_size_t,
                                  ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "hydro_amr_set_columns": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "hydro_amr_free": ([ctypes.c_void_p], ctypes.c_int),
     "hydro_set_pencil_planes": ([_HP, ctypes.c_int], ctypes.c_int),
     "hydro_set_tile": ([_HP, ctypes.c_int], ctypes.c_int),
@@ -526,6 +527,11 @@ class Amr:
         out = (ctypes.c_longlong * 3)()
         _check(lib().hydro_amr_counters(self.handle, out))
         return np.array(list(out), dtype=np.int64)
+
+    def set_columns(self, cap: int) -> None:
+        """Leaf-step pencils over columns of up to cap z-stacked leaves (1, 2
+        or 4), or chosen per leaf list (0); results do not depend on it."""
+        _check(lib().hydro_amr_set_columns(self.handle, int(cap)))
 
     def estimate(self, eps: float = 0.01, refine_cutoff: float = 0.8, derefine_cutoff: float = 0.2):
         """(new refinement flags, per-root-block indicator E^2) from the

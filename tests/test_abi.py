@@ -208,6 +208,7 @@ def test_amr_sizes_and_validation(L):
     out = ctypes.c_double()
     assert L.hydro_amr_dt(None, 0.8, ctypes.byref(out)) == hydro.HYDRO_EINVAL
     assert L.hydro_amr_counters(None, None) == hydro.HYDRO_EINVAL
+    assert L.hydro_amr_set_columns(None, 0) == hydro.HYDRO_EINVAL
     assert L.hydro_amr_free(None) == hydro.HYDRO_OK
     assert L.hydro_amr_estimate(None, 0.01, 0.8, 0.2, None, None) == hydro.HYDRO_EINVAL
     assert L.hydro_amr_transfer(None, None) == hydro.HYDRO_EINVAL

@@ -467,3 +467,46 @@ def test_amr_tree_adaptive_trajectory(hy):
         assert_close((got[0], np.concatenate(got[1:])), (U[0], np.concatenate(U[1:])), f"cycle {cycle} regrid")
     assert changed >= 1
     A.close()
+
+
+# ---- tuning -----------------------------------------------------------------
+
+def _run_columns(hy, build, cap, steps=3):
+    A = build()
+    A.set_columns(cap)
+    for _ in range(steps):
+        A.step_cfl(0.8)
+    out = (A.download(), A.last_dt(), A.counters())
+    A.close()
+    return out
+
+
+@pytest.mark.parametrize("case", ["n8_2x2x2_one", "n8_3x2x2_mixed_bc", "n16_2x2x1_periodic_z1", "n8_4x1x1_outflow",
+                                  "n32_2x1x1", "n8_none_refined"])
+def test_amr_column_length_is_bitwise_invariant(hy, case):
+    """Leaf-step pencils over columns of one, two or four z-stacked leaves
+    (and the length chosen per list) give the same bits: states, dt and
+    counters after three steps with device dt."""
+    ref = _run_columns(hy, lambda: make(hy, case)[3], 1)
+    for cap in (2, 4, 0):
+        (R, F), d, c = _run_columns(hy, lambda: make(hy, case)[3], cap)
+        assert np.array_equal(R, ref[0][0]) and np.array_equal(F, ref[0][1]), (case, cap)
+        assert d == ref[1] and np.array_equal(c, ref[2]), (case, cap)
+
+
+@pytest.mark.parametrize("case", TREE_CASES)
+def test_amr_tree_column_length_is_bitwise_invariant(hy, case):
+    t, U = _tree_case(case)
+    ref = _run_columns(hy, lambda: _tree_gpu(hy, t, U), 1)
+    for cap in (2, 4):
+        (R, F), d, c = _run_columns(hy, lambda: _tree_gpu(hy, t, U), cap)
+        assert np.array_equal(R, ref[0][0]) and np.array_equal(F, ref[0][1]), (case, cap)
+        assert d == ref[1] and np.array_equal(c, ref[2]), (case, cap)
+
+
+def test_amr_column_argument_errors(hy):
+    A = make(hy, "n8_2x2x2_one")[3]
+    for bad in (-1, 3, 5, 8):
+        with pytest.raises(hy.HydroError):
+            A.set_columns(bad)
+    A.close()

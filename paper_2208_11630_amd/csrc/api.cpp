@@ -1082,13 +1082,12 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
     L.o_first = take(L.first.size());
   }
   A.tab_ints = t;
-  const size_t P = (size_t)N + 4;   // the step's internal views keep two guard layers
   size_t o = A.o_tab + al256(sizeof(int) * t);
   for (int l = 0; l < A.nlev; ++l) {
     AmrLevelHost& L = A.lev[l];
     const size_t nblk = L.flag.size();
     L.o_G = o;
-    o += al256(sizeof(double) * 5 * P * P * P * nblk);
+    o += al256(sizeof(double) * hydro::amr_view_doubles(N) * nblk);
     L.o_flux = o;
     o += al256(sizeof(double) * 30 * (size_t)N * N * nblk);
   }

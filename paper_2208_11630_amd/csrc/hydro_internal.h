@@ -102,10 +102,19 @@ hipError_t launch_copy(const double* src, double* dst, long n, hipStream_t s);
 // Block-structured AMR (see hydro_kernels.hip): an octree of blocks, level
 // 0 the root grid, level l+1 the children of level l's refined blocks.
 constexpr int AMR_MAX_LEVELS = 8;
+// Doubles per block of a level's leaf views.  n = 8, 16 (the leaf step's
+// tile spans the block plane): plane halos, the two guard layers only, plane
+// by plane -- planes 0..n-1 the ring of width two around the interior,
+// planes -2, -1, n, n+1 whole (the kernels' PlaneHalo<n>); n = 32: whole
+// views of (n + 4)^3 cells.  Five variables.
+constexpr long amr_view_doubles(int n) {
+  return n == 32 ? 5L * (n + 4) * (n + 4) * (n + 4)
+                 : 5L * ((long)n * ((n + 4) * (n + 4) - n * n) + 4L * (n + 4) * (n + 4));
+}
 struct AmrLevel {
   GridGeom g;                 // nb = root nb << l, inv_dx = root inv_dx * 2^l
   double* U;                  // the level's state (compact), updated in place
-  double* G;                  // views with two guard layers, every block of the level
+  double* G;                  // leaf views (amr_view_doubles per block), every block of the level
   double* flux;               // face fluxes per block (those at fine-coarse faces are used)
   const int* lookup;          // block index at each level-l block position, or -1
   const int4* pos;            // block positions (x, y, z, 0)

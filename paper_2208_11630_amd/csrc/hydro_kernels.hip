@@ -57,6 +57,62 @@ struct Guarded {
   static constexpr long BS = 5 * VS;
 };
 
+// Plane halos of a block (AMR leaf views for N = 8, 16, where the leaf
+// step's tile spans the block plane and reads the block's interior from its
+// state): the cells of the two guard layers, plane by plane, so that a fill
+// writes whole rows.  Planes k = 0..N-1 hold the ring of width two around
+// the interior -- rows -2, -1 whole, then the four guard cells of rows
+// 0..N-1, then rows N, N+1 whole -- and planes -2, -1, N, N+1 are whole.
+// Per variable VS doubles; block b's variable v at b*BS + v*VS.
+template <int N>
+struct PlaneHalo {
+  static constexpr int P = N + 2 * VG;
+  static constexpr int RP = P * P - N * N;  // ring plane
+  static constexpr int FP = P * P;          // whole plane
+  static constexpr long VS = (long)N * RP + 4L * FP;
+  static constexpr long BS = 5 * VS;
+  // slot of (i, j) in a ring plane; (i, j) outside [0, N)^2
+  __device__ static int ring_index(int i, int j) {
+    if (j < 0) return (j + VG) * P + (i + VG);
+    if (j >= N) return 2 * P + 4 * N + (j - N) * P + (i + VG);
+    return 2 * P + 4 * j + (i < 0 ? i + VG : i - N + VG);
+  }
+  // slot of (i, j) in a whole plane
+  __device__ static int full_index(int i, int j) { return (j + VG) * P + (i + VG); }
+  // slot of a guard cell (i, j, k), block-local indices, not in the interior
+  __device__ static long slot(int i, int j, int k) {
+    if (k >= 0 && k < N) return (long)k * RP + ring_index(i, j);
+    return (long)N * RP + (long)(k < 0 ? k + VG : k - N + VG) * FP + full_index(i, j);
+  }
+  // the cell of slot s
+  __device__ static void cell(int s, int& i, int& j, int& k) {
+    if (s < N * RP) {
+      k = s / RP;
+      const int r = s - k * RP;
+      if (r < 2 * P) {
+        j = r / P - VG;
+        i = r % P - VG;
+      } else if (r < 2 * P + 4 * N) {
+        const int q = r - 2 * P, c = q % 4;
+        j = q / 4;
+        i = c < 2 ? c - VG : N + c - VG;
+      } else {
+        const int q = r - 2 * P - 4 * N;
+        j = N + q / P;
+        i = q % P - VG;
+      }
+    } else {
+      const int q = s - N * RP, kk = q / FP, r = q - kk * FP;
+      k = kk < 2 ? kk - VG : N + kk - VG;
+      j = r / P - VG;
+      i = r % P - VG;
+    }
+  }
+};
+static_assert(PlaneHalo<16>::BS == amr_view_doubles(16) && PlaneHalo<8>::BS == amr_view_doubles(8) &&
+                  Guarded<32, VG>::BS == amr_view_doubles(32),
+              "leaf view sizes");
+
 __device__ __forceinline__ int map_axis(int I, int n, int bc) {
   // n = cells along the axis; |offset| beyond the domain is at most 2 < n
   if (bc == 0) return I < 0 ? I + n : (I >= n ? I - n : I);
@@ -93,6 +149,13 @@ __device__ __forceinline__ void load_cons_at(const double* P, unsigned xyb, doub
     if constexpr (LAST) u[v] = __builtin_nontemporal_load(a);
     else u[v] = *a;
   }
+}
+
+// Same, with the variable stride VSX (plane halos).
+template <long VSX>
+__device__ __forceinline__ void load_cons_vs(const double* P, unsigned xyb, double (&u)[5]) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) u[v] = *(const double*)((const char*)(P + v * VSX) + xyb);
 }
 
 // Maximum over a workgroup of a non-negative double, folded into *slot with
@@ -405,6 +468,10 @@ struct Smem {
 // first block and above the last from their guard layers; since a block's
 // guard planes toward the next block of its column hold copies of that
 // block's cells, the pencil reads exactly what one pencil per block reads.
+// With a tile spanning the block plane (T == N) Uin holds plane halos
+// (PlaneHalo<N>: the guard cells only) and the own column's interior
+// planes come from the blocks' states in Uout, which this workgroup reads
+// before it writes them.
 // The result goes to the blocks in compact layout in Uout, dt is the one
 // recorded in ws->dt_last, and the new state's signal speed goes to
 // ws->sig[(slot+1)%3] only when gv_emit is set (event counters always).
@@ -517,6 +584,44 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   const unsigned sec_xy = !(is_ring || is_extra) ? 0u
                           : GV ? 8u * (unsigned)((ly0 + sy2 + VG) * GP + (lx0 + sx2 + VG))
                                : 8u * (unsigned)cell_offset<N>(g, X0 + sx2, Y0 + sy2, 0);
+  // GV with a tile spanning the block plane: Uin holds plane halos, the own
+  // column's interior planes come from the state in Uout (each block of the
+  // column is read here before this workgroup overwrites it); whole halo
+  // planes take the view's in-plane offsets (own_xy, sec_xy)
+  constexpr bool GVH = GV && T == N;
+  using PH = PlaneHalo<N>;
+  const unsigned sec_ring = (GVH && (is_ring || is_extra)) ? 8u * (unsigned)PH::ring_index(sx2, sy2) : 0u;
+  // block of the column holding plane k, and the plane's index in it
+  auto col_block = [&](int k, int& kl) -> int {
+    const int kb = k < 0 ? 0 : min(k / N, ncolb - 1);
+    kl = k - kb * N;
+    return kb == 0 ? gcol.x : kb == 1 ? gcol.y : kb == 2 ? gcol.z : gcol.w;
+  };
+  auto halo_plane = [&](int kl) -> long {  // whole halo plane kl (kl < 0 or kl >= N)
+    return (long)N * PH::RP + (long)(kl < 0 ? kl + VG : kl - N + VG) * PH::FP;
+  };
+  // own column, plane k
+  auto load_own = [&](int k, double (&u)[5]) {
+    if constexpr (GVH) {
+      int kl;
+      const int b = col_block(k, kl);
+      if (kl >= 0 && kl < N) load_cons_at<N>(Uout + (long)b * Layout<N>::BS + (long)kl * PS, own_out, u);
+      else load_cons_vs<PH::VS>(Uin + (long)b * PH::BS + halo_plane(kl), own_xy, u);
+    } else {
+      load_cons_at<N, GV>(Uin + plane_off(k), own_xy, u);
+    }
+  };
+  // second item (ring or halo cell), plane k
+  auto load_sec = [&](int k, double (&u)[5]) {
+    if constexpr (GVH) {
+      int kl;
+      const int b = col_block(k, kl);
+      if (kl >= 0 && kl < N) load_cons_vs<PH::VS>(Uin + (long)b * PH::BS + (long)kl * PH::RP, sec_ring, u);
+      else load_cons_vs<PH::VS>(Uin + (long)b * PH::BS + halo_plane(kl), sec_xy, u);
+    } else {
+      load_cons_at<N, GV>(Uin + plane_off(k), sec_xy, u);
+    }
+  };
 
   // Wb, Wc: primitives of planes j, j+1; dzm: Wb minus the plane below
   // (the z slope's lower difference, carried instead of that plane)
@@ -538,23 +643,23 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   // prologue: planes z0-2, z0-1 of the own column, prefetch plane z0
   if (inner) {
     double u[5], tmp;
-    load_cons_at<N, GV>(Uin + plane_off(z0 - 2), own_xy, u);
+    load_own(z0 - 2, u);
     prim(u, gamma, g.small_p, dzm, tmp);
-    load_cons_at<N, GV>(Uin + plane_off(z0 - 1), own_xy, u);
+    load_own(z0 - 1, u);
     prim(u, gamma, g.small_p, Wb, inv_b);
 #pragma unroll
     for (int v = 0; v < 5; ++v) dzm[v] = Wb[v] - dzm[v];
-    load_cons_at<N, GV>(Uin + plane_off(z0), own_xy, un_next);
+    load_own(z0, un_next);
   }
   if (is_ring) {
     double u[5], w[5], tmp;
-    load_cons_at<N, GV>(Uin + plane_off(z0 - 1), sec_xy, u);
+    load_sec(z0 - 1, u);
     prim(u, gamma, g.small_p, w, tmp);
 #pragma unroll
     for (int v = 0; v < 5; ++v) sm.sRing[(z0 + 2) % 3][v][ring_id] = w[v];
-    load_cons_at<N, GV>(Uin + plane_off(z0), sec_xy, u2_next);
+    load_sec(z0, u2_next);
   }
-  if (is_extra) load_cons_at<N, GV>(Uin + plane_off(z0), sec_xy, u2_next);
+  if (is_extra) load_sec(z0, u2_next);
 
   for (int j = z0 - 1; j <= z1; ++j) {
     const bool mid = (j >= z0) && (j < z1);
@@ -589,9 +694,9 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
     // values are consumed: they then land in the same registers, and nothing
     // waits for them until the next plane
     __builtin_amdgcn_sched_barrier(0);
-    if (inner && j + 2 <= z1 + 1) load_cons_at<N, GV>(Uin + plane_off(j + 2), own_xy, un_next);
-    if (is_ring && j + 2 <= z1 + 1) load_cons_at<N, GV>(Uin + plane_off(j + 2), sec_xy, u2_next);
-    if (is_extra && mid && j + 1 < z1) load_cons_at<N, GV>(Uin + plane_off(j + 1), sec_xy, u2_next);
+    if (inner && j + 2 <= z1 + 1) load_own(j + 2, un_next);
+    if (is_ring && j + 2 <= z1 + 1) load_sec(j + 2, u2_next);
+    if (is_extra && mid && j + 1 < z1) load_sec(j + 1, u2_next);
     __syncthreads();
 
     // -- predictor: own cell (every plane), ring cell (pencil planes)
@@ -1470,6 +1575,40 @@ __global__ __launch_bounds__(256) void amr_fill_level_kernel(GridGeom g, GridGeo
   }
 }
 
+// Plane halos (PlaneHalo<N>) of the listed blocks of level l, slot after
+// slot, so each workgroup writes whole rows: a position (mapped at level l)
+// inside a block of level l copies its cell, otherwise (level l >= 1) it is
+// prolonged from level l-1.  Every level-0 position has a block.
+template <int N>
+__global__ __launch_bounds__(256) void amr_fill_halo_kernel(GridGeom g, GridGeom gp, const int* __restrict__ lookup,
+                                                            const int* __restrict__ lookup_p,
+                                                            const int4* __restrict__ pos,
+                                                            const double* __restrict__ U,
+                                                            const double* __restrict__ Up,
+                                                            double* __restrict__ H, const int* __restrict__ list) {
+  using PH = PlaneHalo<N>;
+  const int f = list[blockIdx.x];
+  const int4 q = pos[f];
+  const int X0 = q.x * N, Y0 = q.y * N, Z0 = q.z * N;
+  const int NX = g.nb[0] * N, NY = g.nb[1] * N, NZ = g.nb[2] * N;
+  double* out = H + (long)f * PH::BS;
+  for (int t = threadIdx.x; t < (int)PH::VS; t += blockDim.x) {
+    int i, j, k;
+    PH::cell(t, i, j, k);
+    const int I = map_axis(X0 + i, NX, g.bc[0]);
+    const int J = map_axis(Y0 + j, NY, g.bc[1]);
+    const int K = map_axis(Z0 + k, NZ, g.bc[2]);
+    const int b = lookup[(I / N) + g.nb[0] * ((J / N) + g.nb[1] * (K / N))];
+    double val[5];
+    if (b >= 0)
+      load_cons<N>(U, Layout<N>::at(b, I % N, J % N, K % N), val);
+    else
+      prolong_cell<N>(gp, lookup_p, Up, I, J, K, val);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[v * PH::VS + t] = val[v];
+  }
+}
+
 // Start of an AMR step: dt = cfl / ws->sig[slot] (cfl > 0) or dt_host,
 // recorded in ws->dt_last for every later kernel of the step; the signal
 // slot of the step after next is cleared.
@@ -1478,7 +1617,7 @@ __global__ void amr_begin_kernel(WorkHeader* ws, double dt_host, double cfl, int
   ws->sig[(slot + 2) % 3] = 0ull;
 }
 
-// Leaf step: the fused tile step over guarded views, one workgroup per
+// Leaf step: the fused tile step over the leaf views, one workgroup per
 // column tile of a column of z-stacked blocks (the whole z extent of its
 // blocks), columns cols[0..ncols) (tile_step's gv_cols), XCD-aware order;
 // emit: reduce the new state's signal speed into ws->sig[(slot+1)%3].
@@ -1493,20 +1632,35 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void amr_tile_kernel(GridGeom g, co
                                StageArgs{nullptr, 0.0, 0.0, 0, 1}, cols, emit != 0);
 }
 
-// Face state of cell (i, j, k) of a guarded view V on its low (hi = 0) or
-// high (hi = 1) d face, formed as the leaf step forms it: primitives of the
-// cell and its six neighbours, van Leer slopes, predictor with fallback.
+// Face state of cell (i, j, k) of a block on its low (hi = 0) or high
+// (hi = 1) d face, formed as the leaf step forms it: primitives of the cell
+// and its six neighbours, van Leer slopes, predictor with fallback.  Cells
+// of the block come from its state Ub (compact, not yet stepped), the
+// others from its leaf view V (plane halo for N = 8, 16, whole view for 32).
 template <int N>
-__device__ __forceinline__ void amr_face_state(const double* V, int i, int j, int k, int d, int hi,
-                                               const GridGeom& g, double lamx, double lamy, double lamz,
+__device__ __forceinline__ void amr_face_state(const double* V, const double* Ub, int i, int j, int k, int d,
+                                               int hi, const GridGeom& g, double lamx, double lamy, double lamz,
                                                double (&out)[5]) {
+  constexpr bool HALO = N != 32;
   constexpr int P = Guarded<N, VG>::P;
-  constexpr long VSg = Guarded<N, VG>::VS;
+  constexpr long VSv = HALO ? PlaneHalo<N>::VS : Guarded<N, VG>::VS;
   auto w_at = [&](int a, int b, int c, double (&w)[5]) {
-    const long o = ((long)(c + VG) * P + (b + VG)) * P + (a + VG);
+    const bool in = a >= 0 && a < N && b >= 0 && b < N && c >= 0 && c < N;
+    const double* src;
+    long vs;
+    if (in) {
+      src = Ub + ((long)c * N + b) * N + a;
+      vs = Layout<N>::VS;
+    } else {
+      long o;
+      if constexpr (HALO) o = PlaneHalo<N>::slot(a, b, c);
+      else o = ((long)(c + VG) * P + (b + VG)) * P + (a + VG);
+      src = V + o;
+      vs = VSv;
+    }
     double u[5], inv;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) u[v] = V[o + v * VSg];
+    for (int v = 0; v < 5; ++v) u[v] = src[v * vs];
     prim(u, g.gamma, g.small_p, w, inv);
   };
   double wc[5], wm[5], wp[5], sx[5], sy[5], sz[5], wt[5], h;
@@ -1529,8 +1683,9 @@ __device__ __forceinline__ void amr_face_state(const double* V, int i, int j, in
   for (int v = 0; v < 5; ++v) out[v] = fma(hs, d == 0 ? sx[v] : (d == 1 ? sy[v] : sz[v]), wt[v]);
 }
 
-// Fluxes on the faces that refluxing uses, recomputed from the guarded
-// views with the leaf step's arithmetic: workgroup 5e + part of reflux
+// Fluxes on the faces that refluxing uses, computed before the leaf steps
+// from the old states and the leaf views with the leaf step's arithmetic:
+// workgroup 5e + part of reflux
 // entry e = (coarse leaf b, d, side, refined r): part 0 is b's face 2d+side
 // (level 0), parts 1..4 the faces 2d+(1-side) of r's four children on the
 // side toward b (level 1).  Output flux[block][face][v][a1][a0], a0 / a1 the
@@ -1540,7 +1695,9 @@ __global__ __launch_bounds__(256) void amr_face_flux_kernel(GridGeom g0, GridGeo
                                                             const int4* __restrict__ entries,
                                                             const int* __restrict__ child_base,
                                                             const double* __restrict__ G0,
-                                                            const double* __restrict__ G1, double* flux0,
+                                                            const double* __restrict__ G1,
+                                                            const double* __restrict__ U0,
+                                                            const double* __restrict__ U1, double* flux0,
                                                             double* flux1, const WorkHeader* ws) {
   using A = AmrStep<N>;
   const double dt = ws->dt_last;
@@ -1561,7 +1718,8 @@ __global__ __launch_bounds__(256) void amr_face_flux_kernel(GridGeom g0, GridGeo
     blk = child_base[e.w] + co[0] + 2 * co[1] + 4 * co[2];
   }
   const GridGeom& g = part ? g1 : g0;
-  const double* V = (part ? G1 : G0) + (long)blk * Guarded<N, VG>::BS;
+  const double* V = (part ? G1 : G0) + (long)blk * amr_view_doubles(N);
+  const double* Ub = (part ? U1 : U0) + (long)blk * Layout<N>::BS;
   double* out = (part ? flux1 : flux0) + (long)blk * A::NF + (long)(2 * d + fs) * 5 * N * N;
   const double lamx = dt * g.inv_dx[0], lamy = dt * g.inv_dx[1], lamz = dt * g.inv_dx[2];
   const double gm1inv = 1.0 / (g.gamma - 1.0);
@@ -1572,8 +1730,8 @@ __global__ __launch_bounds__(256) void amr_face_flux_kernel(GridGeom g0, GridGeo
     c[t0] = a0;
     c[t1] = a1;
     double L[5], R[5], F[5];
-    amr_face_state<N>(V, c[0] - (d == 0), c[1] - (d == 1), c[2] - (d == 2), d, 1, g, lamx, lamy, lamz, L);
-    amr_face_state<N>(V, c[0], c[1], c[2], d, 0, g, lamx, lamy, lamz, R);
+    amr_face_state<N>(V, Ub, c[0] - (d == 0), c[1] - (d == 1), c[2] - (d == 2), d, 1, g, lamx, lamy, lamz, L);
+    amr_face_state<N>(V, Ub, c[0], c[1], c[2], d, 0, g, lamx, lamy, lamz, R);
     hllc_dir(d, L, R, g.gamma, gm1inv, F);
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[(long)v * N * N + t] = F[v];
@@ -1957,20 +2115,41 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
   // 1. views: level 0 by the same-level map, deeper levels by copies and
   //    prolongation from the level above (states only: any order)
   const AmrLevel& R = L.lev[0];
-  // (views of leaves only: the leaf steps and the face fluxes read no others)
-  if (R.nleaves)
-    hipLaunchKernelGGL((fill_guards_kernel<N, VG>), dim3((unsigned)(R.nleaves * Guarded<N, VG>::P)), dim3(256), 0, s,
-                       R.g, R.U, R.G, R.leaves);
+  // (views of leaves only: the leaf steps and the face fluxes read no
+  // others; plane halos when the leaf step's tile spans the block plane)
+  constexpr bool HALO = T == N;
+  if (R.nleaves) {
+    if constexpr (HALO)
+      hipLaunchKernelGGL(amr_fill_halo_kernel<N>, dim3((unsigned)R.nleaves), dim3(256), 0, s, R.g, R.g, R.lookup,
+                         R.lookup, R.pos, R.U, R.U, R.G, R.leaves);
+    else
+      hipLaunchKernelGGL((fill_guards_kernel<N, VG>), dim3((unsigned)(R.nleaves * Guarded<N, VG>::P)), dim3(256),
+                         0, s, R.g, R.U, R.G, R.leaves);
+  }
   for (int l = 1; l < L.nlev; ++l) {
     const AmrLevel& A = L.lev[l];
     const AmrLevel& B = L.lev[l - 1];
-    if (A.nleaves)
+    if (!A.nleaves) continue;
+    if constexpr (HALO)
+      hipLaunchKernelGGL(amr_fill_halo_kernel<N>, dim3((unsigned)A.nleaves), dim3(256), 0, s, A.g, B.g, A.lookup,
+                         B.lookup, A.pos, A.U, B.U, A.G, A.leaves);
+    else
       hipLaunchKernelGGL(amr_fill_level_kernel<N>, dim3((unsigned)A.nleaves), dim3(256), 0, s, A.g, B.g, A.lookup,
                          B.lookup, A.pos, A.U, B.U, A.G, A.leaves);
   }
-  // 2. leaf steps (fused tile step over the views), written over the state:
-  //    every read of the old state went to the views.  Leaves next to a
-  //    refined block reduce their signal speed after refluxing instead.
+  // 2. fluxes at the fine-coarse faces, from the old states and the views,
+  //    before the leaf steps write the new states over them
+  for (int l = 0; l + 1 < L.nlev; ++l) {
+    const AmrLevel& A = L.lev[l];
+    const AmrLevel& B = L.lev[l + 1];
+    if (A.nreflux)
+      hipLaunchKernelGGL(amr_face_flux_kernel<N>, dim3((unsigned)(5 * A.nreflux)), dim3(256), 0, s, A.g, B.g,
+                         A.reflux, A.child_base, A.G, B.G, A.U, B.U, A.flux, B.flux, (const WorkHeader*)L.ws);
+  }
+  // 3. leaf steps (fused tile step over the views), written over the state:
+  //    every read of another block's old state goes to the views.  Leaves
+  //    next to a refined block reduce their signal speed after refluxing
+  //    instead.
   auto tiles = [&](const AmrLevel& A, const int4* cols, long ncols, int emit) {
     if (!ncols) return;
     const long nt = ncols * TPB;
@@ -1981,17 +2160,15 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
     tiles(L.lev[l], L.lev[l].cols_plain, L.lev[l].ncols_plain, 1);
     tiles(L.lev[l], L.lev[l].cols_rx, L.lev[l].ncols_rx, 0);
   }
-  // 3. fluxes at the fine-coarse faces (from the views), refluxing
+  // 4. refluxing
   for (int l = 0; l + 1 < L.nlev; ++l) {
     const AmrLevel& A = L.lev[l];
     const AmrLevel& B = L.lev[l + 1];
     if (!A.nreflux) continue;
-    hipLaunchKernelGGL(amr_face_flux_kernel<N>, dim3((unsigned)(5 * A.nreflux)), dim3(256), 0, s, A.g, B.g,
-                       A.reflux, A.child_base, A.G, B.G, A.flux, B.flux, (const WorkHeader*)L.ws);
     hipLaunchKernelGGL(amr_reflux_kernel<N>, dim3((unsigned)A.ngroups), dim3(256), 0, s, A.g, A.reflux,
                        A.reflux_first, A.flux, B.flux, A.child_base, A.U, L.ws, slot);
   }
-  // 4. restriction, finest level first
+  // 5. restriction, finest level first
   for (int l = L.nlev - 2; l >= 0; --l) {
     const AmrLevel& A = L.lev[l];
     if (A.nrefined)

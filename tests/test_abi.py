@@ -168,10 +168,13 @@ def test_amr_sizes_and_validation(L):
     d = hydro.make_amr_desc(n, nb, [0, 1, 0, 1], bc=(0, 1, 0))
     assert L.hydro_amr_fine_blocks(ctypes.byref(d)) == 16
     P = n + 4
-    # views (two guard layers) and face fluxes of every block of both levels,
-    # the indicators, the header; the mesh tables take a few KB more
+    # leaf views (plane halos: planes 0..n-1 keep the guard ring two cells
+    # wide, P^2 - n^2 cells, the four guard planes are whole) and face fluxes
+    # of every block of both levels, the indicators, the header; the mesh
+    # tables take a few KB more
     al = lambda x: (x + 255) // 256 * 256
-    big = (256 + al(8 * 5 * P ** 3 * 4) + al(8 * 5 * P ** 3 * 16) + al(8 * 30 * n * n * 4)
+    halo = 5 * (n * (P * P - n * n) + 4 * P * P)
+    big = (256 + al(8 * halo * 4) + al(8 * halo * 16) + al(8 * 30 * n * n * 4)
            + al(8 * 30 * n * n * 16) + al(8 * 4))
     total = L.hydro_amr_work_bytes(ctypes.byref(d))
     assert big + 256 <= total <= big + 8192, (total, big)

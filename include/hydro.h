@@ -339,9 +339,12 @@ const char *hydro_last_error(void);
  *      their children.
  * Layouts (device, caller-owned, 256-byte aligned): Ur [nroot][5][nxb^3]
  * (block id bx + nb0*(by + nb1*bz)); Uf: the blocks of levels 1, 2, ...
- * concatenated, [5][nxb^3] each.  The step updates Ur and Uf in place (it
- * reads the old state only through views with two guard layers, formed in
- * the workspace first).  refine: host flags of level 0, one per root block;
+ * concatenated, [5][nxb^3] each.  The step updates Ur and Uf in place: a
+ * leaf's own cells are read by the workgroup that then writes them, every
+ * other read of the old state goes through the leaves' guard views formed in
+ * the workspace first (two guard layers; for nxb 8 and 16 only those
+ * layers, for nxb 32 with the interior), and the refluxing fluxes are
+ * formed before the leaf steps.  refine: host flags of level 0, one per root block;
  * refine_deep: host flags of levels 1, 2, ... (one per block of each level,
  * concatenated; NULL with nrefine_deep 0 for two levels); both copied at
  * creation. */
@@ -369,9 +372,10 @@ size_t hydro_amr_fine_blocks(const hydro_amr_desc *d);
 /* Number of levels (>= 1) and the blocks of each (nblocks[l], 0 beyond);
  * a negative error code for an invalid descriptor (bad nesting included). */
 int hydro_amr_levels(const hydro_amr_desc *d, long nblocks[8]);
-/* Workspace bytes: header, mesh tables, views with two guard layers of every
- * block of every level, fluxes on block faces (used at fine-coarse faces),
- * one refinement indicator per root block. */
+/* Workspace bytes: header, mesh tables, guard views of every block of every
+ * level (nxb 8, 16: the two guard layers, 5*(nxb*((nxb+4)^2 - nxb^2) +
+ * 4*(nxb+4)^2) doubles per block; nxb 32: 5*(nxb+4)^3), fluxes on block
+ * faces (used at fine-coarse faces), one refinement indicator per block. */
 size_t hydro_amr_work_bytes(const hydro_amr_desc *d);
 /* Validate and build the mesh tables (uploaded to the workspace; waits for
  * the upload).  Errors: HYDRO_EINVAL, HYDRO_ESIZE, HYDRO_EDEVICE. */

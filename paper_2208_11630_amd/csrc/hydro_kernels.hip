@@ -1486,12 +1486,13 @@ __global__ __launch_bounds__(CtuTile::NT) void ctu_tile_kernel(GridGeom g, StepA
 }
 
 // ---------------------------------------------------------------------------
-// Two-level static AMR (the Grid unit's block-structured refinement): a root
-// grid (level 0) whose refined blocks are covered by eight children at half
-// the cell size (level 1).  Kernels: the guard fill of the fine blocks
-// (copies from fine neighbours, prolongation from the root cells elsewhere),
-// the predictor-corrector step of a leaf from its guarded view (also writing
-// its boundary fluxes), refluxing at fine-coarse faces and restriction.
+// Block-structured AMR (the Grid unit's refinement): an octree of blocks,
+// level 0 the root grid, level l+1 the eight children (half the cell size)
+// of each refined block of level l.  Kernels: the leaves' guard views
+// (copies of same-level cells, prolongation from the level above), the
+// fluxes at fine-coarse faces that refluxing uses (formed before the leaf
+// steps), the leaf step (the fused tile step over the views), refluxing,
+// restriction, the refinement indicators and the regrid transfer.
 
 template <int N>
 struct AmrStep {

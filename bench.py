@@ -378,10 +378,12 @@ def run_served(args):
         srv.max_cells = max_cells_launch
         srv.max_inflight = inflight
         ex.host_s.clear()
+        ex.moved.clear()
         st = srv.run(arr)
         torch.cuda.synchronize()
         out = st.summary()
         out["executor_host_s"] = {k: round(v, 4) for k, v in ex.host_s.items()}
+        out["host_GB"] = {k: round(v / 1e9, 2) for k, v in ex.moved.items()}
         return out
 
     def burst(nreq, seed, targets=None):
@@ -390,7 +392,7 @@ def run_served(args):
         return [(0.0, int(x)) for x in pick]
 
     keys = ("completed", "requests_per_s", "cell_updates_per_s", "p50_ms", "p99_ms", "mean_batch",
-            "launches", "evictions", "admissions", "wall_s", "executor_host_s")
+            "launches", "evictions", "admissions", "wall_s", "executor_host_s", "host_GB")
     pick = lambda st: {k: st.get(k) for k in keys}
 
     # host-link ceiling: a request for a simulation that is not resident
@@ -411,6 +413,12 @@ def run_served(args):
     print(f"[bench] saturated batched: {pick(sat)}", file=sys.stderr, flush=True)
     sat_loop = trace_run(arr_sat, 1, 1)
     print(f"[bench] saturated looped: {pick(sat_loop)}", file=sys.stderr, flush=True)
+    # the burst's own link bound: the bytes its admissions and evictions
+    # moved (the larger direction; both run at once) at the measured rate.
+    # Requests for one simulation share its admission, so this is below the
+    # per-request miss model of `link` for a burst.
+    gb = sat["host_GB"]
+    sat_link_s = max(gb.get("in", 0.0), gb.get("out", 0.0)) / link["h2d_and_d2h_GB_per_s_each_way"]
 
     def ramp(burst_rate, fractions, targets, seed):
         """Poisson arrivals at a rising offered rate until the achieved rate
@@ -470,6 +478,8 @@ def run_served(args):
         "host_link": link,
         "saturated": {"batched": pick(sat), "looped_one_sim_per_launch": pick(sat_loop),
                       "batched_over_looped": sat["cell_updates_per_s"] / max(sat_loop["cell_updates_per_s"], 1e-30),
+                      "link_seconds_of_batched_copies": sat_link_s,
+                      "batched_wall_over_link_seconds": sat["wall_s"] / max(sat_link_s, 1e-30),
                       "trace": "the same 2000 requests at t = 0, uniform targets (seed 7)"},
         "latency_sweep": sweep,
         "latency_points_with_mean_batch_above_1": len(batched_pts),

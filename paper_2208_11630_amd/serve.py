@@ -182,6 +182,10 @@ class Server:
         t0 = self.clock()
         i = 0
         n = len(arrivals)
+        # simulations with requests waiting whose state is not on the device,
+        # oldest request first, and those whose admission copy is in flight
+        to_admit: "collections.OrderedDict[int, None]" = collections.OrderedDict()
+        copying: set = set()
 
         def ingest() -> float:
             # take in every request due by now
@@ -192,6 +196,8 @@ class Server:
                 r = Request(s, t0 + t, t_seen=t0 + now)
                 self.stats.requests.append(r)
                 pending.setdefault(s, collections.deque()).append(r)
+                if not self.ex.is_resident(s):
+                    to_admit[s] = None
                 i += 1
             return now
 
@@ -220,60 +226,51 @@ class Server:
                     still.append((h, reqs, sims))
             inflight = still
             # requests of quarantined sims fail at once
-            for s in [s for s in pending if s in self.quarantined]:
-                for r in pending.pop(s):
-                    self._fail(r, self.quarantined[s])
-            # form the next launch from whatever is ready: first the waiting
-            # simulations whose state is on the device (oldest request first),
-            # then admissions of the others (their copies start now and a
-            # later launch takes them), at most `max_admitting` copies in flight
+            if self.quarantined:
+                for s in [s for s in pending if s in self.quarantined]:
+                    for r in pending.pop(s):
+                        self._fail(r, self.quarantined[s])
+            # admissions: keep up to `max_admitting` state copies in flight
+            # whether or not a launch slot is free, so the copies overlap the
+            # launches; requests that came due meanwhile count as waiting
+            # before any eviction is decided
+            copying = {s for s in copying if self.ex.is_resident(s) and not self.ex.is_ready(s)}
+            if to_admit and len(copying) < self.max_admitting:
+                ingest()
+                for s in list(to_admit):
+                    if len(copying) >= self.max_admitting:
+                        break
+                    if s not in pending or s in self.quarantined or self.ex.is_resident(s):
+                        # requests gone (or about to fail), or on the device already
+                        del to_admit[s]
+                        continue
+                    if self.ex.bytes_of(s) > self.budget:
+                        # can never be resident: refuse its requests (left incomplete)
+                        self.stats.refused += len(pending.pop(s))
+                        del to_admit[s]
+                        continue
+                    if not self._admit(s, set(), pending):
+                        break  # wait for memory to free up
+                    del to_admit[s]
+                    if not self.ex.is_ready(s):  # (first touch: in place at once)
+                        copying.add(s)
+            # the next launch: the waiting simulations whose state is on the
+            # device and in place, oldest request first, up to the cell cap
             if len(inflight) < self.max_inflight:
                 chosen, reqs, cells = [], [], 0
-                pinned = set()
-                full = False
                 for s in list(pending.keys()):
-                    if s in self.busy or not self.ex.is_resident(s) or not self.ex.is_ready(s):
+                    if s in self.busy or s in self.quarantined or not self.ex.is_ready(s):
                         continue
                     c = self.ex.cells_of(s)
                     if self.max_cells and chosen and cells + c > self.max_cells:
-                        full = True
                         break
                     self.lru.move_to_end(s)
-                    pinned.add(s)
                     chosen.append(s)
                     cells += c
                     q = pending[s]
                     reqs.append(q.popleft())
                     if not q:
                         del pending[s]
-                # requests that came due while the launch was formed count as
-                # waiting before any eviction is decided
-                ingest()
-                admitting = sum(1 for s in pending if self.ex.is_resident(s) and not self.ex.is_ready(s))
-                for s in list(pending.keys()):
-                    if admitting >= self.max_admitting:
-                        break
-                    if s in self.busy or self.ex.is_resident(s):
-                        continue
-                    if self.ex.bytes_of(s) > self.budget:
-                        # can never be resident: refuse its requests (left incomplete)
-                        self.stats.refused += len(pending.pop(s))
-                        continue
-                    pinned.add(s)
-                    if not self._admit(s, pinned, pending):
-                        pinned.discard(s)  # wait for memory to free up
-                        break
-                    if self.ex.is_ready(s) and not full:  # in place at once (first touch, pageable copy)
-                        c = self.ex.cells_of(s)
-                        if not (self.max_cells and chosen and cells + c > self.max_cells):
-                            chosen.append(s)
-                            cells += c
-                            q = pending[s]
-                            reqs.append(q.popleft())
-                            if not q:
-                                del pending[s]
-                            continue
-                    admitting += 1
                 if chosen:
                     try:
                         h = self.ex.launch(chosen)
@@ -298,7 +295,7 @@ class Server:
             if horizon is not None and now > horizon and not until_done:
                 break
             # idle: wait a little for an arrival or a completion
-            if not inflight and i < n:
+            if not inflight and not copying and i < n:
                 dt = arrivals[i][0] - (self.clock() - t0)
                 if dt > 2e-4:
                     time.sleep(min(dt, 1e-3))
@@ -410,6 +407,7 @@ class GpuExecutor(Executor):
         self.pool = PinnedPool(torch)
         self.steps_done = collections.Counter()
         self.host_s = collections.Counter()    # host seconds spent in each executor call
+        self.moved = collections.Counter()     # state bytes copied "in" (host -> device) and "out"
 
     def shape_of(self, sim: int):
         nb = self.sizes[sim] // self.nxb
@@ -450,6 +448,7 @@ class GpuExecutor(Executor):
         t = torch.empty(self.shape_of(sim), dtype=torch.float64, device=self.device)
         if sim in self.host:
             h, evicted, buf = self.host.pop(sim)
+            self.moved["in"] += t.numel() * t.element_size()
             if buf is None:                            # pageable fallback: synchronous copy
                 t.copy_(h)
             else:
@@ -482,6 +481,7 @@ class GpuExecutor(Executor):
             inc[0].synchronize()                       # its admission copy has to land first
             self.pool.put(inc[1])
         buf = self.pool.get(t.numel() * t.element_size())
+        self.moved["out"] += t.numel() * t.element_size()
         if buf is None:                                # pool exhausted: pageable, synchronous
             torch.cuda.current_stream().synchronize()
             self.host[sim] = (t.cpu(), None, None)

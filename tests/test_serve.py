@@ -239,3 +239,50 @@ def test_failures_stay_local_and_quarantine_the_sim():
     assert srv.quarantined.keys() == {1, 4}
     summ = stats.summary()
     assert summ["completed"] == 40 and summ["failed"] == 20
+
+
+class SlowCopyExecutor(FakeExecutor):
+    """Admissions whose copies take `copy_s` to land: a simulation is
+    resident at once but in place (ready) only after its copy."""
+
+    def __init__(self, sizes, copy_s, cost_per_cell):
+        super().__init__(sizes, cost_per_cell=cost_per_cell)
+        self.copy_s = copy_s
+        self.landed = {}
+        self.admits_under_launch = 0
+        self.max_copies = 0
+
+    def make_resident(self, s):
+        super().make_resident(s)
+        now = time.perf_counter()
+        self.landed[s] = now + self.copy_s
+        if self.inflight:
+            self.admits_under_launch += 1
+        self.max_copies = max(self.max_copies, sum(1 for t in self.landed.values() if t > now))
+
+    def evict(self, s):
+        super().evict(s)
+        self.landed.pop(s, None)
+
+    def is_ready(self, s):
+        return s in self.res and time.perf_counter() >= self.landed.get(s, 0.0)
+
+    def launch(self, sims):
+        for s in sims:
+            assert self.is_ready(s), "launched a simulation whose copy had not landed"
+        return super().launch(sims)
+
+
+def test_admission_copies_overlap_the_launches():
+    """With the launch slot busy the loop still starts admission copies
+    (at most `max_admitting` in flight), and a launch takes a simulation only
+    once its copy has landed."""
+    sizes = [64] * 30
+    ex = SlowCopyExecutor(sizes, copy_s=2e-3, cost_per_cell=2e-8)   # ~5 ms per 64^3 step
+    srv = serve.Server(ex, budget_bytes=10 ** 12, max_inflight=1, max_cells_per_launch=2 * 64 ** 3,
+                       max_admitting=4)
+    arr = [(0.0, k % 30) for k in range(90)]
+    st = srv.run(arr)
+    assert st.summary()["completed"] == 90
+    assert ex.admits_under_launch > 0
+    assert ex.max_copies <= 4

@@ -846,8 +846,10 @@ struct hydro_amr {
   struct Cols {
     long nb[3];
     std::vector<int> lookup, plain, rx;
+    std::vector<int> face;  // blocks whose views the fine-coarse face fluxes read
     int* d_plain;  // device column tables, room for one column per block
     int* d_rx;
+    int* d_zneed;  // device, one entry per block
   };
   std::vector<Cols> cols;
   long tpb = 1, slots = 1;  // column tiles per block; leaf-step workgroup slots of the device
@@ -864,6 +866,7 @@ struct AmrLevelHost {
   std::vector<int> lookup, parent, child_base, refined, leaves, leaf_plain, rx_blocks, reflux, first;
   size_t o_pos, o_reflux, o_lookup, o_parent, o_child, o_refined, o_leaves, o_plain, o_rx, o_first;  // int offsets
   size_t o_cplain, o_crx;  // int offsets of the column tables (room for one column per block)
+  size_t o_zneed;          // int offset of the halo-plane table (one per block)
   size_t o_G, o_flux;                                                                                 // bytes
 };
 
@@ -913,6 +916,31 @@ std::vector<int> amr_columns(const long nb[3], const std::vector<int>& lookup, c
     }
   }
   return out;
+}
+
+// Blocks of each level whose leaf views the fine-coarse face fluxes read
+// (every halo plane): the leaves next to a refined block of their level,
+// and that block's children on the face toward them (the face flux
+// kernel's parts 0 and 1..4).
+std::vector<std::vector<int>> amr_face_blocks(const AmrLayout& A);
+
+// The whole halo planes each block's fill writes (bit 0: planes -2, -1;
+// bit 1: planes n, n+1): below the bottom block of each column and above
+// its top block, the only ones a column's pencil reads, and every plane
+// for the blocks in `face`.
+std::vector<int> amr_zneed(size_t nblk, const std::vector<int>& cp, const std::vector<int>& cr,
+                           const std::vector<int>& face) {
+  std::vector<int> z(nblk, 0);
+  for (const std::vector<int>* c : {&cp, &cr})
+    for (size_t i = 0; i + 3 < c->size(); i += 4) {
+      int top = (*c)[i];
+      for (int m = 1; m < 4; ++m)
+        if ((*c)[i + m] >= 0) top = (*c)[i + m];
+      z[(*c)[i]] |= 1;
+      z[top] |= 2;
+    }
+  for (int b : face) z[b] = 3;
+  return z;
 }
 
 // Column length for a leaf list: `cap` when it is 1, 2 or 4, else (0) the
@@ -1070,6 +1098,7 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
     L.o_cplain = take(4 * L.leaf_plain.size());
     L.o_crx = take(4 * L.rx_blocks.size());
   }
+  for (int l = 0; l < A.nlev; ++l) A.lev[l].o_zneed = take(A.lev[l].flag.size());
   for (int l = 0; l < A.nlev; ++l) {
     AmrLevelHost& L = A.lev[l];
     L.o_lookup = take(L.lookup.size());
@@ -1098,6 +1127,27 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
   for (int l = 0; l < A.nlev; ++l) nall += A.lev[l].flag.size();
   A.total = o + al256(sizeof(double) * nall);
   return HYDRO_OK;
+}
+
+std::vector<std::vector<int>> amr_face_blocks(const AmrLayout& A) {
+  std::vector<std::vector<int>> out(A.nlev);
+  for (int l = 0; l < A.nlev; ++l) {
+    const AmrLevelHost& L = A.lev[l];
+    for (size_t e = 0; e + 3 < L.reflux.size(); e += 4) {
+      const int b = L.reflux[e], d = L.reflux[e + 1], side = L.reflux[e + 2], r = L.reflux[e + 3];
+      out[l].push_back(b);
+      if (l + 1 >= A.nlev) continue;  // (a refined block always has a level below it)
+      const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      for (int c = 0; c < 4; ++c) {
+        int co[3];
+        co[d] = side ? 0 : 1;
+        co[t0] = c & 1;
+        co[t1] = c >> 1;
+        out[l + 1].push_back(L.child_base[r] + co[0] + 2 * co[1] + 4 * co[2]);
+      }
+    }
+  }
+  return out;
 }
 
 }  // namespace
@@ -1161,6 +1211,7 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
   std::vector<int> host(A.tab_ints, 0);
   L.nlev = A.nlev;
   size_t fine_off = 0;
+  const std::vector<std::vector<int>> face = amr_face_blocks(A);
   for (int l = 0; l < A.nlev; ++l) {
     const AmrLevelHost& H = A.lev[l];
     hydro::AmrLevel& V = L.lev[l];
@@ -1191,8 +1242,10 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
     const std::vector<int> crx = amr_best_columns(H.nb, H.lookup, H.pos, H.rx_blocks, N, tpb, slots, 0);
     put(H.o_cplain, cplain);
     put(H.o_crx, crx);
-    a->cols.push_back(hydro_amr::Cols{{H.nb[0], H.nb[1], H.nb[2]}, H.lookup, H.leaf_plain, H.rx_blocks,
-                                      tab + H.o_cplain, tab + H.o_crx});
+    put(H.o_zneed, amr_zneed((size_t)nblk, cplain, crx, face[l]));
+    a->cols.push_back(hydro_amr::Cols{{H.nb[0], H.nb[1], H.nb[2]}, H.lookup, H.leaf_plain, H.rx_blocks, face[l],
+                                      tab + H.o_cplain, tab + H.o_crx, tab + H.o_zneed});
+    V.zneed = tab + H.o_zneed;
     V.cols_plain = (const int4*)(tab + H.o_cplain);
     V.cols_rx = (const int4*)(tab + H.o_crx);
     V.ncols_plain = (long)cplain.size() / 4;
@@ -1549,10 +1602,12 @@ int hydro_amr_set_columns(hydro_amr* a, int cap) {
     const hydro_amr::Cols& C = a->cols[l];
     const std::vector<int> cp = amr_best_columns(C.nb, C.lookup, a->pos[l], C.plain, a->d.nxb, a->tpb, a->slots, cap);
     const std::vector<int> cr = amr_best_columns(C.nb, C.lookup, a->pos[l], C.rx, a->d.nxb, a->tpb, a->slots, cap);
+    const std::vector<int> zn = amr_zneed(a->pos[l].size() / 4, cp, cr, C.face);
     hipError_t e = hipSuccess;
     if (!cp.empty()) e = hipMemcpyAsync(C.d_plain, cp.data(), sizeof(int) * cp.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !cr.empty())
       e = hipMemcpyAsync(C.d_rx, cr.data(), sizeof(int) * cr.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(C.d_zneed, zn.data(), sizeof(int) * zn.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host tables are temporary
     if (e != hipSuccess) return hip_fail(e, "AMR column table upload");
     a->L.lev[l].ncols_plain = (long)cp.size() / 4;

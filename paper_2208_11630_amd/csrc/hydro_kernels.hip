@@ -1579,21 +1579,30 @@ __global__ __launch_bounds__(256) void amr_fill_level_kernel(GridGeom g, GridGeo
 // Plane halos (PlaneHalo<N>) of the listed blocks of level l, slot after
 // slot, so each workgroup writes whole rows: a position (mapped at level l)
 // inside a block of level l copies its cell, otherwise (level l >= 1) it is
-// prolonged from level l-1.  Every level-0 position has a block.
+// prolonged from level l-1.  Every level-0 position has a block.  The ring
+// planes are always written, the whole planes -2, -1 only when bit 0 of
+// zneed[block] is set and N, N+1 only with bit 1: a block inside a column
+// of z-stacked blocks has neither read (the column's pencil reads the
+// next block's own cells there).
 template <int N>
 __global__ __launch_bounds__(256) void amr_fill_halo_kernel(GridGeom g, GridGeom gp, const int* __restrict__ lookup,
                                                             const int* __restrict__ lookup_p,
                                                             const int4* __restrict__ pos,
                                                             const double* __restrict__ U,
                                                             const double* __restrict__ Up,
-                                                            double* __restrict__ H, const int* __restrict__ list) {
+                                                            double* __restrict__ H, const int* __restrict__ list,
+                                                            const int* __restrict__ zneed) {
   using PH = PlaneHalo<N>;
+  constexpr int NRP = N * PH::RP, FP2 = 2 * PH::FP;
   const int f = list[blockIdx.x];
   const int4 q = pos[f];
+  const int need = zneed[f];
+  const int lowp = (need & 1) ? FP2 : 0, count = NRP + lowp + ((need & 2) ? FP2 : 0);
   const int X0 = q.x * N, Y0 = q.y * N, Z0 = q.z * N;
   const int NX = g.nb[0] * N, NY = g.nb[1] * N, NZ = g.nb[2] * N;
   double* out = H + (long)f * PH::BS;
-  for (int t = threadIdx.x; t < (int)PH::VS; t += blockDim.x) {
+  for (int u = threadIdx.x; u < count; u += blockDim.x) {
+    const int t = u < NRP + lowp ? u : u + (FP2 - lowp);  // slot: skip the low planes when not written
     int i, j, k;
     PH::cell(t, i, j, k);
     const int I = map_axis(X0 + i, NX, g.bc[0]);
@@ -2122,7 +2131,7 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
   if (R.nleaves) {
     if constexpr (HALO)
       hipLaunchKernelGGL(amr_fill_halo_kernel<N>, dim3((unsigned)R.nleaves), dim3(256), 0, s, R.g, R.g, R.lookup,
-                         R.lookup, R.pos, R.U, R.U, R.G, R.leaves);
+                         R.lookup, R.pos, R.U, R.U, R.G, R.leaves, R.zneed);
     else
       hipLaunchKernelGGL((fill_guards_kernel<N, VG>), dim3((unsigned)(R.nleaves * Guarded<N, VG>::P)), dim3(256),
                          0, s, R.g, R.U, R.G, R.leaves);
@@ -2133,7 +2142,7 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
     if (!A.nleaves) continue;
     if constexpr (HALO)
       hipLaunchKernelGGL(amr_fill_halo_kernel<N>, dim3((unsigned)A.nleaves), dim3(256), 0, s, A.g, B.g, A.lookup,
-                         B.lookup, A.pos, A.U, B.U, A.G, A.leaves);
+                         B.lookup, A.pos, A.U, B.U, A.G, A.leaves, A.zneed);
     else
       hipLaunchKernelGGL(amr_fill_level_kernel<N>, dim3((unsigned)A.nleaves), dim3(256), 0, s, A.g, B.g, A.lookup,
                          B.lookup, A.pos, A.U, B.U, A.G, A.leaves);

@@ -864,7 +864,9 @@ struct AmrLevelHost {
   std::vector<int> pos;  // 4 ints per block
   std::vector<unsigned char> flag;
   std::vector<int> lookup, parent, child_base, refined, leaves, leaf_plain, rx_blocks, reflux, first;
+  std::vector<int> roct;  // restriction octants the pass takes (8 r + c)
   size_t o_pos, o_reflux, o_lookup, o_parent, o_child, o_refined, o_leaves, o_plain, o_rx, o_first;  // int offsets
+  size_t o_roct;
   size_t o_cplain, o_crx;  // int offsets of the column tables (room for one column per block)
   size_t o_zneed;          // int offset of the halo-plane table (one per block)
   size_t o_G, o_flux;                                                                                 // bytes
@@ -1084,6 +1086,21 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
       }
     }
   }
+  // octants of the refined blocks left to the restriction pass: those whose
+  // child is refined or takes refluxing (a plain leaf's step writes the
+  // mean of its new state into its parent octant itself)
+  for (int l = 0; l + 1 < A.nlev; ++l) {
+    AmrLevelHost& L = A.lev[l];
+    const AmrLevelHost& F = A.lev[l + 1];
+    std::vector<unsigned char> rx(F.flag.size(), 0);
+    for (int b : F.rx_blocks) rx[b] = 1;
+    L.roct.clear();
+    for (int r : L.refined)
+      for (int c = 0; c < 8; ++c) {
+        const int ch = L.child_base[r] + c;
+        if (F.flag[ch] || rx[ch]) L.roct.push_back(8 * r + c);
+      }
+  }
   // table (ints): int4 arrays first (16-byte aligned), then the int arrays
   size_t t = 0;
   auto take = [&](size_t nints) {
@@ -1098,7 +1115,10 @@ int amr_layout(const hydro_amr_desc* d, AmrLayout& A) {
     L.o_cplain = take(4 * L.leaf_plain.size());
     L.o_crx = take(4 * L.rx_blocks.size());
   }
-  for (int l = 0; l < A.nlev; ++l) A.lev[l].o_zneed = take(A.lev[l].flag.size());
+  for (int l = 0; l < A.nlev; ++l) {
+    A.lev[l].o_zneed = take(A.lev[l].flag.size());
+    A.lev[l].o_roct = take(A.lev[l].roct.size());
+  }
   for (int l = 0; l < A.nlev; ++l) {
     AmrLevelHost& L = A.lev[l];
     L.o_lookup = take(L.lookup.size());
@@ -1246,6 +1266,9 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
     a->cols.push_back(hydro_amr::Cols{{H.nb[0], H.nb[1], H.nb[2]}, H.lookup, H.leaf_plain, H.rx_blocks, face[l],
                                       tab + H.o_cplain, tab + H.o_crx, tab + H.o_zneed});
     V.zneed = tab + H.o_zneed;
+    put(H.o_roct, H.roct);
+    V.roct = tab + H.o_roct;
+    V.nroct = (long)H.roct.size();
     V.cols_plain = (const int4*)(tab + H.o_cplain);
     V.cols_rx = (const int4*)(tab + H.o_crx);
     V.ncols_plain = (long)cplain.size() / 4;

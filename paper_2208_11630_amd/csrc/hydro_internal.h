@@ -128,9 +128,11 @@ struct AmrLevel {
   const int* reflux_first;    // ngroups + 1 offsets into reflux
   const int4* cols_plain;     // leaf_plain as columns of up to 4 z-stacked blocks (bottom first, -1 unused)
   const int4* cols_rx;        // rx_blocks likewise
+  const int* roct;            // restriction octants 8 r + c of the pass (child c of refined block r is
+                              // refined or takes refluxing; the other children's leaf steps restrict)
   const int* zneed;           // per block (n = 8, 16): the whole halo planes its fill writes, bit 0 planes
                               // -2, -1, bit 1 planes n, n+1 (those its column's pencil or a face flux reads)
-  long nblk, nrefined, nleaves, nleaf_plain, nreflux, ngroups, ncols_plain, ncols_rx;
+  long nblk, nrefined, nleaves, nleaf_plain, nreflux, ngroups, ncols_plain, ncols_rx, nroct;
 };
 struct AmrLaunch {
   AmrLevel lev[AMR_MAX_LEVELS];

@@ -441,6 +441,20 @@ struct Smem {
   int sCnt[3];
 };
 
+// Leaf steps over views (GV): the restriction of the new state into the
+// parent block, fused into the update.  Cell (i, j, k) of a block at
+// position (x, y, z) of its level lies in octant (x&1, y&1, z&1) of its
+// parent; the parent cell ((x&1) N + i, (y&1) N + j, (z&1) N + k) / 2 takes
+// the mean of its eight cells, the 2 x 2 of a plane from neighbouring lanes
+// (cells (i, i^1) are lanes t, t^1, rows (j, j^1) lanes t, t^T), then the
+// even plane plus the odd one.  For leaves whose state is final after the
+// step (refluxing leaves it alone); U null: no restriction.
+struct ParentOut {
+  double* U;           // the parent level's state
+  const int* parent;   // parent block of each block of the leaf's level
+  const int4* pos;     // block positions of the leaf's level
+};
+
 // One z pencil of one T x T column tile of an N^3 block, updated from Uin into
 // Uout.  A pencil is plen consecutive planes of the global z axis (part of
 // a block, or several blocks); tile_in_sim = layer * (column tiles of one
@@ -480,7 +494,8 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
                                           WorkHeader* ws, double dt_host, double cfl, int slot,
                                           long tile_in_sim, int plen, Smem<T>& sm,
                                           const StageArgs& st = StageArgs{nullptr, 0.0, 0.0, 0, 1},
-                                          const int4* gv_cols = nullptr, bool gv_emit = false) {
+                                          const int4* gv_cols = nullptr, bool gv_emit = false,
+                                          ParentOut po = ParentOut{nullptr, nullptr, nullptr}) {
   static_assert(!(GV && MOL), "guarded-view input is for the predictor-corrector step");
   using TL = Tile<T>;
   constexpr int NT = TL::NT, NI = TL::NI, NR = TL::NR, NE = TL::NE, WS = TL::WS;
@@ -631,11 +646,13 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   // acc: plane j-1's x/y flux divergence minus its lower z flux, carried to
   // the next plane, whose z flux completes the update of plane j-1
   double zp_prev[5], acc[5];
+  double psum[5];  // GV restriction: the 2 x 2 sums of the even plane
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     Wb[v] = Wc[v] = dzm[v] = dzp[v] = 0.0;
     un_next[v] = u2_next[v] = 0.0;
     zp_prev[v] = acc[v] = 0.0;
+    psum[v] = 0.0;
   }
   int n_floor = 0, n_fb = 0, n_bad = 0;
   double smax = 0.0;
@@ -864,6 +881,27 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
         if (emit) {
           const double s = signal_speed(un, g);
           smax = (s > smax || !(s == s)) ? s : smax;
+        }
+        if constexpr (GV) {
+          if (po.U) {  // (uniform; every lane of the wavefront is an inner cell)
+            double q[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) q[v] = un[v] + __shfl_xor(un[v], 1, 64);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) q[v] = q[v] + __shfl_xor(q[v], T, 64);
+            int kl;
+            const int b = col_block(j - 1, kl);
+            if ((kl & 1) == 0) {
+#pragma unroll
+              for (int v = 0; v < 5; ++v) psum[v] = q[v];
+            } else if (((cx | cy) & 1) == 0) {
+              const int4 bp = po.pos[b];
+              const long pc = Layout<N>::at(po.parent[b], ((bp.x & 1) * N + lx0 + cx) >> 1,
+                                            ((bp.y & 1) * N + ly0 + cy) >> 1, ((bp.z & 1) * N + kl) >> 1);
+#pragma unroll
+              for (int v = 0; v < 5; ++v) po.U[pc + v * VS] = (psum[v] + q[v]) * 0.125;
+            }
+          }
         }
       }
 #pragma unroll
@@ -1634,12 +1672,13 @@ __global__ void amr_begin_kernel(WorkHeader* ws, double dt_host, double cfl, int
 template <int N, int T>
 __global__ __launch_bounds__(Tile<T>::NT, 2) void amr_tile_kernel(GridGeom g, const double* __restrict__ Gin,
                                                                   double* Uout, const int4* __restrict__ cols,
-                                                                  long ntiles, int slot, int emit, WorkHeader* ws) {
+                                                                  long ntiles, int slot, int emit, WorkHeader* ws,
+                                                                  ParentOut po) {
   __shared__ Smem<T> sm;
   const long tile_id = xcd_tile(blockIdx.x, ntiles);
   if (tile_id >= ntiles) return;
   tile_step<N, T, false, true>(g, Gin, Uout, ws, 0.0, 0.0, slot, tile_id, N, sm,
-                               StageArgs{nullptr, 0.0, 0.0, 0, 1}, cols, emit != 0);
+                               StageArgs{nullptr, 0.0, 0.0, 0, 1}, cols, emit != 0, po);
 }
 
 // Face state of cell (i, j, k) of a block on its low (hi = 0) or high
@@ -1979,22 +2018,36 @@ __global__ __launch_bounds__(256) void amr_transfer_level_kernel(GridGeom g, Gri
   }
 }
 
-// Restriction: root block refined[w] takes the mean of its children.
+// Restriction: each cell of a refined block takes the mean of the eight
+// cells of its child that cover it: the 2 x 2 sums of the child's two
+// planes, each in the order (0,0), (1,0), (0,1), (1,1), added -- the
+// order of the leaf step's fused restriction.  Workgroup w covers octant
+// oct[w] = 8 r + c, the part of refined block r over its child c (child
+// cx + 2cy + 4cz covers cells (cx N/2.., cy N/2.., cz N/2..)), or with oct
+// null the octant w % 8 of block refined[w / 8].  The two cells of a fine
+// row that one parent cell takes are one 16-byte load.
 template <int N>
-__global__ __launch_bounds__(256) void amr_restrict_kernel(const int* __restrict__ refined,
+__global__ __launch_bounds__(256) void amr_restrict_kernel(const int* __restrict__ oct,
+                                                           const int* __restrict__ refined,
                                                            const int* __restrict__ child_base,
                                                            const double* __restrict__ Uf, double* __restrict__ Ur) {
   constexpr int H = N / 2;
-  const int r = refined[blockIdx.x];
-  for (int t = threadIdx.x; t < N * N * N; t += blockDim.x) {
-    const int i = t % N, j = (t / N) % N, k = t / (N * N);
-    const int fb = child_base[r] + (i / H) + 2 * (j / H) + 4 * (k / H);
-    const int fi = 2 * (i % H), fj = 2 * (j % H), fk = 2 * (k % H);
+  const int w = oct ? oct[blockIdx.x] : 8 * refined[blockIdx.x >> 3] + (int)(blockIdx.x & 7);
+  const int r = w >> 3;
+  const int c = w & 7;
+  const long fb = child_base[r] + c;
+  const int i0 = (c & 1) * H, j0 = ((c >> 1) & 1) * H, k0 = (c >> 2) * H;
+  for (int t = threadIdx.x; t < H * H * H; t += blockDim.x) {
+    const int ii = t % H, jj = (t / H) % H, kk = t / (H * H);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      double s = 0.0;
-      for (int q = 0; q < 8; ++q) s += Uf[Layout<N>::at(fb, fi + (q & 1), fj + ((q >> 1) & 1), fk + ((q >> 2) & 1)) + v * Layout<N>::VS];
-      Ur[Layout<N>::at(r, i, j, k) + v * Layout<N>::VS] = s * 0.125;
+      const double* f = Uf + Layout<N>::at(fb, 2 * ii, 2 * jj, 2 * kk) + v * Layout<N>::VS;
+      const double2 a = *(const double2*)f;
+      const double2 b = *(const double2*)(f + N);
+      const double2 e = *(const double2*)(f + N * N);
+      const double2 h = *(const double2*)(f + N * N + N);
+      const double s0 = (a.x + a.y) + (b.x + b.y), s1 = (e.x + e.y) + (h.x + h.y);
+      Ur[Layout<N>::at(r, i0 + ii, j0 + jj, k0 + kk) + v * Layout<N>::VS] = (s0 + s1) * 0.125;
     }
   }
 }
@@ -2159,16 +2212,19 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
   // 3. leaf steps (fused tile step over the views), written over the state:
   //    every read of another block's old state goes to the views.  Leaves
   //    next to a refined block reduce their signal speed after refluxing
-  //    instead.
-  auto tiles = [&](const AmrLevel& A, const int4* cols, long ncols, int emit) {
+  //    instead.  The other leaves of levels >= 1 also write the restriction
+  //    of their new state into their parent octant.
+  auto tiles = [&](const AmrLevel& A, const int4* cols, long ncols, int emit, ParentOut po) {
     if (!ncols) return;
     const long nt = ncols * TPB;
     hipLaunchKernelGGL((amr_tile_kernel<N, T>), dim3((unsigned)(8 * ((nt + 7) / 8))), dim3(Tile<T>::NT), 0, s, A.g,
-                       A.G, A.U, cols, nt, slot, emit, L.ws);
+                       A.G, A.U, cols, nt, slot, emit, L.ws, po);
   };
   for (int l = 0; l < L.nlev; ++l) {
-    tiles(L.lev[l], L.lev[l].cols_plain, L.lev[l].ncols_plain, 1);
-    tiles(L.lev[l], L.lev[l].cols_rx, L.lev[l].ncols_rx, 0);
+    const AmrLevel& A = L.lev[l];
+    const ParentOut po = l ? ParentOut{L.lev[l - 1].U, A.parent, A.pos} : ParentOut{nullptr, nullptr, nullptr};
+    tiles(A, A.cols_plain, A.ncols_plain, 1, po);
+    tiles(A, A.cols_rx, A.ncols_rx, 0, ParentOut{nullptr, nullptr, nullptr});
   }
   // 4. refluxing
   for (int l = 0; l + 1 < L.nlev; ++l) {
@@ -2178,12 +2234,13 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL(amr_reflux_kernel<N>, dim3((unsigned)A.ngroups), dim3(256), 0, s, A.g, A.reflux,
                        A.reflux_first, A.flux, B.flux, A.child_base, A.U, L.ws, slot);
   }
-  // 5. restriction, finest level first
+  // 5. restriction of the octants over refined or refluxed children,
+  //    finest level first
   for (int l = L.nlev - 2; l >= 0; --l) {
     const AmrLevel& A = L.lev[l];
-    if (A.nrefined)
-      hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)A.nrefined), dim3(256), 0, s, A.refined,
-                         A.child_base, L.lev[l + 1].U, A.U);
+    if (A.nroct)
+      hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)A.nroct), dim3(N == 8 ? 64 : 256), 0, s, A.roct,
+                         A.refined, A.child_base, L.lev[l + 1].U, A.U);
   }
   return hipGetLastError();
 }
@@ -2212,8 +2269,8 @@ void launch_amr_adapt_t(const AmrLaunch& L, double eps, double* E2, double* cons
     for (int l = L.nlev - 2; l >= 0; --l) {
       const AmrLevel& A = L.lev[l];
       if (A.nrefined)
-        hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)A.nrefined), dim3(256), 0, s, A.refined,
-                           A.child_base, L.lev[l + 1].U, A.U);
+        hipLaunchKernelGGL(amr_restrict_kernel<N>, dim3((unsigned)(8 * A.nrefined)), dim3(N == 8 ? 64 : 256), 0, s,
+                           (const int*)nullptr, A.refined, A.child_base, L.lev[l + 1].U, A.U);
     }
   }
 }

@@ -945,6 +945,14 @@ std::vector<int> amr_zneed(size_t nblk, const std::vector<int>& cp, const std::v
   return z;
 }
 
+// Longest column of a column table (blocks).
+int amr_kmax(const std::vector<int>& cols) {
+  int k = 0;
+  for (size_t i = 0; i + 3 < cols.size(); i += 4)
+    k = std::max(k, 1 + (cols[i + 1] >= 0) + (cols[i + 2] >= 0) + (cols[i + 3] >= 0));
+  return k;
+}
+
 // Column length for a leaf list: `cap` when it is 1, 2 or 4, else (0) the
 // one whose tiles, dealt in order to `slots` workgroup slots (each tile of
 // a column of k blocks costs k*N + 3 planes: the pencil and its z halo),
@@ -1273,6 +1281,8 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
     V.cols_rx = (const int4*)(tab + H.o_crx);
     V.ncols_plain = (long)cplain.size() / 4;
     V.ncols_rx = (long)crx.size() / 4;
+    V.kmax_plain = amr_kmax(cplain);
+    V.kmax_rx = amr_kmax(crx);
     V.pos = (const int4*)(tab + H.o_pos);
     V.reflux = (const int4*)(tab + H.o_reflux);
     V.lookup = tab + H.o_lookup;
@@ -1298,6 +1308,7 @@ int hydro_amr_create(const hydro_amr_desc* d, hydro_amr** out) {
   L.cfl = 0.0;
   L.slot = 0;
   hipStream_t s = (hipStream_t)d->stream;
+  hydro::amr_segments(N, L, L.segs);
   hipError_t e = hipMemsetAsync(w, 0, 256, s);
   if (e == hipSuccess && !host.empty())
     e = hipMemcpyAsync(tab, host.data(), sizeof(int) * host.size(), hipMemcpyHostToDevice, s);
@@ -1635,7 +1646,10 @@ int hydro_amr_set_columns(hydro_amr* a, int cap) {
     if (e != hipSuccess) return hip_fail(e, "AMR column table upload");
     a->L.lev[l].ncols_plain = (long)cp.size() / 4;
     a->L.lev[l].ncols_rx = (long)cr.size() / 4;
+    a->L.lev[l].kmax_plain = amr_kmax(cp);
+    a->L.lev[l].kmax_rx = amr_kmax(cr);
   }
+  hydro::amr_segments(a->d.nxb, a->L, a->L.segs);
   return HYDRO_OK;
 }
 

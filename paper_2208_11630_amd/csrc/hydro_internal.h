@@ -133,16 +133,49 @@ struct AmrLevel {
   const int* zneed;           // per block (n = 8, 16): the whole halo planes its fill writes, bit 0 planes
                               // -2, -1, bit 1 planes n, n+1 (those its column's pencil or a face flux reads)
   long nblk, nrefined, nleaves, nleaf_plain, nreflux, ngroups, ncols_plain, ncols_rx, nroct;
+  int kmax_plain, kmax_rx;    // longest column of each list (blocks)
+};
+// Leaf steps over views: the restriction of the new state into the parent
+// block, fused into the update (U null: none; see tile_step).
+struct ParentOut {
+  double* U;           // the parent level's state
+  const int* parent;   // parent block of each block of the leaf's level
+  const int4* pos;     // block positions of the leaf's level
+};
+// One column list of an AMR step's leaf-step launch: the launch's
+// workgroups first .. first + ncols * (column tiles per block) - 1 step the
+// columns of `cols` on level geometry g.
+struct AmrSeg {
+  GridGeom g;
+  const double* G;     // the level's leaf views
+  double* U;           // the level's state
+  const int4* cols;
+  ParentOut po;
+  long first;
+  int emit;            // reduce the new state's signal speed
+  int pad;
+};
+constexpr int AMR_MAX_SEGS = 2 * AMR_MAX_LEVELS;
+// The segments, passed by value as a kernel argument (kernel-argument
+// memory is constant, so their fields stay loaded across barriers).
+struct AmrSegs {
+  AmrSeg s[AMR_MAX_SEGS];
+  int n;
+  long tiles;                 // the launch's workgroups
 };
 struct AmrLaunch {
   AmrLevel lev[AMR_MAX_LEVELS];
   int nlev;
+  AmrSegs segs;               // the leaf-step launch (amr_segments)
   WorkHeader* ws;
   double dt;                  // used when cfl <= 0
   double cfl;                 // > 0: dt = cfl / ws->sig[slot]
   int slot;                   // step number mod 3
 };
 hipError_t launch_amr_step(int nxb, const AmrLaunch& L, hipStream_t s);
+// The leaf-step launch's segments: every nonempty column list of every
+// level, longest columns first.
+void amr_segments(int nxb, const AmrLaunch& L, AmrSegs& out);
 hipError_t launch_amr_signal(int nxb, const AmrLaunch& L, int slot, hipStream_t s);
 // Refinement indicator per root block into E2[nroot] (device).
 hipError_t launch_amr_indicator(int nxb, const AmrLaunch& L, double eps, double* E2, hipStream_t s);

@@ -30,6 +30,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 #include <mutex>
 
 namespace hydro {
@@ -441,19 +443,14 @@ struct Smem {
   int sCnt[3];
 };
 
-// Leaf steps over views (GV): the restriction of the new state into the
-// parent block, fused into the update.  Cell (i, j, k) of a block at
+// Leaf steps over views (GV) may restrict the new state into the parent
+// block (ParentOut), fused into the update.  Cell (i, j, k) of a block at
 // position (x, y, z) of its level lies in octant (x&1, y&1, z&1) of its
 // parent; the parent cell ((x&1) N + i, (y&1) N + j, (z&1) N + k) / 2 takes
 // the mean of its eight cells, the 2 x 2 of a plane from neighbouring lanes
 // (cells (i, i^1) are lanes t, t^1, rows (j, j^1) lanes t, t^T), then the
 // even plane plus the odd one.  For leaves whose state is final after the
-// step (refluxing leaves it alone); U null: no restriction.
-struct ParentOut {
-  double* U;           // the parent level's state
-  const int* parent;   // parent block of each block of the leaf's level
-  const int4* pos;     // block positions of the leaf's level
-};
+// step (refluxing leaves it alone).
 
 // One z pencil of one T x T column tile of an N^3 block, updated from Uin into
 // Uout.  A pencil is plen consecutive planes of the global z axis (part of
@@ -495,7 +492,8 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
                                           long tile_in_sim, int plen, Smem<T>& sm,
                                           const StageArgs& st = StageArgs{nullptr, 0.0, 0.0, 0, 1},
                                           const int4* gv_cols = nullptr, bool gv_emit = false,
-                                          ParentOut po = ParentOut{nullptr, nullptr, nullptr}) {
+                                          ParentOut po = ParentOut{nullptr, nullptr, nullptr},
+                                          double* psum = nullptr) {
   static_assert(!(GV && MOL), "guarded-view input is for the predictor-corrector step");
   using TL = Tile<T>;
   constexpr int NT = TL::NT, NI = TL::NI, NR = TL::NR, NE = TL::NE, WS = TL::WS;
@@ -646,13 +644,11 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
   // acc: plane j-1's x/y flux divergence minus its lower z flux, carried to
   // the next plane, whose z flux completes the update of plane j-1
   double zp_prev[5], acc[5];
-  double psum[5];  // GV restriction: the 2 x 2 sums of the even plane
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     Wb[v] = Wc[v] = dzm[v] = dzp[v] = 0.0;
     un_next[v] = u2_next[v] = 0.0;
     zp_prev[v] = acc[v] = 0.0;
-    psum[v] = 0.0;
   }
   int n_floor = 0, n_fb = 0, n_bad = 0;
   double smax = 0.0;
@@ -891,15 +887,18 @@ __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __res
             for (int v = 0; v < 5; ++v) q[v] = q[v] + __shfl_xor(q[v], T, 64);
             int kl;
             const int b = col_block(j - 1, kl);
-            if ((kl & 1) == 0) {
+            if (((cx | cy) & 1) == 0) {  // one lane per 2 x 2; psum: its even-plane sums (LDS, own slot)
+              double* ps = psum + (cy >> 1) * (T / 2) + (cx >> 1);
+              if ((kl & 1) == 0) {
 #pragma unroll
-              for (int v = 0; v < 5; ++v) psum[v] = q[v];
-            } else if (((cx | cy) & 1) == 0) {
-              const int4 bp = po.pos[b];
-              const long pc = Layout<N>::at(po.parent[b], ((bp.x & 1) * N + lx0 + cx) >> 1,
-                                            ((bp.y & 1) * N + ly0 + cy) >> 1, ((bp.z & 1) * N + kl) >> 1);
+                for (int v = 0; v < 5; ++v) ps[v * (NI / 4)] = q[v];
+              } else {
+                const int4 bp = po.pos[b];
+                const long pc = Layout<N>::at(po.parent[b], ((bp.x & 1) * N + lx0 + cx) >> 1,
+                                              ((bp.y & 1) * N + ly0 + cy) >> 1, ((bp.z & 1) * N + kl) >> 1);
 #pragma unroll
-              for (int v = 0; v < 5; ++v) po.U[pc + v * VS] = (psum[v] + q[v]) * 0.125;
+                for (int v = 0; v < 5; ++v) po.U[pc + v * VS] = (ps[v * (NI / 4)] + q[v]) * 0.125;
+              }
             }
           }
         }
@@ -1665,20 +1664,25 @@ __global__ void amr_begin_kernel(WorkHeader* ws, double dt_host, double cfl, int
   ws->sig[(slot + 2) % 3] = 0ull;
 }
 
-// Leaf step: the fused tile step over the leaf views, one workgroup per
-// column tile of a column of z-stacked blocks (the whole z extent of its
-// blocks), columns cols[0..ncols) (tile_step's gv_cols), XCD-aware order;
-// emit: reduce the new state's signal speed into ws->sig[(slot+1)%3].
+// Leaf steps of every level in one launch: workgroup w steps column tile
+// w - first of the segment holding w (segments in order of `first`), the
+// fused tile step over that level's leaf views (the whole z extent of a
+// column of z-stacked blocks, tile_step's gv_cols).  Segments with the
+// longest columns come first, so the longest workgroups start first.  The
+// leaf steps are independent of each other (each reads its own views and
+// cells and writes its own cells and parent octant), so one launch holds
+// them all.
 template <int N, int T>
-__global__ __launch_bounds__(Tile<T>::NT, 2) void amr_tile_kernel(GridGeom g, const double* __restrict__ Gin,
-                                                                  double* Uout, const int4* __restrict__ cols,
-                                                                  long ntiles, int slot, int emit, WorkHeader* ws,
-                                                                  ParentOut po) {
+__global__ __launch_bounds__(Tile<T>::NT, 2) void amr_tile_kernel(AmrSegs S, int slot, WorkHeader* ws) {
   __shared__ Smem<T> sm;
-  const long tile_id = xcd_tile(blockIdx.x, ntiles);
-  if (tile_id >= ntiles) return;
-  tile_step<N, T, false, true>(g, Gin, Uout, ws, 0.0, 0.0, slot, tile_id, N, sm,
-                               StageArgs{nullptr, 0.0, 0.0, 0, 1}, cols, emit != 0, po);
+  __shared__ double psum[5 * Tile<T>::NI / 4];  // fused restriction: even-plane 2 x 2 sums
+  const long w = blockIdx.x;
+  if (w >= S.tiles) return;
+  int q = 0;
+  while (q + 1 < S.n && w >= S.s[q + 1].first) ++q;
+  const AmrSeg& a = S.s[q];
+  tile_step<N, T, false, true>(a.g, a.G, a.U, ws, 0.0, 0.0, slot, w - a.first, N, sm,
+                               StageArgs{nullptr, 0.0, 0.0, 0, 1}, a.cols, a.emit != 0, a.po, psum);
 }
 
 // Face state of cell (i, j, k) of a block on its low (hi = 0) or high
@@ -2172,7 +2176,6 @@ hipError_t launch_step(int nxb, int tile, const GridGeom& g, const StepArgs& a, 
 template <int N>
 hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
   constexpr int T = N == 8 ? 8 : 16;
-  constexpr long TPB = (N / T) * (N / T);
   const int slot = L.slot;
   hipLaunchKernelGGL(amr_begin_kernel, dim3(1), dim3(1), 0, s, L.ws, L.dt, L.cfl, slot);
   // 1. views: level 0 by the same-level map, deeper levels by copies and
@@ -2209,23 +2212,15 @@ hipError_t launch_amr_t(const AmrLaunch& L, hipStream_t s) {
       hipLaunchKernelGGL(amr_face_flux_kernel<N>, dim3((unsigned)(5 * A.nreflux)), dim3(256), 0, s, A.g, B.g,
                          A.reflux, A.child_base, A.G, B.G, A.U, B.U, A.flux, B.flux, (const WorkHeader*)L.ws);
   }
-  // 3. leaf steps (fused tile step over the views), written over the state:
-  //    every read of another block's old state goes to the views.  Leaves
-  //    next to a refined block reduce their signal speed after refluxing
-  //    instead.  The other leaves of levels >= 1 also write the restriction
-  //    of their new state into their parent octant.
-  auto tiles = [&](const AmrLevel& A, const int4* cols, long ncols, int emit, ParentOut po) {
-    if (!ncols) return;
-    const long nt = ncols * TPB;
-    hipLaunchKernelGGL((amr_tile_kernel<N, T>), dim3((unsigned)(8 * ((nt + 7) / 8))), dim3(Tile<T>::NT), 0, s, A.g,
-                       A.G, A.U, cols, nt, slot, emit, L.ws, po);
-  };
-  for (int l = 0; l < L.nlev; ++l) {
-    const AmrLevel& A = L.lev[l];
-    const ParentOut po = l ? ParentOut{L.lev[l - 1].U, A.parent, A.pos} : ParentOut{nullptr, nullptr, nullptr};
-    tiles(A, A.cols_plain, A.ncols_plain, 1, po);
-    tiles(A, A.cols_rx, A.ncols_rx, 0, ParentOut{nullptr, nullptr, nullptr});
-  }
+  // 3. leaf steps (fused tile step over the views, one launch for every
+  //    level: amr_segments), written over the state: every read of another
+  //    block's old state goes to the views.  Leaves next to a refined block
+  //    reduce their signal speed after refluxing instead.  The other leaves
+  //    of levels >= 1 also write the restriction of their new state into
+  //    their parent octant.
+  if (L.segs.tiles)
+    hipLaunchKernelGGL((amr_tile_kernel<N, T>), dim3((unsigned)L.segs.tiles), dim3(Tile<T>::NT), 0, s, L.segs, slot,
+                       L.ws);
   // 4. refluxing
   for (int l = 0; l + 1 < L.nlev; ++l) {
     const AmrLevel& A = L.lev[l];
@@ -2294,6 +2289,34 @@ hipError_t launch_amr_leaf_indicator(int nxb, const AmrLaunch& L, double eps, do
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+void amr_segments(int nxb, const AmrLaunch& L, AmrSegs& out) {
+  const int T = nxb == 8 ? 8 : 16;
+  const long tpb = (long)(nxb / T) * (nxb / T);
+  struct Cand {
+    AmrSeg s;
+    int k;
+    long ntiles;
+  };
+  Cand c[AMR_MAX_SEGS];
+  int n = 0;
+  for (int l = 0; l < L.nlev; ++l) {
+    const AmrLevel& A = L.lev[l];
+    const ParentOut none{nullptr, nullptr, nullptr};
+    const ParentOut po = l ? ParentOut{L.lev[l - 1].U, A.parent, A.pos} : none;
+    if (A.ncols_plain) c[n++] = Cand{AmrSeg{A.g, A.G, A.U, A.cols_plain, po, 0, 1, 0}, A.kmax_plain, A.ncols_plain * tpb};
+    if (A.ncols_rx) c[n++] = Cand{AmrSeg{A.g, A.G, A.U, A.cols_rx, none, 0, 0, 0}, A.kmax_rx, A.ncols_rx * tpb};
+  }
+  std::stable_sort(c, c + n, [](const Cand& a, const Cand& b) { return a.k > b.k; });
+  long first = 0;
+  for (int i = 0; i < n; ++i) {
+    out.s[i] = c[i].s;
+    out.s[i].first = first;
+    first += c[i].ntiles;
+  }
+  out.n = n;
+  out.tiles = first;
 }
 
 hipError_t launch_amr_transfer(int nxb, const AmrLaunch& from, const AmrLaunch& to, hipStream_t s) {

@@ -1528,8 +1528,11 @@ __global__ __launch_bounds__(CtuTile::NT) void ctu_tile_kernel(GridGeom g, StepA
 // of each refined block of level l.  Kernels: the leaves' guard views
 // (copies of same-level cells, prolongation from the level above), the
 // fluxes at fine-coarse faces that refluxing uses (formed before the leaf
-// steps), the leaf step (the fused tile step over the views), refluxing,
-// restriction, the refinement indicators and the regrid transfer.
+// steps), the leaf steps of every level in one launch (the fused tile step
+// over the views; a leaf that refluxing leaves alone also restricts its new
+// state into its parent), refluxing, the restriction of the parent octants
+// over refined or refluxed children, the refinement indicators and the
+// regrid transfer.
 
 template <int N>
 struct AmrStep {

@@ -504,6 +504,28 @@ def test_amr_tree_column_length_is_bitwise_invariant(hy, case):
         assert d == ref[1] and np.array_equal(c, ref[2]), (case, cap)
 
 
+@pytest.mark.parametrize("case", ["n8_2x2x2_one", "n16_2x2x1_periodic_z1", "tree:n8_three_levels"])
+def test_amr_column_length_change_mid_run_is_bitwise(hy, case):
+    """Changing the column length between steps rebuilds the column,
+    halo-plane and launch tables: a block that ends a column only after the
+    change gets its whole halo planes written again, so five steps with
+    lengths 4, 4, 1, 2, 2 give the bits of five steps with length 1."""
+    if case.startswith("tree:"):
+        t, U = _tree_case(case[5:])
+        build = lambda: _tree_gpu(hy, t, U)
+    else:
+        build = lambda: make(hy, case)[3]
+    ref = _run_columns(hy, build, 1, steps=5)
+    A = build()
+    for cap in (4, 4, 1, 2, 2):
+        A.set_columns(cap)
+        A.step_cfl(0.8)
+    (R, F), d, c = A.download(), A.last_dt(), A.counters()
+    A.close()
+    assert np.array_equal(R, ref[0][0]) and np.array_equal(F, ref[0][1]), case
+    assert d == ref[1] and np.array_equal(c, ref[2]), case
+
+
 def test_amr_column_argument_errors(hy):
     A = make(hy, "n8_2x2x2_one")[3]
     for bad in (-1, 3, 5, 8):

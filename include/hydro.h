@@ -336,7 +336,9 @@ const char *hydro_last_error(void);
  *   3. refluxing: a leaf next to a refined block of its level replaces the
  *      flux of each cell on that face by the mean of the four finer fluxes;
  *   4. restriction, finest level first: refined blocks take the mean of
- *      their children.
+ *      their children (a cell: the two 2 x 2 sums of its eight child cells'
+ *      planes, added, times 1/8; the children that refluxing leaves alone
+ *      write it from their own step).
  * Layouts (device, caller-owned, 256-byte aligned): Ur [nroot][5][nxb^3]
  * (block id bx + nb0*(by + nb1*bz)); Uf: the blocks of levels 1, 2, ...
  * concatenated, [5][nxb^3] each.  The step updates Ur and Uf in place: a

@@ -486,6 +486,9 @@ struct Smem {
 // The result goes to the blocks in compact layout in Uout, dt is the one
 // recorded in ws->dt_last, and the new state's signal speed goes to
 // ws->sig[(slot+1)%3] only when gv_emit is set (event counters always).
+// With po.U set, the new state's restriction also goes to the parent
+// blocks (ParentOut above), the even planes' 2 x 2 sums held in psum
+// (LDS, 5 (T/2)^2 doubles, each slot used by one thread only).
 template <int N, int T, bool MOL = false, bool GV = false>
 __device__ __forceinline__ void tile_step(const GridGeom& g, const double* __restrict__ Uin, double* Uout,
                                           WorkHeader* ws, double dt_host, double cfl, int slot,

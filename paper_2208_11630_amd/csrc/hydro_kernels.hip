@@ -977,7 +977,7 @@ __global__ __launch_bounds__(Tile<T>::NT, 2) void batch_step_kernel(const BatchS
   const int end = min(nitems, (x + 1) * per);
   for (int it = x * per + l; it < end; it += nx) {
     const BatchItem w = items[it];
-    const BatchSim& d = sims[w.sim];
+    const BatchSim d = sims[w.sim];  // a copy: its fields stay loaded across the tile step's barriers
     const int par = (int)((d.parity0 + step) & 1);
     const int slot = (int)((d.slot0 + step) % 3);
     const double* Uin = par ? d.U1 : d.U0;

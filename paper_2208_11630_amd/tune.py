@@ -9,8 +9,8 @@ advanced).  Results are cached as JSON (``HYDRO_TUNE_CACHE``, default
 signature.
 
 Tunables:
-  * planes per z pencil (one workgroup each): for a single grid any divisor
-    of its z extent from nxb/4 to 8*nxb (pencils may span several blocks:
+  * planes per z pencil (one workgroup each): for a single grid 2, nxb/8,
+    nxb/4, ... 8*nxb where they divide its z extent (pencils may span several blocks:
     fewer halo planes re-read per updated plane on tall grids; shorter
     pencils fill the 256 CUs on small grids); for batches 1, 2 or 4 pencils
     per block column per block size;
@@ -89,7 +89,7 @@ def grid_signature(G: "hydro.Grid") -> str:
 
 def pencil_candidates(G: "hydro.Grid") -> List[int]:
     nz = G.nblk[2] * G.nxb
-    return [p for p in (G.nxb // 4, G.nxb // 2, G.nxb, 2 * G.nxb, 4 * G.nxb, 8 * G.nxb)
+    return [p for p in sorted({2, G.nxb // 8, G.nxb // 4, G.nxb // 2, G.nxb, 2 * G.nxb, 4 * G.nxb, 8 * G.nxb})
             if p >= 2 and p <= nz and nz % p == 0]
 
 

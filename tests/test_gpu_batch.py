@@ -124,7 +124,7 @@ def test_grid_pencils_bitwise_invariant(hy, nseg):
     assert np.array_equal(a, b) and da == db
 
 
-@pytest.mark.parametrize("planes", [8, 32, 64, 128])
+@pytest.mark.parametrize("planes", [2, 8, 32, 64, 128])
 @pytest.mark.parametrize("case", ["kh", "outflow_n8"])
 def test_grid_pencil_planes_bitwise_invariant(hy, planes, case):
     """Pencils spanning several blocks along z (or part of one) give the same

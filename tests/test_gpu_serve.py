@@ -47,6 +47,10 @@ def test_served_states_equal_alone(env):
     print("served:", s, flush=True)
     assert s["completed"] == len(arr)
     assert st.evictions > 0
+    # state bytes copied each way: every copy in follows a copy out, and a
+    # state is 40 B per cell of whole 16^3 blocks
+    assert ex.moved["out"] > 0 and ex.moved["in"] <= ex.moved["out"]
+    assert ex.moved["out"] % (40 * 16 ** 3) == 0 and ex.moved["in"] % (40 * 16 ** 3) == 0
     for sim, L in enumerate(sizes):
         k = ex.steps_done[sim]
         got = ex.current_state(sim)
